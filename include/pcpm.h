@@ -1,0 +1,161 @@
+/*
+ * pcpm.h -- C ABI of libpcpm: Partition-Centric Processing (PCPM) PageRank
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lakhotia, Kannan, Prasanna, "Accelerating PageRank using
+ * Partition-Centric Processing" (arXiv 1709.07122).  Section references
+ * below are to that paper.
+ *
+ * Conventions for every entry point
+ *   - Pointers are HIP device pointers owned by the caller unless marked
+ *     (host).  Inputs are never modified.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     All device work of a call is ordered on that stream.
+ *   - Every call returns a pcpm_status_t and never aborts the process.  On an
+ *     error the outputs are undefined, except PCPM_ERR_NOT_CONVERGED, which
+ *     leaves valid ranks, iteration count and residual.  pcpm_last_error()
+ *     returns a message for the calling thread's last failure.
+ *   - A graph is a directed CSR: row_off[n+1] (int32, row_off[0] = 0,
+ *     row_off[n] = m, non-decreasing) and col[m] (int32), every row sorted
+ *     strictly ascending (no duplicate edges), no self-loops.  n < 2^31 because
+ *     the top bit of a destination ID is reserved as the message flag
+ *     (Sec. 3.2), and m < 2^31.
+ *   - A handle may be used by one stream at a time; calls on one handle that
+ *     overlap in time race on its scratch buffers.
+ *   - Ranks are FP32; the L1 residual and the dangling mass are accumulated
+ *     in FP64 on the device.
+ */
+#ifndef PCPM_H
+#define PCPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PCPM_OK = 0,
+  PCPM_ERR_INVALID_ARG = 1,  /* bad size, pointer, q, d, tol or iteration cap  */
+  PCPM_ERR_GRAPH = 2,        /* CSR breaks the conventions above             */
+  PCPM_ERR_OVERFLOW = 3,     /* n or m >= 2^31                               */
+  PCPM_ERR_OOM = 4,          /* device allocation failed                     */
+  PCPM_ERR_DEVICE = 5,       /* HIP runtime or launch failure                */
+  PCPM_ERR_NOT_CONVERGED = 6,/* max_iters reached above tol (outputs valid)  */
+  PCPM_ERR_NUMERIC = 7       /* residual or dangling mass became non-finite   */
+} pcpm_status_t;
+
+typedef struct pcpm_png* pcpm_png_t;
+
+/* Build options.  Zero-initialise and set what you need. */
+typedef struct {
+  int32_t part_log2;     /* q = 2^part_log2 nodes per partition (Sec. 3.1),
+                            1..15 (the q*4-byte rank slice lives in the LDS of
+                            one compute unit) with k = ceil(n/q) <= 16384;
+                            0 = 14 (q = 16384)                                */
+  int32_t reserved0;
+  int64_t scatter_chunk; /* PNG edges per scatter work item; 0 = automatic   */
+  int64_t gather_chunk;  /* destination IDs per gather work item; 0 = auto   */
+} pcpm_build_opts_t;
+
+typedef struct {
+  int64_t n, m;          /* nodes, edges                                      */
+  int64_t q, k;          /* partition size and count, k = ceil(n/q)           */
+  int64_t eprime;        /* |E'|: PNG edges = updates per iteration (Sec. 3.3) */
+  int64_t nseg;          /* non-empty (source, destination) partition pairs   */
+  int64_t n_dangling;    /* nodes without out-edges                           */
+  int64_t scatter_items; /* scatter work items                                */
+  int64_t gather_items;  /* gather work items                                 */
+  int64_t split_bins;    /* destination bins gathered by more than one item   */
+  int64_t device_bytes;  /* device memory held by the handle                  */
+  double build_ms;       /* wall time of pcpm_build_png, device work included */
+} pcpm_png_info_t;
+
+/*
+ * Pre-processing (Sec. 3.1 partitioning and write offsets, Sec. 3.3 PNG
+ * construction): partitions P_i = [i*q, (i+1)*q); for every source partition
+ * p and destination partition p' the list U(p,p') of nodes of p with an
+ * out-edge into p' (one update per node and destination partition,
+ * Sec. 3.2), the update-bin write offsets ordered by source partition ID,
+ * and the destination-ID bins with the top bit set on the first ID of each
+ * message.  Validates the CSR (PCPM_ERR_GRAPH) and keeps every buffer the
+ * iterations need, so the iteration calls allocate nothing.
+ * Synchronises `stream`.  *out receives a handle owning its device memory.
+ */
+pcpm_status_t pcpm_build_png(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col,
+                             const pcpm_build_opts_t* opts /* (host) nullable */, void* stream,
+                             pcpm_png_t* out /* (host) */);
+
+/* Sizes and statistics of a built handle (host struct). */
+pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out /* (host) */);
+
+/*
+ * Copy the layout to host arrays in its canonical form (any pointer may be
+ * NULL to skip that array); all arrays are (host):
+ *   png_off[k][k+1]  per source partition p: sum over p'' < j of |U(p,p'')|
+ *   png_src[E']      U(p,p') concatenated over p, then p' (node IDs, no flag)
+ *   upd_start[k+1]   first update slot of each destination bin
+ *   wo[k][k]         write offset of partition p into bin p' (Sec. 3.1):
+ *                    sum over p'' < p of |U(p'',p')|
+ *   did_start[k+1]   first destination-ID position of each bin
+ *   did[m]           destination IDs in bin order, top bit = first of message
+ * Synchronises the device.
+ */
+pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src,
+                              int64_t* upd_start, int64_t* wo, int64_t* did_start,
+                              uint32_t* did);
+
+/* Release a handle and its device memory (NULL is ignored). */
+void pcpm_png_free(pcpm_png_t g);
+
+/*
+ * One PageRank iteration (Eq. 1, Sec. 2.1) carried out as PCPM scatter
+ * (Alg. 3 over the PNG), gather (Alg. 5, branch-free) and apply (Alg. 2):
+ *   pr_out(v) = (1-d)/n + d * ( sum_{u->v} pr_in(u)/outdeg(u) + D/n )
+ * with D the FP64 sum of pr_in over dangling nodes (their mass is spread
+ * uniformly).  pr_in and pr_out (n floats each) must not overlap.  If resid
+ * is non-NULL the FP64 L1 distance sum_v |pr_out(v) - pr_in(v)| is written
+ * there and the call synchronises `stream`.  0 <= d < 1.
+ */
+pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr_out,
+                           double* resid /* (host) nullable */, void* stream);
+
+/*
+ * PageRank to convergence: starts from init (n floats, used as given) or,
+ * when init is NULL, from 1/n everywhere; iterates as pcpm_iterate until the
+ * FP64 L1 residual of an iteration is below tol (then pr_out holds that
+ * iteration's output) or max_iters iterations have run.  tol <= 0 runs
+ * exactly max_iters iterations and returns PCPM_OK.  *iters receives the
+ * number of iterations run, *resid the last residual, res_hist (host,
+ * nullable, max_iters entries) every residual.  1 <= max_iters <= 100000.
+ * Synchronises `stream`.
+ */
+pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iters,
+                            const float* init /* nullable */, float* pr_out,
+                            int32_t* iters /* (host) */, double* resid /* (host) */,
+                            double* res_hist /* (host) nullable */, void* stream);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* pcpm_last_error(void);
+
+/*
+ * Per-kernel device timing (HIP events recorded around every launch on the
+ * launch stream).  pcpm_timing_enable(1) starts recording, (0) stops it.
+ * pcpm_timing_collect synchronises the recorded events, fills up to
+ * max_entries (host) records, returns how many kernels had launches and
+ * clears the record.
+ */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} pcpm_kernel_time_t;
+
+void pcpm_timing_enable(int on);
+int pcpm_timing_collect(pcpm_kernel_time_t* out /* (host) */, int max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCPM_H */

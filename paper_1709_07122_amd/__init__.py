@@ -1,0 +1,16 @@
+"""PCPM PageRank on AMD MI355X (gfx950).
+
+Python face of libpcpm (see include/pcpm.h): the Partition-Centric Processing
+Methodology of Lakhotia, Kannan and Prasanna (arXiv 1709.07122) as
+hand-written HIP kernels.  This package only marshals arguments; PyTorch
+provides device memory and streams.
+"""
+from ._pcpm import (EXPORTS, LIB_PATH, PCPM_ERR_GRAPH, PCPM_ERR_INVALID_ARG, PCPM_ERR_NOT_CONVERGED,
+                    PCPM_ERR_NUMERIC, PCPM_ERR_OVERFLOW, PCPM_OK, PNG, PCPMError, PagerankResult, build_png,
+                    iterate, last_error, lib, pagerank, timing_collect, timing_enable)
+from . import commmodel
+
+__all__ = ["EXPORTS", "LIB_PATH", "PNG", "PCPMError", "PagerankResult", "build_png", "iterate", "pagerank",
+           "last_error", "lib", "timing_enable", "timing_collect", "commmodel", "PCPM_OK",
+           "PCPM_ERR_GRAPH", "PCPM_ERR_INVALID_ARG", "PCPM_ERR_NOT_CONVERGED", "PCPM_ERR_NUMERIC",
+           "PCPM_ERR_OVERFLOW"]

@@ -1,0 +1,242 @@
+"""ctypes binding of libpcpm (include/pcpm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libpcpm.  PyTorch supplies device memory and the stream.  There is
+no CPU fallback; if the library is not built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcpm.so")
+
+PCPM_OK = 0
+PCPM_ERR_INVALID_ARG = 1
+PCPM_ERR_GRAPH = 2
+PCPM_ERR_OVERFLOW = 3
+PCPM_ERR_OOM = 4
+PCPM_ERR_DEVICE = 5
+PCPM_ERR_NOT_CONVERGED = 6
+PCPM_ERR_NUMERIC = 7
+
+STATUS_NAMES = {
+    0: "PCPM_OK", 1: "PCPM_ERR_INVALID_ARG", 2: "PCPM_ERR_GRAPH", 3: "PCPM_ERR_OVERFLOW",
+    4: "PCPM_ERR_OOM", 5: "PCPM_ERR_DEVICE", 6: "PCPM_ERR_NOT_CONVERGED", 7: "PCPM_ERR_NUMERIC",
+}
+
+# every symbol include/pcpm.h declares
+EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
+           "pcpm_pagerank", "pcpm_last_error", "pcpm_timing_enable", "pcpm_timing_collect"]
+
+
+class PCPMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("part_log2", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64)]
+
+
+class PngInfo(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in
+                ("n", "m", "q", "k", "eprime", "nseg", "n_dangling", "scatter_items", "gather_items",
+                 "split_bins", "device_bytes")] + [("build_ms", ctypes.c_double)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpcpm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.pcpm_build_png.restype = ctypes.c_int
+    L.pcpm_build_png.argtypes = [i64, i64, vp, vp, ctypes.POINTER(BuildOpts), vp, ctypes.POINTER(vp)]
+    L.pcpm_png_info.restype = ctypes.c_int
+    L.pcpm_png_info.argtypes = [vp, ctypes.POINTER(PngInfo)]
+    L.pcpm_png_export.restype = ctypes.c_int
+    L.pcpm_png_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.pcpm_png_free.restype = None
+    L.pcpm_png_free.argtypes = [vp]
+    L.pcpm_iterate.restype = ctypes.c_int
+    L.pcpm_iterate.argtypes = [vp, dbl, vp, vp, ctypes.POINTER(dbl), vp]
+    L.pcpm_pagerank.restype = ctypes.c_int
+    L.pcpm_pagerank.argtypes = [vp, dbl, dbl, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, vp]
+    L.pcpm_last_error.restype = ctypes.c_char_p
+    L.pcpm_last_error.argtypes = []
+    L.pcpm_timing_enable.restype = None
+    L.pcpm_timing_enable.argtypes = [ctypes.c_int]
+    L.pcpm_timing_collect.restype = ctypes.c_int
+    L.pcpm_timing_collect.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int]
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().pcpm_last_error().decode()
+
+
+def _check(status: int, allow=()):
+    if status != PCPM_OK and status not in allow:
+        raise PCPMError(status, last_error())
+    return status
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_tensor(t, dtype, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class PNG:
+    """A built Partition-Node Graph (owns device memory in libpcpm)."""
+
+    def __init__(self, handle, row_off, col):
+        self._h = handle
+        # keep the CSR alive as long as the handle (the handle does not read it
+        # after the build, but callers expect the pair to travel together)
+        self.row_off = row_off
+        self.col = col
+        self.info = self._info()
+
+    def _info(self):
+        inf = PngInfo()
+        _check(lib().pcpm_png_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in PngInfo._fields_}
+
+    @property
+    def n(self):
+        return self.info["n"]
+
+    @property
+    def m(self):
+        return self.info["m"]
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("PNG handle is closed")
+        return self._h
+
+    def export(self) -> dict:
+        """Canonical layout as host numpy arrays (see pcpm_png_export)."""
+        k, ep, m = self.info["k"], self.info["eprime"], self.info["m"]
+        out = dict(png_off=np.zeros(k * (k + 1), np.int64), png_src=np.zeros(max(ep, 1), np.int32),
+                   upd_start=np.zeros(k + 1, np.int64), wo=np.zeros(k * k, np.int64),
+                   did_start=np.zeros(k + 1, np.int64), did=np.zeros(max(m, 1), np.uint32))
+        _check(lib().pcpm_png_export(self.handle, *(ctypes.c_void_p(a.ctypes.data) for a in out.values())))
+        out["png_off"] = out["png_off"].reshape(k, k + 1)
+        out["wo"] = out["wo"].reshape(k, k)
+        out["png_src"] = out["png_src"][:ep]
+        out["did"] = out["did"][:m]
+        return out
+
+    def close(self):
+        if self._h:
+            lib().pcpm_png_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_chunk: int = 0,
+              stream=None) -> PNG:
+    """pcpm_build_png on device CSR tensors (int32 row_off[n+1], col[m])."""
+    import torch
+    n = row_off.numel() - 1
+    m = col.numel()
+    rp = _dev_tensor(row_off, torch.int32, name="row_off")
+    cp = _dev_tensor(col, torch.int32, name="col") if m else ctypes.c_void_p(0)
+    opts = BuildOpts(int(part_log2), 0, int(scatter_chunk), int(gather_chunk))
+    h = ctypes.c_void_p()
+    _check(lib().pcpm_build_png(n, m, rp, cp, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
+    return PNG(h, row_off, col)
+
+
+def iterate(png: PNG, pr_in, pr_out=None, d: float = 0.85, want_resid: bool = True, stream=None):
+    """One PCPM iteration; returns (pr_out, residual or None)."""
+    import torch
+    n = png.n
+    ip = _dev_tensor(pr_in, torch.float32, n, "pr_in")
+    if pr_out is None:
+        pr_out = torch.empty_like(pr_in)
+    op = _dev_tensor(pr_out, torch.float32, n, "pr_out")
+    r = ctypes.c_double(0.0)
+    _check(lib().pcpm_iterate(png.handle, float(d), ip, op, ctypes.byref(r) if want_resid else None,
+                              _stream(stream)))
+    return pr_out, (r.value if want_resid else None)
+
+
+@dataclass
+class PagerankResult:
+    pr: object
+    iters: int
+    resid: float
+    res_hist: np.ndarray
+    converged: bool
+    status: int
+
+
+def pagerank(png: PNG, d: float = 0.85, tol: float = 1e-6, max_iters: int = 100, init=None, out=None,
+             want_hist: bool = True, stream=None) -> PagerankResult:
+    """pcpm_pagerank: iterate to L1 residual < tol (tol <= 0: exactly max_iters)."""
+    import torch
+    n = png.n
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=png.row_off.device)
+    op = _dev_tensor(out, torch.float32, n, "out")
+    ip = _dev_tensor(init, torch.float32, n, "init") if init is not None else None
+    it = ctypes.c_int32(0)
+    r = ctypes.c_double(0.0)
+    hist = np.zeros(max_iters, np.float64)
+    st = _check(lib().pcpm_pagerank(png.handle, float(d), float(tol), int(max_iters), ip, op, ctypes.byref(it),
+                                    ctypes.byref(r), ctypes.c_void_p(hist.ctypes.data) if want_hist else None,
+                                    _stream(stream)), allow=(PCPM_ERR_NOT_CONVERGED,))
+    return PagerankResult(out, it.value, r.value, hist[: it.value], st == PCPM_OK and tol > 0, st)
+
+
+def timing_enable(on: bool = True):
+    lib().pcpm_timing_enable(1 if on else 0)
+
+
+def timing_collect() -> dict:
+    """{kernel name: (launches, total_ms)} since the last collect."""
+    arr = (KernelTime * 64)()
+    cnt = lib().pcpm_timing_collect(arr, 64)
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(cnt, 64))}

@@ -1,0 +1,73 @@
+"""Memory-traffic models of Sec. 4 and the byte accounting of the GPU kernels.
+
+Sec. 4.1 (Table 2 notation): n nodes, m edges, k partitions, r = m/|E'|
+compression ratio, d_i index bytes, d_v value bytes, c_mr cache-miss ratio of
+pull-direction value reads, l cache-line bytes.
+"""
+from __future__ import annotations
+
+
+def pdpr_comm(n, m, c_mr, l=64, d_i=4, d_v=4):
+    """Eq. 3: bytes per iteration of pull-direction PageRank."""
+    return m * (d_i + c_mr * l) + n * (d_i + d_v)
+
+
+def bvgas_comm(n, m, d_i=4, d_v=4):
+    """Eq. 4: bytes per iteration of binning with vertex-centric GAS."""
+    return 2 * m * (d_i + d_v) + n * (d_i + 2 * d_v)
+
+
+def pcpm_comm(n, m, k, r, d_i=4, d_v=4):
+    """Eq. 5: bytes per iteration of PCPM over the PNG layout: m(d_i(1+1/r) +
+    2 d_v / r) + k^2 d_i + 2 n d_v."""
+    return m * (d_i * (1 + 1 / r) + 2 * d_v / r) + k * k * d_i + 2 * n * d_v
+
+
+def pcpm_comm_bounds(m, d_i=4, d_v=4):
+    """Sec. 4.1: with k^2 << n << m, PCPM traffic lies in [m d_i, m(2 d_i + 2 d_v)]
+    (r = m/n at best, r = 1 at worst)."""
+    return m * d_i, m * (2 * d_i + 2 * d_v)
+
+
+def bvgas_random_accesses(m, d_v=4, l=64):
+    """Sec. 4.2: at most one random DRAM access per cache line of updates."""
+    return m * d_v / l
+
+
+def pcpm_random_accesses(k):
+    """Sec. 4.2: at most k bin switches for each of the k partitions."""
+    return k * k
+
+
+def compression_ratio(m, eprime):
+    """r = |E| / |E'| (Table 2)."""
+    return m / eprime
+
+
+def gteps(m, seconds_per_iteration):
+    """Sec. 5.3: giga edges of the graph per second of one iteration."""
+    return m / seconds_per_iteration / 1e9
+
+
+# ---- byte accounting of this implementation (per launch) ---------------------
+
+TILE = 1024  # destination IDs / PNG edges per stored flag-prefix entry
+
+
+def scatter_bytes(n, eprime, nseg):
+    """Algorithmic bytes of one scatter pass: ranks and out-degrees of every
+    node (8n), the PNG source IDs (4E'), one write offset per non-empty
+    (source, destination) pair (4 nseg, the k^2 d_i term of Eq. 5), the tile
+    flag prefixes (4E'/1024) and the update writes (4E')."""
+    return 8 * n + 4 * eprime + 4 * nseg + 4 * (eprime // TILE + 1) + 4 * eprime
+
+
+def gather_bytes(n, m, eprime):
+    """Algorithmic bytes of one gather+apply pass: destination IDs (4m), tile
+    flag prefixes (4m/1024), updates (4E'), the previous ranks for the
+    residual (4n), the new ranks (4n) and the dangling bitmask (n/8)."""
+    return 4 * m + 4 * (m // TILE + 1) + 4 * eprime + 8 * n + n // 8
+
+
+def iteration_bytes(n, m, eprime, nseg):
+    return scatter_bytes(n, eprime, nseg) + gather_bytes(n, m, eprime)

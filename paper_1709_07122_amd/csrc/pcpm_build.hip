@@ -1,0 +1,645 @@
+// Partition-Node Graph construction (Sec. 3.1 write offsets, Sec. 3.3 merged
+// compression + transposition) on the GPU.
+//
+// Pipeline (all on the caller's stream):
+//   node pass    validate rows, out-degrees, dangling bitmask, edge -> source
+//   count        per source partition p (one workgroup, LDS histograms):
+//                |U(p,p')| and raw edges p -> p' for every p'
+//   scans        write offsets (column prefix over source partitions),
+//                partition-local PNG offsets (row prefix), bin starts
+//   fill         per source partition, one wavefront walks p's edges in CSR
+//                order; a ballot multisplit ranks each edge among the edges of
+//                the same destination partition, so every bin is written in
+//                the canonical (p, u, v) order without atomics and the PNG in
+//                (p, p', u) order
+//   tile flags   flags before every 1024-entry tile of both arrays
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "pcpm_internal.hpp"
+
+namespace pcpm {
+
+enum : int32_t {
+  kErrOffsets = 1,   // row_off entries out of [0,m] or decreasing
+  kErrRange = 2,     // column outside [0,n)
+  kErrSelfLoop = 4,
+  kErrOrder = 8,     // row not strictly ascending (unsorted or duplicate)
+  kErrEnds = 16,     // row_off[0] != 0 or row_off[n] != m
+  kErrInternal = 32,
+};
+
+constexpr int kBigRow = 64;  // rows longer than this are validated by a workgroup
+
+// ---------------------------------------------------------------------------------
+// Node pass: one lane per node.  Short rows are validated and expanded by their
+// lane; long rows are queued for k_big_rows.
+__global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
+                                                   const int32_t* __restrict__ col, int32_t* __restrict__ outdeg,
+                                                   uint32_t* __restrict__ dmask, int32_t* __restrict__ src,
+                                                   int32_t* __restrict__ big, int64_t big_cap,
+                                                   int32_t* __restrict__ counters /* [0]=err [1]=nbig [2]=ndang */) {
+  const int64_t nwords = (n + 31) >> 5;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < n; base += stride) {
+    const int64_t u = base + threadIdx.x;
+    bool dang = false;
+    int32_t err = 0;
+    if (u < n) {
+      const int32_t lo = row_off[u], hi = row_off[u + 1];
+      if (lo < 0 || hi < lo || static_cast<int64_t>(hi) > m) {
+        err |= kErrOffsets;
+        outdeg[u] = 0;
+      } else {
+        outdeg[u] = hi - lo;
+        dang = (hi == lo);
+        if (hi - lo > kBigRow) {
+          const int32_t idx = atomicAdd(&counters[1], 1);
+          if (idx < big_cap) big[idx] = static_cast<int32_t>(u);
+          else err |= kErrInternal;
+        } else {
+          int32_t prev = -1;
+          for (int32_t j = lo; j < hi; ++j) {
+            const int32_t c = col[j];
+            if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
+            if (c == u) err |= kErrSelfLoop;
+            if (c <= prev) err |= kErrOrder;
+            prev = c;
+            src[j] = static_cast<int32_t>(u);
+          }
+        }
+      }
+    }
+    if (err) atomicOr(&counters[0], err);
+    const uint64_t bal = wave_ballot(dang);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t first = base + (threadIdx.x & ~(kWave - 1));
+    if (lane == 0 && first < n) {
+      const int64_t w = first >> 5;
+      dmask[w] = static_cast<uint32_t>(bal);
+      if (w + 1 < nwords) dmask[w + 1] = static_cast<uint32_t>(bal >> 32);
+      if (bal) atomicAdd(&counters[2], __popcll(bal));
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (row_off[0] != 0 || static_cast<int64_t>(row_off[n]) != m) atomicOr(&counters[0], kErrEnds);
+  }
+}
+
+// Long rows: one workgroup per queued row.
+__global__ __launch_bounds__(256) void k_big_rows(int64_t n, const int32_t* __restrict__ row_off,
+                                                  const int32_t* __restrict__ col, int32_t* __restrict__ src,
+                                                  const int32_t* __restrict__ big, int64_t big_cap,
+                                                  int32_t* __restrict__ counters) {
+  const int64_t nbig = min(static_cast<int64_t>(counters[1]), big_cap);
+  for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const int32_t u = big[i];
+    const int32_t lo = row_off[u], hi = row_off[u + 1];
+    int32_t err = 0;
+    for (int32_t j = lo + static_cast<int32_t>(threadIdx.x); j < hi; j += blockDim.x) {
+      const int32_t c = col[j];
+      const int32_t prev = (j > lo) ? col[j - 1] : -1;
+      if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
+      if (c == u) err |= kErrSelfLoop;
+      if (c <= prev) err |= kErrOrder;
+      src[j] = u;
+    }
+    if (err) atomicOr(&counters[0], err);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Count: workgroup p histograms the destination partitions of p's edges.
+// An edge is the first of its message when it starts its row or its
+// destination partition differs from the previous edge's (rows are sorted).
+__global__ __launch_bounds__(1024) void k_count(int64_t n, int s, int32_t k, const int32_t* __restrict__ row_off,
+                                                const int32_t* __restrict__ col, const int32_t* __restrict__ src,
+                                                int32_t* __restrict__ cnt, int32_t* __restrict__ raw) {
+  extern __shared__ int32_t sh[];
+  int32_t* c_l = sh;
+  int32_t* r_l = sh + k;
+  for (int32_t i = threadIdx.x; i < 2 * k; i += blockDim.x) sh[i] = 0;
+  __syncthreads();
+  const int64_t p = blockIdx.x;
+  const int64_t u0 = p << s;
+  const int64_t u1 = min(n, u0 + (int64_t{1} << s));
+  const int32_t e0 = row_off[u0], e1 = row_off[u1];
+  for (int32_t e = e0 + static_cast<int32_t>(threadIdx.x); e < e1; e += blockDim.x) {
+    const int32_t u = src[e];
+    const int32_t pp = col[e] >> s;
+    const bool first = (e == 0) || (src[e - 1] != u) || ((col[e - 1] >> s) != pp);
+    atomicAdd(&r_l[pp], 1);
+    if (first) atomicAdd(&c_l[pp], 1);
+  }
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < k; i += blockDim.x) {
+    cnt[p * k + i] = c_l[i];
+    raw[p * k + i] = r_l[i];
+  }
+}
+
+// Column prefix over source partitions: write offsets wo[p][p'] (updates) and
+// dwo[p][p'] (destination IDs); column totals.  One lane per column p'.
+__global__ __launch_bounds__(256) void k_colscan(int32_t k, const int32_t* __restrict__ cnt,
+                                                 const int32_t* __restrict__ raw, int32_t* __restrict__ wo,
+                                                 int32_t* __restrict__ dwo, int32_t* __restrict__ coltot,
+                                                 int32_t* __restrict__ coltot_raw) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  int32_t s = 0, sr = 0;
+  for (int64_t p = 0; p < k; ++p) {
+    const int64_t idx = p * k + j;
+    const int32_t c = cnt[idx], r = raw[idx];
+    wo[idx] = s;
+    dwo[idx] = sr;
+    s += c;
+    sr += r;
+  }
+  coltot[j] = s;
+  coltot_raw[j] = sr;
+}
+
+// Block-wide exclusive scan of one value per thread (blockDim <= 1024).
+__device__ int64_t block_excl_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t sh[1024];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
+    int64_t t = (threadIdx.x >= static_cast<unsigned>(off)) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const int64_t incl = sh[threadIdx.x];
+  *total = sh[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// Row prefix over destination partitions: png_off[p][0..k], row totals and the
+// number of non-empty segments of each row.  One workgroup per row.
+__global__ __launch_bounds__(256) void k_rowscan(int32_t k, const int32_t* __restrict__ cnt,
+                                                 int32_t* __restrict__ png_off, int32_t* __restrict__ rowtot,
+                                                 int32_t* __restrict__ rowseg) {
+  const int64_t p = blockIdx.x;
+  const int32_t per = (k + blockDim.x - 1) / blockDim.x;
+  const int32_t j0 = min(k, static_cast<int32_t>(threadIdx.x) * per), j1 = min(k, j0 + per);
+  int64_t sum = 0, nz = 0;
+  for (int32_t j = j0; j < j1; ++j) {
+    const int32_t c = cnt[p * k + j];
+    sum += c;
+    nz += (c > 0);
+  }
+  int64_t tot = 0, ntot = 0;
+  int64_t run = block_excl_scan(sum, &tot);
+  (void)block_excl_scan(nz, &ntot);
+  for (int32_t j = j0; j < j1; ++j) {
+    png_off[p * (k + 1) + j] = static_cast<int32_t>(run);
+    run += cnt[p * k + j];
+  }
+  if (threadIdx.x == 0) {
+    png_off[p * (k + 1) + k] = static_cast<int32_t>(tot);
+    rowtot[p] = static_cast<int32_t>(tot);
+    rowseg[p] = static_cast<int32_t>(ntot);
+  }
+}
+
+// Exclusive scan of in[0..L) into out[0..L] (out[L] = total), one workgroup.
+__global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                    int64_t L) {
+  const int64_t per = (L + blockDim.x - 1) / blockDim.x;
+  const int64_t i0 = min(L, static_cast<int64_t>(threadIdx.x) * per), i1 = min(L, i0 + per);
+  int64_t sum = 0;
+  for (int64_t i = i0; i < i1; ++i) sum += in[i];
+  int64_t tot = 0;
+  int64_t run = block_excl_scan(sum, &tot);
+  for (int64_t i = i0; i < i1; ++i) {
+    const int32_t v = in[i];
+    out[i] = static_cast<int32_t>(run);
+    run += v;
+  }
+  if (threadIdx.x == 0) out[L] = static_cast<int32_t>(tot);
+}
+
+// seg_delta[s] for the s-th non-empty segment in (p, p') order: update slot of
+// the segment's first entry minus its PNG position.  One workgroup per row.
+__global__ __launch_bounds__(256) void k_segdelta(int32_t k, const int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ wo, const int32_t* __restrict__ png_off,
+                                                  const int32_t* __restrict__ upd_start,
+                                                  const int32_t* __restrict__ png_base,
+                                                  const int32_t* __restrict__ segbase, int32_t* __restrict__ seg_delta) {
+  const int64_t p = blockIdx.x;
+  const int32_t per = (k + blockDim.x - 1) / blockDim.x;
+  const int32_t j0 = min(k, static_cast<int32_t>(threadIdx.x) * per), j1 = min(k, j0 + per);
+  int64_t nz = 0;
+  for (int32_t j = j0; j < j1; ++j) nz += (cnt[p * k + j] > 0);
+  int64_t tot = 0;
+  int64_t idx = segbase[p] + block_excl_scan(nz, &tot);
+  for (int32_t j = j0; j < j1; ++j) {
+    if (cnt[p * k + j] > 0) {
+      const int64_t slot = static_cast<int64_t>(upd_start[j]) + wo[p * k + j];
+      const int64_t pos = static_cast<int64_t>(png_base[p]) + png_off[p * (k + 1) + j];
+      seg_delta[idx++] = static_cast<int32_t>(slot - pos);
+    }
+  }
+}
+
+// Fill: one wavefront per source partition, edges in CSR order, 64 at a time.
+// Lanes with the same destination partition form a peer group (found with one
+// ballot per key bit); an edge's position in its bin is the group cursor plus
+// the number of peer lanes below it.  The lowest peer advances the cursors.
+__global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nbits,
+                                             const int32_t* __restrict__ row_off, const int32_t* __restrict__ col,
+                                             const int32_t* __restrict__ src, const int32_t* __restrict__ did_start,
+                                             const int32_t* __restrict__ dwo, const int32_t* __restrict__ png_base,
+                                             const int32_t* __restrict__ png_off, uint32_t* __restrict__ did,
+                                             uint32_t* __restrict__ png_src) {
+  extern __shared__ int32_t sh[];
+  int32_t* cur_did = sh;   // absolute destination-ID position per p'
+  int32_t* cur_rank = sh + k;  // rank inside U(p,p') per p'
+  const int64_t p = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int32_t j = lane; j < k; j += kWave) {
+    cur_did[j] = did_start[j] + dwo[p * k + j];
+    cur_rank[j] = 0;
+  }
+  __syncthreads();
+  const int64_t u0 = p << s;
+  const int64_t u1 = min(n, u0 + (int64_t{1} << s));
+  const int32_t e0 = row_off[u0], e1 = row_off[u1];
+  const int32_t pbase = png_base[p];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int32_t cb = e0; cb < e1; cb += kWave) {
+    const int32_t e = cb + lane;
+    const bool valid = e < e1;
+    int32_t u = 0, v = 0, pp = 0;
+    bool first = false;
+    if (valid) {
+      u = src[e];
+      v = col[e];
+      pp = v >> s;
+      first = (e == 0) || (src[e - 1] != u) || ((col[e - 1] >> s) != pp);
+    }
+    uint64_t peers = wave_ballot(valid);
+    const uint64_t fmask = wave_ballot(first);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (pp >> b) & 1;
+      const uint64_t bb = wave_ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint64_t fpeers = peers & fmask;
+    const int rank = __popcll(peers & below);
+    const int frank = __popcll(fpeers & below);
+    int32_t cd = 0, cr = 0;
+    if (valid) {
+      cd = cur_did[pp];
+      cr = cur_rank[pp];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+      did[cd + rank] = static_cast<uint32_t>(v) | (first ? kFlag : 0u);
+      if (first) {
+        const int32_t r = cr + frank;
+        const int64_t pos = static_cast<int64_t>(pbase) + png_off[p * (k + 1) + pp] + r;
+        png_src[pos] = static_cast<uint32_t>(u) | (r == 0 ? kFlag : 0u);
+      }
+      if ((peers & below) == 0) {
+        cur_did[pp] = cd + __popcll(peers);
+        cur_rank[pp] = cr + __popcll(fpeers);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Number of flagged entries in each kTile tile (one wavefront per tile).
+__global__ __launch_bounds__(256) void k_tile_flags(const uint32_t* __restrict__ a, int64_t ntiles,
+                                                    int32_t* __restrict__ cnt) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  for (int64_t t = wave; t < ntiles; t += nwaves) {
+    int32_t c = 0;
+    for (int j = 0; j < kSub; ++j) c += __popcll(wave_ballot((a[t * kTile + j * kWave + lane] >> 31) != 0));
+    if (lane == 0) cnt[t] = c;
+  }
+}
+
+pcpm_status_t set_lds_limits() {
+  static bool done = false;
+  if (done) return PCPM_OK;
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_count),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kMaxParts * 4));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fill),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kMaxParts * 4));
+  done = true;
+  return PCPM_OK;
+}
+
+pcpm_status_t iter_lds_limits();  // pcpm_iter.hip
+
+static bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hipStream_t st) {
+  const int64_t k = g->k;
+  std::vector<int32_t> png_base(k + 1), did_start(k + 1);
+  PCPM_TRY_HIP(hipMemcpyAsync(png_base.data(), g->png_base, (k + 1) * 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(did_start.data(), g->did_start, (k + 1) * 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+
+  auto chunk_for = [&](int64_t total, int64_t requested) -> int64_t {
+    if (requested > 0) return requested;
+    const int64_t mean = (total + k - 1) / std::max<int64_t>(k, 1);
+    return std::max<int64_t>(2 * mean, 65536);
+  };
+  const int64_t sc = chunk_for(g->eprime, opts ? opts->scatter_chunk : 0);
+  const int64_t gc = chunk_for(g->m, opts ? opts->gather_chunk : 0);
+
+  std::vector<Item> sc_items, ga_items;
+  std::vector<Merge> mg;
+  for (int64_t p = 0; p < k; ++p) {
+    const int64_t a = png_base[p], b = png_base[p + 1];
+    if (b == a) continue;
+    const int64_t nch = (b - a + sc - 1) / sc;
+    const int64_t step = (b - a + nch - 1) / nch;
+    for (int64_t lo = a; lo < b; lo += step)
+      sc_items.push_back({static_cast<int32_t>(p), static_cast<int32_t>(lo),
+                          static_cast<int32_t>(std::min(b, lo + step)), 0});
+  }
+  int32_t slot = 0;
+  for (int64_t p = 0; p < k; ++p) {
+    const int64_t a = did_start[p], b = did_start[p + 1];
+    const int64_t nch = std::max<int64_t>(1, (b - a + gc - 1) / gc);
+    if (nch == 1) {
+      ga_items.push_back({static_cast<int32_t>(p), static_cast<int32_t>(a), static_cast<int32_t>(b), -1});
+      continue;
+    }
+    const int64_t step = (b - a + nch - 1) / nch;
+    const int32_t first = slot;
+    for (int64_t lo = a; lo < b; lo += step)
+      ga_items.push_back({static_cast<int32_t>(p), static_cast<int32_t>(lo),
+                          static_cast<int32_t>(std::min(b, lo + step)), slot++});
+    mg.push_back({static_cast<int32_t>(p), first, slot - first, 0});
+  }
+  // largest work first
+  auto bigger = [](const Item& x, const Item& y) { return (x.hi - x.lo) > (y.hi - y.lo); };
+  std::stable_sort(sc_items.begin(), sc_items.end(), bigger);
+  std::stable_sort(ga_items.begin(), ga_items.end(), bigger);
+
+  g->n_sc = static_cast<int32_t>(sc_items.size());
+  g->n_ga = static_cast<int32_t>(ga_items.size());
+  g->n_mg = static_cast<int32_t>(mg.size());
+  g->n_split_slots = slot;
+  PCPM_TRY(dalloc(g, &g->sc_items, g->n_sc));
+  PCPM_TRY(dalloc(g, &g->ga_items, g->n_ga));
+  PCPM_TRY(dalloc(g, &g->mg_items, g->n_mg));
+  PCPM_TRY(dalloc(g, &g->partial, static_cast<int64_t>(slot) * g->q));
+  if (g->n_sc)
+    PCPM_TRY_HIP(hipMemcpyAsync(g->sc_items, sc_items.data(), sc_items.size() * sizeof(Item),
+                                hipMemcpyHostToDevice, st));
+  if (g->n_ga)
+    PCPM_TRY_HIP(hipMemcpyAsync(g->ga_items, ga_items.data(), ga_items.size() * sizeof(Item),
+                                hipMemcpyHostToDevice, st));
+  if (g->n_mg)
+    PCPM_TRY_HIP(hipMemcpyAsync(g->mg_items, mg.data(), mg.size() * sizeof(Merge), hipMemcpyHostToDevice, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  return PCPM_OK;
+}
+
+static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col,
+                           const pcpm_build_opts_t* opts, hipStream_t st, pcpm_png* g) {
+  const int s = (opts && opts->part_log2) ? opts->part_log2 : 14;
+  if (s < kMinLog2 || s > kMaxLog2)
+    return set_error(PCPM_ERR_INVALID_ARG, "part_log2 %d outside [%d, %d]", s, kMinLog2, kMaxLog2);
+  const int64_t q = int64_t{1} << s;
+  const int64_t k = (n + q - 1) / q;
+  if (k > kMaxParts)
+    return set_error(PCPM_ERR_INVALID_ARG, "k = ceil(n/q) = %lld exceeds %d partitions",
+                     static_cast<long long>(k), kMaxParts);
+  g->n = n;
+  g->m = m;
+  g->q = q;
+  g->k = k;
+  g->part_log2 = s;
+  PCPM_TRY(set_lds_limits());
+  PCPM_TRY(iter_lds_limits());
+
+  // ---- node pass -------------------------------------------------------------
+  int32_t* src = nullptr;
+  int32_t* big = nullptr;
+  int32_t* counters = nullptr;
+  const int64_t big_cap = m / kBigRow + 1;
+  PCPM_TRY(dalloc(g, &g->outdeg, n));
+  PCPM_TRY(dalloc(g, &g->dmask, (n + 31) / 32));
+  PCPM_TRY(dalloc(g, &src, m));
+  PCPM_TRY(dalloc(g, &big, big_cap));
+  PCPM_TRY(dalloc(g, &counters, 4));
+  PCPM_TRY_HIP(hipMemsetAsync(counters, 0, 16, st));
+  {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    PCPM_LAUNCH("pcpm_build_nodes", k_node_pass, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, n, m,
+                row_off, col, g->outdeg, g->dmask, src, big, big_cap, counters);
+    PCPM_LAUNCH("pcpm_build_bigrows", k_big_rows, dim3(1024), dim3(256), 0, st, n, row_off, col, src, big,
+                big_cap, counters);
+  }
+  int32_t hc[4] = {0, 0, 0, 0};
+  PCPM_TRY_HIP(hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  if (hc[0]) {
+    const char* what = (hc[0] & kErrOffsets)    ? "row offsets out of range or decreasing"
+                       : (hc[0] & kErrEnds)     ? "row_off[0] != 0 or row_off[n] != m"
+                       : (hc[0] & kErrRange)    ? "column index outside [0, n)"
+                       : (hc[0] & kErrSelfLoop) ? "self-loop"
+                       : (hc[0] & kErrOrder)    ? "row not strictly ascending (unsorted or duplicate edge)"
+                                                : "internal queue overflow";
+    return set_error(hc[0] & kErrInternal ? PCPM_ERR_DEVICE : PCPM_ERR_GRAPH, "invalid CSR: %s (flags 0x%x)",
+                     what, hc[0]);
+  }
+  g->n_dangling = hc[2];
+
+  // ---- counts and scans ----------------------------------------------------------
+  int32_t *cnt, *raw, *dwo, *coltot, *coltot_raw, *rowtot, *rowseg, *segbase;
+  PCPM_TRY(dalloc(g, &cnt, k * k));
+  PCPM_TRY(dalloc(g, &raw, k * k));
+  PCPM_TRY(dalloc(g, &g->wo, k * k));
+  PCPM_TRY(dalloc(g, &dwo, k * k));
+  PCPM_TRY(dalloc(g, &coltot, k));
+  PCPM_TRY(dalloc(g, &coltot_raw, k));
+  PCPM_TRY(dalloc(g, &rowtot, k));
+  PCPM_TRY(dalloc(g, &rowseg, k));
+  PCPM_TRY(dalloc(g, &segbase, k + 1));
+  PCPM_TRY(dalloc(g, &g->png_off, k * (k + 1)));
+  PCPM_TRY(dalloc(g, &g->upd_start, k + 1));
+  PCPM_TRY(dalloc(g, &g->did_start, k + 1));
+  PCPM_TRY(dalloc(g, &g->png_base, k + 1));
+  const unsigned kk = static_cast<unsigned>(k);
+  PCPM_LAUNCH("pcpm_build_count", k_count, dim3(kk), dim3(1024), static_cast<size_t>(2 * k * 4), st, n, s,
+              static_cast<int32_t>(k), row_off, col, src, cnt, raw);
+  PCPM_LAUNCH("pcpm_build_colscan", k_colscan, dim3((kk + 255) / 256), dim3(256), 0, st, static_cast<int32_t>(k),
+              cnt, raw, g->wo, dwo, coltot, coltot_raw);
+  PCPM_LAUNCH("pcpm_build_rowscan", k_rowscan, dim3(kk), dim3(256), 0, st, static_cast<int32_t>(k), cnt,
+              g->png_off, rowtot, rowseg);
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, coltot, g->upd_start, k);
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, coltot_raw, g->did_start, k);
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowtot, g->png_base, k);
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowseg, segbase, k);
+  int32_t tot[2] = {0, 0};
+  PCPM_TRY_HIP(hipMemcpyAsync(&tot[0], g->upd_start + k, 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(&tot[1], segbase + k, 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  g->eprime = tot[0];
+  g->nseg = tot[1];
+
+  PCPM_TRY(dalloc(g, &g->seg_delta, g->nseg));
+  PCPM_LAUNCH("pcpm_build_segdelta", k_segdelta, dim3(kk), dim3(256), 0, st, static_cast<int32_t>(k), cnt, g->wo,
+              g->png_off, g->upd_start, g->png_base, segbase, g->seg_delta);
+
+  // ---- fill --------------------------------------------------------------------
+  const int64_t ntp = (g->eprime + kTile - 1) / kTile;
+  const int64_t ntd = (m + kTile - 1) / kTile;
+  PCPM_TRY(dalloc(g, &g->png_src, std::max<int64_t>(ntp, 1) * kTile));
+  PCPM_TRY(dalloc(g, &g->did, std::max<int64_t>(ntd, 1) * kTile));
+  PCPM_TRY_HIP(hipMemsetAsync(g->png_src, 0, std::max<int64_t>(ntp, 1) * kTile * 4, st));
+  PCPM_TRY_HIP(hipMemsetAsync(g->did, 0, std::max<int64_t>(ntd, 1) * kTile * 4, st));
+  int nbits = 0;
+  while ((int64_t{1} << nbits) < k) ++nbits;
+  PCPM_LAUNCH("pcpm_build_fill", k_fill, dim3(kk), dim3(64), static_cast<size_t>(2 * k * 4), st, n, s,
+              static_cast<int32_t>(k), nbits, row_off, col, src, g->did_start, dwo, g->png_base, g->png_off, g->did,
+              g->png_src);
+
+  // ---- tile flag prefixes ----------------------------------------------------
+  int32_t* tcnt = nullptr;
+  PCPM_TRY(dalloc(g, &tcnt, std::max(ntp, ntd) + 1));
+  PCPM_TRY(dalloc(g, &g->png_blk, ntp + 1));
+  PCPM_TRY(dalloc(g, &g->did_blk, ntd + 1));
+  if (ntp > 0) {
+    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags, dim3(static_cast<unsigned>(std::min<int64_t>((ntp + 3) / 4, 16384))),
+                dim3(256), 0, st, g->png_src, ntp, tcnt);
+  }
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, g->png_blk, ntp);
+  if (ntd > 0) {
+    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags, dim3(static_cast<unsigned>(std::min<int64_t>((ntd + 3) / 4, 16384))),
+                dim3(256), 0, st, g->did, ntd, tcnt);
+  }
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, g->did_blk, ntd);
+
+  // ---- iteration buffers -----------------------------------------------------------
+  PCPM_TRY(dalloc(g, &g->upd, g->eprime));
+  PCPM_TRY(dalloc(g, &g->red, 2 * k));
+  PCPM_TRY(dalloc(g, &g->red_init, kInitBlocks));
+  PCPM_TRY(dalloc(g, &g->hist, kMaxHist));
+  PCPM_TRY(dalloc(g, &g->ctl, 1));
+  PCPM_TRY(dalloc(g, &g->tmp_pr, n));
+  PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->ctl_host), sizeof(Ctl), hipHostMallocDefault));
+  PCPM_TRY(build_items(g, opts, st));
+
+  // ---- release build-only buffers ------------------------------------------------
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  for (void* p : {static_cast<void*>(src), static_cast<void*>(big), static_cast<void*>(counters),
+                  static_cast<void*>(raw), static_cast<void*>(dwo), static_cast<void*>(coltot),
+                  static_cast<void*>(coltot_raw), static_cast<void*>(rowtot), static_cast<void*>(rowseg),
+                  static_cast<void*>(segbase), static_cast<void*>(tcnt), static_cast<void*>(cnt)})
+    dfree(g, p);
+  return PCPM_OK;
+}
+
+}  // namespace pcpm
+
+extern "C" {
+
+pcpm_status_t pcpm_build_png(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col,
+                             const pcpm_build_opts_t* opts, void* stream, pcpm_png_t* out) {
+  using namespace pcpm;
+  if (!out) return set_error(PCPM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || m < 0) return set_error(PCPM_ERR_INVALID_ARG, "n must be >= 1 and m >= 0");
+  if (n >= (int64_t{1} << 31) || m >= (int64_t{1} << 31))
+    return set_error(PCPM_ERR_OVERFLOW, "n and m must be below 2^31 (the top ID bit is the message flag)");
+  if (!row_off || (m > 0 && !col)) return set_error(PCPM_ERR_INVALID_ARG, "row_off or col is NULL");
+  if (!is_device_ptr(row_off) || (m > 0 && !is_device_ptr(col)))
+    return set_error(PCPM_ERR_INVALID_ARG, "row_off and col must be device pointers");
+  const auto t0 = std::chrono::steady_clock::now();
+  pcpm_png* g = new (std::nothrow) pcpm_png();
+  if (!g) return set_error(PCPM_ERR_OOM, "host allocation failed");
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    return set_error(PCPM_ERR_DEVICE, "no current HIP device");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pcpm_status_t rc = build(n, m, row_off, col, opts, st, g);
+  if (rc != PCPM_OK) {
+    (void)hipStreamSynchronize(st);
+    free_handle(g);
+    return rc;
+  }
+  g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = g;
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out) {
+  using namespace pcpm;
+  if (!g || !out) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or output");
+  out->n = g->n;
+  out->m = g->m;
+  out->q = g->q;
+  out->k = g->k;
+  out->eprime = g->eprime;
+  out->nseg = g->nseg;
+  out->n_dangling = g->n_dangling;
+  out->scatter_items = g->n_sc;
+  out->gather_items = g->n_ga;
+  out->split_bins = g->n_mg;
+  out->device_bytes = g->device_bytes;
+  out->build_ms = g->build_ms;
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src, int64_t* upd_start, int64_t* wo,
+                              int64_t* did_start, uint32_t* did) {
+  using namespace pcpm;
+  if (!g) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle");
+  PCPM_TRY_HIP(hipSetDevice(g->device));
+  PCPM_TRY_HIP(hipDeviceSynchronize());
+  const int64_t k = g->k;
+  auto widen = [](const std::vector<int32_t>& a, int64_t* out) {
+    for (size_t i = 0; i < a.size(); ++i) out[i] = a[i];
+  };
+  if (png_off) {
+    std::vector<int32_t> t(k * (k + 1));
+    PCPM_TRY_HIP(hipMemcpy(t.data(), g->png_off, t.size() * 4, hipMemcpyDeviceToHost));
+    widen(t, png_off);
+  }
+  if (wo) {
+    std::vector<int32_t> t(k * k);
+    PCPM_TRY_HIP(hipMemcpy(t.data(), g->wo, t.size() * 4, hipMemcpyDeviceToHost));
+    widen(t, wo);
+  }
+  if (upd_start) {
+    std::vector<int32_t> t(k + 1);
+    PCPM_TRY_HIP(hipMemcpy(t.data(), g->upd_start, t.size() * 4, hipMemcpyDeviceToHost));
+    widen(t, upd_start);
+  }
+  if (did_start) {
+    std::vector<int32_t> t(k + 1);
+    PCPM_TRY_HIP(hipMemcpy(t.data(), g->did_start, t.size() * 4, hipMemcpyDeviceToHost));
+    widen(t, did_start);
+  }
+  if (png_src && g->eprime > 0) {
+    PCPM_TRY_HIP(hipMemcpy(png_src, g->png_src, g->eprime * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < g->eprime; ++i) png_src[i] &= static_cast<int32_t>(kIdMask);
+  }
+  if (did && g->m > 0) PCPM_TRY_HIP(hipMemcpy(did, g->did, g->m * 4, hipMemcpyDeviceToHost));
+  return PCPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// Internal declarations of libpcpm (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "pcpm.h"
+
+namespace pcpm {
+
+// Destination IDs and PNG source IDs carry a flag in their top bit: the first
+// ID of a message (Sec. 3.2) and the first node of a (source, destination)
+// partition segment respectively.
+constexpr uint32_t kFlag = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+
+// Flag-decoding tile: 16 sub-blocks of one wavefront (64 lanes) each.  The
+// running flag count before every tile is stored, so any wavefront can decode
+// any tile on its own.
+constexpr int kWave = 64;
+constexpr int kSub = 16;
+constexpr int kTile = kWave * kSub;
+
+constexpr int kMaxHist = 100000;   // residual history kept on the device
+constexpr int kMaxParts = 16384;   // k limit (LDS cursors of the fill kernel)
+constexpr int kMinLog2 = 1;
+constexpr int kMaxLog2 = 15;       // 32768 * 4 B = 128 KB rank slice
+constexpr int kIterBlock = 512;    // threads per scatter / gather workgroup
+constexpr int kInitBlocks = 256;   // workgroups of the dangling-mass reduction
+
+// Device control block of one handle.
+struct Ctl {
+  double base;      // (1-d)/n + d*D/n: jump plus dangling share for the next apply
+  double dmass;     // dangling mass D of the current input vector
+  double res;       // residual of the last iteration
+  double tol;       // stop threshold (<= 0: never)
+  double d;         // damping factor
+  int32_t iter;     // iterations completed
+  int32_t done;     // residual fell below tol, or a non-finite value appeared
+  int32_t nonfinite;
+  int32_t pad;
+};
+
+// A unit of scatter or gather work: a contiguous range [lo, hi) of PNG edges
+// (scatter, part = source partition) or of destination IDs (gather, part =
+// destination partition).  aux: gather partial slot (-1 = whole bin).
+struct Item {
+  int32_t part, lo, hi, aux;
+};
+
+// Merge work: a destination bin split over `count` gather items whose partial
+// sums sit in consecutive partial slots starting at `first`.
+struct Merge {
+  int32_t part, first, count, pad;
+};
+
+// ---- errors ----------------------------------------------------------------
+pcpm_status_t set_error(pcpm_status_t st, const char* fmt, ...);
+
+#define PCPM_TRY_HIP(expr)                                                              \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return ::pcpm::set_error(_e == hipErrorOutOfMemory ? PCPM_ERR_OOM : PCPM_ERR_DEVICE, \
+                               "%s failed: %s", #expr, hipGetErrorString(_e));          \
+  } while (0)
+
+#define PCPM_TRY(expr)                          \
+  do {                                          \
+    pcpm_status_t _s = (expr);                  \
+    if (_s != PCPM_OK) return _s;               \
+  } while (0)
+
+// ---- per-kernel timing -------------------------------------------------------
+struct TimerScope {
+  TimerScope(const char* name, hipStream_t s);
+  ~TimerScope();
+  const char* name;
+  hipStream_t stream;
+  hipEvent_t start = nullptr;
+};
+
+// Launch with optional event timing and a launch-error check.
+#define PCPM_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                     \
+  do {                                                                                  \
+    ::pcpm::TimerScope _ts(name, stream);                                               \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                \
+    hipError_t _e = hipGetLastError();                                                  \
+    if (_e != hipSuccess)                                                               \
+      return ::pcpm::set_error(PCPM_ERR_DEVICE, "launch of %s failed: %s", name,       \
+                               hipGetErrorString(_e));                                  \
+  } while (0)
+
+// ---- wave-level helpers (device) -------------------------------------------------
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+}  // namespace pcpm
+
+// ---- the handle ------------------------------------------------------------------
+struct pcpm_png {
+  int64_t n = 0, m = 0, q = 0, k = 0, eprime = 0, nseg = 0, n_dangling = 0;
+  int part_log2 = 0;
+  int device = 0;
+  double build_ms = 0.0;
+  int64_t device_bytes = 0;
+
+  // per node
+  int32_t* outdeg = nullptr;    // n
+  uint32_t* dmask = nullptr;    // ceil(n/32) dangling bitmask
+
+  // scatter side: PNG in (source partition, destination partition, node) order
+  uint32_t* png_src = nullptr;  // ceil(E'/kTile)*kTile, top bit = segment start
+  int32_t* png_blk = nullptr;   // flags before each tile, ceil(E'/kTile)+1
+  int32_t* seg_delta = nullptr; // nseg: update slot minus PNG position per segment
+  int32_t* png_base = nullptr;  // k+1: first PNG edge of each source partition
+  int32_t* png_off = nullptr;   // k*(k+1): partition-local PNG offsets
+  int32_t* wo = nullptr;        // k*k: write offsets (Sec. 3.1)
+  int32_t* upd_start = nullptr; // k+1: first update slot of each bin
+
+  // gather side: destination-ID bins
+  uint32_t* did = nullptr;      // ceil(m/kTile)*kTile, top bit = first of message
+  int32_t* did_blk = nullptr;   // flags before each tile, ceil(m/kTile)+1
+  int32_t* did_start = nullptr; // k+1
+  float* upd = nullptr;         // E' update bins (rewritten every iteration)
+
+  // work lists
+  pcpm::Item* sc_items = nullptr;
+  pcpm::Item* ga_items = nullptr;
+  pcpm::Merge* mg_items = nullptr;
+  int32_t n_sc = 0, n_ga = 0, n_mg = 0, n_split_slots = 0;
+  float* partial = nullptr;     // n_split_slots * q
+
+  // reductions and control
+  double* red = nullptr;        // 2*k: per-bin (residual, dangling) partial sums
+  double* red_init = nullptr;   // kInitBlocks
+  double* hist = nullptr;       // kMaxHist residuals
+  pcpm::Ctl* ctl = nullptr;
+  pcpm::Ctl* ctl_host = nullptr;  // pinned mirror
+  float* tmp_pr = nullptr;      // n: second rank buffer
+
+  std::vector<std::pair<void*, size_t>> allocations;
+};
+
+namespace pcpm {
+// Device allocation tracked by the handle.
+template <class T>
+pcpm_status_t dalloc(pcpm_png* g, T** p, int64_t count) {
+  size_t bytes = static_cast<size_t>(count > 0 ? count : 1) * sizeof(T);
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(PCPM_ERR_OOM, "hipMalloc of %zu bytes failed: %s", bytes,
+                     hipGetErrorString(e));
+  }
+  g->allocations.emplace_back(ptr, bytes);
+  g->device_bytes += static_cast<int64_t>(bytes);
+  *p = static_cast<T*>(ptr);
+  return PCPM_OK;
+}
+
+// Free one tracked allocation early (build-only buffers).
+void dfree(pcpm_png* g, void* p);
+void free_handle(pcpm_png* g);
+pcpm_status_t set_lds_limits();
+}  // namespace pcpm
