@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of PCPM PageRank on one MI355X.
+
+Workload: PageRank (d = 0.85, dangling mass spread uniformly, FP32 ranks,
+FP64 residual) on a directed RMAT graph of scale 24 with edge factor 16
+(a, b, c = 0.57, 0.19, 0.19; self-loops and duplicate edges dropped), random
+node labels, partitions of 16384 nodes, iterated to an L1 residual below 1e-6.
+A step is one solve from the uniform vector; the graph and its partition-node
+graph are resident in HBM before the timed region starts.  The same graph with
+in-degree-sorted labels is measured as well and reported under "indegree".
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS/iter + HBM GB/s; time to L1 resid 1e-6, warm vs cold init"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def measure(P, torch, r, c, args, label):
+    """Build the PNG, warm up, then time `steps` solves with per-kernel events."""
+    from paper_1709_07122_amd import commmodel as cm
+
+    n, m = len(r) - 1, len(c)
+    rt = torch.from_numpy(r).cuda()
+    ct = torch.from_numpy(c).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    png = P.build_png(rt, ct, part_log2=args.part_log2)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = png.info
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters, out=out, want_hist=False)
+    log(f"[{label}] n={n} m={m} q={info['q']} k={info['k']} E'={info['eprime']} "
+        f"r={m / max(info['eprime'], 1):.3f} build={build_s * 1e3:.1f} ms")
+
+    P.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(args.steps):
+        res = P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters, out=out, want_hist=False)
+        iters.append(res.iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.timing_enable(False)
+    kt = P.timing_collect()
+    total_s = t1 - t0
+    tot_iters = sum(iters)
+    sec_per_iter = total_s / tot_iters
+    eprime, nseg = info["eprime"], info["nseg"]
+    kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in kt.items()}
+    g_bytes = cm.gather_bytes(n, m, eprime)
+    s_bytes = cm.scatter_bytes(n, eprime, nseg)
+    it_bytes = g_bytes + s_bytes
+    eq5 = cm.pcpm_comm(n, m, info["k"], m / max(eprime, 1))
+    result = {
+        "n": n, "m": m, "q": info["q"], "k": info["k"], "eprime": eprime, "r": m / max(eprime, 1),
+        "iters": iters[-1], "ms_per_step": total_s / args.steps * 1e3, "ms_per_iter": sec_per_iter * 1e3,
+        "gteps": m / sec_per_iter / 1e9, "time_to_tol_ms": total_s / args.steps * 1e3,
+        "alg_bytes_per_iter": it_bytes, "alg_bytes_per_edge": it_bytes / m, "eq5_bytes_per_edge": eq5 / m,
+        "hbm_gbs_alg": it_bytes / sec_per_iter / 1e9, "build_ms": build_s * 1e3,
+        "kernels": kernels, "gather_bytes": g_bytes, "scatter_bytes": s_bytes,
+        "split_bins": info["split_bins"], "gather_items": info["gather_items"],
+        "scatter_items": info["scatter_items"],
+    }
+    log(f"[{label}] iters={iters} {result['ms_per_step']:.3f} ms/solve, {result['gteps']:.1f} GTEPS, "
+        f"{result['hbm_gbs_alg']:.0f} GB/s (algorithmic)")
+    for k, v in sorted(kernels.items()):
+        log(f"    {k:16s} launches={v['launches']:5d} avg={v['avg_ms'] * 1e3:9.1f} us")
+    return result, out.cpu().numpy(), png
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--edge-factor", type=float, default=16)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--part-log2", type=int, default=14)
+    ap.add_argument("--d", type=float, default=0.85)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iters", type=int, default=200)
+    ap.add_argument("--no-indegree", action="store_true", help="skip the in-degree-sorted labelling")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md describes how it "
+              "would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1709_07122_amd as P
+
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    raw_r, raw_c = graphgen.rmat(args.scale, args.edge_factor, 0.57, 0.19, 0.19, seed=args.seed)
+    n = len(raw_r) - 1
+    perm = np.empty(n, dtype=np.int32)
+    graphgen._load().gg_perm_random(n, (args.seed * 7919 + 17) & (2**64 - 1), perm.ctypes.data)
+    r, c = graphgen.apply_labels(raw_r, raw_c, perm)
+    log(f"generated RMAT-{args.scale} EF{args.edge_factor}: n={n} m={len(c)} in {time.perf_counter() - t:.1f} s")
+
+    main_res, x_gpu, png = measure(P, torch, r, c, args, "random")
+    png.close()
+
+    detail = {"random": main_res}
+    if not args.no_indegree:
+        ri, ci = graphgen.apply_labels(raw_r, raw_c, graphgen.indegree_labels(raw_r, raw_c))
+        ind_res, _, png_i = measure(P, torch, ri, ci, args, "indegree")
+        png_i.close()
+        detail["indegree"] = ind_res
+        del ri, ci
+    del raw_r, raw_c
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        iters = main_res["iters"]
+        t = time.perf_counter()
+        o = oracle.pagerank(r, c, d=args.d, iters=iters)
+        wall = time.perf_counter() - t
+        x_ref = o.x
+        l1 = float(np.abs(x_gpu.astype(np.float64) - x_ref).sum())
+        big = x_ref > 1.0 / n
+        rel = float((np.abs(x_gpu.astype(np.float64) - x_ref)[big] / x_ref[big]).max())
+        detail["parity"] = {"l1": l1, "max_rel_above_1_over_n": rel, "iters": iters}
+        cpu = {"value": len(c) / o.sec_per_iter / 1e9, "unit": "GTEPS", "cores": threads(), "kind": "oracle",
+               "sample": f"the same RMAT-{args.scale} graph (random labels), {iters} FP64 pull iterations of "
+                         f"the oracle, transpose excluded ({wall:.1f} s wall incl. transpose)",
+               "sec_per_iter": o.sec_per_iter}
+        log(f"oracle: {o.sec_per_iter * 1e3:.1f} ms/iter on {threads()} threads; parity L1={l1:.2e} rel={rel:.2e}")
+
+    g = main_res["kernels"].get("pcpm_gather", {"avg_ms": float("nan")})
+    achieved = main_res["gather_bytes"] / (g["avg_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(main_res["gteps"], 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"PageRank d={args.d} to L1 residual {args.tol:g} on RMAT scale {args.scale}, edge factor "
+                        f"{args.edge_factor:g} (a,b,c=.57,.19,.19, seed {args.seed}), random node labels, "
+                        f"partition {1 << args.part_log2} nodes",
+            "n": main_res["n"], "m": main_res["m"], "q": main_res["q"], "k": main_res["k"],
+            "eprime": main_res["eprime"], "tol": args.tol, "d": args.d,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "pcpm_gather", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": main_res["gather_bytes"], "avg_launch_ms": g["avg_ms"],
+        },
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    print(json.dumps(line, default=lambda o: None if isinstance(o, float) and math.isnan(o) else o))
+
+
+if __name__ == "__main__":
+    main()

@@ -23,7 +23,8 @@
  *   - A handle may be used by one stream at a time; calls on one handle that
  *     overlap in time race on its scratch buffers.
  *   - Ranks are FP32; the L1 residual and the dangling mass are accumulated
- *     in FP64 on the device.
+ *     in FP64 on the device.  The gather adds the FP32 updates of a node
+ *     exactly (64-bit fixed point), so ranks are reproducible run to run.
  */
 #ifndef PCPM_H
 #define PCPM_H
@@ -50,8 +51,9 @@ typedef struct pcpm_png* pcpm_png_t;
 /* Build options.  Zero-initialise and set what you need. */
 typedef struct {
   int32_t part_log2;     /* q = 2^part_log2 nodes per partition (Sec. 3.1),
-                            1..15 (the q*4-byte rank slice lives in the LDS of
-                            one compute unit) with k = ceil(n/q) <= 16384;
+                            1..14 (the gather keeps an 8-byte exact sum per
+                            node of a partition in the LDS of one compute
+                            unit) with k = ceil(n/q) <= 16384;
                             0 = 14 (q = 16384)                                */
   int32_t reserved0;
   int64_t scatter_chunk; /* PNG edges per scatter work item; 0 = automatic   */

@@ -388,7 +388,10 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
     for (int64_t lo = a; lo < b; lo += step)
       ga_items.push_back({static_cast<int32_t>(p), static_cast<int32_t>(lo),
                           static_cast<int32_t>(std::min(b, lo + step)), slot++});
-    mg.push_back({static_cast<int32_t>(p), first, slot - first, 0});
+    ++g->n_split_bins;
+    const int64_t qn = std::min<int64_t>(g->q, g->n - p * g->q);
+    for (int64_t nl = 0; nl < qn; nl += 256) mg.push_back({static_cast<int32_t>(p), first, slot - first,
+                                                           static_cast<int32_t>(nl)});
   }
   // largest work first
   auto bigger = [](const Item& x, const Item& y) { return (x.hi - x.lo) > (y.hi - y.lo); };
@@ -402,7 +405,11 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
   PCPM_TRY(dalloc(g, &g->sc_items, g->n_sc));
   PCPM_TRY(dalloc(g, &g->ga_items, g->n_ga));
   PCPM_TRY(dalloc(g, &g->mg_items, g->n_mg));
-  PCPM_TRY(dalloc(g, &g->partial, static_cast<int64_t>(slot) * g->q));
+  PCPM_TRY(dalloc(g, &g->partial, static_cast<int64_t>(slot) * g->q));  // int64 slices
+  // one (residual, dangling) pair per apply unit: bins applied by the gather
+  // use slot p, merge units use k + unit; slots of split bins stay zero
+  PCPM_TRY(dalloc(g, &g->red, 2 * (k + g->n_mg)));
+  PCPM_TRY_HIP(hipMemsetAsync(g->red, 0, static_cast<size_t>(2 * (k + g->n_mg)) * sizeof(double), st));
   if (g->n_sc)
     PCPM_TRY_HIP(hipMemcpyAsync(g->sc_items, sc_items.data(), sc_items.size() * sizeof(Item),
                                 hipMemcpyHostToDevice, st));
@@ -533,9 +540,8 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, g->did_blk, ntd);
 
   // ---- iteration buffers -----------------------------------------------------------
-  PCPM_TRY(dalloc(g, &g->upd, g->eprime));
-  PCPM_TRY(dalloc(g, &g->red, 2 * k));
-  PCPM_TRY(dalloc(g, &g->red_init, kInitBlocks));
+  PCPM_TRY(dalloc(g, &g->upd, g->eprime + 1));  // + spare slot for masked stores
+  PCPM_TRY(dalloc(g, &g->red_init, 3 * kInitBlocks));
   PCPM_TRY(dalloc(g, &g->hist, kMaxHist));
   PCPM_TRY(dalloc(g, &g->ctl, 1));
   PCPM_TRY(dalloc(g, &g->tmp_pr, n));
@@ -598,7 +604,7 @@ pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out) {
   out->n_dangling = g->n_dangling;
   out->scatter_items = g->n_sc;
   out->gather_items = g->n_ga;
-  out->split_bins = g->n_mg;
+  out->split_bins = g->n_split_bins;
   out->device_bytes = g->device_bytes;
   out->build_ms = g->build_ms;
   return PCPM_OK;

@@ -29,8 +29,15 @@ constexpr int kTile = kWave * kSub;
 constexpr int kMaxHist = 100000;   // residual history kept on the device
 constexpr int kMaxParts = 16384;   // k limit (LDS cursors of the fill kernel)
 constexpr int kMinLog2 = 1;
-constexpr int kMaxLog2 = 15;       // 32768 * 4 B = 128 KB rank slice
-constexpr int kIterBlock = 512;    // threads per scatter / gather workgroup
+constexpr int kMaxLog2 = 14;       // 16384 * 8 B = 128 KB fixed-point slice in LDS
+#ifndef PCPM_SCATTER_BLOCK
+#define PCPM_SCATTER_BLOCK 512
+#endif
+#ifndef PCPM_GATHER_BLOCK
+#define PCPM_GATHER_BLOCK 1024
+#endif
+constexpr int kScatterBlock = PCPM_SCATTER_BLOCK;  // threads per scatter workgroup
+constexpr int kGatherBlock = PCPM_GATHER_BLOCK;    // threads per gather / merge workgroup
 constexpr int kInitBlocks = 256;   // workgroups of the dangling-mass reduction
 
 // Device control block of one handle.
@@ -38,12 +45,13 @@ struct Ctl {
   double base;      // (1-d)/n + d*D/n: jump plus dangling share for the next apply
   double dmass;     // dangling mass D of the current input vector
   double res;       // residual of the last iteration
+  double res_prev;  // residual of the iteration before
   double tol;       // stop threshold (<= 0: never)
   double d;         // damping factor
   int32_t iter;     // iterations completed
   int32_t done;     // residual fell below tol, or a non-finite value appeared
   int32_t nonfinite;
-  int32_t pad;
+  int32_t fx_shift; // gather sums are kept as integers in units of 2^-fx_shift
 };
 
 // A unit of scatter or gather work: a contiguous range [lo, hi) of PNG edges
@@ -53,10 +61,11 @@ struct Item {
   int32_t part, lo, hi, aux;
 };
 
-// Merge work: a destination bin split over `count` gather items whose partial
-// sums sit in consecutive partial slots starting at `first`.
+// Merge work: nodes [node_lo, node_lo + 256) of a destination bin split over
+// `count` gather items whose partial sums sit in consecutive partial slots
+// starting at `first`.
 struct Merge {
-  int32_t part, first, count, pad;
+  int32_t part, first, count, node_lo;
 };
 
 // ---- errors ----------------------------------------------------------------
@@ -131,18 +140,18 @@ struct pcpm_png {
   uint32_t* did = nullptr;      // ceil(m/kTile)*kTile, top bit = first of message
   int32_t* did_blk = nullptr;   // flags before each tile, ceil(m/kTile)+1
   int32_t* did_start = nullptr; // k+1
-  float* upd = nullptr;         // E' update bins (rewritten every iteration)
+  float* upd = nullptr;         // E'+1: update bins (rewritten every iteration) + spare slot
 
   // work lists
   pcpm::Item* sc_items = nullptr;
   pcpm::Item* ga_items = nullptr;
   pcpm::Merge* mg_items = nullptr;
-  int32_t n_sc = 0, n_ga = 0, n_mg = 0, n_split_slots = 0;
-  float* partial = nullptr;     // n_split_slots * q
+  int32_t n_sc = 0, n_ga = 0, n_mg = 0, n_split_slots = 0, n_split_bins = 0;
+  int64_t* partial = nullptr;   // n_split_slots * q fixed-point partial sums
 
   // reductions and control
-  double* red = nullptr;        // 2*k: per-bin (residual, dangling) partial sums
-  double* red_init = nullptr;   // kInitBlocks
+  double* red = nullptr;        // 2*(k + n_mg): (residual, dangling) partial sums per apply unit
+  double* red_init = nullptr;   // 3*kInitBlocks
   double* hist = nullptr;       // kMaxHist residuals
   pcpm::Ctl* ctl = nullptr;
   pcpm::Ctl* ctl_host = nullptr;  // pinned mirror

@@ -13,64 +13,88 @@
 //               sums build up in an LDS slice of the destination partition.
 //               A whole bin is applied in place; a split bin stores its
 //               partial slice for k_merge.
-//   k_merge     applies split bins, adding their partial slices in order.
+//   k_merge     applies split bins, adding their partial slices in order;
+//               one workgroup per slice of a split bin's nodes.
 //   k_finalize  one workgroup: residual and next dangling mass in FP64, in a
 //               fixed order; sets the convergence flag that makes the kernels
 //               of later iterations return at once.
+//
+// Sums in the gather are exact: every FP32 update is converted to a 64-bit
+// integer in units of 2^-fx_shift (a power of two chosen from the start
+// vector's L1 mass, so no sum can overflow) and added with LDS integer
+// atomics.  Integer addition is associative, so the ranks do not depend on
+// the order in which wavefronts add, and split bins merge exactly.
 #include <algorithm>
+#include <cmath>
 
 #include "pcpm_internal.hpp"
 
 namespace pcpm {
 
-// Sum two FP64 values over the workgroup; the result is valid in thread 0.
-template <int BS>
-__device__ __forceinline__ void block_sum2(double& a, double& b) {
+constexpr int kMergeNodes = 256;  // nodes per merge workgroup (one per thread)
+
+// Sum N FP64 values over the workgroup; results are valid in thread 0.
+template <int BS, int N>
+__device__ __forceinline__ void block_sum(double (&v)[N]) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
-    a += __shfl_xor(a, off);
-    b += __shfl_xor(b, off);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off);
   }
-  __shared__ double sh[2 * (BS / kWave)];
+  __shared__ double sh[N * (BS / kWave)];
   const int w = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    sh[2 * w] = a;
-    sh[2 * w + 1] = b;
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh[N * w + i] = v[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    a = 0.0;
-    b = 0.0;
-    for (int i = 0; i < BS / kWave; ++i) {
-      a += sh[2 * i];
-      b += sh[2 * i + 1];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      v[i] = 0.0;
+      for (int k = 0; k < BS / kWave; ++k) v[i] += sh[N * k + i];
     }
   }
 }
 
-// Apply (Alg. 2) for the nodes v0 .. v0+qn-1 of one destination partition:
+// Exact conversion of an FP32 value to a signed integer in units of 2^-sh
+// (truncated below one unit).  |v| * 2^sh must stay below 2^62; larger
+// magnitudes (only non-finite or corrupt input) saturate.
+__device__ __forceinline__ int64_t to_fixed(float v, int sh) {
+  const uint32_t b = __float_as_uint(v);
+  const int e = static_cast<int>((b >> 23) & 0xFFu);
+  const uint64_t mant = (b & 0x7FFFFFu) | (e ? 0x800000u : 0u);
+  const int a = (e ? e : 1) - 150 + sh;  // v = mant * 2^(a - sh)
+  const uint64_t up = mant << min(max(a, 0), 39);
+  const uint64_t down = (a > -64) ? (mant >> min(max(-a, 0), 63)) : 0ull;
+  const uint64_t mag = a > 39 ? (1ull << 62) : (a >= 0 ? up : down);
+  return (b >> 31) ? -static_cast<int64_t>(mag) : static_cast<int64_t>(mag);
+}
+
+// Apply (Alg. 2) for nodes v0+i0 .. v0+i1-1 of one destination partition:
 //   x_new(v) = d * acc(v) + base,  base = (1-d)/n + d*D/n
-// plus this partition's share of sum |x_new - x_old| and of the next
-// dangling mass, both FP64.
+// plus their share of sum |x_new - x_old| and of the next dangling mass.
 template <int BS, class AccFn>
-__device__ __forceinline__ void apply_partition(const Ctl* __restrict__ ctl, int64_t v0, int qn, AccFn acc,
-                                                const float* __restrict__ pr_in, float* __restrict__ pr_out,
-                                                const uint32_t* __restrict__ dmask, double* __restrict__ red_slot) {
+__device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, int64_t v0, int i0, int i1, AccFn acc,
+                                            const float* __restrict__ pr_in, float* __restrict__ pr_out,
+                                            const uint32_t* __restrict__ dmask, double* __restrict__ red_slot) {
   const double base = ctl->base;
   const double d = ctl->d;
-  double r = 0.0, dm = 0.0;
-  for (int i = threadIdx.x; i < qn; i += BS) {
+  const double unit = ldexp(1.0, -ctl->fx_shift);
+  double sums[2] = {0.0, 0.0};  // residual, dangling mass
+  for (int i = i0 + static_cast<int>(threadIdx.x); i < i1; i += BS) {
     const int64_t v = v0 + i;
-    const float xn = static_cast<float>(fma(d, static_cast<double>(acc(i)), base));
+    const double s = static_cast<double>(acc(i)) * unit;
+    const float xn = static_cast<float>(fma(d, s, base));
     const float xo = pr_in[v];
-    r += fabs(static_cast<double>(xn) - static_cast<double>(xo));
-    if ((dmask[v >> 5] >> (v & 31)) & 1u) dm += static_cast<double>(xn);
+    sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(xo));
+    if ((dmask[v >> 5] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
     pr_out[v] = xn;
   }
-  block_sum2<BS>(r, dm);
+  block_sum<BS>(sums);
   if (threadIdx.x == 0) {
-    red_slot[0] = r;
-    red_slot[1] = dm;
+    red_slot[0] = sums[0];
+    red_slot[1] = sums[1];
   }
 }
 
@@ -80,7 +104,8 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
                                                 const int32_t* __restrict__ outdeg,
                                                 const uint32_t* __restrict__ png_src,
                                                 const int32_t* __restrict__ png_blk,
-                                                const int32_t* __restrict__ seg_delta, float* __restrict__ upd) {
+                                                const int32_t* __restrict__ seg_delta, float* __restrict__ upd,
+                                                int64_t spare) {
   if (ctl->done) return;
   extern __shared__ float spr[];
   const Item it = items[blockIdx.x];
@@ -93,11 +118,25 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t lo = it.lo, hi = it.hi;
-  for (int64_t t = lo / kTile + threadIdx.x / kWave; t * kTile < hi; t += BS / kWave) {
-    const int64_t tb = t * kTile;
-    uint32_t x[kSub];
+  const int64_t t_end = (hi + kTile - 1) / kTile;
+  constexpr int kNW = BS / kWave;
+  uint32_t x[kSub], xn[kSub];
+  int64_t t = lo / kTile + threadIdx.x / kWave;
+  if (t < t_end) {
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = png_src[tb + j * kWave + lane];
+    for (int j = 0; j < kSub; ++j) x[j] = png_src[t * kTile + j * kWave + lane];
+  }
+  for (; t < t_end; t += kNW) {
+    const int64_t tb = t * kTile;
+    if (t + kNW < t_end) {  // the next tile's loads overlap this tile's work
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) xn[j] = png_src[(t + kNW) * kTile + j * kWave + lane];
+    }
+    // Every entry of a tile has a valid segment index (entry 0 of the array
+    // is flagged and padding follows the last segment), so the loads below
+    // need no predicate; entries outside [lo, hi) store to the spare slot
+    // upd[E'] instead of a real one.
+    const bool full = tb >= lo && tb + kTile <= hi;
     int32_t run = png_blk[t];
     int32_t seg[kSub];
 #pragma unroll
@@ -107,14 +146,19 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
       seg[j] = run + lanes_below(bal) + static_cast<int32_t>(f) - 1;
       run += __popcll(bal);
     }
+    int32_t dl[kSub];
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
       const int64_t e = tb + j * kWave + lane;
-      if (e >= lo && e < hi) {
-        const int64_t slot = e + seg_delta[seg[j]];
-        upd[slot] = spr[static_cast<int64_t>(x[j] & kIdMask) - v0];
-      }
+      const bool in = full || (e >= lo && e < hi);
+      const int32_t li = in ? static_cast<int32_t>(static_cast<int64_t>(x[j] & kIdMask) - v0) : 0;
+      const int64_t slot = in ? e + dl[j] : spare;
+      upd[slot] = spr[li];
     }
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) x[j] = xn[j];
   }
 }
 
@@ -123,23 +167,37 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
                                                const Item* __restrict__ items, const uint32_t* __restrict__ did,
                                                const int32_t* __restrict__ did_blk, const float* __restrict__ upd,
                                                const float* __restrict__ pr_in, float* __restrict__ pr_out,
-                                               const uint32_t* __restrict__ dmask, float* __restrict__ partial,
+                                               const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
                                                double* __restrict__ red) {
   if (ctl->done) return;
-  extern __shared__ float acc[];
+  extern __shared__ unsigned long long acc[];
   const Item it = items[blockIdx.x];
   const int64_t q = int64_t{1} << s;
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
-  for (int i = threadIdx.x; i < qn; i += BS) acc[i] = 0.0f;
+  const int sh = ctl->fx_shift;
+  for (int i = threadIdx.x; i < qn; i += BS) acc[i] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t lo = it.lo, hi = it.hi;
-  for (int64_t t = lo / kTile + threadIdx.x / kWave; t * kTile < hi; t += BS / kWave) {
-    const int64_t tb = t * kTile;
-    uint32_t x[kSub];
+  const int64_t t_end = (hi + kTile - 1) / kTile;
+  constexpr int kNW = BS / kWave;
+  uint32_t x[kSub], xn[kSub];
+  int64_t t = lo / kTile + threadIdx.x / kWave;
+  if (t < t_end) {
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = did[tb + j * kWave + lane];
+    for (int j = 0; j < kSub; ++j) x[j] = did[t * kTile + j * kWave + lane];
+  }
+  for (; t < t_end; t += kNW) {
+    const int64_t tb = t * kTile;
+    if (t + kNW < t_end) {  // the next tile's IDs are in flight during this tile's work
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) xn[j] = did[(t + kNW) * kTile + j * kWave + lane];
+    }
+    // Every entry of a tile has a valid update index (entry 0 of the array is
+    // flagged, padding follows the last message), so update loads need no
+    // predicate; entries outside [lo, hi) add zero to slot 0.
+    const bool full = tb >= lo && tb + kTile <= hi;
     int32_t run = did_blk[t];
     int32_t ui[kSub];
 #pragma unroll
@@ -151,57 +209,64 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
     }
     float val[kSub];
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const int64_t e = tb + j * kWave + lane;
-      val[j] = (e >= lo && e < hi) ? upd[ui[j]] : 0.0f;
-    }
+    for (int j = 0; j < kSub; ++j) val[j] = upd[ui[j]];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
       const int64_t e = tb + j * kWave + lane;
-      if (e >= lo && e < hi) atomicAdd(&acc[static_cast<int64_t>(x[j] & kIdMask) - v0], val[j]);
+      const bool in = full || (e >= lo && e < hi);
+      const int32_t li = in ? static_cast<int32_t>(static_cast<int64_t>(x[j] & kIdMask) - v0) : 0;
+      const int64_t fx = in ? to_fixed(val[j], sh) : 0;
+      atomicAdd(&acc[li], static_cast<unsigned long long>(fx));
     }
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) x[j] = xn[j];
   }
   __syncthreads();
   if (it.aux >= 0) {
-    float* dst = partial + static_cast<int64_t>(it.aux) * q;
-    for (int i = threadIdx.x; i < qn; i += BS) dst[i] = acc[i];
+    int64_t* dst = partial + static_cast<int64_t>(it.aux) * q;
+    for (int i = threadIdx.x; i < qn; i += BS) dst[i] = static_cast<int64_t>(acc[i]);
     return;
   }
-  apply_partition<BS>(ctl, v0, qn, [&](int i) { return acc[i]; }, pr_in, pr_out, dmask, red + 2 * it.part);
+  apply_nodes<BS>(ctl, v0, 0, qn, [&](int i) { return static_cast<int64_t>(acc[i]); }, pr_in, pr_out, dmask,
+                  red + 2 * it.part);
 }
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_merge(const Ctl* __restrict__ ctl, int64_t n, int s,
-                                              const Merge* __restrict__ mg, const float* __restrict__ partial,
+                                              const Merge* __restrict__ mg, const int64_t* __restrict__ partial,
                                               const float* __restrict__ pr_in, float* __restrict__ pr_out,
-                                              const uint32_t* __restrict__ dmask, double* __restrict__ red) {
+                                              const uint32_t* __restrict__ dmask, double* __restrict__ red,
+                                              int64_t red_base) {
   if (ctl->done) return;
-  const Merge mi = mg[blockIdx.x];
+  const Merge mu = mg[blockIdx.x];
   const int64_t q = int64_t{1} << s;
-  const int64_t v0 = static_cast<int64_t>(mi.part) << s;
+  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
-  const float* base = partial + static_cast<int64_t>(mi.first) * q;
-  const int cnt = mi.count;
+  const int64_t* base = partial + static_cast<int64_t>(mu.first) * q;
+  const int cnt = mu.count;
   auto acc = [&](int i) {
-    float sum = 0.0f;
+    int64_t sum = 0;
     for (int c = 0; c < cnt; ++c) sum += base[static_cast<int64_t>(c) * q + i];
     return sum;
   };
-  apply_partition<BS>(ctl, v0, qn, acc, pr_in, pr_out, dmask, red + 2 * mi.part);
+  apply_nodes<BS>(ctl, v0, mu.node_lo, min(qn, mu.node_lo + kMergeNodes), acc, pr_in, pr_out, dmask,
+                  red + 2 * (red_base + blockIdx.x));
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, const double* __restrict__ red,
-                                                   int64_t k, double* __restrict__ hist, int64_t n) {
+                                                   int64_t nslots, double* __restrict__ hist, int64_t n) {
   if (ctl->done) return;
-  double r = 0.0, dm = 0.0;
-  for (int64_t j = threadIdx.x; j < k; j += 1024) {
-    r += red[2 * j];
-    dm += red[2 * j + 1];
+  double sums[2] = {0.0, 0.0};
+  for (int64_t j = threadIdx.x; j < nslots; j += 1024) {
+    sums[0] += red[2 * j];
+    sums[1] += red[2 * j + 1];
   }
-  block_sum2<1024>(r, dm);
+  block_sum<1024>(sums);
   if (threadIdx.x == 0) {
+    const double r = sums[0], dm = sums[1];
     const double d = ctl->d;
     const int32_t it = ctl->iter;
+    ctl->res_prev = ctl->res;
     ctl->res = r;
     hist[it] = r;
     ctl->iter = it + 1;
@@ -222,12 +287,13 @@ __global__ void k_ctl_init(Ctl* ctl, double tol, double d) {
     ctl->base = 0.0;
     ctl->dmass = 0.0;
     ctl->res = 0.0;
+    ctl->res_prev = 0.0;
     ctl->tol = tol;
     ctl->d = d;
     ctl->iter = 0;
     ctl->done = 0;
     ctl->nonfinite = 0;
-    ctl->pad = 0;
+    ctl->fx_shift = 62;
   }
 }
 
@@ -237,31 +303,49 @@ __global__ __launch_bounds__(256) void k_fill_value(float* __restrict__ x, int64
     x[i] = v;
 }
 
-// Dangling mass of the starting vector: fixed grid, fixed per-thread order.
-__global__ __launch_bounds__(256) void k_dangling_partial(const float* __restrict__ x,
-                                                          const uint32_t* __restrict__ dmask, int64_t n,
-                                                          double* __restrict__ red_init) {
-  double dm = 0.0, nonfin = 0.0;
+// Dangling mass, L1 mass and non-finite count of the starting vector: fixed
+// grid, fixed per-thread order.
+__global__ __launch_bounds__(256) void k_start_partial(const float* __restrict__ x,
+                                                       const uint32_t* __restrict__ dmask, int64_t n,
+                                                       double* __restrict__ red_init) {
+  double sums[3] = {0.0, 0.0, 0.0};
   for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
        v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const float xv = x[v];
-    if (!isfinite(xv)) nonfin += 1.0;
-    if ((dmask[v >> 5] >> (v & 31)) & 1u) dm += static_cast<double>(xv);
+    if (!isfinite(xv)) sums[2] += 1.0;
+    sums[1] += fabs(static_cast<double>(xv));
+    if ((dmask[v >> 5] >> (v & 31)) & 1u) sums[0] += static_cast<double>(xv);
   }
-  block_sum2<256>(dm, nonfin);
-  if (threadIdx.x == 0) red_init[blockIdx.x] = nonfin > 0.0 ? NAN : dm;
+  block_sum<256>(sums);
+  if (threadIdx.x == 0) {
+    red_init[3 * blockIdx.x] = sums[0];
+    red_init[3 * blockIdx.x + 1] = sums[1];
+    red_init[3 * blockIdx.x + 2] = sums[2];
+  }
 }
 
+// D, base and the fixed-point scale of the gather: every gather sum is bounded
+// by max(1, L1 mass of the start vector), which later iterates never exceed
+// (teleport vectors are non-negative and sum to one), so 2^fx_shift times
+// that bound stays below 2^62.
 __global__ __launch_bounds__(256) void k_init_finalize(Ctl* __restrict__ ctl, const double* __restrict__ red_init,
                                                        int nb, int64_t n) {
-  double dm = 0.0, unused = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) dm += red_init[i];
-  block_sum2<256>(dm, unused);
+  double sums[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    sums[0] += red_init[3 * i];
+    sums[1] += red_init[3 * i + 1];
+    sums[2] += red_init[3 * i + 2];
+  }
+  block_sum<256>(sums);
   if (threadIdx.x == 0) {
     const double d = ctl->d;
+    const double dm = sums[0], mass = sums[1];
     ctl->dmass = dm;
     ctl->base = (1.0 - d) / static_cast<double>(n) + d * dm / static_cast<double>(n);
-    if (!isfinite(dm)) {
+    int e = 0;
+    if (isfinite(mass) && mass > 1.0) e = static_cast<int>(ceil(log2(mass)));
+    ctl->fx_shift = 62 - min(e, 120);
+    if (sums[2] > 0.0 || !isfinite(dm) || !isfinite(mass)) {
       ctl->nonfinite = 1;
       ctl->done = 1;
     }
@@ -271,35 +355,35 @@ __global__ __launch_bounds__(256) void k_init_finalize(Ctl* __restrict__ ctl, co
 pcpm_status_t iter_lds_limits() {
   static bool done = false;
   if (done) return PCPM_OK;
-  const int bytes = (1 << kMaxLog2) * 4;
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter<kIterBlock>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kIterBlock>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter<kScatterBlock>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 4));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
   done = true;
   return PCPM_OK;
 }
 
 static pcpm_status_t start_solve(pcpm_png* g, double tol, double d, const float* x0, hipStream_t st) {
   PCPM_LAUNCH("pcpm_init", k_ctl_init, dim3(1), dim3(64), 0, st, g->ctl, tol, d);
-  PCPM_LAUNCH("pcpm_init", k_dangling_partial, dim3(kInitBlocks), dim3(256), 0, st, x0, g->dmask, g->n,
+  PCPM_LAUNCH("pcpm_init", k_start_partial, dim3(kInitBlocks), dim3(256), 0, st, x0, g->dmask, g->n,
               g->red_init);
   PCPM_LAUNCH("pcpm_init", k_init_finalize, dim3(1), dim3(256), 0, st, g->ctl, g->red_init, kInitBlocks, g->n);
   return PCPM_OK;
 }
 
 static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hipStream_t st) {
-  const size_t lds = static_cast<size_t>(g->q) * 4;
-  const dim3 bs(kIterBlock);
   if (g->n_sc)
-    PCPM_LAUNCH("pcpm_scatter", k_scatter<kIterBlock>, dim3(static_cast<unsigned>(g->n_sc)), bs, lds, st, g->ctl,
-                g->n, g->part_log2, g->sc_items, in, g->outdeg, g->png_src, g->png_blk, g->seg_delta, g->upd);
-  PCPM_LAUNCH("pcpm_gather", k_gather<kIterBlock>, dim3(static_cast<unsigned>(g->n_ga)), bs, lds, st, g->ctl, g->n,
-              g->part_log2, g->ga_items, g->did, g->did_blk, g->upd, in, out, g->dmask, g->partial, g->red);
+    PCPM_LAUNCH("pcpm_scatter", k_scatter<kScatterBlock>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kScatterBlock),
+                static_cast<size_t>(g->q) * 4, st, g->ctl, g->n, g->part_log2, g->sc_items, in, g->outdeg,
+                g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
+  PCPM_LAUNCH("pcpm_gather", k_gather<kGatherBlock>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kGatherBlock),
+              static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items, g->did, g->did_blk,
+              g->upd, in, out, g->dmask, g->partial, g->red);
   if (g->n_mg)
-    PCPM_LAUNCH("pcpm_merge", k_merge<kIterBlock>, dim3(static_cast<unsigned>(g->n_mg)), bs, 0, st, g->ctl, g->n,
-                g->part_log2, g->mg_items, g->partial, in, out, g->dmask, g->red);
-  PCPM_LAUNCH("pcpm_finalize", k_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->red, g->k, g->hist, g->n);
+    PCPM_LAUNCH("pcpm_merge", k_merge<kMergeNodes>, dim3(static_cast<unsigned>(g->n_mg)), dim3(kMergeNodes), 0,
+                st, g->ctl, g->n, g->part_log2, g->mg_items, g->partial, in, out, g->dmask, g->red, g->k);
+  PCPM_LAUNCH("pcpm_finalize", k_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->red, g->k + g->n_mg, g->hist,
+              g->n);
   return PCPM_OK;
 }
 
@@ -354,21 +438,31 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
                 static_cast<float>(1.0 / static_cast<double>(g->n)));
   }
   PCPM_TRY(start_solve(g, tol, d, a, st));
-  // Iterations are queued in small batches; after convergence the queued
-  // kernels of the remaining iterations return immediately.
-  constexpr int kBatch = 4;
+  // Iterations are queued in batches between host checks of the device
+  // control block.  After the first batch the batch length is the number of
+  // iterations the observed per-iteration residual ratio predicts until tol,
+  // so few iterations are queued past convergence (those return at once).
   int launched = 0;
+  int next = std::min(tol > 0.0 ? 4 : 64, max_iters);
   while (launched < max_iters) {
-    const int nb = std::min(kBatch, max_iters - launched);
-    for (int i = 0; i < nb; ++i) {
+    for (int i = 0; i < next; ++i) {
       const int it = launched + i;
       const bool even = (it % 2) == 0;
       PCPM_TRY(run_iteration(g, even ? a : b, even ? b : a, st));
     }
-    launched += nb;
+    launched += next;
     PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     PCPM_TRY_HIP(hipStreamSynchronize(st));
     if (g->ctl_host->done) break;
+    int want = 64;
+    if (tol > 0.0) {
+      const double res = g->ctl_host->res, prev = g->ctl_host->res_prev;
+      double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
+      rho = std::min(std::max(rho, 0.05), 0.995);
+      const double est = std::ceil(std::log(tol / res) / std::log(rho));
+      want = static_cast<int>(std::min(std::max(est, 1.0), 16.0));
+    }
+    next = std::min(want, max_iters - launched);
   }
   const Ctl c = *g->ctl_host;
   *iters = c.iter;
