@@ -91,6 +91,24 @@ def measure(P, torch, r, c, args, label):
     return result, out.cpu().numpy(), png
 
 
+def calibrate_copy(torch):
+    """A plain copy kernel of known size: 2 GiB read + 2 GiB written per launch."""
+    nbytes = 2 << 30
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "ms": dt * 1e3,
+                      "gbs_read_plus_write": 2 * nbytes / dt / 1e9}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +123,8 @@ def main():
     ap.add_argument("--max-iters", type=int, default=200)
     ap.add_argument("--no-indegree", action="store_true", help="skip the in-degree-sorted labelling")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -115,6 +135,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
 
     import graphgen
     import paper_1709_07122_amd as P

@@ -19,11 +19,11 @@
 //               fixed order; sets the convergence flag that makes the kernels
 //               of later iterations return at once.
 //
-// Sums in the gather are exact: every FP32 update is converted to a 64-bit
-// integer in units of 2^-fx_shift (a power of two chosen from the start
-// vector's L1 mass, so no sum can overflow) and added with LDS integer
-// atomics.  Integer addition is associative, so the ranks do not depend on
-// the order in which wavefronts add, and split bins merge exactly.
+// Sums in the gather are kept in 64-bit fixed point: every FP32 update is
+// rounded to a multiple of 2^-fx_shift (fx_shift = 50 for a start vector of
+// unit mass, so each update moves by at most 4.4e-16) and added with LDS
+// integer atomics.  Integer addition is associative, so the ranks do not
+// depend on the order in which wavefronts add, and split bins merge exactly.
 #include <algorithm>
 #include <cmath>
 
@@ -57,19 +57,20 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
   }
 }
 
-// Exact conversion of an FP32 value to a signed integer in units of 2^-sh
-// (truncated below one unit).  |v| * 2^sh must stay below 2^62; larger
-// magnitudes (only non-finite or corrupt input) saturate.
-__device__ __forceinline__ int64_t to_fixed(float v, int sh) {
-  const uint32_t b = __float_as_uint(v);
-  const int e = static_cast<int>((b >> 23) & 0xFFu);
-  const uint64_t mant = (b & 0x7FFFFFu) | (e ? 0x800000u : 0u);
-  const int a = (e ? e : 1) - 150 + sh;  // v = mant * 2^(a - sh)
-  const uint64_t up = mant << min(max(a, 0), 39);
-  const uint64_t down = (a > -64) ? (mant >> min(max(-a, 0), 63)) : 0ull;
-  const uint64_t mag = a > 39 ? (1ull << 62) : (a >= 0 ? up : down);
-  return (b >> 31) ? -static_cast<int64_t>(mag) : static_cast<int64_t>(mag);
-}
+// Conversion of an FP32 update to a signed integer in units of 2^-sh,
+// rounded to nearest: v * 2^sh + 1.5*2^52 is formed by one FP64 FMA (exact
+// product, one rounding) and the integer is read from the low mantissa bits.
+// Valid for |v| * 2^sh < 2^51, which the choice of sh guarantees for every
+// finite update; the result then carries the update to within 2^-(sh+1).
+struct FixedConv {
+  double scale;
+  __device__ explicit FixedConv(int sh) : scale(ldexp(1.0, sh)) {}
+  __device__ __forceinline__ int64_t operator()(float v) const {
+    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+    const double y = fma(static_cast<double>(v), scale, kMagic);
+    return __double_as_longlong(y) - __double_as_longlong(kMagic);
+  }
+};
 
 // Apply (Alg. 2) for nodes v0+i0 .. v0+i1-1 of one destination partition:
 //   x_new(v) = d * acc(v) + base,  base = (1-d)/n + d*D/n
@@ -82,14 +83,30 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, int64_t
   const double d = ctl->d;
   const double unit = ldexp(1.0, -ctl->fx_shift);
   double sums[2] = {0.0, 0.0};  // residual, dangling mass
-  for (int i = i0 + static_cast<int>(threadIdx.x); i < i1; i += BS) {
-    const int64_t v = v0 + i;
-    const double s = static_cast<double>(acc(i)) * unit;
-    const float xn = static_cast<float>(fma(d, s, base));
-    const float xo = pr_in[v];
-    sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(xo));
-    if ((dmask[v >> 5] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
-    pr_out[v] = xn;
+  // kU nodes per thread per step, loads first, so their latencies overlap
+  constexpr int kU = 4;
+  for (int i = i0 + static_cast<int>(threadIdx.x); i < i1; i += kU * BS) {
+    float xo[kU];
+    uint32_t dw[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int ii = i + u * BS;
+      const int64_t v = v0 + min(ii, i1 - 1);
+      xo[u] = pr_in[v];
+      dw[u] = dmask[v >> 5];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int ii = i + u * BS;
+      if (ii < i1) {
+        const int64_t v = v0 + ii;
+        const double sv = static_cast<double>(acc(ii)) * unit;
+        const float xn = static_cast<float>(fma(d, sv, base));
+        sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
+        if ((dw[u] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
+        pr_out[v] = xn;
+      }
+    }
   }
   block_sum<BS>(sums);
   if (threadIdx.x == 0) {
@@ -117,45 +134,52 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t qmask = (1u << s) - 1u;
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
   uint32_t x[kSub], xn[kSub];
   int64_t t = lo / kTile + threadIdx.x / kWave;
   if (t < t_end) {
+    const uint32_t* pt = png_src + t * kTile;
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = png_src[t * kTile + j * kWave + lane];
+    for (int j = 0; j < kSub; ++j) x[j] = pt[j * kWave + lane];
   }
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     if (t + kNW < t_end) {  // the next tile's loads overlap this tile's work
+      const uint32_t* pt = png_src + (t + kNW) * kTile;
 #pragma unroll
-      for (int j = 0; j < kSub; ++j) xn[j] = png_src[(t + kNW) * kTile + j * kWave + lane];
+      for (int j = 0; j < kSub; ++j) xn[j] = pt[j * kWave + lane];
     }
     // Every entry of a tile has a valid segment index (entry 0 of the array
     // is flagged and padding follows the last segment), so the loads below
-    // need no predicate; entries outside [lo, hi) store to the spare slot
-    // upd[E'] instead of a real one.
-    const bool full = tb >= lo && tb + kTile <= hi;
+    // need no predicate.  A source ID masked with q-1 is its slot in the rank
+    // slice (entries of other partitions, in edge tiles, only read a stale
+    // slot and store to the spare update slot E').
     int32_t run = png_blk[t];
     int32_t seg[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
-      const uint32_t f = x[j] >> 31;
-      const uint64_t bal = wave_ballot(f != 0);
-      seg[j] = run + lanes_below(bal) + static_cast<int32_t>(f) - 1;
+      const bool f = static_cast<int32_t>(x[j]) < 0;
+      const uint64_t bal = wave_ballot(f);
+      seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
       run += __popcll(bal);
     }
     int32_t dl[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
+    if (tb >= lo && tb + kTile <= hi) {
+      float* ut = upd + tb;
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const int64_t e = tb + j * kWave + lane;
-      const bool in = full || (e >= lo && e < hi);
-      const int32_t li = in ? static_cast<int32_t>(static_cast<int64_t>(x[j] & kIdMask) - v0) : 0;
-      const int64_t slot = in ? e + dl[j] : spare;
-      upd[slot] = spr[li];
+      for (int j = 0; j < kSub; ++j) ut[static_cast<int64_t>(j * kWave + lane + dl[j])] = spr[x[j] & qmask];
+    } else {
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) {
+        const int64_t e = tb + j * kWave + lane;
+        const bool in = e >= lo && e < hi;
+        upd[in ? e + dl[j] : spare] = spr[x[j] & qmask];
+      }
     }
 #pragma unroll
     for (int j = 0; j < kSub; ++j) x[j] = xn[j];
@@ -175,7 +199,8 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
   const int64_t q = int64_t{1} << s;
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
-  const int sh = ctl->fx_shift;
+  const FixedConv to_fixed(ctl->fx_shift);
+  const uint32_t qmask = static_cast<uint32_t>(q - 1);
   for (int i = threadIdx.x; i < qn; i += BS) acc[i] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
@@ -185,38 +210,47 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
   uint32_t x[kSub], xn[kSub];
   int64_t t = lo / kTile + threadIdx.x / kWave;
   if (t < t_end) {
+    const uint32_t* dt = did + t * kTile;
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = did[t * kTile + j * kWave + lane];
+    for (int j = 0; j < kSub; ++j) x[j] = dt[j * kWave + lane];
   }
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     if (t + kNW < t_end) {  // the next tile's IDs are in flight during this tile's work
+      const uint32_t* dt = did + (t + kNW) * kTile;
 #pragma unroll
-      for (int j = 0; j < kSub; ++j) xn[j] = did[(t + kNW) * kTile + j * kWave + lane];
+      for (int j = 0; j < kSub; ++j) xn[j] = dt[j * kWave + lane];
     }
-    // Every entry of a tile has a valid update index (entry 0 of the array is
-    // flagged, padding follows the last message), so update loads need no
-    // predicate; entries outside [lo, hi) add zero to slot 0.
-    const bool full = tb >= lo && tb + kTile <= hi;
-    int32_t run = did_blk[t];
-    int32_t ui[kSub];
+    // Update indices of a tile lie in [did_blk[t]-1, did_blk[t+1]-1]: the
+    // loads below take a per-tile base and a 32-bit lane offset.  Every entry
+    // has a valid index (entry 0 of the array is flagged and padding follows
+    // the last message), so update loads need no predicate.
+    const int32_t ubase = did_blk[t];
+    const char* ub = reinterpret_cast<const char*>(upd) + (static_cast<int64_t>(ubase) - 1) * 4;
+    int32_t run = 0;  // flags in the earlier sub-blocks of this tile
+    uint32_t off[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
-      const uint32_t f = x[j] >> 31;
-      const uint64_t bal = wave_ballot(f != 0);
-      ui[j] = run + lanes_below(bal) + static_cast<int32_t>(f) - 1;  // Alg. 5 update pointer
+      const bool f = static_cast<int32_t>(x[j]) < 0;
+      const uint64_t bal = wave_ballot(f);
+      // Alg. 5 update pointer (flags so far, inclusive, minus one) relative to ub
+      off[j] = static_cast<uint32_t>(run + lanes_below(bal) + (f ? 1 : 0)) * 4u;
       run += __popcll(bal);
     }
     float val[kSub];
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) val[j] = upd[ui[j]];
+    for (int j = 0; j < kSub; ++j) val[j] = *reinterpret_cast<const float*>(ub + off[j]);
+    if (tb >= lo && tb + kTile <= hi) {
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const int64_t e = tb + j * kWave + lane;
-      const bool in = full || (e >= lo && e < hi);
-      const int32_t li = in ? static_cast<int32_t>(static_cast<int64_t>(x[j] & kIdMask) - v0) : 0;
-      const int64_t fx = in ? to_fixed(val[j], sh) : 0;
-      atomicAdd(&acc[li], static_cast<unsigned long long>(fx));
+      for (int j = 0; j < kSub; ++j)
+        atomicAdd(&acc[x[j] & qmask], static_cast<unsigned long long>(to_fixed(val[j])));
+    } else {  // edge tile: entries outside [lo, hi) add nothing
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) {
+        const int64_t e = tb + j * kWave + lane;
+        const bool in = e >= lo && e < hi;
+        atomicAdd(&acc[in ? (x[j] & qmask) : 0u], static_cast<unsigned long long>(in ? to_fixed(val[j]) : 0));
+      }
     }
 #pragma unroll
     for (int j = 0; j < kSub; ++j) x[j] = xn[j];
@@ -293,7 +327,7 @@ __global__ void k_ctl_init(Ctl* ctl, double tol, double d) {
     ctl->iter = 0;
     ctl->done = 0;
     ctl->nonfinite = 0;
-    ctl->fx_shift = 62;
+    ctl->fx_shift = 50;
   }
 }
 
@@ -327,7 +361,7 @@ __global__ __launch_bounds__(256) void k_start_partial(const float* __restrict__
 // D, base and the fixed-point scale of the gather: every gather sum is bounded
 // by max(1, L1 mass of the start vector), which later iterates never exceed
 // (teleport vectors are non-negative and sum to one), so 2^fx_shift times
-// that bound stays below 2^62.
+// that bound stays below 2^51 and every conversion is in range.
 __global__ __launch_bounds__(256) void k_init_finalize(Ctl* __restrict__ ctl, const double* __restrict__ red_init,
                                                        int nb, int64_t n) {
   double sums[3] = {0.0, 0.0, 0.0};
@@ -344,7 +378,7 @@ __global__ __launch_bounds__(256) void k_init_finalize(Ctl* __restrict__ ctl, co
     ctl->base = (1.0 - d) / static_cast<double>(n) + d * dm / static_cast<double>(n);
     int e = 0;
     if (isfinite(mass) && mass > 1.0) e = static_cast<int>(ceil(log2(mass)));
-    ctl->fx_shift = 62 - min(e, 120);
+    ctl->fx_shift = 50 - min(e, 1000);
     if (sums[2] > 0.0 || !isfinite(dm) || !isfinite(mass)) {
       ctl->nonfinite = 1;
       ctl->done = 1;
