@@ -91,6 +91,22 @@ def measure(P, torch, r, c, args, label):
     return result, out.cpu().numpy(), png
 
 
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", "pcpm_rmat24_random.json")))
+        src = open(os.path.join(ROOT, "paper_1709_07122_amd", "csrc", "pcpm_iter.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != prof.get("kernel_source_sha256_16"):
+        return None
+    k = prof["kernels"].get(kernel)
+    return None if k is None else int(k["traffic_bytes"])
+
+
 def calibrate_copy(torch):
     """A plain copy kernel of known size: 2 GiB read + 2 GiB written per launch."""
     nbytes = 2 << 30
@@ -207,7 +223,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "kernel": "pcpm_gather", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": counter_traffic("pcpm::k_gather<1024>") if args.part_log2 == 14 and args.scale == 24 else None,
             "bytes_per_launch": main_res["gather_bytes"], "avg_launch_ms": g["avg_ms"],
         },
         "cpu_baseline": cpu,
