@@ -55,13 +55,24 @@ typedef struct {
                             node of a partition in the LDS of one compute
                             unit) with k = ceil(n/q) <= 16384;
                             0 = 14 (q = 16384)                                */
-  int32_t reserved0;
+  int32_t num_graphs;    /* 0 or 1: one graph.  G > 1: the CSR is the block-
+                            diagonal union of G graphs; graph g owns nodes
+                            [graph_node_off[g], graph_node_off[g] +
+                            graph_nodes[g]); every graph_node_off[g] is a
+                            multiple of q (partitions never straddle graphs),
+                            graph_node_off[G] = n, nodes between a graph's
+                            last node and the next offset are padding without
+                            edges, and no edge leaves its graph.  Each graph
+                            gets its own uniform jump, dangling spread,
+                            residual and convergence.                        */
+  const int64_t* graph_node_off; /* (host) G+1, required when G > 1          */
+  const int64_t* graph_nodes;    /* (host) G, required when G > 1            */
   int64_t scatter_chunk; /* PNG edges per scatter work item; 0 = automatic   */
   int64_t gather_chunk;  /* destination IDs per gather work item; 0 = auto   */
 } pcpm_build_opts_t;
 
 typedef struct {
-  int64_t n, m;          /* nodes, edges                                      */
+  int64_t n, m;          /* nodes (padding included), edges                   */
   int64_t q, k;          /* partition size and count, k = ceil(n/q)           */
   int64_t eprime;        /* |E'|: PNG edges = updates per iteration (Sec. 3.3) */
   int64_t nseg;          /* non-empty (source, destination) partition pairs   */
@@ -70,6 +81,7 @@ typedef struct {
   int64_t gather_items;  /* gather work items                                 */
   int64_t split_bins;    /* destination bins gathered by more than one item   */
   int64_t device_bytes;  /* device memory held by the handle                  */
+  int64_t num_graphs;    /* G (1 for a single graph)                          */
   double build_ms;       /* wall time of pcpm_build_png, device work included */
 } pcpm_png_info_t;
 
@@ -131,11 +143,20 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
  * number of iterations run, *resid the last residual, res_hist (host,
  * nullable, max_iters entries) every residual.  1 <= max_iters <= 100000.
  * Synchronises `stream`.
+ * For a handle of G > 1 graphs every graph runs Eq. 1 with its own n_g
+ * (1/n_g start, jump and dangling spread on its own nodes, 0 on padding);
+ * a graph whose residual falls below tol keeps that iterate while the others
+ * go on; *iters and *resid are the largest over graphs, res_hist is graph 0's,
+ * and pcpm_graph_results gives every graph's.
  */
 pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iters,
                             const float* init /* nullable */, float* pr_out,
                             int32_t* iters /* (host) */, double* resid /* (host) */,
                             double* res_hist /* (host) nullable */, void* stream);
+
+/* Per-graph outcome of the last pcpm_pagerank on a handle: iterations run and
+ * last residual of each of the G graphs (host arrays of G). */
+pcpm_status_t pcpm_graph_results(pcpm_png_t g, int32_t* iters /* (host) G */, double* resid /* (host) G */);
 
 /* Message of the calling thread's last failure ("" if none). */
 const char* pcpm_last_error(void);

@@ -31,7 +31,8 @@ STATUS_NAMES = {
 
 # every symbol include/pcpm.h declares
 EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
-           "pcpm_pagerank", "pcpm_last_error", "pcpm_timing_enable", "pcpm_timing_collect"]
+           "pcpm_pagerank", "pcpm_graph_results", "pcpm_last_error", "pcpm_timing_enable",
+           "pcpm_timing_collect"]
 
 
 class PCPMError(RuntimeError):
@@ -41,14 +42,15 @@ class PCPMError(RuntimeError):
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("part_log2", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("part_log2", ctypes.c_int32), ("num_graphs", ctypes.c_int32),
+                ("graph_node_off", ctypes.c_void_p), ("graph_nodes", ctypes.c_void_p),
                 ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64)]
 
 
 class PngInfo(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ("n", "m", "q", "k", "eprime", "nseg", "n_dangling", "scatter_items", "gather_items",
-                 "split_bins", "device_bytes")] + [("build_ms", ctypes.c_double)]
+                 "split_bins", "device_bytes", "num_graphs")] + [("build_ms", ctypes.c_double)]
 
 
 class KernelTime(ctypes.Structure):
@@ -80,6 +82,8 @@ def lib():
     L.pcpm_iterate.argtypes = [vp, dbl, vp, vp, ctypes.POINTER(dbl), vp]
     L.pcpm_pagerank.restype = ctypes.c_int
     L.pcpm_pagerank.argtypes = [vp, dbl, dbl, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, vp]
+    L.pcpm_graph_results.restype = ctypes.c_int
+    L.pcpm_graph_results.argtypes = [vp, vp, vp]
     L.pcpm_last_error.restype = ctypes.c_char_p
     L.pcpm_last_error.argtypes = []
     L.pcpm_timing_enable.restype = None
@@ -163,6 +167,14 @@ class PNG:
         out["did"] = out["did"][:m]
         return out
 
+    def graph_results(self):
+        """(iters[G], resid[G]) of the last pagerank call on this handle."""
+        G = self.info["num_graphs"]
+        it = np.zeros(G, np.int32)
+        r = np.zeros(G, np.float64)
+        _check(lib().pcpm_graph_results(self.handle, it.ctypes.data, r.ctypes.data))
+        return it, r
+
     def close(self):
         if self._h:
             lib().pcpm_png_free(self._h)
@@ -176,14 +188,21 @@ class PNG:
 
 
 def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_chunk: int = 0,
-              stream=None) -> PNG:
-    """pcpm_build_png on device CSR tensors (int32 row_off[n+1], col[m])."""
+              graph_node_off=None, graph_nodes=None, stream=None) -> PNG:
+    """pcpm_build_png on device CSR tensors (int32 row_off[n+1], col[m]).
+
+    For several graphs in one handle pass the padded union (see union_csr)
+    with its graph_node_off (G+1) and graph_nodes (G)."""
     import torch
     n = row_off.numel() - 1
     m = col.numel()
     rp = _dev_tensor(row_off, torch.int32, name="row_off")
     cp = _dev_tensor(col, torch.int32, name="col") if m else ctypes.c_void_p(0)
-    opts = BuildOpts(int(part_log2), 0, int(scatter_chunk), int(gather_chunk))
+    G = 0 if graph_node_off is None else len(graph_nodes)
+    goff = np.ascontiguousarray(graph_node_off if G else [0], dtype=np.int64)
+    gn = np.ascontiguousarray(graph_nodes if G else [0], dtype=np.int64)
+    opts = BuildOpts(int(part_log2), G, goff.ctypes.data if G else None, gn.ctypes.data if G else None,
+                     int(scatter_chunk), int(gather_chunk))
     h = ctypes.c_void_p()
     _check(lib().pcpm_build_png(n, m, rp, cp, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return PNG(h, row_off, col)
@@ -240,3 +259,29 @@ def timing_collect() -> dict:
     arr = (KernelTime * 64)()
     cnt = lib().pcpm_timing_collect(arr, 64)
     return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(min(cnt, 64))}
+
+
+def union_csr(graphs, part_log2: int):
+    """Block-diagonal union of CSR graphs [(row_off, col), ...] in which graph g
+    starts at a multiple of q = 2^part_log2 (padding nodes without edges fill
+    the gaps).  Returns (row_off, col, graph_node_off[G+1], graph_nodes[G]) as
+    host arrays; only IDs are shifted, nothing is computed."""
+    q = 1 << part_log2
+    offs, sizes, rows, cols = [0], [], [], []
+    base_e = 0
+    for r, c in graphs:
+        r = np.asarray(r, dtype=np.int64)
+        n_g = len(r) - 1
+        padded = -(-n_g // q) * q
+        start = offs[-1]
+        rr = np.empty(padded, dtype=np.int64)
+        rr[:n_g] = r[:-1] + base_e
+        rr[n_g:] = r[-1] + base_e
+        rows.append(rr)
+        cols.append(np.asarray(c, dtype=np.int64) + start)
+        base_e += int(r[-1])
+        sizes.append(n_g)
+        offs.append(start + padded)
+    row_off = np.concatenate(rows + [np.array([base_e])]).astype(np.int32)
+    col = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+    return row_off, col, np.array(offs, dtype=np.int64), np.array(sizes, dtype=np.int64)

@@ -29,6 +29,7 @@ enum : int32_t {
   kErrOrder = 8,     // row not strictly ascending (unsorted or duplicate)
   kErrEnds = 16,     // row_off[0] != 0 or row_off[n] != m
   kErrInternal = 32,
+  kErrGraphs = 64,   // an edge leaves its graph, or a padding node has edges
 };
 
 constexpr int kBigRow = 64;  // rows longer than this are validated by a workgroup
@@ -36,11 +37,21 @@ constexpr int kBigRow = 64;  // rows longer than this are validated by a workgro
 // ---------------------------------------------------------------------------------
 // Node pass: one lane per node.  Short rows are validated and expanded by their
 // lane; long rows are queued for k_big_rows.
+// Edge u -> c stays inside u's graph and avoids padding nodes.
+__device__ __forceinline__ bool same_graph(int64_t u, int32_t c, int s, const int32_t* __restrict__ part_group,
+                                           const int32_t* __restrict__ part_valid) {
+  const int32_t pc = c >> s;
+  const int32_t mask = (1 << s) - 1;
+  return part_group[pc] == part_group[u >> s] && (c & mask) < part_valid[pc];
+}
+
 __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
                                                    const int32_t* __restrict__ col, int32_t* __restrict__ outdeg,
                                                    uint32_t* __restrict__ dmask, int32_t* __restrict__ src,
                                                    int32_t* __restrict__ big, int64_t big_cap,
-                                                   int32_t* __restrict__ counters /* [0]=err [1]=nbig [2]=ndang */) {
+                                                   int32_t* __restrict__ counters /* [0]=err [1]=nbig [2]=ndang */,
+                                                   int s, const int32_t* __restrict__ part_group,
+                                                   const int32_t* __restrict__ part_valid) {
   const int64_t nwords = (n + 31) >> 5;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < n; base += stride) {
@@ -55,6 +66,7 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
       } else {
         outdeg[u] = hi - lo;
         dang = (hi == lo);
+        if (hi > lo && (u & ((int64_t{1} << s) - 1)) >= part_valid[u >> s]) err |= kErrGraphs;
         if (hi - lo > kBigRow) {
           const int32_t idx = atomicAdd(&counters[1], 1);
           if (idx < big_cap) big[idx] = static_cast<int32_t>(u);
@@ -64,6 +76,7 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
           for (int32_t j = lo; j < hi; ++j) {
             const int32_t c = col[j];
             if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
+            else if (!same_graph(u, c, s, part_group, part_valid)) err |= kErrGraphs;
             if (c == u) err |= kErrSelfLoop;
             if (c <= prev) err |= kErrOrder;
             prev = c;
@@ -92,7 +105,9 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
 __global__ __launch_bounds__(256) void k_big_rows(int64_t n, const int32_t* __restrict__ row_off,
                                                   const int32_t* __restrict__ col, int32_t* __restrict__ src,
                                                   const int32_t* __restrict__ big, int64_t big_cap,
-                                                  int32_t* __restrict__ counters) {
+                                                  int32_t* __restrict__ counters, int s,
+                                                  const int32_t* __restrict__ part_group,
+                                                  const int32_t* __restrict__ part_valid) {
   const int64_t nbig = min(static_cast<int64_t>(counters[1]), big_cap);
   for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
     const int32_t u = big[i];
@@ -102,6 +117,7 @@ __global__ __launch_bounds__(256) void k_big_rows(int64_t n, const int32_t* __re
       const int32_t c = col[j];
       const int32_t prev = (j > lo) ? col[j - 1] : -1;
       if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
+      else if (!same_graph(u, c, s, part_group, part_valid)) err |= kErrGraphs;
       if (c == u) err |= kErrSelfLoop;
       if (c <= prev) err |= kErrOrder;
       src[j] = u;
@@ -349,6 +365,56 @@ static bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// Graphs of a multi-graph handle ("groups"): partition -> group, real nodes
+// per partition, per-group 1/n_g.
+static pcpm_status_t setup_groups(pcpm_png* g, const pcpm_build_opts_t* opts, hipStream_t st) {
+  const int64_t G = (opts && opts->num_graphs > 1) ? opts->num_graphs : 1;
+  const int64_t q = g->q, k = g->k, n = g->n;
+  g->group_off.assign(G + 1, 0);
+  g->group_n.assign(G, 0);
+  if (G == 1) {
+    g->group_off[1] = n;
+    g->group_n[0] = n;
+  } else {
+    if (!opts->graph_node_off || !opts->graph_nodes)
+      return set_error(PCPM_ERR_INVALID_ARG, "num_graphs > 1 needs graph_node_off and graph_nodes");
+    for (int64_t i = 0; i <= G; ++i) g->group_off[i] = opts->graph_node_off[i];
+    for (int64_t i = 0; i < G; ++i) g->group_n[i] = opts->graph_nodes[i];
+    if (g->group_off[0] != 0 || g->group_off[G] != n)
+      return set_error(PCPM_ERR_INVALID_ARG, "graph_node_off must start at 0 and end at n");
+    for (int64_t i = 0; i < G; ++i) {
+      if (g->group_off[i] % q != 0 || g->group_off[i + 1] <= g->group_off[i])
+        return set_error(PCPM_ERR_INVALID_ARG, "graph %lld: offsets must increase in multiples of q",
+                         static_cast<long long>(i));
+      if (g->group_n[i] < 1 || g->group_n[i] > g->group_off[i + 1] - g->group_off[i])
+        return set_error(PCPM_ERR_INVALID_ARG, "graph %lld: node count outside its range",
+                         static_cast<long long>(i));
+    }
+  }
+  g->ngroups = static_cast<int32_t>(G);
+  std::vector<int32_t> pg(k), pv(k);
+  for (int64_t grp = 0, p = 0; p < k; ++p) {
+    while (p * q >= g->group_off[grp + 1]) ++grp;
+    pg[p] = static_cast<int32_t>(grp);
+    const int64_t real_end = g->group_off[grp] + g->group_n[grp];
+    pv[p] = static_cast<int32_t>(std::max<int64_t>(0, std::min<int64_t>({q, n - p * q, real_end - p * q})));
+  }
+  std::vector<GCtl> gc(G);
+  for (int64_t i = 0; i < G; ++i) {
+    memset(&gc[i], 0, sizeof(GCtl));
+    gc[i].inv_n = 1.0 / static_cast<double>(g->group_n[i]);
+  }
+  PCPM_TRY(dalloc(g, &g->part_group, k));
+  PCPM_TRY(dalloc(g, &g->part_valid, k));
+  PCPM_TRY(dalloc(g, &g->gctl, G));
+  PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->gctl_host), sizeof(GCtl) * G, hipHostMallocDefault));
+  PCPM_TRY_HIP(hipMemcpyAsync(g->part_group, pg.data(), k * 4, hipMemcpyHostToDevice, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(g->part_valid, pv.data(), k * 4, hipMemcpyHostToDevice, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(g->gctl, gc.data(), sizeof(GCtl) * G, hipMemcpyHostToDevice, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  return PCPM_OK;
+}
+
 static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hipStream_t st) {
   const int64_t k = g->k;
   std::vector<int32_t> png_base(k + 1), did_start(k + 1);
@@ -406,10 +472,25 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
   PCPM_TRY(dalloc(g, &g->ga_items, g->n_ga));
   PCPM_TRY(dalloc(g, &g->mg_items, g->n_mg));
   PCPM_TRY(dalloc(g, &g->partial, static_cast<int64_t>(slot) * g->q));  // int64 slices
-  // one (residual, dangling) pair per apply unit: bins applied by the gather
-  // use slot p, merge units use k + unit; slots of split bins stay zero
-  PCPM_TRY(dalloc(g, &g->red, 2 * (k + g->n_mg)));
-  PCPM_TRY_HIP(hipMemsetAsync(g->red, 0, static_cast<size_t>(2 * (k + g->n_mg)) * sizeof(double), st));
+  // one (residual, dangling, mass) triple per apply unit: bins applied by the
+  // gather use slot p, merge units use k + unit; slots of split bins stay zero
+  PCPM_TRY(dalloc(g, &g->red, 3 * (k + g->n_mg)));
+  PCPM_TRY(dalloc(g, &g->red_start, 3 * k));
+  PCPM_TRY_HIP(hipMemsetAsync(g->red, 0, static_cast<size_t>(3 * (k + g->n_mg)) * sizeof(double), st));
+  // per group: first partition and first merge unit (units are in partition order)
+  {
+    const int64_t G = g->ngroups;
+    std::vector<int32_t> gs(2 * (G + 1));
+    size_t u = 0;
+    for (int64_t grp = 0; grp <= G; ++grp) {
+      const int64_t p0 = g->group_off[grp] / g->q;
+      gs[2 * grp] = static_cast<int32_t>(grp == G ? k : p0);
+      while (u < mg.size() && mg[u].part < (grp == G ? k : p0)) ++u;
+      gs[2 * grp + 1] = static_cast<int32_t>(grp == G ? mg.size() : u);
+    }
+    PCPM_TRY(dalloc(g, &g->group_slots, 2 * (G + 1)));
+    PCPM_TRY_HIP(hipMemcpyAsync(g->group_slots, gs.data(), gs.size() * 4, hipMemcpyHostToDevice, st));
+  }
   if (g->n_sc)
     PCPM_TRY_HIP(hipMemcpyAsync(g->sc_items, sc_items.data(), sc_items.size() * sizeof(Item),
                                 hipMemcpyHostToDevice, st));
@@ -439,6 +520,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   g->part_log2 = s;
   PCPM_TRY(set_lds_limits());
   PCPM_TRY(iter_lds_limits());
+  PCPM_TRY(setup_groups(g, opts, st));
 
   // ---- node pass -------------------------------------------------------------
   int32_t* src = nullptr;
@@ -454,9 +536,9 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   {
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
     PCPM_LAUNCH("pcpm_build_nodes", k_node_pass, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, n, m,
-                row_off, col, g->outdeg, g->dmask, src, big, big_cap, counters);
+                row_off, col, g->outdeg, g->dmask, src, big, big_cap, counters, s, g->part_group, g->part_valid);
     PCPM_LAUNCH("pcpm_build_bigrows", k_big_rows, dim3(1024), dim3(256), 0, st, n, row_off, col, src, big,
-                big_cap, counters);
+                big_cap, counters, s, g->part_group, g->part_valid);
   }
   int32_t hc[4] = {0, 0, 0, 0};
   PCPM_TRY_HIP(hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
@@ -467,6 +549,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
                        : (hc[0] & kErrRange)    ? "column index outside [0, n)"
                        : (hc[0] & kErrSelfLoop) ? "self-loop"
                        : (hc[0] & kErrOrder)    ? "row not strictly ascending (unsorted or duplicate edge)"
+                       : (hc[0] & kErrGraphs)   ? "an edge leaves its graph or a padding node has edges"
                                                 : "internal queue overflow";
     return set_error(hc[0] & kErrInternal ? PCPM_ERR_DEVICE : PCPM_ERR_GRAPH, "invalid CSR: %s (flags 0x%x)",
                      what, hc[0]);
@@ -541,7 +624,6 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
 
   // ---- iteration buffers -----------------------------------------------------------
   PCPM_TRY(dalloc(g, &g->upd, g->eprime + 1));  // + spare slot for masked stores
-  PCPM_TRY(dalloc(g, &g->red_init, 3 * kInitBlocks));
   PCPM_TRY(dalloc(g, &g->hist, kMaxHist));
   PCPM_TRY(dalloc(g, &g->ctl, 1));
   PCPM_TRY(dalloc(g, &g->tmp_pr, n));
@@ -606,6 +688,7 @@ pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out) {
   out->gather_items = g->n_ga;
   out->split_bins = g->n_split_bins;
   out->device_bytes = g->device_bytes;
+  out->num_graphs = g->ngroups;
   out->build_ms = g->build_ms;
   return PCPM_OK;
 }

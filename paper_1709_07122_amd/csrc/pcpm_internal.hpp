@@ -38,20 +38,30 @@ constexpr int kMaxLog2 = 14;       // 16384 * 8 B = 128 KB fixed-point slice in 
 #endif
 constexpr int kScatterBlock = PCPM_SCATTER_BLOCK;  // threads per scatter workgroup
 constexpr int kGatherBlock = PCPM_GATHER_BLOCK;    // threads per gather / merge workgroup
-constexpr int kInitBlocks = 256;   // workgroups of the dangling-mass reduction
 
-// Device control block of one handle.
+// Device control block of one handle (one solve at a time).
 struct Ctl {
-  double base;      // (1-d)/n + d*D/n: jump plus dangling share for the next apply
-  double dmass;     // dangling mass D of the current input vector
-  double res;       // residual of the last iteration
-  double res_prev;  // residual of the iteration before
+  double res;       // largest residual over groups, last iteration
+  double res_prev;  // the same one iteration before
   double tol;       // stop threshold (<= 0: never)
   double d;         // damping factor
   int32_t iter;     // iterations completed
-  int32_t done;     // residual fell below tol, or a non-finite value appeared
+  int32_t done;     // every group converged, or a non-finite value appeared
   int32_t nonfinite;
   int32_t fx_shift; // gather sums are kept as integers in units of 2^-fx_shift
+  int32_t ngroups;
+  int32_t pad;
+};
+
+// Per-group state: a group is one graph of a multi-graph handle (the whole
+// graph for a single one).
+struct GCtl {
+  double base;      // (1-d)/n_g + d*D_g/n_g: jump plus dangling share per node
+  double dmass;     // dangling mass D_g of the current input
+  double res;       // residual of the group's last iteration
+  double inv_n;     // 1/n_g
+  int32_t iter;     // iterations the group has run
+  int32_t done;     // residual fell below tol: the group keeps its iterate
 };
 
 // A unit of scatter or gather work: a contiguous range [lo, hi) of PNG edges
@@ -149,10 +159,19 @@ struct pcpm_png {
   int32_t n_sc = 0, n_ga = 0, n_mg = 0, n_split_slots = 0, n_split_bins = 0;
   int64_t* partial = nullptr;   // n_split_slots * q fixed-point partial sums
 
+  // groups (graphs of a multi-graph handle)
+  int32_t ngroups = 1;
+  int32_t* part_group = nullptr;  // k: group of each partition
+  int32_t* part_valid = nullptr;  // k: real (non-padding) nodes of each partition
+  int32_t* group_slots = nullptr; // 2*(G+1): first partition and first merge unit of each group
+  pcpm::GCtl* gctl = nullptr;     // G
+  pcpm::GCtl* gctl_host = nullptr;  // pinned mirror
+  std::vector<int64_t> group_off, group_n;  // host copies
+
   // reductions and control
-  double* red = nullptr;        // 2*(k + n_mg): (residual, dangling) partial sums per apply unit
-  double* red_init = nullptr;   // 3*kInitBlocks
-  double* hist = nullptr;       // kMaxHist residuals
+  double* red = nullptr;        // 3*(k + n_mg): (residual, dangling, -) partial sums per apply unit
+  double* red_start = nullptr;  // 3*k: (non-finite count, dangling, L1 mass) of the start vector per partition
+  double* hist = nullptr;       // kMaxHist residuals (group 0)
   pcpm::Ctl* ctl = nullptr;
   pcpm::Ctl* ctl_host = nullptr;  // pinned mirror
   float* tmp_pr = nullptr;      // n: second rank buffer

@@ -72,14 +72,22 @@ struct FixedConv {
   }
 };
 
-// Apply (Alg. 2) for nodes v0+i0 .. v0+i1-1 of one destination partition:
-//   x_new(v) = d * acc(v) + base,  base = (1-d)/n + d*D/n
-// plus their share of sum |x_new - x_old| and of the next dangling mass.
+// Apply (Alg. 2) for nodes v0+i0 .. v0+i1-1 of partition `part`:
+//   x_new(v) = d * acc(v) + base_g,  base_g = (1-d)/n_g + d*D_g/n_g
+// for the partition's group g, plus their share of sum |x_new - x_old| and of
+// the next dangling mass.  Padding nodes (past the group's last node) stay 0;
+// a converged group keeps its iterate.
 template <int BS, class AccFn>
-__device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, int64_t v0, int i0, int i1, AccFn acc,
-                                            const float* __restrict__ pr_in, float* __restrict__ pr_out,
-                                            const uint32_t* __restrict__ dmask, double* __restrict__ red_slot) {
-  const double base = ctl->base;
+__device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const GCtl* __restrict__ gctl,
+                                            const int32_t* __restrict__ part_group,
+                                            const int32_t* __restrict__ part_valid, int part, int64_t v0, int i0,
+                                            int i1, AccFn acc, const float* __restrict__ pr_in,
+                                            float* __restrict__ pr_out, const uint32_t* __restrict__ dmask,
+                                            double* __restrict__ red_slot) {
+  const GCtl& gc = gctl[part_group[part]];
+  const double base = gc.base;
+  const bool frozen = gc.done != 0;
+  const int valid = part_valid[part];
   const double d = ctl->d;
   const double unit = ldexp(1.0, -ctl->fx_shift);
   double sums[2] = {0.0, 0.0};  // residual, dangling mass
@@ -100,8 +108,11 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, int64_t
       const int ii = i + u * BS;
       if (ii < i1) {
         const int64_t v = v0 + ii;
-        const double sv = static_cast<double>(acc(ii)) * unit;
-        const float xn = static_cast<float>(fma(d, sv, base));
+        float xn = 0.0f;
+        if (ii < valid) {
+          const double sv = static_cast<double>(acc(ii)) * unit;
+          xn = frozen ? xo[u] : static_cast<float>(fma(d, sv, base));
+        }
         sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
         if ((dw[u] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
         pr_out[v] = xn;
@@ -112,6 +123,7 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, int64_t
   if (threadIdx.x == 0) {
     red_slot[0] = sums[0];
     red_slot[1] = sums[1];
+    red_slot[2] = 0.0;
   }
 }
 
@@ -192,7 +204,9 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
                                                const int32_t* __restrict__ did_blk, const float* __restrict__ upd,
                                                const float* __restrict__ pr_in, float* __restrict__ pr_out,
                                                const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
-                                               double* __restrict__ red) {
+                                               double* __restrict__ red, const GCtl* __restrict__ gctl,
+                                               const int32_t* __restrict__ part_group,
+                                               const int32_t* __restrict__ part_valid) {
   if (ctl->done) return;
   extern __shared__ unsigned long long acc[];
   const Item it = items[blockIdx.x];
@@ -261,8 +275,8 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
     for (int i = threadIdx.x; i < qn; i += BS) dst[i] = static_cast<int64_t>(acc[i]);
     return;
   }
-  apply_nodes<BS>(ctl, v0, 0, qn, [&](int i) { return static_cast<int64_t>(acc[i]); }, pr_in, pr_out, dmask,
-                  red + 2 * it.part);
+  apply_nodes<BS>(ctl, gctl, part_group, part_valid, it.part, v0, 0, qn,
+                  [&](int i) { return static_cast<int64_t>(acc[i]); }, pr_in, pr_out, dmask, red + 3 * it.part);
 }
 
 template <int BS>
@@ -270,7 +284,9 @@ __global__ __launch_bounds__(BS) void k_merge(const Ctl* __restrict__ ctl, int64
                                               const Merge* __restrict__ mg, const int64_t* __restrict__ partial,
                                               const float* __restrict__ pr_in, float* __restrict__ pr_out,
                                               const uint32_t* __restrict__ dmask, double* __restrict__ red,
-                                              int64_t red_base) {
+                                              int64_t red_base, const GCtl* __restrict__ gctl,
+                                              const int32_t* __restrict__ part_group,
+                                              const int32_t* __restrict__ part_valid) {
   if (ctl->done) return;
   const Merge mu = mg[blockIdx.x];
   const int64_t q = int64_t{1} << s;
@@ -283,43 +299,87 @@ __global__ __launch_bounds__(BS) void k_merge(const Ctl* __restrict__ ctl, int64
     for (int c = 0; c < cnt; ++c) sum += base[static_cast<int64_t>(c) * q + i];
     return sum;
   };
-  apply_nodes<BS>(ctl, v0, mu.node_lo, min(qn, mu.node_lo + kMergeNodes), acc, pr_in, pr_out, dmask,
-                  red + 2 * (red_base + blockIdx.x));
+  apply_nodes<BS>(ctl, gctl, part_group, part_valid, mu.part, v0, mu.node_lo, min(qn, mu.node_lo + kMergeNodes),
+                  acc, pr_in, pr_out, dmask, red + 3 * (red_base + blockIdx.x));
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, const double* __restrict__ red,
-                                                   int64_t nslots, double* __restrict__ hist, int64_t n) {
-  if (ctl->done) return;
-  double sums[2] = {0.0, 0.0};
-  for (int64_t j = threadIdx.x; j < nslots; j += 1024) {
-    sums[0] += red[2 * j];
-    sums[1] += red[2 * j + 1];
+// Per-group totals of the apply units' (residual, dangling, mass) partial
+// sums: one wavefront per group, partitions then merge units, in order.
+__device__ __forceinline__ void group_sums(const int32_t* __restrict__ group_slots, const double* __restrict__ red,
+                                           int64_t k, int grp, bool with_merge, double (&s)[3]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  s[0] = s[1] = s[2] = 0.0;
+  const int p0 = group_slots[2 * grp], p1 = group_slots[2 * grp + 2];
+  for (int j = p0 + lane; j < p1; j += kWave)
+    for (int c = 0; c < 3; ++c) s[c] += red[3 * j + c];
+  if (with_merge) {
+    const int u0 = group_slots[2 * grp + 1], u1 = group_slots[2 * grp + 3];
+    for (int j = u0 + lane; j < u1; j += kWave)
+      for (int c = 0; c < 3; ++c) s[c] += red[3 * (k + j) + c];
   }
-  block_sum<1024>(sums);
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1)
+    for (int c = 0; c < 3; ++c) s[c] += __shfl_xor(s[c], off);
+}
+
+// End of an iteration: per-group residual, next dangling mass and base, group
+// convergence; then the largest residual, the iteration count and the flag
+// that makes the kernels of later iterations return at once.
+__global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
+                                                   const int32_t* __restrict__ group_slots,
+                                                   const double* __restrict__ red, int64_t k,
+                                                   double* __restrict__ hist) {
+  if (ctl->done) return;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const int G = ctl->ngroups;
+  const double d = ctl->d, tol = ctl->tol;
+  for (int grp = threadIdx.x / kWave; grp < G; grp += 1024 / kWave) {
+    double sm[3];
+    group_sums(group_slots, red, k, grp, true, sm);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      GCtl& gc = gctl[grp];
+      if (!gc.done) {
+        gc.res = sm[0];
+        gc.iter += 1;
+        gc.dmass = sm[1];
+        gc.base = (1.0 - d) * gc.inv_n + d * sm[1] * gc.inv_n;
+        if (!isfinite(sm[0]) || !isfinite(sm[1])) atomicOr(&bad, 1);
+        else if (tol > 0.0 && sm[0] < tol) gc.done = 1;
+      }
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double r = sums[0], dm = sums[1];
-    const double d = ctl->d;
+    double rmax = 0.0;
+    int all_done = 1;
+    for (int grp = 0; grp < G; ++grp) {
+      rmax = fmax(rmax, gctl[grp].res);
+      all_done &= gctl[grp].done;
+    }
+    if (bad) rmax = NAN;
     const int32_t it = ctl->iter;
     ctl->res_prev = ctl->res;
-    ctl->res = r;
-    hist[it] = r;
+    ctl->res = rmax;
+    hist[it] = rmax;
     ctl->iter = it + 1;
-    ctl->dmass = dm;
-    ctl->base = (1.0 - d) / static_cast<double>(n) + d * dm / static_cast<double>(n);
-    if (!isfinite(r) || !isfinite(dm)) {
-      ctl->nonfinite = 1;
-      ctl->done = 1;
-    } else if (ctl->tol > 0.0 && r < ctl->tol) {
-      ctl->done = 1;
-    }
+    if (bad) ctl->nonfinite = 1;
+    if (bad || all_done) ctl->done = 1;
   }
 }
 
 // ---- start of a solve ----------------------------------------------------------------
-__global__ void k_ctl_init(Ctl* ctl, double tol, double d) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ctl->base = 0.0;
-    ctl->dmass = 0.0;
+__global__ __launch_bounds__(256) void k_ctl_init(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl, int G, double tol,
+                                                  double d) {
+  for (int grp = threadIdx.x; grp < G; grp += 256) {
+    gctl[grp].base = 0.0;
+    gctl[grp].dmass = 0.0;
+    gctl[grp].res = 0.0;
+    gctl[grp].iter = 0;
+    gctl[grp].done = 0;
+  }
+  if (threadIdx.x == 0) {
     ctl->res = 0.0;
     ctl->res_prev = 0.0;
     ctl->tol = tol;
@@ -328,58 +388,87 @@ __global__ void k_ctl_init(Ctl* ctl, double tol, double d) {
     ctl->done = 0;
     ctl->nonfinite = 0;
     ctl->fx_shift = 50;
+    ctl->ngroups = G;
   }
 }
 
-__global__ __launch_bounds__(256) void k_fill_value(float* __restrict__ x, int64_t n, float v) {
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    x[i] = v;
+// 1/n_g on every real node of its group, 0 on padding.  One workgroup per
+// partition.
+__global__ __launch_bounds__(256) void k_fill_uniform(float* __restrict__ x, int64_t n, int s,
+                                                      const GCtl* __restrict__ gctl,
+                                                      const int32_t* __restrict__ part_group,
+                                                      const int32_t* __restrict__ part_valid) {
+  const int64_t v0 = static_cast<int64_t>(blockIdx.x) << s;
+  const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
+  const int valid = part_valid[blockIdx.x];
+  const float u = static_cast<float>(gctl[part_group[blockIdx.x]].inv_n);
+  for (int i = threadIdx.x; i < qn; i += 256) x[v0 + i] = i < valid ? u : 0.0f;
 }
 
-// Dangling mass, L1 mass and non-finite count of the starting vector: fixed
-// grid, fixed per-thread order.
-__global__ __launch_bounds__(256) void k_start_partial(const float* __restrict__ x,
-                                                       const uint32_t* __restrict__ dmask, int64_t n,
-                                                       double* __restrict__ red_init) {
+// Start vector statistics per partition: non-finite count, dangling mass and
+// L1 mass, into the partition's start slot.  Padding entries are cleared.
+__global__ __launch_bounds__(256) void k_start_parts(float* __restrict__ x, const uint32_t* __restrict__ dmask,
+                                                     int64_t n, int s, const int32_t* __restrict__ part_valid,
+                                                     double* __restrict__ red) {
+  const int64_t v0 = static_cast<int64_t>(blockIdx.x) << s;
+  const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
+  const int valid = part_valid[blockIdx.x];
   double sums[3] = {0.0, 0.0, 0.0};
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  for (int i = threadIdx.x; i < qn; i += 256) {
+    const int64_t v = v0 + i;
+    if (i >= valid) {
+      x[v] = 0.0f;
+      continue;
+    }
     const float xv = x[v];
-    if (!isfinite(xv)) sums[2] += 1.0;
-    sums[1] += fabs(static_cast<double>(xv));
-    if ((dmask[v >> 5] >> (v & 31)) & 1u) sums[0] += static_cast<double>(xv);
+    if (!isfinite(xv)) sums[0] += 1.0;
+    if ((dmask[v >> 5] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xv);
+    sums[2] += fabs(static_cast<double>(xv));
   }
   block_sum<256>(sums);
   if (threadIdx.x == 0) {
-    red_init[3 * blockIdx.x] = sums[0];
-    red_init[3 * blockIdx.x + 1] = sums[1];
-    red_init[3 * blockIdx.x + 2] = sums[2];
+    red[3 * blockIdx.x] = sums[0];
+    red[3 * blockIdx.x + 1] = sums[1];
+    red[3 * blockIdx.x + 2] = sums[2];
   }
 }
 
-// D, base and the fixed-point scale of the gather: every gather sum is bounded
-// by max(1, L1 mass of the start vector), which later iterates never exceed
-// (teleport vectors are non-negative and sum to one), so 2^fx_shift times
-// that bound stays below 2^51 and every conversion is in range.
-__global__ __launch_bounds__(256) void k_init_finalize(Ctl* __restrict__ ctl, const double* __restrict__ red_init,
-                                                       int nb, int64_t n) {
-  double sums[3] = {0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < nb; i += 256) {
-    sums[0] += red_init[3 * i];
-    sums[1] += red_init[3 * i + 1];
-    sums[2] += red_init[3 * i + 2];
+// Per-group dangling mass and base of the start vector; the fixed-point scale
+// of the gather: every gather sum is bounded by max(1, L1 mass of the start
+// vector), which later iterates never exceed (teleport vectors are
+// non-negative and sum to one per group), so 2^fx_shift times that bound stays
+// below 2^51 and every conversion is in range.
+__global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
+                                                         const int32_t* __restrict__ group_slots,
+                                                         const double* __restrict__ red, int64_t k) {
+  __shared__ int bad;
+  __shared__ double mass_w[1024 / kWave];
+  if (threadIdx.x == 0) bad = 0;
+  if (threadIdx.x < 1024 / kWave) mass_w[threadIdx.x] = 0.0;
+  __syncthreads();
+  const int G = ctl->ngroups;
+  const double d = ctl->d;
+  double wmass = 0.0;
+  for (int grp = threadIdx.x / kWave; grp < G; grp += 1024 / kWave) {
+    double sm[3];
+    group_sums(group_slots, red, k, grp, false, sm);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      GCtl& gc = gctl[grp];
+      gc.dmass = sm[1];
+      gc.base = (1.0 - d) * gc.inv_n + d * sm[1] * gc.inv_n;
+      if (sm[0] > 0.0 || !isfinite(sm[1]) || !isfinite(sm[2])) atomicOr(&bad, 1);
+      wmass += sm[2];
+    }
   }
-  block_sum<256>(sums);
+  if ((threadIdx.x & (kWave - 1)) == 0) mass_w[threadIdx.x / kWave] = wmass;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double d = ctl->d;
-    const double dm = sums[0], mass = sums[1];
-    ctl->dmass = dm;
-    ctl->base = (1.0 - d) / static_cast<double>(n) + d * dm / static_cast<double>(n);
+    double mass = 0.0;
+    for (int w = 0; w < 1024 / kWave; ++w) mass += mass_w[w];
     int e = 0;
     if (isfinite(mass) && mass > 1.0) e = static_cast<int>(ceil(log2(mass)));
     ctl->fx_shift = 50 - min(e, 1000);
-    if (sums[2] > 0.0 || !isfinite(dm) || !isfinite(mass)) {
+    if (bad) {
       ctl->nonfinite = 1;
       ctl->done = 1;
     }
@@ -397,11 +486,17 @@ pcpm_status_t iter_lds_limits() {
   return PCPM_OK;
 }
 
-static pcpm_status_t start_solve(pcpm_png* g, double tol, double d, const float* x0, hipStream_t st) {
-  PCPM_LAUNCH("pcpm_init", k_ctl_init, dim3(1), dim3(64), 0, st, g->ctl, tol, d);
-  PCPM_LAUNCH("pcpm_init", k_start_partial, dim3(kInitBlocks), dim3(256), 0, st, x0, g->dmask, g->n,
-              g->red_init);
-  PCPM_LAUNCH("pcpm_init", k_init_finalize, dim3(1), dim3(256), 0, st, g->ctl, g->red_init, kInitBlocks, g->n);
+static pcpm_status_t start_solve(pcpm_png* g, double /*tol*/, double /*d*/, float* x0, hipStream_t st) {
+  const unsigned kk = static_cast<unsigned>(g->k);
+  PCPM_LAUNCH("pcpm_init", k_start_parts, dim3(kk), dim3(256), 0, st, x0, g->dmask, g->n, g->part_log2,
+              g->part_valid, g->red_start);
+  PCPM_LAUNCH("pcpm_init", k_start_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->gctl, g->group_slots,
+              g->red_start, g->k);
+  return PCPM_OK;
+}
+
+static pcpm_status_t reset_ctl(pcpm_png* g, double tol, double d, hipStream_t st) {
+  PCPM_LAUNCH("pcpm_init", k_ctl_init, dim3(1), dim3(256), 0, st, g->ctl, g->gctl, g->ngroups, tol, d);
   return PCPM_OK;
 }
 
@@ -412,12 +507,13 @@ static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hip
                 g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
   PCPM_LAUNCH("pcpm_gather", k_gather<kGatherBlock>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kGatherBlock),
               static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items, g->did, g->did_blk,
-              g->upd, in, out, g->dmask, g->partial, g->red);
+              g->upd, in, out, g->dmask, g->partial, g->red, g->gctl, g->part_group, g->part_valid);
   if (g->n_mg)
     PCPM_LAUNCH("pcpm_merge", k_merge<kMergeNodes>, dim3(static_cast<unsigned>(g->n_mg)), dim3(kMergeNodes), 0,
-                st, g->ctl, g->n, g->part_log2, g->mg_items, g->partial, in, out, g->dmask, g->red, g->k);
-  PCPM_LAUNCH("pcpm_finalize", k_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->red, g->k + g->n_mg, g->hist,
-              g->n);
+                st, g->ctl, g->n, g->part_log2, g->mg_items, g->partial, in, out, g->dmask, g->red, g->k, g->gctl,
+                g->part_group, g->part_valid);
+  PCPM_LAUNCH("pcpm_finalize", k_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->gctl, g->group_slots, g->red,
+              g->k, g->hist);
   return PCPM_OK;
 }
 
@@ -440,8 +536,11 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
   if (pr_in == pr_out) return set_error(PCPM_ERR_INVALID_ARG, "pr_in and pr_out must differ");
   PCPM_TRY(check_device(g));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  PCPM_TRY(start_solve(g, 0.0, d, pr_in, st));
-  PCPM_TRY(run_iteration(g, pr_in, pr_out, st));
+  // the start statistics clear padding entries, so they run on a copy
+  PCPM_TRY_HIP(hipMemcpyAsync(g->tmp_pr, pr_in, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
+  PCPM_TRY(reset_ctl(g, 0.0, d, st));
+  PCPM_TRY(start_solve(g, 0.0, d, g->tmp_pr, st));
+  PCPM_TRY(run_iteration(g, g->tmp_pr, pr_out, st));
   if (resid) {
     PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     PCPM_TRY_HIP(hipStreamSynchronize(st));
@@ -463,13 +562,13 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
   hipStream_t st = static_cast<hipStream_t>(stream);
   float* a = pr_out;
   float* b = g->tmp_pr;
+  PCPM_TRY(reset_ctl(g, tol, d, st));
   if (init) {
     if (init != pr_out)
       PCPM_TRY_HIP(hipMemcpyAsync(a, init, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
   } else {
-    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((g->n + 255) / 256, 4096));
-    PCPM_LAUNCH("pcpm_init", k_fill_value, dim3(blocks), dim3(256), 0, st, a, g->n,
-                static_cast<float>(1.0 / static_cast<double>(g->n)));
+    PCPM_LAUNCH("pcpm_init", k_fill_uniform, dim3(static_cast<unsigned>(g->k)), dim3(256), 0, st, a, g->n,
+                g->part_log2, g->gctl, g->part_group, g->part_valid);
   }
   PCPM_TRY(start_solve(g, tol, d, a, st));
   // Iterations are queued in batches between host checks of the device
@@ -510,6 +609,17 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
   if (tol > 0.0 && !c.done)
     return set_error(PCPM_ERR_NOT_CONVERGED, "residual %.3e still above tol %.3e after %d iterations", c.res, tol,
                      c.iter);
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_graph_results(pcpm_png_t g, int32_t* iters, double* resid) {
+  using namespace pcpm;
+  if (!g) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle");
+  PCPM_TRY_HIP(hipMemcpy(g->gctl_host, g->gctl, sizeof(GCtl) * g->ngroups, hipMemcpyDeviceToHost));
+  for (int grp = 0; grp < g->ngroups; ++grp) {
+    if (iters) iters[grp] = g->gctl_host[grp].iter;
+    if (resid) resid[grp] = g->gctl_host[grp].res;
+  }
   return PCPM_OK;
 }
 

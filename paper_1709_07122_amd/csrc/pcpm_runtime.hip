@@ -70,7 +70,9 @@ void free_handle(pcpm_png* g) {
   for (auto& a : g->allocations) (void)hipFree(a.first);
   g->allocations.clear();
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
+  if (g->gctl_host) (void)hipHostFree(g->gctl_host);
   g->ctl_host = nullptr;
+  g->gctl_host = nullptr;
   delete g;
 }
 
