@@ -154,6 +154,32 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
                             int32_t* iters /* (host) */, double* resid /* (host) */,
                             double* res_hist /* (host) nullable */, void* stream);
 
+/*
+ * Personalised PageRank for k vectors on a single-graph handle.  Vector j
+ * runs the recurrence of Eq. 1 with the uniform jump 1/n replaced by t_j,
+ * uniform on its seed set S_j (the dangling mass D_j is spread by t_j too),
+ * from x_0 = t_j:
+ *   x'(v) = (1-d) t_j(v) + d * ( sum_{u->v} x(u)/outdeg(u) + D_j t_j(v) ).
+ * S_j = seeds[seed_off[j] .. seed_off[j+1]) (host arrays; every set non-empty,
+ * nodes in [0, n), no node twice in a set).  Vectors run in tiles of
+ * pcpm_ppr_tile_width(g) that share every PNG edge and destination ID of the
+ * scatter and gather; a vector whose FP64 L1 residual falls below tol keeps
+ * that iterate.  pr_out (device) receives the ranks as [n][k] row-major;
+ * iters and resid (host, k each) every vector's iteration count and last
+ * residual.  tol <= 0 runs exactly max_iters iterations.  Returns
+ * PCPM_ERR_NOT_CONVERGED (outputs valid) when some vector stays above tol.
+ * The first call on a handle allocates the working set for its tile width
+ * and keeps it.  Synchronises `stream`.
+ */
+pcpm_status_t pcpm_ppr_batch(pcpm_png_t g, double d, int32_t k, const int32_t* seed_off /* (host) k+1 */,
+                             const int32_t* seeds /* (host) */, double tol, int32_t max_iters,
+                             float* pr_out /* [n][k] */, int32_t* iters /* (host) k */,
+                             double* resid /* (host) k */, void* stream);
+
+/* Vectors per tile of pcpm_ppr_batch on this handle: the largest power of two
+ * (at most 16) whose q * width 8-byte sums fit the gather's LDS slice. */
+int32_t pcpm_ppr_tile_width(pcpm_png_t g);
+
 /* Per-graph outcome of the last pcpm_pagerank on a handle: iterations run and
  * last residual of each of the G graphs (host arrays of G). */
 pcpm_status_t pcpm_graph_results(pcpm_png_t g, int32_t* iters /* (host) G */, double* resid /* (host) G */);

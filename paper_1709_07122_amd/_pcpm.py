@@ -31,8 +31,8 @@ STATUS_NAMES = {
 
 # every symbol include/pcpm.h declares
 EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
-           "pcpm_pagerank", "pcpm_graph_results", "pcpm_last_error", "pcpm_timing_enable",
-           "pcpm_timing_collect"]
+           "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_last_error",
+           "pcpm_timing_enable", "pcpm_timing_collect"]
 
 
 class PCPMError(RuntimeError):
@@ -82,6 +82,10 @@ def lib():
     L.pcpm_iterate.argtypes = [vp, dbl, vp, vp, ctypes.POINTER(dbl), vp]
     L.pcpm_pagerank.restype = ctypes.c_int
     L.pcpm_pagerank.argtypes = [vp, dbl, dbl, i32, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, vp]
+    L.pcpm_ppr_batch.restype = ctypes.c_int
+    L.pcpm_ppr_batch.argtypes = [vp, dbl, i32, vp, vp, dbl, i32, vp, vp, vp, vp]
+    L.pcpm_ppr_tile_width.restype = ctypes.c_int32
+    L.pcpm_ppr_tile_width.argtypes = [vp]
     L.pcpm_graph_results.restype = ctypes.c_int
     L.pcpm_graph_results.argtypes = [vp, vp, vp]
     L.pcpm_last_error.restype = ctypes.c_char_p
@@ -248,6 +252,40 @@ def pagerank(png: PNG, d: float = 0.85, tol: float = 1e-6, max_iters: int = 100,
                                     ctypes.byref(r), ctypes.c_void_p(hist.ctypes.data) if want_hist else None,
                                     _stream(stream)), allow=(PCPM_ERR_NOT_CONVERGED,))
     return PagerankResult(out, it.value, r.value, hist[: it.value], st == PCPM_OK and tol > 0, st)
+
+
+@dataclass
+class PprResult:
+    pr: object          # [n][k] float32 device tensor
+    iters: np.ndarray   # per vector
+    resid: np.ndarray   # per vector
+    converged: bool
+    status: int
+
+
+def ppr_batch(png: PNG, seed_off, seeds, d: float = 0.85, tol: float = 1e-6, max_iters: int = 100, out=None,
+              stream=None) -> PprResult:
+    """pcpm_ppr_batch: k personalised PageRank vectors; seed set j is
+    seeds[seed_off[j]:seed_off[j+1]] (host int32 arrays)."""
+    import torch
+    seed_off = np.ascontiguousarray(seed_off, dtype=np.int32)
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    k = len(seed_off) - 1
+    n = png.n
+    if out is None:
+        out = torch.empty((n, k), dtype=torch.float32, device=png.row_off.device)
+    op = _dev_tensor(out, torch.float32, n * k, "out")
+    it = np.zeros(k, np.int32)
+    r = np.zeros(k, np.float64)
+    st = _check(lib().pcpm_ppr_batch(png.handle, float(d), k, seed_off.ctypes.data,
+                                     seeds.ctypes.data if len(seeds) else None, float(tol), int(max_iters), op,
+                                     it.ctypes.data, r.ctypes.data, _stream(stream)),
+                allow=(PCPM_ERR_NOT_CONVERGED,))
+    return PprResult(out, it, r, st == PCPM_OK and tol > 0, st)
+
+
+def ppr_tile_width(png: PNG) -> int:
+    return int(lib().pcpm_ppr_tile_width(png.handle))
 
 
 def timing_enable(on: bool = True):

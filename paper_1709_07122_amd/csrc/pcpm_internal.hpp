@@ -64,6 +64,16 @@ struct GCtl {
   int32_t done;     // residual fell below tol: the group keeps its iterate
 };
 
+// Per-vector state of batched personalised PageRank.
+struct VCtl {
+  double coef;      // ((1-d) + d*D_j)/|S_j|: jump plus dangling share of each seed node
+  double inv_s;     // 1/|S_j|
+  double dmass;     // dangling mass D_j of the current iterate
+  double res;       // residual of the vector's last iteration
+  int32_t iter;     // iterations the vector has run
+  int32_t done;     // residual fell below tol: the vector keeps its iterate
+};
+
 // A unit of scatter or gather work: a contiguous range [lo, hi) of PNG edges
 // (scatter, part = source partition) or of destination IDs (gather, part =
 // destination partition).  aux: gather partial slot (-1 = whole bin).
@@ -175,6 +185,20 @@ struct pcpm_png {
   pcpm::Ctl* ctl = nullptr;
   pcpm::Ctl* ctl_host = nullptr;  // pinned mirror
   float* tmp_pr = nullptr;      // n: second rank buffer
+
+  // batched personalised PageRank working set (grown by pcpm_ppr_batch)
+  int32_t ppr_kt = 0;
+  float* ppr_x[2] = {nullptr, nullptr};  // n * kt, vector-minor
+  float* ppr_upd = nullptr;              // (E'+1) * kt
+  int64_t* ppr_partial = nullptr;        // n_split_slots * q * kt
+  double* ppr_red = nullptr;             // (k + n_mg) * kt * 2
+  pcpm::VCtl* ppr_vctl = nullptr;        // kt
+  pcpm::VCtl* ppr_vctl_host = nullptr;   // pinned mirror (64 entries)
+  uint32_t* ppr_mask = nullptr;          // n: seed bits of the tile's vectors
+  int32_t* ppr_seeds = nullptr;
+  int64_t ppr_seed_cap = 0;
+  int32_t* ppr_seed_off = nullptr;
+  int64_t ppr_off_cap = 0;
 
   std::vector<std::pair<void*, size_t>> allocations;
 };

@@ -27,50 +27,12 @@
 #include <algorithm>
 #include <cmath>
 
+#include "pcpm_device.hpp"
 #include "pcpm_internal.hpp"
 
 namespace pcpm {
 
 constexpr int kMergeNodes = 256;  // nodes per merge workgroup (one per thread)
-
-// Sum N FP64 values over the workgroup; results are valid in thread 0.
-template <int BS, int N>
-__device__ __forceinline__ void block_sum(double (&v)[N]) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off);
-  }
-  __shared__ double sh[N * (BS / kWave)];
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) sh[N * w + i] = v[i];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      v[i] = 0.0;
-      for (int k = 0; k < BS / kWave; ++k) v[i] += sh[N * k + i];
-    }
-  }
-}
-
-// Conversion of an FP32 update to a signed integer in units of 2^-sh,
-// rounded to nearest: v * 2^sh + 1.5*2^52 is formed by one FP64 FMA (exact
-// product, one rounding) and the integer is read from the low mantissa bits.
-// Valid for |v| * 2^sh < 2^51, which the choice of sh guarantees for every
-// finite update; the result then carries the update to within 2^-(sh+1).
-struct FixedConv {
-  double scale;
-  __device__ explicit FixedConv(int sh) : scale(ldexp(1.0, sh)) {}
-  __device__ __forceinline__ int64_t operator()(float v) const {
-    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
-    const double y = fma(static_cast<double>(v), scale, kMagic);
-    return __double_as_longlong(y) - __double_as_longlong(kMagic);
-  }
-};
 
 // Apply (Alg. 2) for nodes v0+i0 .. v0+i1-1 of partition `part`:
 //   x_new(v) = d * acc(v) + base_g,  base_g = (1-d)/n_g + d*D_g/n_g

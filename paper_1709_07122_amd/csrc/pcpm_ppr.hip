@@ -1,0 +1,501 @@
+// Batched personalised PageRank over one PNG: kt vectors share every PNG
+// edge and every destination ID.
+//
+// Vector j teleports to its seed set S_j: x'(v) = (1-d) t_j(v) + d (sum_{u->v}
+// x(u)/outdeg(u) + D_j t_j(v)) with t_j uniform on S_j and D_j the vector's
+// dangling mass, i.e. the recurrence of Eq. 1 with the uniform jump replaced
+// by t_j.  An update slot holds kt values (one per vector of the tile), so the
+// scatter of Alg. 3 writes kt floats per PNG edge and the gather of Alg. 5
+// decodes each destination ID once for kt accumulations.  Vectors are
+// processed in tiles of kt; a vector whose residual falls below tol keeps
+// its iterate while the rest of its tile goes on.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pcpm_device.hpp"
+#include "pcpm_internal.hpp"
+
+namespace pcpm {
+
+constexpr int kPprBlock = 512;
+
+template <int KT>
+__device__ __forceinline__ void copy_kt(float* __restrict__ dst, const float* __restrict__ src) {
+  if constexpr (KT % 4 == 0) {
+#pragma unroll
+    for (int c = 0; c < KT; c += 4)
+      *reinterpret_cast<float4*>(dst + c) = *reinterpret_cast<const float4*>(src + c);
+  } else {
+#pragma unroll
+    for (int c = 0; c < KT; ++c) dst[c] = src[c];
+  }
+}
+
+template <int KT>
+__global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                           const Item* __restrict__ items, const float* __restrict__ x,
+                                                           const int32_t* __restrict__ outdeg,
+                                                           const uint32_t* __restrict__ png_src,
+                                                           const int32_t* __restrict__ png_blk,
+                                                           const int32_t* __restrict__ seg_delta,
+                                                           float* __restrict__ upd, int64_t spare) {
+  if (ctl->done) return;
+  extern __shared__ float spr[];  // q * KT scaled values of the source partition
+  const Item it = items[blockIdx.x];
+  const int64_t v0 = static_cast<int64_t>(it.part) << s;
+  const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
+  for (int i = threadIdx.x; i < qn * KT; i += kPprBlock) {
+    const int od = outdeg[v0 + i / KT];
+    spr[i] = od > 0 ? x[v0 * KT + i] / static_cast<float>(od) : 0.0f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t qmask = (1u << s) - 1u;
+  const int64_t lo = it.lo, hi = it.hi;
+  const int64_t t_end = (hi + kTile - 1) / kTile;
+  for (int64_t t = lo / kTile + threadIdx.x / kWave; t < t_end; t += kPprBlock / kWave) {
+    const int64_t tb = t * kTile;
+    int32_t run = png_blk[t];
+    for (int j = 0; j < kSub; ++j) {
+      const int64_t e = tb + j * kWave + lane;
+      const uint32_t xv = png_src[e];
+      const bool f = static_cast<int32_t>(xv) < 0;
+      const uint64_t bal = wave_ballot(f);
+      const int32_t seg = run + lanes_below(bal) + (f ? 0 : -1);
+      run += __popcll(bal);
+      const bool in = e >= lo && e < hi;
+      const int64_t slot = in ? e + seg_delta[seg] : spare;
+      copy_kt<KT>(upd + slot * KT, spr + (xv & qmask) * KT);
+    }
+  }
+}
+
+// Apply for nodes n0..n1-1 of a destination partition and all KT vectors:
+//   x'(v, j) = d * acc(v, j) + [v in S_j] * ((1-d) + d*D_j)/|S_j|
+// and each vector's share of the residual and of the next dangling mass.
+template <int KT, int BS, class AccFn>
+__device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCtl* __restrict__ vctl, int64_t v0,
+                                          int n0, int n1, AccFn acc, const float* __restrict__ x_in,
+                                          float* __restrict__ x_out, const uint32_t* __restrict__ dmask,
+                                          const uint32_t* __restrict__ seedmask, double* __restrict__ red_slot) {
+  static_assert(BS % KT == 0 && kWave % KT == 0, "vectors per tile must divide the wavefront");
+  const int kk = threadIdx.x % KT;
+  const bool frozen = vctl[kk].done != 0;
+  const double coef = vctl[kk].coef;
+  const double d = ctl->d;
+  const double unit = ldexp(1.0, -ctl->fx_shift);
+  double r = 0.0, dm = 0.0;
+  for (int node = n0 + static_cast<int>(threadIdx.x) / KT; node < n1; node += BS / KT) {
+    const int64_t v = v0 + node;
+    const int64_t idx = v * KT + kk;
+    const float xo = x_in[idx];
+    const bool seed = (seedmask[v] >> kk) & 1u;
+    const double a = static_cast<double>(acc(node * KT + kk)) * unit;
+    const float xn = frozen ? xo : static_cast<float>(fma(d, a, seed ? coef : 0.0));
+    r += fabs(static_cast<double>(xn) - static_cast<double>(xo));
+    if ((dmask[v >> 5] >> (v & 31)) & 1u) dm += static_cast<double>(xn);
+    x_out[idx] = xn;
+  }
+  // lanes of one vector are those congruent to kk modulo KT
+#pragma unroll
+  for (int off = kWave / 2; off >= KT; off >>= 1) {
+    r += __shfl_xor(r, off);
+    dm += __shfl_xor(dm, off);
+  }
+  __shared__ double sh[(BS / kWave) * KT * 2];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (lane < KT) {
+    sh[(w * KT + lane) * 2] = r;
+    sh[(w * KT + lane) * 2 + 1] = dm;
+  }
+  __syncthreads();
+  if (threadIdx.x < KT) {
+    double rs = 0.0, ds = 0.0;
+    for (int ww = 0; ww < BS / kWave; ++ww) {
+      rs += sh[(ww * KT + threadIdx.x) * 2];
+      ds += sh[(ww * KT + threadIdx.x) * 2 + 1];
+    }
+    red_slot[threadIdx.x * 2] = rs;
+    red_slot[threadIdx.x * 2 + 1] = ds;
+  }
+}
+
+template <int KT>
+__global__ __launch_bounds__(kPprBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                          const Item* __restrict__ items,
+                                                          const uint32_t* __restrict__ did,
+                                                          const int32_t* __restrict__ did_blk,
+                                                          const float* __restrict__ upd,
+                                                          const float* __restrict__ x_in, float* __restrict__ x_out,
+                                                          const uint32_t* __restrict__ dmask,
+                                                          const uint32_t* __restrict__ seedmask,
+                                                          int64_t* __restrict__ partial, double* __restrict__ red,
+                                                          const VCtl* __restrict__ vctl) {
+  if (ctl->done) return;
+  extern __shared__ unsigned long long acc[];  // q * KT fixed-point sums
+  const Item it = items[blockIdx.x];
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = static_cast<int64_t>(it.part) << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  const FixedConv to_fixed(ctl->fx_shift);
+  for (int i = threadIdx.x; i < qn * KT; i += kPprBlock) acc[i] = 0ull;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t qmask = static_cast<uint32_t>(q - 1);
+  const int64_t lo = it.lo, hi = it.hi;
+  const int64_t t_end = (hi + kTile - 1) / kTile;
+  for (int64_t t = lo / kTile + threadIdx.x / kWave; t < t_end; t += kPprBlock / kWave) {
+    const int64_t tb = t * kTile;
+    int32_t run = did_blk[t];
+    for (int j = 0; j < kSub; ++j) {
+      const int64_t e = tb + j * kWave + lane;
+      const uint32_t xv = did[e];
+      const bool f = static_cast<int32_t>(xv) < 0;
+      const uint64_t bal = wave_ballot(f);
+      const int32_t ui = run + lanes_below(bal) + (f ? 0 : -1);  // Alg. 5 update pointer
+      run += __popcll(bal);
+      const bool in = e >= lo && e < hi;
+      float vals[KT];
+      copy_kt<KT>(vals, upd + static_cast<int64_t>(ui) * KT);
+      const uint32_t li = in ? (xv & qmask) : 0u;
+#pragma unroll
+      for (int c = 0; c < KT; ++c)
+        atomicAdd(&acc[li * KT + c], static_cast<unsigned long long>(in ? to_fixed(vals[c]) : 0));
+    }
+  }
+  __syncthreads();
+  if (it.aux >= 0) {
+    int64_t* dst = partial + static_cast<int64_t>(it.aux) * q * KT;
+    for (int i = threadIdx.x; i < qn * KT; i += kPprBlock) dst[i] = static_cast<int64_t>(acc[i]);
+    return;
+  }
+  apply_ppr<KT, kPprBlock>(ctl, vctl, v0, 0, qn, [&](int i) { return static_cast<int64_t>(acc[i]); }, x_in, x_out,
+                           dmask, seedmask, red + static_cast<int64_t>(it.part) * KT * 2);
+}
+
+template <int KT>
+__global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                         const Merge* __restrict__ mg,
+                                                         const int64_t* __restrict__ partial,
+                                                         const float* __restrict__ x_in, float* __restrict__ x_out,
+                                                         const uint32_t* __restrict__ dmask,
+                                                         const uint32_t* __restrict__ seedmask,
+                                                         double* __restrict__ red, int64_t red_base,
+                                                         const VCtl* __restrict__ vctl) {
+  if (ctl->done) return;
+  const Merge mu = mg[blockIdx.x];
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  const int64_t* base = partial + static_cast<int64_t>(mu.first) * q * KT;
+  const int cnt = mu.count;
+  auto acc = [&](int i) {
+    int64_t sum = 0;
+    for (int c = 0; c < cnt; ++c) sum += base[static_cast<int64_t>(c) * q * KT + i];
+    return sum;
+  };
+  apply_ppr<KT, kPprBlock>(ctl, vctl, v0, mu.node_lo, min(qn, mu.node_lo + 256), acc, x_in, x_out, dmask, seedmask,
+                           red + (red_base + blockIdx.x) * KT * 2);
+}
+
+// Per-vector residual, dangling mass and jump coefficient; one wavefront per
+// vector, apply units in order.
+__global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VCtl* __restrict__ vctl, int kt,
+                                                       const double* __restrict__ red, int64_t nslots,
+                                                       double* __restrict__ hist) {
+  if (ctl->done) return;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const double d = ctl->d, tol = ctl->tol;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int kk = threadIdx.x / kWave; kk < kt; kk += 1024 / kWave) {
+    double r = 0.0, dm = 0.0;
+    for (int64_t sl = lane; sl < nslots; sl += kWave) {
+      r += red[(sl * kt + kk) * 2];
+      dm += red[(sl * kt + kk) * 2 + 1];
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      r += __shfl_xor(r, off);
+      dm += __shfl_xor(dm, off);
+    }
+    if (lane == 0) {
+      VCtl& vc = vctl[kk];
+      if (!vc.done) {
+        vc.res = r;
+        vc.iter += 1;
+        vc.dmass = dm;
+        vc.coef = ((1.0 - d) + d * dm) * vc.inv_s;
+        if (!isfinite(r) || !isfinite(dm)) atomicOr(&bad, 1);
+        else if (tol > 0.0 && r < tol) vc.done = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double rmax = 0.0;
+    int all_done = 1;
+    for (int kk = 0; kk < kt; ++kk) {
+      rmax = fmax(rmax, vctl[kk].res);
+      all_done &= vctl[kk].done;
+    }
+    if (bad) rmax = NAN;
+    const int32_t it = ctl->iter;
+    ctl->res_prev = ctl->res;
+    ctl->res = rmax;
+    hist[it] = rmax;
+    ctl->iter = it + 1;
+    if (bad) ctl->nonfinite = 1;
+    if (bad || all_done) ctl->done = 1;
+  }
+}
+
+// Start of a tile: x_0 = t_j (1/|S_j| on the seeds), the seed bitmask, and
+// each vector's dangling mass and jump coefficient.  One wavefront per vector;
+// slots past the tile's last vector are marked converged (they stay zero).
+__global__ __launch_bounds__(1024) void k_ppr_seed(float* __restrict__ x, uint32_t* __restrict__ mask,
+                                                   const int32_t* __restrict__ seeds,
+                                                   const int32_t* __restrict__ seed_off, int first, int kv, int kt,
+                                                   VCtl* __restrict__ vctl, const uint32_t* __restrict__ dmask,
+                                                   double d) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int kk = threadIdx.x / kWave; kk < kt; kk += 1024 / kWave) {
+    double dm = 0.0, inv = 0.0;
+    if (kk < kv) {
+      const int a = seed_off[first + kk], b = seed_off[first + kk + 1];
+      inv = 1.0 / static_cast<double>(b - a);
+      for (int i = a + lane; i < b; i += kWave) {
+        const int v = seeds[i];
+        x[static_cast<int64_t>(v) * kt + kk] = static_cast<float>(inv);
+        atomicOr(&mask[v], 1u << kk);
+        if ((dmask[v >> 5] >> (v & 31)) & 1u) dm += inv;
+      }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) dm += __shfl_xor(dm, off);
+    if (lane == 0) {
+      VCtl& vc = vctl[kk];
+      vc.inv_s = inv;
+      vc.dmass = dm;
+      vc.coef = ((1.0 - d) + d * dm) * inv;
+      vc.res = 0.0;
+      vc.iter = 0;
+      vc.done = kk < kv ? 0 : 1;
+    }
+  }
+}
+
+// pr_out[v][first + j] = x[v][j] for the tile's kv vectors.
+__global__ __launch_bounds__(256) void k_ppr_store(float* __restrict__ out, const float* __restrict__ x, int64_t n,
+                                                   int k, int first, int kv, int kt) {
+  const int64_t total = n * kv;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t v = i / kv;
+    const int j = static_cast<int>(i - v * kv);
+    out[v * k + first + j] = x[v * kt + j];
+  }
+}
+
+__global__ void k_ppr_ctl(Ctl* ctl, double tol, double d) {
+  if (threadIdx.x == 0) {
+    ctl->res = 0.0;
+    ctl->res_prev = 0.0;
+    ctl->tol = tol;
+    ctl->d = d;
+    ctl->iter = 0;
+    ctl->done = 0;
+    ctl->nonfinite = 0;
+    ctl->fx_shift = 50;  // every vector has unit mass
+    ctl->ngroups = 1;
+  }
+}
+
+// ---- host ------------------------------------------------------------------
+
+template <int KT>
+static pcpm_status_t ppr_set_lds(int s) {
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ppr_scatter<KT>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << s) * KT * 4));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ppr_gather<KT>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << s) * KT * 8));
+  return PCPM_OK;
+}
+
+template <int KT>
+static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, hipStream_t st) {
+  const int s = g->part_log2;
+  if (g->n_sc)
+    PCPM_LAUNCH("pcpm_ppr_scatter", k_ppr_scatter<KT>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kPprBlock),
+                static_cast<size_t>(g->q) * KT * 4, st, g->ctl, g->n, s, g->sc_items, in, g->outdeg, g->png_src,
+                g->png_blk, g->seg_delta, g->ppr_upd, g->eprime);
+  PCPM_LAUNCH("pcpm_ppr_gather", k_ppr_gather<KT>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kPprBlock),
+              static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->ga_items, g->did, g->did_blk, g->ppr_upd,
+              in, out, g->dmask, g->ppr_mask, g->ppr_partial, g->ppr_red, g->ppr_vctl);
+  if (g->n_mg)
+    PCPM_LAUNCH("pcpm_ppr_merge", k_ppr_merge<KT>, dim3(static_cast<unsigned>(g->n_mg)), dim3(kPprBlock), 0, st,
+                g->ctl, g->n, s, g->mg_items, g->ppr_partial, in, out, g->dmask, g->ppr_mask, g->ppr_red, g->k,
+                g->ppr_vctl);
+  PCPM_LAUNCH("pcpm_ppr_finalize", k_ppr_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->ppr_vctl, KT, g->ppr_red,
+              g->k + g->n_mg, g->hist);
+  return PCPM_OK;
+}
+
+// Working set for tiles of kt vectors (kept in the handle, grown on demand).
+static pcpm_status_t ppr_alloc(pcpm_png* g, int kt, int64_t nseeds, int k, hipStream_t st) {
+  if (g->ppr_kt < kt) {
+    for (void* p : {static_cast<void*>(g->ppr_x[0]), static_cast<void*>(g->ppr_x[1]),
+                    static_cast<void*>(g->ppr_upd), static_cast<void*>(g->ppr_partial),
+                    static_cast<void*>(g->ppr_red), static_cast<void*>(g->ppr_vctl), static_cast<void*>(g->ppr_mask)})
+      if (p) dfree(g, p);
+    g->ppr_kt = 0;
+    PCPM_TRY(dalloc(g, &g->ppr_x[0], g->n * kt));
+    PCPM_TRY(dalloc(g, &g->ppr_x[1], g->n * kt));
+    PCPM_TRY(dalloc(g, &g->ppr_upd, (g->eprime + 1) * kt));
+    PCPM_TRY(dalloc(g, &g->ppr_partial, static_cast<int64_t>(g->n_split_slots) * g->q * kt));
+    PCPM_TRY(dalloc(g, &g->ppr_red, (g->k + g->n_mg) * kt * 2));
+    PCPM_TRY(dalloc(g, &g->ppr_vctl, kt));
+    PCPM_TRY(dalloc(g, &g->ppr_mask, g->n));
+    g->ppr_kt = kt;
+  }
+  if (g->ppr_seed_cap < nseeds) {
+    if (g->ppr_seeds) dfree(g, g->ppr_seeds);
+    g->ppr_seeds = nullptr;
+    PCPM_TRY(dalloc(g, &g->ppr_seeds, nseeds));
+    g->ppr_seed_cap = nseeds;
+  }
+  if (g->ppr_off_cap < k + 1) {
+    if (g->ppr_seed_off) dfree(g, g->ppr_seed_off);
+    g->ppr_seed_off = nullptr;
+    PCPM_TRY(dalloc(g, &g->ppr_seed_off, k + 1));
+    g->ppr_off_cap = k + 1;
+  }
+  if (!g->ppr_vctl_host)
+    PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->ppr_vctl_host), sizeof(VCtl) * 64, hipHostMallocDefault));
+  return PCPM_OK;
+}
+
+template <int KT>
+static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_iters, float* pr_out, int32_t* iters,
+                             double* resid, hipStream_t st, bool* all_converged, bool* nonfinite) {
+  PCPM_TRY(ppr_set_lds<KT>(g->part_log2));
+  const int64_t n = g->n;
+  *all_converged = true;
+  *nonfinite = false;
+  // slots of split bins are never written by the gather: keep them zero
+  PCPM_TRY_HIP(hipMemsetAsync(g->ppr_red, 0, static_cast<size_t>((g->k + g->n_mg) * KT * 2) * 8, st));
+  for (int first = 0; first < k; first += KT) {
+    const int kv = std::min(KT, k - first);
+    float* a = g->ppr_x[0];
+    float* b = g->ppr_x[1];
+    PCPM_TRY_HIP(hipMemsetAsync(a, 0, static_cast<size_t>(n) * KT * 4, st));
+    PCPM_TRY_HIP(hipMemsetAsync(g->ppr_mask, 0, static_cast<size_t>(n) * 4, st));
+    PCPM_LAUNCH("pcpm_ppr_init", k_ppr_ctl, dim3(1), dim3(64), 0, st, g->ctl, tol, d);
+    PCPM_LAUNCH("pcpm_ppr_init", k_ppr_seed, dim3(1), dim3(1024), 0, st, a, g->ppr_mask, g->ppr_seeds,
+                g->ppr_seed_off, first, kv, KT, g->ppr_vctl, g->dmask, d);
+    int launched = 0;
+    int next = std::min(tol > 0.0 ? 4 : 64, max_iters);
+    while (launched < max_iters) {
+      for (int i = 0; i < next; ++i) {
+        const bool even = ((launched + i) % 2) == 0;
+        PCPM_TRY(ppr_iteration<KT>(g, even ? a : b, even ? b : a, st));
+      }
+      launched += next;
+      PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      PCPM_TRY_HIP(hipStreamSynchronize(st));
+      if (g->ctl_host->done) break;
+      int want = 64;
+      if (tol > 0.0) {
+        const double res = g->ctl_host->res, prev = g->ctl_host->res_prev;
+        double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
+        rho = std::min(std::max(rho, 0.05), 0.995);
+        want = static_cast<int>(std::min(std::max(std::ceil(std::log(tol / res) / std::log(rho)), 1.0), 16.0));
+      }
+      next = std::min(want, max_iters - launched);
+    }
+    const int it_done = g->ctl_host->iter;
+    const float* xr = (it_done > 0 && ((it_done - 1) % 2) == 0) ? b : a;
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((n * kv + 255) / 256, 8192));
+    PCPM_LAUNCH("pcpm_ppr_store", k_ppr_store, dim3(blocks), dim3(256), 0, st, pr_out, xr, n, k, first, kv, KT);
+    PCPM_TRY_HIP(hipMemcpyAsync(g->ppr_vctl_host, g->ppr_vctl, sizeof(VCtl) * KT, hipMemcpyDeviceToHost, st));
+    PCPM_TRY_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < kv; ++j) {
+      iters[first + j] = g->ppr_vctl_host[j].iter;
+      resid[first + j] = g->ppr_vctl_host[j].res;
+      if (!g->ppr_vctl_host[j].done) *all_converged = false;
+    }
+    if (g->ctl_host->nonfinite) *nonfinite = true;
+  }
+  return PCPM_OK;
+}
+
+static pcpm_status_t check_device_ppr(pcpm_png* g) {
+  int dev = -1;
+  PCPM_TRY_HIP(hipGetDevice(&dev));
+  if (dev != g->device)
+    return set_error(PCPM_ERR_INVALID_ARG, "handle lives on device %d but device %d is current", g->device, dev);
+  return PCPM_OK;
+}
+
+}  // namespace pcpm
+
+extern "C" {
+
+pcpm_status_t pcpm_ppr_batch(pcpm_png_t g, double d, int32_t k, const int32_t* seed_off, const int32_t* seeds,
+                             double tol, int32_t max_iters, float* pr_out, int32_t* iters, double* resid,
+                             void* stream) {
+  using namespace pcpm;
+  if (!g || !seed_off || !seeds || !pr_out || !iters || !resid)
+    return set_error(PCPM_ERR_INVALID_ARG, "NULL handle, seed list or output");
+  if (g->ngroups != 1) return set_error(PCPM_ERR_INVALID_ARG, "personalised PageRank needs a single-graph handle");
+  if (k < 1) return set_error(PCPM_ERR_INVALID_ARG, "k must be >= 1");
+  if (!(d >= 0.0 && d < 1.0)) return set_error(PCPM_ERR_INVALID_ARG, "d must lie in [0, 1)");
+  if (max_iters < 1 || max_iters > kMaxHist)
+    return set_error(PCPM_ERR_INVALID_ARG, "max_iters must lie in [1, %d]", kMaxHist);
+  if (!(tol == tol)) return set_error(PCPM_ERR_INVALID_ARG, "tol is NaN");
+  PCPM_TRY(check_device_ppr(g));
+  // validate the seed sets on the host: non-empty, in range, distinct
+  if (seed_off[0] != 0) return set_error(PCPM_ERR_INVALID_ARG, "seed_off[0] must be 0");
+  std::vector<int32_t> scratch;
+  for (int j = 0; j < k; ++j) {
+    const int32_t a = seed_off[j], b = seed_off[j + 1];
+    if (b <= a) return set_error(PCPM_ERR_INVALID_ARG, "seed set %d is empty", j);
+    scratch.assign(seeds + a, seeds + b);
+    std::sort(scratch.begin(), scratch.end());
+    if (scratch.front() < 0 || scratch.back() >= g->n)
+      return set_error(PCPM_ERR_INVALID_ARG, "seed set %d has a node outside [0, n)", j);
+    if (std::adjacent_find(scratch.begin(), scratch.end()) != scratch.end())
+      return set_error(PCPM_ERR_INVALID_ARG, "seed set %d repeats a node", j);
+  }
+  // kt vectors per tile: q * kt fixed-point sums must fit the LDS slice
+  int kt_max = std::max(1, std::min(16, (1 << kMaxLog2) >> g->part_log2));
+  int kt = 1;
+  while (kt < k && kt < kt_max) kt <<= 1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PCPM_TRY(ppr_alloc(g, kt, seed_off[k], k, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(g->ppr_seeds, seeds, static_cast<size_t>(seed_off[k]) * 4, hipMemcpyHostToDevice, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(g->ppr_seed_off, seed_off, static_cast<size_t>(k + 1) * 4, hipMemcpyHostToDevice, st));
+  bool conv = true, bad = false;
+  pcpm_status_t rc;
+  switch (kt) {
+    case 1: rc = ppr_run<1>(g, d, k, tol, max_iters, pr_out, iters, resid, st, &conv, &bad); break;
+    case 2: rc = ppr_run<2>(g, d, k, tol, max_iters, pr_out, iters, resid, st, &conv, &bad); break;
+    case 4: rc = ppr_run<4>(g, d, k, tol, max_iters, pr_out, iters, resid, st, &conv, &bad); break;
+    case 8: rc = ppr_run<8>(g, d, k, tol, max_iters, pr_out, iters, resid, st, &conv, &bad); break;
+    default: rc = ppr_run<16>(g, d, k, tol, max_iters, pr_out, iters, resid, st, &conv, &bad); break;
+  }
+  if (rc != PCPM_OK) return rc;
+  if (bad) return set_error(PCPM_ERR_NUMERIC, "non-finite residual or dangling mass");
+  if (tol > 0.0 && !conv) return set_error(PCPM_ERR_NOT_CONVERGED, "some vectors are above tol after max_iters");
+  return PCPM_OK;
+}
+
+int32_t pcpm_ppr_tile_width(pcpm_png_t g) {
+  if (!g) return 0;
+  return std::max(1, std::min(16, (1 << pcpm::kMaxLog2) >> g->part_log2));
+}
+
+}  // extern "C"

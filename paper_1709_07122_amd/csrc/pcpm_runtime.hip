@@ -71,6 +71,8 @@ void free_handle(pcpm_png* g) {
   g->allocations.clear();
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
   if (g->gctl_host) (void)hipHostFree(g->gctl_host);
+  if (g->ppr_vctl_host) (void)hipHostFree(g->ppr_vctl_host);
+  g->ppr_vctl_host = nullptr;
   g->ctl_host = nullptr;
   g->gctl_host = nullptr;
   delete g;
