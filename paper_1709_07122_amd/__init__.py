@@ -9,9 +9,9 @@ from ._pcpm import (EXPORTS, LIB_PATH, PCPM_ERR_GRAPH, PCPM_ERR_INVALID_ARG, PCP
                     PCPM_ERR_NUMERIC, PCPM_ERR_OVERFLOW, PCPM_OK, PNG, PCPMError, PagerankResult, build_png,
                     iterate, last_error, lib, pagerank, ppr_batch, ppr_tile_width, timing_collect, timing_enable,
                     union_csr)
-from . import commmodel
+from . import autotune, commmodel
 
 __all__ = ["EXPORTS", "LIB_PATH", "PNG", "PCPMError", "PagerankResult", "build_png", "iterate", "pagerank", "ppr_batch", "ppr_tile_width",
-           "last_error", "lib", "timing_enable", "timing_collect", "union_csr", "commmodel", "PCPM_OK",
+           "last_error", "lib", "timing_enable", "timing_collect", "union_csr", "autotune", "commmodel", "PCPM_OK",
            "PCPM_ERR_GRAPH", "PCPM_ERR_INVALID_ARG", "PCPM_ERR_NOT_CONVERGED", "PCPM_ERR_NUMERIC",
            "PCPM_ERR_OVERFLOW"]
