@@ -180,6 +180,60 @@ pcpm_status_t pcpm_ppr_batch(pcpm_png_t g, double d, int32_t k, const int32_t* s
  * (at most 16) whose q * width 8-byte sums fit the gather's LDS slice. */
 int32_t pcpm_ppr_tile_width(pcpm_png_t g);
 
+/* ---- learned warm start -------------------------------------------------
+ * A start vector predicted from graph features by a 3-layer MLP (width 64,
+ * ReLU), trained on PageRank vectors this library computes.  Compute is BF16
+ * x BF16 with FP32 accumulation.  Parameters are one FP32 device array of
+ * PCPM_WS_PARAMS floats: W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * Convergence is still certified by the FP64 residual of pcpm_pagerank; a
+ * poor prediction costs iterations, never correctness. */
+#define PCPM_WS_FEATURES 8
+#define PCPM_WS_HIDDEN 64
+#define PCPM_WS_PARAMS 4801
+
+/* Features of every node of a single-graph handle into feat (device,
+ * [n][8] FP32): log1p(indeg), log1p(outdeg), dangling flag,
+ * log(n * PR_1(v)) with PR_1 the first iterate of Eq. 1 from 1/n,
+ * mean of log1p(indeg) and of log1p(outdeg) over in-neighbours, 0, 0.
+ * The graph sums are two multi-vector scatter/gather passes over the PNG,
+ * computed on the first call and kept in the handle (their time, in ms, goes
+ * to *first_call_ms when non-NULL). */
+pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* first_call_ms /* (host) nullable */,
+                               void* stream);
+
+/* yhat[v] = w3 . relu(W2 relu(W1 feat[v] + b1) + b2) + b3 for n nodes
+ * (device arrays); the prediction of log(n * PR(v)).  Runs on MFMA. */
+pcpm_status_t pcpm_ws_forward(const float* params, const float* feat, int64_t n, float* yhat, void* stream);
+
+/* pr0 = softmax of yhat over the n nodes (max-shifted, FP64 sum): a start
+ * vector of unit mass for pcpm_pagerank.  If any prediction is non-finite the
+ * uniform vector 1/n is written instead and *fallback (host) is 1.  work:
+ * device scratch of pcpm_ws_work_floats(1) floats. */
+pcpm_status_t pcpm_ws_init(const float* yhat, int64_t n, float* pr0, float* work, int32_t* fallback /* (host) */,
+                           void* stream);
+
+/* Floats of device scratch pcpm_ws_backward needs for a minibatch of b. */
+int64_t pcpm_ws_work_floats(int64_t b);
+
+/* Gradient of the mean squared error (1/b) sum_i (yhat(idx[i]) - target(idx[i]))^2
+ * with respect to params into grad (PCPM_WS_PARAMS floats), for the b rows
+ * idx (device int64) of feat ([rows][8]) and target ([rows]); the forward
+ * pass rounds as pcpm_ws_forward.  *loss (host) receives the loss.  Sums over
+ * the minibatch run in a fixed order, so the result is deterministic.  An
+ * index outside [0, rows) is not dereferenced: the call returns
+ * PCPM_ERR_INVALID_ARG and grad is unspecified. */
+pcpm_status_t pcpm_ws_backward(const float* params, const float* feat, const float* target, int64_t rows,
+                               const int64_t* idx, int64_t b, float* grad, float* work, double* loss /* (host) */,
+                               void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step
+ * >= 1) on the FP32 master parameters, moments m and v (device). */
+pcpm_status_t pcpm_ws_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr,
+                           void* stream);
+
+/* Training target y[v] = log(n * pr[v]). */
+pcpm_status_t pcpm_ws_targets(const float* pr, int64_t n, float* y, void* stream);
+
 /* Per-graph outcome of the last pcpm_pagerank on a handle: iterations run and
  * last residual of each of the G graphs (host arrays of G). */
 pcpm_status_t pcpm_graph_results(pcpm_png_t g, int32_t* iters /* (host) G */, double* resid /* (host) G */);

@@ -32,7 +32,12 @@ STATUS_NAMES = {
 # every symbol include/pcpm.h declares
 EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
            "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_last_error",
-           "pcpm_timing_enable", "pcpm_timing_collect"]
+           "pcpm_timing_enable", "pcpm_timing_collect", "pcpm_ws_features", "pcpm_ws_forward", "pcpm_ws_init",
+           "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_adam", "pcpm_ws_targets"]
+
+WS_FEATURES = 8
+WS_HIDDEN = 64
+WS_PARAMS = 4801
 
 
 class PCPMError(RuntimeError):
@@ -86,6 +91,20 @@ def lib():
     L.pcpm_ppr_batch.argtypes = [vp, dbl, i32, vp, vp, dbl, i32, vp, vp, vp, vp]
     L.pcpm_ppr_tile_width.restype = ctypes.c_int32
     L.pcpm_ppr_tile_width.argtypes = [vp]
+    L.pcpm_ws_features.restype = ctypes.c_int
+    L.pcpm_ws_features.argtypes = [vp, dbl, vp, ctypes.POINTER(dbl), vp]
+    L.pcpm_ws_forward.restype = ctypes.c_int
+    L.pcpm_ws_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.pcpm_ws_init.restype = ctypes.c_int
+    L.pcpm_ws_init.argtypes = [vp, i64, vp, vp, ctypes.POINTER(i32), vp]
+    L.pcpm_ws_work_floats.restype = i64
+    L.pcpm_ws_work_floats.argtypes = [i64]
+    L.pcpm_ws_backward.restype = ctypes.c_int
+    L.pcpm_ws_backward.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, ctypes.POINTER(dbl), vp]
+    L.pcpm_ws_adam.restype = ctypes.c_int
+    L.pcpm_ws_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
+    L.pcpm_ws_targets.restype = ctypes.c_int
+    L.pcpm_ws_targets.argtypes = [vp, i64, vp, vp]
     L.pcpm_graph_results.restype = ctypes.c_int
     L.pcpm_graph_results.argtypes = [vp, vp, vp]
     L.pcpm_last_error.restype = ctypes.c_char_p
@@ -323,3 +342,77 @@ def union_csr(graphs, part_log2: int):
     row_off = np.concatenate(rows + [np.array([base_e])]).astype(np.int32)
     col = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
     return row_off, col, np.array(offs, dtype=np.int64), np.array(sizes, dtype=np.int64)
+
+
+# ---- learned warm start -------------------------------------------------------
+
+def ws_features(png: PNG, d: float = 0.85, stream=None):
+    """[n][8] float32 features of every node (pcpm_ws_features); returns
+    (features, ms spent on the per-handle graph sums by the first call)."""
+    import torch
+    feat = torch.empty((png.n, WS_FEATURES), dtype=torch.float32, device=png.row_off.device)
+    ms = ctypes.c_double(0.0)
+    _check(lib().pcpm_ws_features(png.handle, float(d), _dev_tensor(feat, torch.float32, name="feat"),
+                                  ctypes.byref(ms), _stream(stream)))
+    return feat, ms.value
+
+
+def ws_forward(params, feat, stream=None):
+    import torch
+    n = feat.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device=feat.device)
+    _check(lib().pcpm_ws_forward(_dev_tensor(params, torch.float32, WS_PARAMS, "params"),
+                                 _dev_tensor(feat, torch.float32, n * WS_FEATURES, "feat"), n,
+                                 _dev_tensor(y, torch.float32, n, "yhat"), _stream(stream)))
+    return y
+
+
+def ws_init(yhat, out=None, stream=None):
+    """Softmax of the prediction over the nodes; returns (pr0, used_uniform)."""
+    import torch
+    n = yhat.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=yhat.device)
+    work = torch.empty(int(lib().pcpm_ws_work_floats(1)), dtype=torch.float32, device=yhat.device)
+    flag = ctypes.c_int32(0)
+    _check(lib().pcpm_ws_init(_dev_tensor(yhat, torch.float32, n, "yhat"), n, _dev_tensor(out, torch.float32, n, "pr0"),
+                              _dev_tensor(work, torch.float32, name="work"), ctypes.byref(flag), _stream(stream)))
+    return out, bool(flag.value)
+
+
+def ws_backward(params, feat, target, idx, grad=None, work=None, stream=None):
+    """Gradient of the minibatch MSE; returns (grad, loss)."""
+    import torch
+    b = idx.numel()
+    if grad is None:
+        grad = torch.empty(WS_PARAMS, dtype=torch.float32, device=params.device)
+    need = int(lib().pcpm_ws_work_floats(b))
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.float32, device=params.device)
+    rows = feat.shape[0]
+    loss = ctypes.c_double(0.0)
+    _check(lib().pcpm_ws_backward(_dev_tensor(params, torch.float32, WS_PARAMS, "params"),
+                                  _dev_tensor(feat, torch.float32, rows * WS_FEATURES, "feat"),
+                                  _dev_tensor(target, torch.float32, rows, "target"), rows,
+                                  _dev_tensor(idx, torch.int64, b, "idx"), b,
+                                  _dev_tensor(grad, torch.float32, WS_PARAMS, "grad"),
+                                  _dev_tensor(work, torch.float32, name="work"), ctypes.byref(loss),
+                                  _stream(stream)))
+    return grad, loss.value
+
+
+def ws_adam(params, grad, m, v, step: int, lr: float, stream=None):
+    import torch
+    _check(lib().pcpm_ws_adam(_dev_tensor(params, torch.float32, WS_PARAMS, "params"),
+                              _dev_tensor(grad, torch.float32, WS_PARAMS, "grad"),
+                              _dev_tensor(m, torch.float32, WS_PARAMS, "m"), _dev_tensor(v, torch.float32, WS_PARAMS, "v"),
+                              int(step), float(lr), _stream(stream)))
+
+
+def ws_targets(pr, stream=None):
+    import torch
+    n = pr.numel()
+    y = torch.empty(n, dtype=torch.float32, device=pr.device)
+    _check(lib().pcpm_ws_targets(_dev_tensor(pr, torch.float32, n, "pr"), n, _dev_tensor(y, torch.float32, n, "y"),
+                                 _stream(stream)))
+    return y

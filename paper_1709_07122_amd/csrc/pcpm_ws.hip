@@ -1,0 +1,540 @@
+// Learned warm start: per-node graph features, a 3-layer MLP (width 64,
+// ReLU) that predicts log(n * PR*(v)), its BF16/FP32 training kernels, and the
+// normalisation of the prediction into a start vector.
+//
+// Features (all functions of the graph and d only, so they are computed once
+// per handle, like the PNG):
+//   0 log1p(indeg)   1 log1p(outdeg)   2 dangling flag
+//   3 log(n * PR_1(v)) = log((1-d) + d * (s1(v) + n_dangling/n)), the first
+//     iterate from the uniform vector, s1(v) = sum_{u->v} 1/outdeg(u)
+//   4 s2(v)/max(indeg,1), s2 = sum_{u->v} log1p(indeg(u))
+//   5 s3(v)/max(indeg,1), s3 = sum_{u->v} log1p(outdeg(u))
+//   6, 7 zero padding
+// The sums are two passes of the batched scatter/gather (two right-hand
+// sides each).
+//
+// Parameters (FP32 master copy, 4801 floats): W1[64][8], b1[64], W2[64][64],
+// b2[64], w3[64], b3.  Compute is BF16 x BF16 -> FP32: weights, features and
+// hidden activations are rounded to BF16 where they enter a product.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "pcpm_device.hpp"
+#include "pcpm_internal.hpp"
+
+namespace pcpm {
+
+constexpr int kF = PCPM_WS_FEATURES;
+constexpr int kH = PCPM_WS_HIDDEN;
+constexpr int kOW1 = 0, kOB1 = kH * kF, kOW2 = kOB1 + kH, kOB2 = kOW2 + kH * kH, kOW3 = kOB2 + kH, kOB3 = kOW3 + kH;
+static_assert(kOB3 + 1 == PCPM_WS_PARAMS, "parameter layout");
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Round to the nearest BF16 (ties to even); returns the bits.
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(static_cast<uint32_t>(bf16_bits(f)) << 16); }
+
+// ---- structure sums and features --------------------------------------------------
+__global__ __launch_bounds__(256) void k_ws_pass_a(float* __restrict__ x, const int32_t* __restrict__ outdeg,
+                                                   int64_t n) {
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    x[2 * v] = static_cast<float>(outdeg[v]);  // / outdeg in the scatter: 1 per in-edge
+    x[2 * v + 1] = 1.0f;                         // 1/outdeg(u) per in-edge
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ws_pass_b(float* __restrict__ x, const float* __restrict__ sums_a,
+                                                   const int32_t* __restrict__ outdeg, int64_t n) {
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float od = static_cast<float>(outdeg[v]);
+    x[2 * v] = log1pf(sums_a[2 * v]) * od;
+    x[2 * v + 1] = log1pf(od) * od;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ws_struct(float* __restrict__ st, const float* __restrict__ a,
+                                                   const float* __restrict__ b, int64_t n) {
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    st[4 * v] = a[2 * v];
+    st[4 * v + 1] = a[2 * v + 1];
+    st[4 * v + 2] = b[2 * v];
+    st[4 * v + 3] = b[2 * v + 1];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, const float* __restrict__ st,
+                                                     const int32_t* __restrict__ outdeg,
+                                                     const uint32_t* __restrict__ dmask, int64_t n, double d,
+                                                     double frac_dangling) {
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float indeg = st[4 * v];
+    const float od = static_cast<float>(outdeg[v]);
+    const float inv = 1.0f / fmaxf(indeg, 1.0f);
+    float* f = feat + kF * v;
+    f[0] = log1pf(indeg);
+    f[1] = log1pf(od);
+    f[2] = static_cast<float>((dmask[v >> 5] >> (v & 31)) & 1u);
+    f[3] = static_cast<float>(log((1.0 - d) + d * (static_cast<double>(st[4 * v + 1]) + frac_dangling)));
+    f[4] = st[4 * v + 2] * inv;
+    f[5] = st[4 * v + 3] * inv;
+    f[6] = 0.0f;
+    f[7] = 0.0f;
+  }
+}
+
+// ---- inference on MFMA ------------------------------------------------------------
+// One wavefront evaluates 32 nodes with transposed products, so the output of
+// each layer is already the B operand of the next:
+//   h1^T = W1 X^T (2 MFMA 32x32x8),  h2^T = W2 h1^T (16),  y = w3 . h2 + b3.
+// Lane l owns node l%32; in a 32x32 output block its value v is row
+// 8(v/4) + 4(l/32) + v%4, which for K-block t of the next product is exactly
+// the four B values that lane must supply (v = 4t .. 4t+3).
+__global__ __launch_bounds__(256) void k_ws_forward(const float* __restrict__ P, const float* __restrict__ feat,
+                                                    int64_t n, float* __restrict__ yhat) {
+  __shared__ float b1s[kH], b2s[kH], w3s[kH];
+  for (int i = threadIdx.x; i < kH; i += 256) {
+    b1s[i] = P[kOB1 + i];
+    b2s[i] = P[kOB2 + i];
+    w3s[i] = bf16_round(P[kOW3 + i]);
+  }
+  __syncthreads();
+  const float b3 = P[kOB3];
+  const int l = threadIdx.x & (kWave - 1);
+  const int col = l & 31, half = l >> 5;
+  // A fragments: row 32*ob + col, columns 4*half .. +4 of each K-block
+  v4s a1[2], a2[2][8];
+#pragma unroll
+  for (int ob = 0; ob < 2; ++ob) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a1[ob][r] = static_cast<short>(bf16_bits(P[kOW1 + (32 * ob + col) * kF + 4 * half + r]));
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        a2[ob][kb][r] = static_cast<short>(bf16_bits(P[kOW2 + (32 * ob + col) * kH + 8 * kb + 4 * half + r]));
+  }
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (256 / kWave);
+  for (int64_t base = (static_cast<int64_t>(blockIdx.x) * (256 / kWave) + threadIdx.x / kWave) * 32; base < n;
+       base += waves * 32) {
+    const int64_t node = base + col;
+    v4s bx;
+    if (node < n) {
+      const float4 fv = *reinterpret_cast<const float4*>(feat + kF * node + 4 * half);
+      bx[0] = static_cast<short>(bf16_bits(fv.x));
+      bx[1] = static_cast<short>(bf16_bits(fv.y));
+      bx[2] = static_cast<short>(bf16_bits(fv.z));
+      bx[3] = static_cast<short>(bf16_bits(fv.w));
+    } else {
+      bx[0] = bx[1] = bx[2] = bx[3] = 0;
+    }
+    const v16f zero = {};
+    v4s b2op[8];
+#pragma unroll
+    for (int ob = 0; ob < 2; ++ob) {
+      const v16f h1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[ob], bx, zero, 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 32 * ob + 8 * t + 4 * half + r;
+          b2op[4 * ob + t][r] = static_cast<short>(bf16_bits(fmaxf(h1[4 * t + r] + b1s[row], 0.0f)));
+        }
+    }
+    float part = 0.0f;
+#pragma unroll
+    for (int ob = 0; ob < 2; ++ob) {
+      v16f h2 = zero;
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) h2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][kb], b2op[kb], h2, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
+        part += w3s[row] * bf16_round(fmaxf(h2[v] + b2s[row], 0.0f));
+      }
+    }
+    part += __shfl_xor(part, 32);  // lanes l and l^32 hold the two halves of node col's rows
+    if (half == 0 && node < n) yhat[node] = part + b3;
+  }
+}
+
+// ---- start vector: softmax over nodes --------------------------------------------
+constexpr int kSoftBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_ws_max(const float* __restrict__ y, int64_t n, float* __restrict__ red) {
+  float mx = -INFINITY;
+  float bad = 0.0f;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * 256) {
+    const float yv = y[v];
+    if (!isfinite(yv)) bad = 1.0f;
+    mx = fmaxf(mx, yv);
+  }
+  __shared__ float sm[256], sb[256];
+  sm[threadIdx.x] = mx;
+  sb[threadIdx.x] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 256; ++i) {
+      mx = fmaxf(mx, sm[i]);
+      bad = fmaxf(bad, sb[i]);
+    }
+    red[2 * blockIdx.x] = mx;
+    red[2 * blockIdx.x + 1] = bad;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ws_expsum(const float* __restrict__ y, int64_t n,
+                                                   const float* __restrict__ red, double* __restrict__ dred) {
+  float mx = -INFINITY;
+  for (int i = 0; i < kSoftBlocks; ++i) mx = fmaxf(mx, red[2 * i]);
+  double sums[1] = {0.0};
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * 256)
+    sums[0] += exp(static_cast<double>(y[v]) - static_cast<double>(mx));
+  block_sum<256>(sums);
+  if (threadIdx.x == 0) dred[blockIdx.x] = sums[0];
+}
+
+__global__ __launch_bounds__(256) void k_ws_normalise(const float* __restrict__ y, int64_t n,
+                                                      const float* __restrict__ red, const double* __restrict__ dred,
+                                                      float* __restrict__ pr0, int32_t* __restrict__ flag) {
+  float mx = -INFINITY, bad = 0.0f;
+  for (int i = 0; i < kSoftBlocks; ++i) {
+    mx = fmaxf(mx, red[2 * i]);
+    bad = fmaxf(bad, red[2 * i + 1]);
+  }
+  double sum = 0.0;
+  for (int i = 0; i < kSoftBlocks; ++i) sum += dred[i];
+  const bool fallback = bad > 0.0f || !(sum > 0.0) || !isfinite(sum);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = fallback ? 1 : 0;
+  const double inv = fallback ? 0.0 : 1.0 / sum;
+  const float uni = static_cast<float>(1.0 / static_cast<double>(n));
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * 256)
+    pr0[v] = fallback ? uni : static_cast<float>(exp(static_cast<double>(y[v]) - static_cast<double>(mx)) * inv);
+}
+
+// ---- training: loss gradient over a minibatch -------------------------------------
+// Loss = mean over the minibatch of (yhat - target)^2.  The forward pass
+// rounds exactly as k_ws_forward does (BF16 weights, features and hidden
+// activations; FP32 sums).  One workgroup takes chunks of 64 samples: four
+// threads per sample for the activations, then every thread accumulates its
+// own 16 + 2 (+3) parameter gradients over the chunk.  Partial gradients per
+// workgroup are summed in a fixed order by k_ws_grad_reduce.
+constexpr int kGradBlock = 256;
+constexpr int kChunk = 64;
+
+__global__ __launch_bounds__(kGradBlock) void k_ws_grad(const float* __restrict__ P, const float* __restrict__ feat,
+                                                        const float* __restrict__ target, int64_t rows,
+                                                        const int64_t* __restrict__ idx, int64_t b, float inv_b,
+                                                        float* __restrict__ part, double* __restrict__ loss_part) {
+  __shared__ float W1s[kH * kF], b1s[kH], W2s[kH * kH], b2s[kH], w3s[kH];
+  __shared__ float xs[kChunk][kF + 1], h1s[kChunk][kH + 1], h2s[kChunk][kH + 1], dh2s[kChunk][kH + 1],
+      dh1s[kChunk][kH + 1], dys[kChunk];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kH * kF; i += kGradBlock) W1s[i] = bf16_round(P[kOW1 + i]);
+  for (int i = tid; i < kH * kH; i += kGradBlock) W2s[i] = bf16_round(P[kOW2 + i]);
+  for (int i = tid; i < kH; i += kGradBlock) {
+    b1s[i] = P[kOB1 + i];
+    b2s[i] = P[kOB2 + i];
+    w3s[i] = bf16_round(P[kOW3 + i]);
+  }
+  const float b3 = P[kOB3];
+  const int s = tid / 4, qtr = tid % 4;  // sample of the chunk, quarter of the hidden units
+  const int gi = tid / 4;                 // dW2 row owned by this thread
+  float gW2[16] = {}, gW1[2] = {}, gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f, gb3 = 0.0f;
+  double loss = 0.0, bad = 0.0;
+  __syncthreads();
+  for (int64_t c0 = static_cast<int64_t>(blockIdx.x) * kChunk; c0 < b; c0 += static_cast<int64_t>(gridDim.x) * kChunk) {
+    const int64_t ri = c0 + s < b ? idx[c0 + s] : -1;
+    const bool in_range = ri >= 0 && ri < rows;
+    if (c0 + s < b && !in_range && qtr == 0) bad += 1.0;
+    const bool valid = c0 + s < b && in_range;
+    const int64_t row = valid ? ri : 0;
+    for (int k = qtr * 2; k < qtr * 2 + 2; ++k) xs[s][k] = valid ? bf16_round(feat[kF * row + k]) : 0.0f;
+    const float tgt = valid ? target[row] : 0.0f;
+    __syncthreads();
+    for (int j = 16 * qtr; j < 16 * qtr + 16; ++j) {
+      float a = b1s[j];
+      for (int k = 0; k < kF; ++k) a += W1s[j * kF + k] * xs[s][k];
+      h1s[s][j] = bf16_round(fmaxf(a, 0.0f));
+    }
+    __syncthreads();
+    float yp = 0.0f;
+    for (int i = 16 * qtr; i < 16 * qtr + 16; ++i) {
+      float a = b2s[i];
+      for (int k = 0; k < kH; ++k) a += W2s[i * kH + k] * h1s[s][k];
+      const float h2 = bf16_round(fmaxf(a, 0.0f));
+      h2s[s][i] = h2;
+      yp += w3s[i] * h2;
+    }
+    yp += __shfl_xor(yp, 1);
+    yp += __shfl_xor(yp, 2);
+    const float y = yp + b3;
+    const float dy = valid ? 2.0f * (y - tgt) * inv_b : 0.0f;
+    if (qtr == 0) {
+      dys[s] = dy;
+      if (valid) loss += static_cast<double>(y - tgt) * static_cast<double>(y - tgt);
+    }
+    for (int i = 16 * qtr; i < 16 * qtr + 16; ++i) dh2s[s][i] = h2s[s][i] > 0.0f ? w3s[i] * dy : 0.0f;
+    __syncthreads();
+    for (int k = 16 * qtr; k < 16 * qtr + 16; ++k) {
+      float a = 0.0f;
+      for (int i = 0; i < kH; ++i) a += W2s[i * kH + k] * dh2s[s][i];
+      dh1s[s][k] = h1s[s][k] > 0.0f ? a : 0.0f;
+    }
+    __syncthreads();
+    // parameter gradients of this chunk
+    for (int ss = 0; ss < kChunk; ++ss) {
+      const float d2 = dh2s[ss][gi];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) gW2[c] += d2 * h1s[ss][16 * qtr + c];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) gW1[c] += dh1s[ss][(2 * tid + c) / kF] * xs[ss][(2 * tid + c) % kF];
+    }
+    if (tid < kH) {
+      for (int ss = 0; ss < kChunk; ++ss) {
+        gb1 += dh1s[ss][tid];
+        gb2 += dh2s[ss][tid];
+        gw3 += dys[ss] * h2s[ss][tid];
+      }
+    }
+    if (tid == 0)
+      for (int ss = 0; ss < kChunk; ++ss) gb3 += dys[ss];
+    __syncthreads();
+  }
+  float* out = part + static_cast<int64_t>(blockIdx.x) * PCPM_WS_PARAMS;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) out[kOW2 + gi * kH + 16 * qtr + c] = gW2[c];
+  out[kOW1 + 2 * tid] = gW1[0];
+  out[kOW1 + 2 * tid + 1] = gW1[1];
+  if (tid < kH) {
+    out[kOB1 + tid] = gb1;
+    out[kOB2 + tid] = gb2;
+    out[kOW3 + tid] = gw3;
+  }
+  if (tid == 0) out[kOB3] = gb3;
+  double sums[2] = {loss, bad};
+  block_sum<kGradBlock>(sums);
+  if (tid == 0) {
+    loss_part[2 * blockIdx.x] = sums[0];
+    loss_part[2 * blockIdx.x + 1] = sums[1];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ws_grad_reduce(const float* __restrict__ part, int nparts,
+                                                        const double* __restrict__ loss_part, float* __restrict__ grad,
+                                                        double* __restrict__ loss) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < PCPM_WS_PARAMS) {
+    float s = 0.0f;
+    for (int w = 0; w < nparts; ++w) s += part[static_cast<int64_t>(w) * PCPM_WS_PARAMS + p];
+    grad[p] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double l = 0.0, bad = 0.0;
+    for (int w = 0; w < nparts; ++w) {
+      l += loss_part[2 * w];
+      bad += loss_part[2 * w + 1];
+    }
+    loss[0] = l;
+    loss[1] = bad;
+  }
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master weights, bias-corrected.
+// The constants 1 - beta and the bias corrections are rounded from FP64 on
+// the host: 1 - 0.999f in FP32 would be off by 1e-5 relative.
+__global__ __launch_bounds__(256) void k_ws_adam(float* __restrict__ P, const float* __restrict__ g,
+                                                 float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                                 float omb1, float b2, float omb2, float eps, float c1, float c2) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= PCPM_WS_PARAMS) return;
+  const float gp = g[p];
+  const float mp = b1 * m[p] + omb1 * gp;
+  const float vp = b2 * v[p] + omb2 * gp * gp;
+  m[p] = mp;
+  v[p] = vp;
+  P[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_ws_targets(const float* __restrict__ pr, int64_t n, float* __restrict__ y) {
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * 256)
+    y[v] = static_cast<float>(log(static_cast<double>(pr[v]) * static_cast<double>(n)));
+}
+
+static unsigned grid_for(int64_t n) { return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192))); }
+
+static int ceil_log2(double x) {
+  int e = 0;
+  while (std::ldexp(1.0, e) < x) ++e;
+  return e;
+}
+
+// Structure sums of a handle (computed on first use).
+static pcpm_status_t ws_structure(pcpm_png* g, hipStream_t st) {
+  if (g->ws_struct) return PCPM_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = g->n;
+  float *xa, *sa, *xb, *sb;
+  PCPM_TRY(dalloc(g, &xa, 2 * n));
+  PCPM_TRY(dalloc(g, &sa, 2 * n));
+  PCPM_TRY(dalloc(g, &xb, 2 * n));
+  PCPM_TRY(dalloc(g, &sb, 2 * n));
+  // column masses bound the sums: pass A sum_u outdeg(u) = m and n; pass B at
+  // most log1p(2^31) * m
+  const double mass_a = std::max<double>(1.0, std::max<double>(g->m, g->n));
+  const double mass_b = std::max<double>(1.0, 22.0 * std::max<double>(g->m, 1));
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_pass_a, dim3(grid_for(n)), dim3(256), 0, st, xa, g->outdeg, n);
+  PCPM_TRY(raw_spmv(g, 2, xa, sa, 50 - ceil_log2(mass_a), st));
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_pass_b, dim3(grid_for(n)), dim3(256), 0, st, xb, sa, g->outdeg, n);
+  PCPM_TRY(raw_spmv(g, 2, xb, sb, 50 - ceil_log2(mass_b), st));
+  float* ws = nullptr;
+  PCPM_TRY(dalloc(g, &ws, 4 * n));
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_struct, dim3(grid_for(n)), dim3(256), 0, st, ws, sa, sb, n);
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  dfree(g, xa);
+  dfree(g, sa);
+  dfree(g, xb);
+  dfree(g, sb);
+  g->ws_struct = ws;
+  g->ws_struct_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return PCPM_OK;
+}
+
+static pcpm_status_t ws_check_device_ptr(const void* p, const char* what) {
+  hipPointerAttribute_t a;
+  if (!p || hipPointerGetAttributes(&a, p) != hipSuccess ||
+      !(a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged)) {
+    (void)hipGetLastError();
+    return set_error(PCPM_ERR_INVALID_ARG, "%s must be a device pointer", what);
+  }
+  return PCPM_OK;
+}
+
+}  // namespace pcpm
+
+extern "C" {
+
+pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* first_call_ms, void* stream) {
+  using namespace pcpm;
+  if (!g || !feat) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or output");
+  if (!(d >= 0.0 && d < 1.0)) return set_error(PCPM_ERR_INVALID_ARG, "d must lie in [0, 1)");
+  if (g->ngroups != 1) return set_error(PCPM_ERR_INVALID_ARG, "warm start needs a single-graph handle");
+  PCPM_TRY(ws_check_device_ptr(feat, "feat"));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PCPM_TRY(ws_structure(g, st));
+  if (first_call_ms) *first_call_ms = g->ws_struct_ms;
+  const double fd = static_cast<double>(g->n_dangling) / static_cast<double>(g->n);
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_features, dim3(grid_for(g->n)), dim3(256), 0, st, feat, g->ws_struct,
+              g->outdeg, g->dmask, g->n, d, fd);
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_ws_forward(const float* params, const float* feat, int64_t n, float* yhat, void* stream) {
+  using namespace pcpm;
+  if (n < 1) return set_error(PCPM_ERR_INVALID_ARG, "n must be >= 1");
+  PCPM_TRY(ws_check_device_ptr(params, "params"));
+  PCPM_TRY(ws_check_device_ptr(feat, "feat"));
+  PCPM_TRY(ws_check_device_ptr(yhat, "yhat"));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t groups = (n + 31) / 32;  // 32 nodes per wavefront, 4 wavefronts per workgroup
+  const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 16384)));
+  PCPM_LAUNCH("pcpm_ws_forward", k_ws_forward, dim3(blocks), dim3(256), 0, st, params, feat, n, yhat);
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_ws_init(const float* yhat, int64_t n, float* pr0, float* work, int32_t* fallback, void* stream) {
+  using namespace pcpm;
+  if (n < 1 || !fallback) return set_error(PCPM_ERR_INVALID_ARG, "bad size or NULL flag");
+  PCPM_TRY(ws_check_device_ptr(yhat, "yhat"));
+  PCPM_TRY(ws_check_device_ptr(pr0, "pr0"));
+  PCPM_TRY(ws_check_device_ptr(work, "work"));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* red = work;                                            // 2 * kSoftBlocks floats
+  double* dred = reinterpret_cast<double*>(work + 2 * kSoftBlocks);  // kSoftBlocks doubles
+  int32_t* flag = reinterpret_cast<int32_t*>(work + 4 * kSoftBlocks);
+  PCPM_LAUNCH("pcpm_ws_init", k_ws_max, dim3(kSoftBlocks), dim3(256), 0, st, yhat, n, red);
+  PCPM_LAUNCH("pcpm_ws_init", k_ws_expsum, dim3(kSoftBlocks), dim3(256), 0, st, yhat, n, red, dred);
+  PCPM_LAUNCH("pcpm_ws_init", k_ws_normalise, dim3(grid_for(n)), dim3(256), 0, st, yhat, n, red, dred, pr0, flag);
+  PCPM_TRY_HIP(hipMemcpyAsync(fallback, flag, 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  return PCPM_OK;
+}
+
+int64_t pcpm_ws_work_floats(int64_t b) {
+  const int64_t parts = std::max<int64_t>(1, std::min<int64_t>((b + pcpm::kChunk - 1) / pcpm::kChunk, 1024));
+  return std::max<int64_t>(parts * PCPM_WS_PARAMS + 4 * (parts + 1), 4 * pcpm::kSoftBlocks + 4);
+}
+
+pcpm_status_t pcpm_ws_backward(const float* params, const float* feat, const float* target, int64_t rows,
+                               const int64_t* idx, int64_t b, float* grad, float* work, double* loss, void* stream) {
+  using namespace pcpm;
+  if (b < 1 || rows < 1 || !loss) return set_error(PCPM_ERR_INVALID_ARG, "empty minibatch, no rows or NULL loss");
+  PCPM_TRY(ws_check_device_ptr(params, "params"));
+  PCPM_TRY(ws_check_device_ptr(feat, "feat"));
+  PCPM_TRY(ws_check_device_ptr(target, "target"));
+  PCPM_TRY(ws_check_device_ptr(idx, "idx"));
+  PCPM_TRY(ws_check_device_ptr(grad, "grad"));
+  PCPM_TRY(ws_check_device_ptr(work, "work"));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int parts = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((b + kChunk - 1) / kChunk, 1024)));
+  // work: 2 (parts + 1) doubles (per-workgroup loss and bad-index count,
+  // then the totals), then parts * PARAMS floats
+  double* lpart = reinterpret_cast<double*>(work);
+  double* ldev = lpart + 2 * parts;
+  float* part = work + 4 * (parts + 1);
+  PCPM_LAUNCH("pcpm_ws_backward", k_ws_grad, dim3(parts), dim3(kGradBlock), 0, st, params, feat, target, rows, idx,
+              b, 1.0f / static_cast<float>(b), part, lpart);
+  PCPM_LAUNCH("pcpm_ws_backward", k_ws_grad_reduce, dim3((PCPM_WS_PARAMS + 255) / 256), dim3(256), 0, st, part,
+              parts, lpart, grad, ldev);
+  double tot[2] = {0.0, 0.0};
+  PCPM_TRY_HIP(hipMemcpyAsync(tot, ldev, 16, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  if (tot[1] != 0.0)
+    return set_error(PCPM_ERR_INVALID_ARG, "%.0f minibatch indices outside [0, %lld)", tot[1],
+                     static_cast<long long>(rows));
+  *loss = tot[0] / static_cast<double>(b);
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_ws_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr,
+                           void* stream) {
+  using namespace pcpm;
+  if (step < 1 || !(lr > 0.0f)) return set_error(PCPM_ERR_INVALID_ARG, "step must be >= 1 and lr > 0");
+  PCPM_TRY(ws_check_device_ptr(params, "params"));
+  PCPM_TRY(ws_check_device_ptr(grad, "grad"));
+  PCPM_TRY(ws_check_device_ptr(m, "m"));
+  PCPM_TRY(ws_check_device_ptr(v, "v"));
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  const double c1 = 1.0 - std::pow(b1, step), c2 = 1.0 - std::pow(b2, step);
+  PCPM_LAUNCH("pcpm_ws_adam", k_ws_adam, dim3((PCPM_WS_PARAMS + 255) / 256), dim3(256), 0,
+              static_cast<hipStream_t>(stream), params, grad, m, v, lr, static_cast<float>(b1),
+              static_cast<float>(1.0 - b1), static_cast<float>(b2), static_cast<float>(1.0 - b2),
+              static_cast<float>(eps), static_cast<float>(c1), static_cast<float>(c2));
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_ws_targets(const float* pr, int64_t n, float* y, void* stream) {
+  using namespace pcpm;
+  if (n < 1) return set_error(PCPM_ERR_INVALID_ARG, "n must be >= 1");
+  PCPM_TRY(ws_check_device_ptr(pr, "pr"));
+  PCPM_TRY(ws_check_device_ptr(y, "y"));
+  PCPM_LAUNCH("pcpm_ws_targets", k_ws_targets, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), pr,
+              n, y);
+  return PCPM_OK;
+}
+
+}  // extern "C"
