@@ -192,12 +192,12 @@ int32_t pcpm_ppr_tile_width(pcpm_png_t g);
 #define PCPM_WS_PARAMS 4801
 
 /* Features of every node of a single-graph handle into feat (device,
- * [n][8] FP32): log1p(indeg), log1p(outdeg), dangling flag,
- * log(n * PR_1(v)) with PR_1 the first iterate of Eq. 1 from 1/n,
- * mean of log1p(indeg) and of log1p(outdeg) over in-neighbours, 0, 0.
- * The graph sums are two multi-vector scatter/gather passes over the PNG,
- * computed on the first call and kept in the handle (their time, in ms, goes
- * to *first_call_ms when non-NULL). */
+ * [n][8] FP32): log1p(indeg), log1p(outdeg), dangling flag, and
+ * log(n * PR_1(v)) with PR_1 the first iterate of Eq. 1 from 1/n (the
+ * one-SpMV aggregate sum_{u->v} 1/outdeg(u) of the in-neighbours' degrees),
+ * then four zeros.  In-degrees are counted from the destination-ID bins on
+ * the first call and kept in the handle (that count's time, in ms, goes to
+ * *first_call_ms when non-NULL); every call runs one PCPM iteration. */
 pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* first_call_ms /* (host) nullable */,
                                void* stream);
 

@@ -62,10 +62,9 @@ def adam_step(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def features(row_off, col, d=0.85):
-    """Warm-start features from their definitions (FP64):
-    log1p(indeg), log1p(outdeg), dangling flag,
-    log(n PR_1(v)) = log((1-d) + d (sum_{u->v} 1/outdeg(u) + n_dangling/n)),
-    mean over in-neighbours of log1p(indeg(u)) and of log1p(outdeg(u)), 0, 0."""
+    """Warm-start features from their definitions (FP64): log1p(indeg),
+    log1p(outdeg), dangling flag, log(n PR_1(v)) = log((1-d) + d (s1(v) +
+    n_dangling/n)) with s1(v) = sum_{u->v} 1/outdeg(u), then four zeros."""
     row_off = np.asarray(row_off, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     n = len(row_off) - 1
@@ -74,16 +73,10 @@ def features(row_off, col, d=0.85):
     indeg = np.bincount(col, minlength=n).astype(np.float64)
     s1 = np.zeros(n)
     np.add.at(s1, col, 1.0 / od[src])
-    s2 = np.zeros(n)
-    np.add.at(s2, col, np.log1p(indeg[src]))
-    s3 = np.zeros(n)
-    np.add.at(s3, col, np.log1p(od[src]))
     fd = float((od == 0).sum()) / n
     X = np.zeros((n, F))
     X[:, 0] = np.log1p(indeg)
     X[:, 1] = np.log1p(od)
     X[:, 2] = (od == 0)
     X[:, 3] = np.log((1 - d) + d * (s1 + fd))
-    X[:, 4] = s2 / np.maximum(indeg, 1)
-    X[:, 5] = s3 / np.maximum(indeg, 1)
     return X

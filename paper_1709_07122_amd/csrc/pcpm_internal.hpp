@@ -200,9 +200,11 @@ struct pcpm_png {
   int32_t* ppr_seed_off = nullptr;
   int64_t ppr_off_cap = 0;
 
-  // warm start: per-node structure sums (in-degree, s1, s2, s3), computed once
-  float* ws_struct = nullptr;            // n * 4
-  double ws_struct_ms = 0.0;
+  // warm start: in-degrees (computed once per handle) and two rank vectors
+  // for the first iterate from the uniform start
+  uint32_t* ws_indeg = nullptr;          // n
+  float* ws_x = nullptr;                 // 2n
+  double ws_indeg_ms = 0.0;
 
   std::vector<std::pair<void*, size_t>> allocations;
 };
@@ -229,6 +231,4 @@ pcpm_status_t dalloc(pcpm_png* g, T** p, int64_t count) {
 void dfree(pcpm_png* g, void* p);
 void free_handle(pcpm_png* g);
 pcpm_status_t set_lds_limits();
-// sum over in-edges of x(u, j) / outdeg(u) for nvec columns ([n][nvec] device arrays)
-pcpm_status_t raw_spmv(pcpm_png* g, int nvec, const float* x, float* out, int fx_shift, hipStream_t st);
 }  // namespace pcpm

@@ -432,76 +432,6 @@ static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_i
   return PCPM_OK;
 }
 
-// Column copies between an [n][nvec] array and the tile's [n][KT] layout.
-__global__ __launch_bounds__(256) void k_cols_in(float* __restrict__ xt, const float* __restrict__ x, int64_t n,
-                                                 int nvec, int first, int kv, int kt) {
-  const int64_t total = n * kt;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t v = i / kt;
-    const int j = static_cast<int>(i - v * kt);
-    xt[i] = j < kv ? x[v * nvec + first + j] : 0.0f;
-  }
-}
-
-__global__ void k_raw_ctl(Ctl* ctl, VCtl* vctl, int kt, int fx_shift) {
-  if (threadIdx.x == 0) {
-    ctl->res = 0.0;
-    ctl->res_prev = 0.0;
-    ctl->tol = 0.0;
-    ctl->d = 1.0;
-    ctl->iter = 0;
-    ctl->done = 0;
-    ctl->nonfinite = 0;
-    ctl->fx_shift = fx_shift;
-    ctl->ngroups = 1;
-  }
-  if (static_cast<int>(threadIdx.x) < kt) {
-    VCtl& vc = vctl[threadIdx.x];
-    vc.coef = 0.0;
-    vc.inv_s = 0.0;
-    vc.dmass = 0.0;
-    vc.res = 0.0;
-    vc.iter = 0;
-    vc.done = 0;
-  }
-}
-
-// out(v, j) = sum over in-edges u -> v of x(u, j) / outdeg(u), for nvec
-// columns: one scatter + gather of the batched kernels with d = 1 and no
-// jump.  fx_shift must bound every column's L1 mass (2^-fx_shift units).
-template <int KT>
-static pcpm_status_t raw_spmv_kt(pcpm_png* g, int nvec, const float* x, float* out, int fx_shift, hipStream_t st) {
-  PCPM_TRY(ppr_set_lds<KT>(g->part_log2));
-  const int64_t n = g->n;
-  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((n * KT + 255) / 256, 8192));
-  PCPM_TRY_HIP(hipMemsetAsync(g->ppr_mask, 0, static_cast<size_t>(n) * 4, st));
-  PCPM_TRY_HIP(hipMemsetAsync(g->ppr_red, 0, static_cast<size_t>((g->k + g->n_mg) * KT * 2) * 8, st));
-  for (int first = 0; first < nvec; first += KT) {
-    const int kv = std::min(KT, nvec - first);
-    PCPM_LAUNCH("pcpm_spmv", k_cols_in, dim3(blocks), dim3(256), 0, st, g->ppr_x[0], x, n, nvec, first, kv, KT);
-    PCPM_LAUNCH("pcpm_spmv", k_raw_ctl, dim3(1), dim3(64), 0, st, g->ctl, g->ppr_vctl, KT, fx_shift);
-    PCPM_TRY(ppr_iteration<KT>(g, g->ppr_x[0], g->ppr_x[1], st));
-    PCPM_LAUNCH("pcpm_spmv", k_ppr_store, dim3(blocks), dim3(256), 0, st, out, g->ppr_x[1], n, nvec, first, kv, KT);
-  }
-  return PCPM_OK;
-}
-
-pcpm_status_t raw_spmv(pcpm_png* g, int nvec, const float* x, float* out, int fx_shift, hipStream_t st) {
-  if (g->ngroups != 1) return set_error(PCPM_ERR_INVALID_ARG, "needs a single-graph handle");
-  const int kt_max = std::max(1, std::min(16, (1 << kMaxLog2) >> g->part_log2));
-  int kt = 1;
-  while (kt < nvec && kt < kt_max) kt <<= 1;
-  PCPM_TRY(ppr_alloc(g, kt, 1, 1, st));
-  switch (g->ppr_kt >= kt ? kt : g->ppr_kt) {
-    case 1: return raw_spmv_kt<1>(g, nvec, x, out, fx_shift, st);
-    case 2: return raw_spmv_kt<2>(g, nvec, x, out, fx_shift, st);
-    case 4: return raw_spmv_kt<4>(g, nvec, x, out, fx_shift, st);
-    case 8: return raw_spmv_kt<8>(g, nvec, x, out, fx_shift, st);
-    default: return raw_spmv_kt<16>(g, nvec, x, out, fx_shift, st);
-  }
-}
-
 static pcpm_status_t check_device_ppr(pcpm_png* g) {
   int dev = -1;
   PCPM_TRY_HIP(hipGetDevice(&dev));

@@ -2,16 +2,14 @@
 // ReLU) that predicts log(n * PR*(v)), its BF16/FP32 training kernels, and the
 // normalisation of the prediction into a start vector.
 //
-// Features (all functions of the graph and d only, so they are computed once
-// per handle, like the PNG):
+// Features:
 //   0 log1p(indeg)   1 log1p(outdeg)   2 dangling flag
 //   3 log(n * PR_1(v)) = log((1-d) + d * (s1(v) + n_dangling/n)), the first
-//     iterate from the uniform vector, s1(v) = sum_{u->v} 1/outdeg(u)
-//   4 s2(v)/max(indeg,1), s2 = sum_{u->v} log1p(indeg(u))
-//   5 s3(v)/max(indeg,1), s3 = sum_{u->v} log1p(outdeg(u))
-//   6, 7 zero padding
-// The sums are two passes of the batched scatter/gather (two right-hand
-// sides each).
+//     iterate of Eq. 1 from the uniform vector; s1(v) = sum_{u->v} 1/outdeg(u)
+//     is the one-SpMV aggregate of the in-neighbours' degrees
+//   4..7 zero padding (the MFMA K-block is 8 wide)
+// In-degrees are counted once per handle from the destination-ID bins; the
+// first iterate is one PCPM iteration (scatter + gather + apply).
 //
 // Parameters (FP32 master copy, 4801 floats): W1[64][8], b1[64], W2[64][64],
 // b2[64], w3[64], b3.  Compute is BF16 x BF16 -> FP32: weights, features and
@@ -41,55 +39,64 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 }
 __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(static_cast<uint32_t>(bf16_bits(f)) << 16); }
 
-// ---- structure sums and features --------------------------------------------------
-__global__ __launch_bounds__(256) void k_ws_pass_a(float* __restrict__ x, const int32_t* __restrict__ outdeg,
-                                                   int64_t n) {
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    x[2 * v] = static_cast<float>(outdeg[v]);  // / outdeg in the scatter: 1 per in-edge
-    x[2 * v + 1] = 1.0f;                         // 1/outdeg(u) per in-edge
+// ---- features -------------------------------------------------------------------
+// In-degrees: one workgroup per gather item counts the destination IDs of its
+// range of a bin in an LDS slice of 32-bit counters, then adds the nonzero
+// counts to the global array (the items of a split bin share nodes).
+constexpr int kCountBlock = 512;
+
+__global__ __launch_bounds__(kCountBlock) void k_ws_count(int64_t n, int s, const Item* __restrict__ items,
+                                                         const uint32_t* __restrict__ did,
+                                                         uint32_t* __restrict__ indeg) {
+  extern __shared__ uint32_t cnt[];
+  const Item it = items[blockIdx.x];
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = static_cast<int64_t>(it.part) << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  const uint32_t qmask = static_cast<uint32_t>(q - 1);  // also drops the message flag
+  for (int i = threadIdx.x; i < qn; i += kCountBlock) cnt[i] = 0u;
+  __syncthreads();
+  constexpr int kU = 4;
+  const int64_t lo = it.lo, hi = it.hi;
+  for (int64_t e = lo + threadIdx.x; e < hi; e += kU * kCountBlock) {
+    uint32_t x[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) x[u] = did[min(e + u * kCountBlock, hi - 1)];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (e + u * kCountBlock < hi) atomicAdd(&cnt[x[u] & qmask], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < qn; i += kCountBlock) {
+    const uint32_t c = cnt[i];
+    if (c) atomicAdd(&indeg[v0 + i], c);
   }
 }
 
-__global__ __launch_bounds__(256) void k_ws_pass_b(float* __restrict__ x, const float* __restrict__ sums_a,
-                                                   const int32_t* __restrict__ outdeg, int64_t n) {
+__global__ __launch_bounds__(256) void k_ws_prep(uint32_t* __restrict__ indeg, float* __restrict__ x0, int64_t n,
+                                                 float uni) {
   for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
        v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const float od = static_cast<float>(outdeg[v]);
-    x[2 * v] = log1pf(sums_a[2 * v]) * od;
-    x[2 * v + 1] = log1pf(od) * od;
+    if (indeg) indeg[v] = 0u;
+    x0[v] = uni;
   }
 }
 
-__global__ __launch_bounds__(256) void k_ws_struct(float* __restrict__ st, const float* __restrict__ a,
-                                                   const float* __restrict__ b, int64_t n) {
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    st[4 * v] = a[2 * v];
-    st[4 * v + 1] = a[2 * v + 1];
-    st[4 * v + 2] = b[2 * v];
-    st[4 * v + 3] = b[2 * v + 1];
-  }
-}
-
-__global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, const float* __restrict__ st,
+__global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, const uint32_t* __restrict__ indeg,
                                                      const int32_t* __restrict__ outdeg,
-                                                     const uint32_t* __restrict__ dmask, int64_t n, double d,
-                                                     double frac_dangling) {
+                                                     const uint32_t* __restrict__ dmask,
+                                                     const float* __restrict__ pr1, int64_t n) {
+  const double dn = static_cast<double>(n);
   for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
        v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const float indeg = st[4 * v];
-    const float od = static_cast<float>(outdeg[v]);
-    const float inv = 1.0f / fmaxf(indeg, 1.0f);
-    float* f = feat + kF * v;
-    f[0] = log1pf(indeg);
-    f[1] = log1pf(od);
-    f[2] = static_cast<float>((dmask[v >> 5] >> (v & 31)) & 1u);
-    f[3] = static_cast<float>(log((1.0 - d) + d * (static_cast<double>(st[4 * v + 1]) + frac_dangling)));
-    f[4] = st[4 * v + 2] * inv;
-    f[5] = st[4 * v + 3] * inv;
-    f[6] = 0.0f;
-    f[7] = 0.0f;
+    float4 f;
+    f.x = log1pf(static_cast<float>(indeg[v]));
+    f.y = log1pf(static_cast<float>(outdeg[v]));
+    f.z = static_cast<float>((dmask[v >> 5] >> (v & 31)) & 1u);
+    f.w = static_cast<float>(log(static_cast<double>(pr1[v]) * dn));
+    float4* out = reinterpret_cast<float4*>(feat + kF * v);
+    out[0] = f;
+    out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
 }
 
@@ -377,40 +384,27 @@ __global__ __launch_bounds__(256) void k_ws_targets(const float* __restrict__ pr
 
 static unsigned grid_for(int64_t n) { return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192))); }
 
-static int ceil_log2(double x) {
-  int e = 0;
-  while (std::ldexp(1.0, e) < x) ++e;
-  return e;
-}
-
-// Structure sums of a handle (computed on first use).
-static pcpm_status_t ws_structure(pcpm_png* g, hipStream_t st) {
-  if (g->ws_struct) return PCPM_OK;
-  const auto t0 = std::chrono::steady_clock::now();
+// In-degrees of a handle (counted on first use) and the rank buffers.
+static pcpm_status_t ws_prepare(pcpm_png* g, hipStream_t st) {
   const int64_t n = g->n;
-  float *xa, *sa, *xb, *sb;
-  PCPM_TRY(dalloc(g, &xa, 2 * n));
-  PCPM_TRY(dalloc(g, &sa, 2 * n));
-  PCPM_TRY(dalloc(g, &xb, 2 * n));
-  PCPM_TRY(dalloc(g, &sb, 2 * n));
-  // column masses bound the sums: pass A sum_u outdeg(u) = m and n; pass B at
-  // most log1p(2^31) * m
-  const double mass_a = std::max<double>(1.0, std::max<double>(g->m, g->n));
-  const double mass_b = std::max<double>(1.0, 22.0 * std::max<double>(g->m, 1));
-  PCPM_LAUNCH("pcpm_ws_features", k_ws_pass_a, dim3(grid_for(n)), dim3(256), 0, st, xa, g->outdeg, n);
-  PCPM_TRY(raw_spmv(g, 2, xa, sa, 50 - ceil_log2(mass_a), st));
-  PCPM_LAUNCH("pcpm_ws_features", k_ws_pass_b, dim3(grid_for(n)), dim3(256), 0, st, xb, sa, g->outdeg, n);
-  PCPM_TRY(raw_spmv(g, 2, xb, sb, 50 - ceil_log2(mass_b), st));
-  float* ws = nullptr;
-  PCPM_TRY(dalloc(g, &ws, 4 * n));
-  PCPM_LAUNCH("pcpm_ws_features", k_ws_struct, dim3(grid_for(n)), dim3(256), 0, st, ws, sa, sb, n);
+  if (!g->ws_x) PCPM_TRY(dalloc(g, &g->ws_x, 2 * n));
+  if (g->ws_indeg) return PCPM_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  uint32_t* indeg = nullptr;
+  PCPM_TRY(dalloc(g, &indeg, n));
+  static bool lds_set = false;
+  if (!lds_set) {
+    PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ws_count),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 4));
+    lds_set = true;
+  }
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, indeg, g->ws_x, n, 0.0f);
+  if (g->n_ga)
+    PCPM_LAUNCH("pcpm_ws_features", k_ws_count, dim3(static_cast<unsigned>(g->n_ga)), dim3(kCountBlock),
+                static_cast<size_t>(g->q) * 4, st, n, g->part_log2, g->ga_items, g->did, indeg);
   PCPM_TRY_HIP(hipStreamSynchronize(st));
-  dfree(g, xa);
-  dfree(g, sa);
-  dfree(g, xb);
-  dfree(g, sb);
-  g->ws_struct = ws;
-  g->ws_struct_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  g->ws_indeg = indeg;
+  g->ws_indeg_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return PCPM_OK;
 }
 
@@ -435,11 +429,14 @@ pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* firs
   if (g->ngroups != 1) return set_error(PCPM_ERR_INVALID_ARG, "warm start needs a single-graph handle");
   PCPM_TRY(ws_check_device_ptr(feat, "feat"));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  PCPM_TRY(ws_structure(g, st));
-  if (first_call_ms) *first_call_ms = g->ws_struct_ms;
-  const double fd = static_cast<double>(g->n_dangling) / static_cast<double>(g->n);
-  PCPM_LAUNCH("pcpm_ws_features", k_ws_features, dim3(grid_for(g->n)), dim3(256), 0, st, feat, g->ws_struct,
-              g->outdeg, g->dmask, g->n, d, fd);
+  PCPM_TRY(ws_prepare(g, st));
+  if (first_call_ms) *first_call_ms = g->ws_indeg_ms;
+  const int64_t n = g->n;
+  const float uni = static_cast<float>(1.0 / static_cast<double>(n));
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, nullptr, g->ws_x, n, uni);
+  PCPM_TRY(pcpm_iterate(g, d, g->ws_x, g->ws_x + n, nullptr, stream));
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_features, dim3(grid_for(n)), dim3(256), 0, st, feat, g->ws_indeg, g->outdeg,
+              g->dmask, g->ws_x + n, n);
   return PCPM_OK;
 }
 

@@ -33,11 +33,12 @@ DEFAULT_WEIGHTS = os.path.join(HERE, "data", "ws_mlp_rmat.npy")
 
 
 def init_params(seed: int = 0) -> np.ndarray:
-    """He-style initialisation; the two padding feature columns of W1 stay 0."""
+    """He-style initialisation; the columns of W1 that see the four padding
+    features stay 0."""
     rng = np.random.default_rng(seed)
     F, H = P.WS_FEATURES, P.WS_HIDDEN
-    W1 = rng.normal(0, np.sqrt(2.0 / 6), (H, F))
-    W1[:, 6:] = 0.0
+    W1 = rng.normal(0, np.sqrt(2.0 / 4), (H, F))
+    W1[:, 4:] = 0.0
     W2 = rng.normal(0, np.sqrt(2.0 / H), (H, H))
     w3 = rng.normal(0, np.sqrt(1.0 / H), H)
     p = np.concatenate([W1.reshape(-1), np.zeros(H), W2.reshape(-1), np.zeros(H), w3, np.zeros(1)])

@@ -63,4 +63,4 @@ def test_features_from_definitions():
     np.testing.assert_allclose(X[:, 3], np.log(n * pr1), rtol=1e-12, atol=1e-12)
     assert X[:, 2].sum() == (np.diff(r) == 0).sum()
     np.testing.assert_allclose(np.expm1(X[:, 0]).sum(), len(c))
-    assert np.all(X[:, 6:] == 0)
+    assert np.all(X[:, 4:] == 0)
