@@ -9,6 +9,12 @@ A step is one solve from the uniform vector; the graph and its partition-node
 graph are resident in HBM before the timed region starts.  The same graph with
 in-degree-sorted labels is measured as well and reported under "indegree".
 
+Further legs (in "detail"): the learned warm start against the uniform start
+on the main graph (network weights shipped with the package, trained on other
+RMAT graphs), batched personalised PageRank on RMAT-22 with 8/32/64 seed sets
+against one vector at a time, and 16 RMAT graphs of uneven size in one handle
+against one handle per graph.
+
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -91,6 +97,116 @@ def measure(P, torch, r, c, args, label):
     return result, out.cpu().numpy(), png
 
 
+def warm_detail(P, torch, png, args):
+    """Time to tol from the uniform start and from the learned start (the
+    committed network), on the graph of the main measurement."""
+    from paper_1709_07122_amd import warmstart as ws
+
+    params = ws.load(ws.DEFAULT_WEIGHTS)
+    res = ws.compare(png, params, d=args.d, tol=args.tol, reps=max(1, args.steps))
+    log(f"[warm] cold {res['cold_iters']} iters {res['cold_ms']:.2f} ms; warm {res['warm_iters']} iters "
+        f"{res['warm_ms']:.2f} ms ({res['warm_ms_first']:.2f} ms with the in-degree count)")
+    return res
+
+
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3, out
+
+
+def ppr_detail(P, torch, args):
+    """Batched personalised PageRank on RMAT-22 (EF 16, random labels) with
+    k = 8, 32, 64 seed sets of 1-100 nodes, partition size from the autotuner,
+    against the same k vectors solved one at a time."""
+    import numpy as np
+
+    import graphgen
+    from paper_1709_07122_amd import autotune
+
+    r, c = graphgen.rmat(22, 16, seed=args.ppr_seed, relabel="random")
+    n, m = len(r) - 1, len(c)
+    rt, ct = torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()
+    one = autotune.tune(rt, ct, vectors=1, cache=None)
+    png1 = P.build_png(rt, ct, part_log2=one.part_log2)
+    rows = []
+    for k in (8, 32, 64):
+        tune = autotune.tune(rt, ct, vectors=k, cache=None)
+        png = P.build_png(rt, ct, part_log2=tune.part_log2)
+        off, seeds = graphgen.seed_sets(n, k, seed=k)
+        reps = max(1, args.steps // 2)
+        b_ms, res = _timed(torch, lambda: P.ppr_batch(png, off, seeds, tol=args.tol, max_iters=args.max_iters), reps)
+        singles = [(np.array([0, off[j + 1] - off[j]], np.int32), seeds[off[j]:off[j + 1]]) for j in range(k)]
+
+        def one_by_one():
+            return [P.ppr_batch(png1, o, s, tol=args.tol, max_iters=args.max_iters) for o, s in singles]
+
+        s_ms, sres = _timed(torch, one_by_one, 1)
+        vec_iters = int(res.iters.sum())
+        rows.append({"k": k, "part_log2": tune.part_log2, "tile_width": tune.tile_width, "batched_ms": b_ms,
+                     "one_at_a_time_ms": s_ms, "one_at_a_time_part_log2": one.part_log2,
+                     "speedup": s_ms / b_ms, "iters_mean": float(res.iters.mean()), "iters_max": int(res.iters.max()),
+                     "converged": bool(res.converged), "vector_gteps": m * vec_iters / (b_ms * 1e-3) / 1e9,
+                     "single_iters_mean": float(np.mean([x.iters[0] for x in sres]))})
+        log(f"[ppr] k={k} q=2^{tune.part_log2} width {tune.tile_width}: {b_ms:.2f} ms batched vs {s_ms:.2f} ms one at "
+            f"a time ({s_ms / b_ms:.2f}x), {rows[-1]['vector_gteps']:.1f} vector-GTEPS")
+        png.close()
+    png1.close()
+    return {"graph": f"RMAT-22 EF16 seed {args.ppr_seed} random labels", "n": n, "m": m, "tol": args.tol, "rows": rows}
+
+
+def multigraph_detail(P, torch, args):
+    """16 RMAT graphs (scale 14-20, edge factor 8-32, seeds 100-115, both
+    extremes present) solved to tol in one handle, against one handle per
+    graph solved in turn; the partition size is the fastest of 2^12..2^14."""
+    import numpy as np
+
+    import graphgen
+
+    rng = np.random.default_rng(100)
+    scales = rng.integers(14, 21, 16)
+    efs = rng.integers(8, 33, 16)
+    scales[0], efs[0], scales[-1], efs[-1] = 14, 8, 20, 32
+    graphs = [graphgen.rmat(int(sc), int(ef), seed=100 + i, relabel="random") for i, (sc, ef) in
+              enumerate(zip(scales, efs))]
+    m_tot = sum(len(c) for _, c in graphs)
+    best = None
+    for pl in (12, 13, 14):
+        r, c, off, sizes = P.union_csr(graphs, pl)
+        png = P.build_png(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), part_log2=pl,
+                          graph_node_off=off, graph_nodes=sizes)
+        ms, _ = _timed(torch, lambda: P.pagerank(png, tol=0.0, max_iters=6, want_hist=False), 2)
+        if best is None or ms < best[1]:
+            if best is not None:
+                best[2].close()
+            best = (pl, ms, png)
+        else:
+            png.close()
+    pl, _, png = best
+    reps = max(1, args.steps // 2)
+    u_ms, res = _timed(torch, lambda: P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters,
+                                                 want_hist=False), reps)
+    it, resid = png.graph_results()
+    png.close()
+    singles = [P.build_png(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), part_log2=pl) for r, c in graphs]
+    s_ms, sres = _timed(torch, lambda: [P.pagerank(g, d=args.d, tol=args.tol, max_iters=args.max_iters,
+                                                   want_hist=False) for g in singles], reps)
+    for g in singles:
+        g.close()
+    edge_iters = sum(len(c) * int(i) for (_, c), i in zip(graphs, it))
+    out = {"graphs": [{"scale": int(sc), "edge_factor": int(ef), "n": len(r) - 1, "m": len(c), "iters": int(i)}
+                      for (r, c), sc, ef, i in zip(graphs, scales, efs, it)],
+           "part_log2": pl, "m_total": m_tot, "one_handle_ms": u_ms, "one_handle_per_graph_ms": s_ms,
+           "speedup": s_ms / u_ms, "gteps": edge_iters / (u_ms * 1e-3) / 1e9, "all_converged": bool(np.all(resid < args.tol))}
+    log(f"[multi] 16 graphs, m={m_tot}, q=2^{pl}: {u_ms:.2f} ms in one handle vs {s_ms:.2f} ms one by one "
+        f"({s_ms / u_ms:.2f}x), {out['gteps']:.1f} GTEPS")
+    return out
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
@@ -139,6 +255,9 @@ def main():
     ap.add_argument("--max-iters", type=int, default=200)
     ap.add_argument("--no-indegree", action="store_true", help="skip the in-degree-sorted labelling")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the personalised and multi-graph legs")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start leg")
+    ap.add_argument("--ppr-seed", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -169,9 +288,12 @@ def main():
     log(f"generated RMAT-{args.scale} EF{args.edge_factor}: n={n} m={len(c)} in {time.perf_counter() - t:.1f} s")
 
     main_res, x_gpu, png = measure(P, torch, r, c, args, "random")
-    png.close()
-
     detail = {"random": main_res}
+    warm = None
+    if not args.no_warm:
+        warm = warm_detail(P, torch, png, args)
+        detail["warm_start"] = warm
+    png.close()
     if not args.no_indegree:
         ri, ci = graphgen.apply_labels(raw_r, raw_c, graphgen.indegree_labels(raw_r, raw_c))
         ind_res, _, png_i = measure(P, torch, ri, ci, args, "indegree")
@@ -179,6 +301,10 @@ def main():
         detail["indegree"] = ind_res
         del ri, ci
     del raw_r, raw_c
+
+    if not args.no_batched:
+        detail["ppr"] = ppr_detail(P, torch, args)
+        detail["multigraph"] = multigraph_detail(P, torch, args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -228,6 +354,11 @@ def main():
             "bytes_per_launch": main_res["gather_bytes"], "avg_launch_ms": g["avg_ms"],
         },
         "cpu_baseline": cpu,
+        "hbm_gbs_algorithmic": round(main_res["hbm_gbs_alg"], 1),
+        "time_to_tol_ms": None if warm is None else {
+            "cold": round(warm["cold_ms"], 3), "warm": round(warm["warm_ms"], 3),
+            "warm_incl_indegree_count": round(warm["warm_ms_first"], 3),
+            "cold_iters": warm["cold_iters"], "warm_iters": warm["warm_iters"]},
         "detail": detail,
     }
     print(json.dumps(line, default=lambda o: None if isinstance(o, float) and math.isnan(o) else o))

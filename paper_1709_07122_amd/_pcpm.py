@@ -348,7 +348,7 @@ def union_csr(graphs, part_log2: int):
 
 def ws_features(png: PNG, d: float = 0.85, stream=None):
     """[n][8] float32 features of every node (pcpm_ws_features); returns
-    (features, ms spent on the per-handle graph sums by the first call)."""
+    (features, ms of the per-handle in-degree count done by the first call)."""
     import torch
     feat = torch.empty((png.n, WS_FEATURES), dtype=torch.float32, device=png.row_off.device)
     ms = ctypes.c_double(0.0)

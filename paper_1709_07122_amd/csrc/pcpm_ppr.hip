@@ -19,7 +19,8 @@
 
 namespace pcpm {
 
-constexpr int kPprBlock = 512;
+constexpr int kPprBlock = 512;         // scatter and merge workgroups
+constexpr int kPprGatherBlock = 1024;  // gather workgroups (a 128 KB slice leaves room for one per CU)
 
 template <int KT>
 __device__ __forceinline__ void copy_kt(float* __restrict__ dst, const float* __restrict__ src) {
@@ -33,6 +34,12 @@ __device__ __forceinline__ void copy_kt(float* __restrict__ dst, const float* __
   }
 }
 
+// Scatter (Alg. 3) for a tile of KT vectors: the source partition's scaled
+// values x(u, j)/outdeg(u) are staged in LDS ([q][KT]); every PNG edge copies
+// its node's KT values to its update slot.  Tiles of 1024 PNG edges are
+// decoded with a ballot per 64 entries; the next tile's source IDs are loaded
+// while this one is written.  Entries of edge tiles outside [lo, hi) write
+// to the spare slot E'.
 template <int KT>
 __global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                            const Item* __restrict__ items, const float* __restrict__ x,
@@ -55,26 +62,57 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict
   const uint32_t qmask = (1u << s) - 1u;
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
-  for (int64_t t = lo / kTile + threadIdx.x / kWave; t < t_end; t += kPprBlock / kWave) {
+  constexpr int kNW = kPprBlock / kWave;
+  uint32_t xs[kSub], xn[kSub];
+  int64_t t = lo / kTile + threadIdx.x / kWave;
+  if (t < t_end) {
+    const uint32_t* pt = png_src + t * kTile;
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) xs[j] = pt[j * kWave + lane];
+  }
+  for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    int32_t run = png_blk[t];
-    for (int j = 0; j < kSub; ++j) {
-      const int64_t e = tb + j * kWave + lane;
-      const uint32_t xv = png_src[e];
-      const bool f = static_cast<int32_t>(xv) < 0;
-      const uint64_t bal = wave_ballot(f);
-      const int32_t seg = run + lanes_below(bal) + (f ? 0 : -1);
-      run += __popcll(bal);
-      const bool in = e >= lo && e < hi;
-      const int64_t slot = in ? e + seg_delta[seg] : spare;
-      copy_kt<KT>(upd + slot * KT, spr + (xv & qmask) * KT);
+    if (t + kNW < t_end) {
+      const uint32_t* pt = png_src + (t + kNW) * kTile;
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) xn[j] = pt[j * kWave + lane];
     }
+    // every entry of a tile has a valid segment (entry 0 is flagged and
+    // padding follows the last segment): no predicate on these loads
+    int32_t run = png_blk[t];
+    int32_t seg[kSub];
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) {
+      const bool f = static_cast<int32_t>(xs[j]) < 0;
+      const uint64_t bal = wave_ballot(f);
+      seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
+      run += __popcll(bal);
+    }
+    int32_t dl[kSub];
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
+    if (tb >= lo && tb + kTile <= hi) {
+      float* ut = upd + tb * KT;
+#pragma unroll
+      for (int j = 0; j < kSub; ++j)
+        copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane + dl[j]) * KT, spr + (xs[j] & qmask) * KT);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) {
+        const int64_t e = tb + j * kWave + lane;
+        const bool in = e >= lo && e < hi;
+        copy_kt<KT>(upd + (in ? e + dl[j] : spare) * KT, spr + (xs[j] & qmask) * KT);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) xs[j] = xn[j];
   }
 }
 
 // Apply for nodes n0..n1-1 of a destination partition and all KT vectors:
 //   x'(v, j) = d * acc(v, j) + [v in S_j] * ((1-d) + d*D_j)/|S_j|
 // and each vector's share of the residual and of the next dangling mass.
+// Thread i serves vector i % KT; kU nodes per step, loads first.
 template <int KT, int BS, class AccFn>
 __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCtl* __restrict__ vctl, int64_t v0,
                                           int n0, int n1, AccFn acc, const float* __restrict__ x_in,
@@ -87,16 +125,31 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
   const double d = ctl->d;
   const double unit = ldexp(1.0, -ctl->fx_shift);
   double r = 0.0, dm = 0.0;
-  for (int node = n0 + static_cast<int>(threadIdx.x) / KT; node < n1; node += BS / KT) {
-    const int64_t v = v0 + node;
-    const int64_t idx = v * KT + kk;
-    const float xo = x_in[idx];
-    const bool seed = (seedmask[v] >> kk) & 1u;
-    const double a = static_cast<double>(acc(node * KT + kk)) * unit;
-    const float xn = frozen ? xo : static_cast<float>(fma(d, a, seed ? coef : 0.0));
-    r += fabs(static_cast<double>(xn) - static_cast<double>(xo));
-    if ((dmask[v >> 5] >> (v & 31)) & 1u) dm += static_cast<double>(xn);
-    x_out[idx] = xn;
+  constexpr int kU = 4;
+  constexpr int kStep = BS / KT;
+  for (int node = n0 + static_cast<int>(threadIdx.x) / KT; node < n1; node += kU * kStep) {
+    float xo[kU];
+    uint32_t sm[kU], dw[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t v = v0 + min(node + u * kStep, n1 - 1);
+      xo[u] = x_in[v * KT + kk];
+      sm[u] = seedmask[v];
+      dw[u] = dmask[v >> 5];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int nd = node + u * kStep;
+      if (nd < n1) {
+        const int64_t v = v0 + nd;
+        const bool seed = (sm[u] >> kk) & 1u;
+        const double a = static_cast<double>(acc(nd * KT + kk)) * unit;
+        const float xn = frozen ? xo[u] : static_cast<float>(fma(d, a, seed ? coef : 0.0));
+        r += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
+        if ((dw[u] >> (v & 31)) & 1u) dm += static_cast<double>(xn);
+        x_out[v * KT + kk] = xn;
+      }
+    }
   }
   // lanes of one vector are those congruent to kk modulo KT
 #pragma unroll
@@ -122,57 +175,103 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
   }
 }
 
+// Gather (Alg. 5) for a tile of KT vectors: each destination ID is decoded
+// once (its update is the one of the message it belongs to: flags so far,
+// inclusive, minus one) and adds KT fixed-point values to the LDS slice
+// ([q][KT] 64-bit sums).  The next tile's IDs are loaded while this one is
+// accumulated; the update values of kG sub-blocks are in flight together.
 template <int KT>
-__global__ __launch_bounds__(kPprBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
-                                                          const Item* __restrict__ items,
-                                                          const uint32_t* __restrict__ did,
-                                                          const int32_t* __restrict__ did_blk,
-                                                          const float* __restrict__ upd,
-                                                          const float* __restrict__ x_in, float* __restrict__ x_out,
-                                                          const uint32_t* __restrict__ dmask,
-                                                          const uint32_t* __restrict__ seedmask,
-                                                          int64_t* __restrict__ partial, double* __restrict__ red,
-                                                          const VCtl* __restrict__ vctl) {
+__global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                                const Item* __restrict__ items,
+                                                                const uint32_t* __restrict__ did,
+                                                                const int32_t* __restrict__ did_blk,
+                                                                const float* __restrict__ upd,
+                                                                const float* __restrict__ x_in,
+                                                                float* __restrict__ x_out,
+                                                                const uint32_t* __restrict__ dmask,
+                                                                const uint32_t* __restrict__ seedmask,
+                                                                int64_t* __restrict__ partial,
+                                                                double* __restrict__ red,
+                                                                const VCtl* __restrict__ vctl) {
   if (ctl->done) return;
+  constexpr int BS = kPprGatherBlock;
   extern __shared__ unsigned long long acc[];  // q * KT fixed-point sums
   const Item it = items[blockIdx.x];
   const int64_t q = int64_t{1} << s;
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
   const FixedConv to_fixed(ctl->fx_shift);
-  for (int i = threadIdx.x; i < qn * KT; i += kPprBlock) acc[i] = 0ull;
+  for (int i = threadIdx.x; i < qn * KT; i += BS) acc[i] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t qmask = static_cast<uint32_t>(q - 1);
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
-  for (int64_t t = lo / kTile + threadIdx.x / kWave; t < t_end; t += kPprBlock / kWave) {
-    const int64_t tb = t * kTile;
-    int32_t run = did_blk[t];
-    for (int j = 0; j < kSub; ++j) {
-      const int64_t e = tb + j * kWave + lane;
-      const uint32_t xv = did[e];
-      const bool f = static_cast<int32_t>(xv) < 0;
-      const uint64_t bal = wave_ballot(f);
-      const int32_t ui = run + lanes_below(bal) + (f ? 0 : -1);  // Alg. 5 update pointer
-      run += __popcll(bal);
-      const bool in = e >= lo && e < hi;
-      float vals[KT];
-      copy_kt<KT>(vals, upd + static_cast<int64_t>(ui) * KT);
-      const uint32_t li = in ? (xv & qmask) : 0u;
+  constexpr int kNW = BS / kWave;
+  constexpr int kG = KT >= 16 ? 2 : (KT >= 8 ? 4 : (KT >= 4 ? 8 : 16));
+  uint32_t xs[kSub], xn[kSub];
+  int64_t t = lo / kTile + threadIdx.x / kWave;
+  if (t < t_end) {
+    const uint32_t* dt = did + t * kTile;
 #pragma unroll
-      for (int c = 0; c < KT; ++c)
-        atomicAdd(&acc[li * KT + c], static_cast<unsigned long long>(in ? to_fixed(vals[c]) : 0));
+    for (int j = 0; j < kSub; ++j) xs[j] = dt[j * kWave + lane];
+  }
+  for (; t < t_end; t += kNW) {
+    const int64_t tb = t * kTile;
+    if (t + kNW < t_end) {
+      const uint32_t* dt = did + (t + kNW) * kTile;
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) xn[j] = dt[j * kWave + lane];
     }
+    // update slots of a tile lie in [did_blk[t]-1, did_blk[t+1]-1]: a per-tile
+    // base and 32-bit offsets; every entry has a valid slot (no predicate)
+    const float* ub = upd + (static_cast<int64_t>(did_blk[t]) - 1) * KT;
+    int32_t run = 0;
+    uint32_t off[kSub];
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) {
+      const bool f = static_cast<int32_t>(xs[j]) < 0;
+      const uint64_t bal = wave_ballot(f);
+      off[j] = static_cast<uint32_t>(run + lanes_below(bal) + (f ? 1 : 0)) * KT;
+      run += __popcll(bal);
+    }
+    const bool full = tb >= lo && tb + kTile <= hi;
+#pragma unroll
+    for (int g0 = 0; g0 < kSub; g0 += kG) {
+      float val[kG][KT];
+#pragma unroll
+      for (int jj = 0; jj < kG; ++jj) copy_kt<KT>(val[jj], ub + off[g0 + jj]);
+      if (full) {
+#pragma unroll
+        for (int jj = 0; jj < kG; ++jj) {
+          const uint32_t li = (xs[g0 + jj] & qmask) * KT;
+#pragma unroll
+          for (int c = 0; c < KT; ++c)
+            atomicAdd(&acc[li + c], static_cast<unsigned long long>(to_fixed(val[jj][c])));
+        }
+      } else {  // edge tile: entries outside [lo, hi) add nothing
+#pragma unroll
+        for (int jj = 0; jj < kG; ++jj) {
+          const int64_t e = tb + (g0 + jj) * kWave + lane;
+          const bool in = e >= lo && e < hi;
+          const uint32_t li = in ? (xs[g0 + jj] & qmask) * KT : 0u;
+#pragma unroll
+          for (int c = 0; c < KT; ++c)
+            atomicAdd(&acc[li + c], static_cast<unsigned long long>(in ? to_fixed(val[jj][c]) : 0));
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) xs[j] = xn[j];
   }
   __syncthreads();
   if (it.aux >= 0) {
     int64_t* dst = partial + static_cast<int64_t>(it.aux) * q * KT;
-    for (int i = threadIdx.x; i < qn * KT; i += kPprBlock) dst[i] = static_cast<int64_t>(acc[i]);
+    for (int i = threadIdx.x; i < qn * KT; i += BS) dst[i] = static_cast<int64_t>(acc[i]);
     return;
   }
-  apply_ppr<KT, kPprBlock>(ctl, vctl, v0, 0, qn, [&](int i) { return static_cast<int64_t>(acc[i]); }, x_in, x_out,
-                           dmask, seedmask, red + static_cast<int64_t>(it.part) * KT * 2);
+  apply_ppr<KT, BS>(ctl, vctl, v0, 0, qn, [&](int i) { return static_cast<int64_t>(acc[i]); }, x_in, x_out, dmask,
+                    seedmask, red + static_cast<int64_t>(it.part) * KT * 2);
 }
 
 template <int KT>
@@ -332,7 +431,7 @@ static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, hip
     PCPM_LAUNCH("pcpm_ppr_scatter", k_ppr_scatter<KT>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kPprBlock),
                 static_cast<size_t>(g->q) * KT * 4, st, g->ctl, g->n, s, g->sc_items, in, g->outdeg, g->png_src,
                 g->png_blk, g->seg_delta, g->ppr_upd, g->eprime);
-  PCPM_LAUNCH("pcpm_ppr_gather", k_ppr_gather<KT>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kPprBlock),
+  PCPM_LAUNCH("pcpm_ppr_gather", k_ppr_gather<KT>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kPprGatherBlock),
               static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->ga_items, g->did, g->did_blk, g->ppr_upd,
               in, out, g->dmask, g->ppr_mask, g->ppr_partial, g->ppr_red, g->ppr_vctl);
   if (g->n_mg)

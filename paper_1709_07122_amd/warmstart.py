@@ -84,9 +84,9 @@ def training_specs(count: int = 200, scales=(18, 22), seed0: int = 1000):
             for i in range(count)]
 
 
-def prepare(spec: GraphSpec, d=0.85, tol=1e-7, part_log2=14, keep=65536, rng=None):
+def prepare(spec: GraphSpec, d=0.85, tol=1e-7, part_log2=14, keep=0, rng=None):
     """Features and targets of one graph (device tensors), subsampled to at
-    most `keep` nodes."""
+    most `keep` nodes when keep > 0."""
     import torch
 
     r, c = spec.generate()
@@ -103,7 +103,7 @@ def prepare(spec: GraphSpec, d=0.85, tol=1e-7, part_log2=14, keep=65536, rng=Non
 
 
 def train(specs, epochs: int = 30, batch: int = 16384, lr: float = 3e-3, seed: int = 0, d: float = 0.85,
-          keep: int = 65536, log=print):
+          keep: int = 0, log=print):
     """Adam on the MSE between prediction and log(n * PR*) over all graphs'
     sampled nodes.  Returns (params tensor, history)."""
     import torch
@@ -145,7 +145,7 @@ def train(specs, epochs: int = 30, batch: int = 16384, lr: float = 3e-3, seed: i
             nb += 1
         hist.append(tot / nb)
         if log:
-            log(f"  epoch {ep + 1}/{epochs}: mse {tot / nb:.5f}")
+            log(f"  epoch {ep + 1}/{epochs}: mse {tot / nb:.5f} ({time.perf_counter() - t1:.1f} s)")
     info = {"samples": N, "graphs": len(specs), "prepare_s": t1 - t0, "train_s": time.perf_counter() - t1,
             "final_mse": hist[-1] if hist else None}
     return params, hist, info
@@ -160,11 +160,12 @@ def warm_start(png, params, d: float = 0.85):
 
 def compare(png, params, d: float = 0.85, tol: float = 1e-6, reps: int = 3):
     """Iterations and time to tol from the uniform start and from the learned
-    start; the warm time includes features (with the per-handle graph sums
-    already computed), the MLP and the normalisation."""
+    start.  The warm time covers features (one PCPM iteration and the feature
+    kernel), the MLP, the normalisation and the solve; the in-degree count,
+    done once per handle, is reported apart and added in warm_ms_first."""
     import torch
 
-    feat, struct_ms = P.ws_features(png, d)  # first call: graph sums (reported separately)
+    _, count_ms = P.ws_features(png, d)
     out = torch.empty(png.n, dtype=torch.float32, device="cuda")
 
     def cold():
@@ -190,7 +191,8 @@ def compare(png, params, d: float = 0.85, tol: float = 1e-6, reps: int = 3):
     torch.cuda.synchronize()
     warm_ms = (time.perf_counter() - t) / reps * 1e3
     return {"cold_iters": rc.iters, "warm_iters": rw.iters, "cold_ms": cold_ms, "warm_ms": warm_ms,
-            "cold_resid": rc.resid, "warm_resid": rw.resid, "fallback": fb, "graph_sums_ms": struct_ms}
+            "warm_ms_first": warm_ms + count_ms, "indeg_count_ms": count_ms, "cold_resid": rc.resid,
+            "warm_resid": rw.resid, "fallback": fb}
 
 
 def main(argv=None):
@@ -203,6 +205,7 @@ def main(argv=None):
     t.add_argument("--epochs", type=int, default=30)
     t.add_argument("--batch", type=int, default=16384)
     t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--keep", type=int, default=0, help="nodes sampled per graph (0: all)")
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
@@ -214,7 +217,7 @@ def main(argv=None):
 
     if args.cmd == "train":
         specs = training_specs(args.graphs, (args.scale_min, args.scale_max))
-        params, hist, info = train(specs, epochs=args.epochs, batch=args.batch, lr=args.lr,
+        params, hist, info = train(specs, epochs=args.epochs, batch=args.batch, lr=args.lr, keep=args.keep,
                                    log=lambda s: print(s, file=sys.stderr, flush=True))
         save(params, args.out)
         print(json.dumps({"weights": args.out, **info}))
