@@ -69,11 +69,11 @@ static inline void gg_edge(const gg_source* s, int64_t e, int64_t* u, int64_t* v
       uint64_t w = gg_draw(s->key, base + (uint64_t)(l / 2));
       for (int h = 0; h < 2 && l + h < L; ++h) {
         uint32_t r = (uint32_t)(h ? (w >> 32) : w);
-        int bu, bv;
-        if (r < s->ta) { bu = 0; bv = 0; }
-        else if (r < s->tab) { bu = 0; bv = 1; }
-        else if (r < s->tabc) { bu = 1; bv = 0; }
-        else { bu = 1; bv = 1; }
+        /* quadrant a [0,ta): (0,0); b [ta,tab): (0,1); c [tab,tabc): (1,0);
+         * d [tabc,2^32): (1,1) -- written without branches, whose outcomes
+         * are random */
+        const int bu = r >= s->tab;
+        const int bv = (r >= s->ta) ^ (r >= s->tab) ^ (r >= s->tabc);
         su = (su << 1) | (uint64_t)bu;
         sv = (sv << 1) | (uint64_t)bv;
       }
@@ -144,55 +144,106 @@ static void gg_set_threads(int nthreads) {
   if (nthreads > 0) omp_set_num_threads(nthreads);
 }
 
-/* Bucket every kept draw by its source row, then sort and dedup each row. */
+/* Bucket every kept draw by its source row, then sort and dedup each row.
+ * Draws are generated twice (the generator is counter-based): a first pass
+ * counts, per thread, the draws of each coarse bucket of rows; a second pass
+ * writes each draw as a (row, column) key to its bucket.  Each bucket is then
+ * laid out row by row with a counting sort in cache, and every row is sorted
+ * and deduplicated.  No atomics, so hub rows cause no contention. */
 static gg_state* gg_build(const gg_source* s, int nthreads) {
   gg_set_threads(nthreads);
   const int64_t n = s->n;
+  const int64_t nd = s->ndraws;
   gg_state* st = (gg_state*)calloc(1, sizeof(gg_state));
   if (!st) return NULL;
   st->n = n;
   st->nthreads = nthreads;
   st->start = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
-  int64_t* cur = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
   st->len = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
-  if (!st->start || !cur || !st->len) abort();
+  if (!st->start || !st->len) abort();
 
-#pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < s->ndraws; ++e) {
-    int64_t u, v;
-    gg_edge(s, e, &u, &v);
-    if (u == v) continue;
-    __atomic_fetch_add(&cur[u], 1, __ATOMIC_RELAXED);
+  int bshift = 0; /* rows per bucket = 2^bshift, at most 4096 buckets */
+  while ((((n - 1) >> bshift) + 1) > 4096) ++bshift;
+  const int64_t nb = n > 0 ? ((n - 1) >> bshift) + 1 : 1;
+  const int T = omp_get_max_threads();
+  int64_t* hist = (int64_t*)calloc((size_t)T * (size_t)nb + 1, sizeof(int64_t));
+  int64_t* boff = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
+  if (!hist || !boff) abort();
+
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    const int64_t e0 = nd * t / T, e1 = nd * (t + 1) / T;
+    int64_t* h = hist + (size_t)t * (size_t)nb;
+    for (int64_t e = e0; e < e1; ++e) {
+      int64_t u, v;
+      gg_edge(s, e, &u, &v);
+      if (u != v) h[u >> bshift]++;
+    }
   }
+  /* bucket-major, thread-minor exclusive offsets */
   int64_t acc = 0;
-  for (int64_t u = 0; u < n; ++u) {
-    st->start[u] = acc;
-    acc += cur[u];
-    cur[u] = st->start[u];
+  for (int64_t b = 0; b < nb; ++b) {
+    boff[b] = acc;
+    for (int t = 0; t < T; ++t) {
+      const int64_t c = hist[(size_t)t * (size_t)nb + b];
+      hist[(size_t)t * (size_t)nb + b] = acc;
+      acc += c;
+    }
   }
-  st->start[n] = acc;
+  boff[nb] = acc;
+  uint64_t* keys = (uint64_t*)malloc((size_t)(acc > 0 ? acc : 1) * sizeof(uint64_t));
   st->tmp = (int32_t*)malloc((size_t)(acc > 0 ? acc : 1) * sizeof(int32_t));
-  if (!st->tmp) abort();
+  if (!keys || !st->tmp) abort();
 
-#pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < s->ndraws; ++e) {
-    int64_t u, v;
-    gg_edge(s, e, &u, &v);
-    if (u == v) continue;
-    int64_t pos = __atomic_fetch_add(&cur[u], 1, __ATOMIC_RELAXED);
-    st->tmp[pos] = (int32_t)v;
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    const int64_t e0 = nd * t / T, e1 = nd * (t + 1) / T;
+    int64_t* cur = hist + (size_t)t * (size_t)nb;
+    for (int64_t e = e0; e < e1; ++e) {
+      int64_t u, v;
+      gg_edge(s, e, &u, &v);
+      if (u != v) keys[cur[u >> bshift]++] = ((uint64_t)u << 32) | (uint64_t)(uint32_t)v;
+    }
   }
-  free(cur);
+  free(hist);
 
   int64_t m = 0;
-#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : m)
-  for (int64_t u = 0; u < n; ++u) {
-    int32_t* row = st->tmp + st->start[u];
-    int64_t l = st->start[u + 1] - st->start[u];
-    gg_sort_i32(row, l);
-    st->len[u] = gg_unique(row, l);
-    m += st->len[u];
+  const int64_t rows_per = (int64_t)1 << bshift;
+#pragma omp parallel reduction(+ : m) num_threads(T)
+  {
+    int64_t* cnt = (int64_t*)malloc((size_t)(rows_per + 1) * sizeof(int64_t));
+    if (!cnt) abort();
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t u0 = b << bshift;
+      const int64_t nr = (u0 + rows_per <= n) ? rows_per : n - u0;
+      const int64_t k0 = boff[b], k1 = boff[b + 1];
+      memset(cnt, 0, (size_t)(nr + 1) * sizeof(int64_t));
+      for (int64_t i = k0; i < k1; ++i) cnt[(int64_t)(keys[i] >> 32) - u0 + 1]++;
+      for (int64_t r = 0; r < nr; ++r) {
+        cnt[r + 1] += cnt[r];
+        st->start[u0 + r] = k0 + cnt[r];
+      }
+      for (int64_t i = k0; i < k1; ++i) {
+        const int64_t r = (int64_t)(keys[i] >> 32) - u0;
+        st->tmp[k0 + cnt[r]++] = (int32_t)(uint32_t)keys[i];
+      }
+      for (int64_t r = 0; r < nr; ++r) {
+        const int64_t u = u0 + r;
+        const int64_t l = k0 + cnt[r] - st->start[u]; /* cnt[r] now ends row r */
+        int32_t* row = st->tmp + st->start[u];
+        gg_sort_i32(row, l);
+        st->len[u] = gg_unique(row, l);
+        m += st->len[u];
+      }
+    }
+    free(cnt);
   }
+  st->start[n] = acc;
+  free(keys);
+  free(boff);
   st->m = m;
   return st;
 }
