@@ -167,12 +167,9 @@ def multigraph_detail(P, torch, args):
 
     import graphgen
 
-    rng = np.random.default_rng(100)
-    scales = rng.integers(14, 21, 16)
-    efs = rng.integers(8, 33, 16)
-    scales[0], efs[0], scales[-1], efs[-1] = 14, 8, 20, 32
-    graphs = [graphgen.rmat(int(sc), int(ef), seed=100 + i, relabel="random") for i, (sc, ef) in
-              enumerate(zip(scales, efs))]
+    graphs, shapes = graphgen.uneven_rmat_batch(16, seed=100)
+    scales = [s for s, _ in shapes]
+    efs = [e for _, e in shapes]
     m_tot = sum(len(c) for _, c in graphs)
     best = None
     for pl in (12, 13, 14):

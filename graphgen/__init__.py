@@ -173,3 +173,18 @@ def seed_sets(n: int, k: int, seed: int, lo: int = 1, hi: int = 100):
         s = rng.choice(n, size=int(sizes[j]), replace=False)
         seeds[off[j]:off[j + 1]] = np.sort(s)
     return off.astype(np.int32), seeds
+
+
+def uneven_rmat_batch(count: int = 16, seed: int = 100, scales=(14, 20), edge_factors=(8, 32),
+                      relabel: str | None = "random"):
+    """`count` RMAT graphs of uneven size: scale and (integer) edge factor
+    drawn uniformly from the given inclusive ranges, graph i seeded seed + i;
+    the first graph takes the smallest scale and edge factor, the last the
+    largest, so both extremes are present.  Returns ([(row_off, col)], [(scale,
+    edge_factor)])."""
+    rng = np.random.default_rng(seed)
+    sc = rng.integers(scales[0], scales[1] + 1, count)
+    ef = rng.integers(edge_factors[0], edge_factors[1] + 1, count)
+    sc[0], ef[0], sc[-1], ef[-1] = scales[0], edge_factors[0], scales[1], edge_factors[1]
+    graphs = [rmat(int(s), int(e), seed=seed + i, relabel=relabel) for i, (s, e) in enumerate(zip(sc, ef))]
+    return graphs, [(int(s), int(e)) for s, e in zip(sc, ef)]

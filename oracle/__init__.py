@@ -14,6 +14,8 @@ Everything here is FP64 and follows the paper's definitions directly:
                  from the set definitions.
 * ``pcpm_iterate`` one iteration carried out over that layout (Alg. 3
                  scatter, Alg. 5 gather, Alg. 2 apply).
+* ``step_at``    one step of Eq. 1 from a given vector, at chosen nodes only
+                 (for checks on graphs too large for full runs).
 * ``mlp``        FP64 reference of the warm-start network (see ``oracle.mlp``).
 """
 from __future__ import annotations
@@ -54,6 +56,8 @@ def _load():
     lib.orc_png_sizes.argtypes = [i64, vp, vp, i64, vp, vp]
     lib.orc_png_layout.restype = ctypes.c_int
     lib.orc_png_layout.argtypes = [i64, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    lib.orc_step_at.restype = ctypes.c_int
+    lib.orc_step_at.argtypes = [i64, vp, vp, ctypes.c_double, vp, vp, vp, i64, ctypes.c_int, vp]
     lib.orc_pcpm_iterate.restype = ctypes.c_int
     lib.orc_pcpm_iterate.argtypes = [i64, vp, i64, vp, vp, vp, vp, vp, vp,
                                      ctypes.c_double, vp, vp, vp, vp]
@@ -110,6 +114,24 @@ def pagerank(row_off, col, d=0.85, iters=20, tol=0.0, tele=None, x0=None, thread
     if rc < 0:
         raise ValueError("oracle rejected its input")
     return Result(x, int(it[0]), hist[: int(it[0])], rc == 0, float(spi[0]))
+
+
+def step_at(row_off, col, x, nodes, d=0.85, tele=None, threads=None) -> np.ndarray:
+    """x_{i+1}(v) of Eq. 1 for v in ``nodes``, from x_i = ``x`` (FP64)."""
+    lib = _load()
+    row_off = np.ascontiguousarray(row_off, dtype=np.int32)
+    n = len(row_off) - 1
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    tele = None if tele is None else np.ascontiguousarray(tele, dtype=np.float64)
+    if len(x) != n:
+        raise ValueError("x must have n entries")
+    out = np.empty(len(nodes), dtype=np.float64)
+    rc = lib.orc_step_at(n, _p(row_off), _p(_col(col)), float(d), _p(tele), _p(x), _p(nodes) if len(nodes) else None,
+                         len(nodes), _threads(threads), _p(out))
+    if rc < 0:
+        raise ValueError("oracle rejected its input")
+    return out
 
 
 def teleport_from_seeds(n, seeds) -> np.ndarray:

@@ -25,6 +25,9 @@
  *                     the scatter of Alg. 3 and the branch-avoiding gather of
  *                     Alg. 5 (update pointer read as "flags seen so far,
  *                     inclusive, minus one"), then the apply of Alg. 2.
+ *   orc_step_at       One step of Eq. 1 from a given vector, evaluated only at
+ *                     chosen nodes (a scan of all edges, no transpose), for
+ *                     checks on graphs too large for full oracle runs.
  */
 #include <math.h>
 #include <stdint.h>
@@ -148,6 +151,55 @@ int orc_pagerank(int64_t n, const int32_t* row_off, const int32_t* col, double d
   if (iters_out) *iters_out = it;
   free(x); free(y); free(spr); free(in_off); free(in_src);
   return rc;
+}
+
+/*
+ * One step of Eq. 1 from x (FP64, length n), at the nodes listed in nodes[s]
+ * (distinct, in [0,n)):
+ *   out[i] = (1-d) t(v) + d (sum_{u->v} x(u)/outdeg(u) + D t(v)),  v = nodes[i]
+ * with D the dangling mass of x and t = tele (or 1/n when tele is NULL).
+ * Every edge is scanned once; each thread keeps its own partial sums, added
+ * in thread order.  Returns 0, negative on bad input.
+ */
+int orc_step_at(int64_t n, const int32_t* row_off, const int32_t* col, double d, const double* tele,
+                const double* x, const int64_t* nodes, int64_t s, int nthreads, double* out) {
+  orc_threads(nthreads);
+  if (n <= 0 || s < 0) return -1;
+  int32_t* slot = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  if (!slot) return -2;
+  for (int64_t v = 0; v < n; ++v) slot[v] = -1;
+  for (int64_t i = 0; i < s; ++i) {
+    if (nodes[i] < 0 || nodes[i] >= n || slot[nodes[i]] >= 0) { free(slot); return -1; }
+    slot[nodes[i]] = (int32_t)i;
+  }
+  orc_sum_ctx ctx = {row_off, x, NULL};
+  const double D = orc_fixed_sum(n, orc_dangling_term, &ctx);
+  const int T = omp_get_max_threads();
+  double* part = (double*)calloc((size_t)T * (size_t)(s > 0 ? s : 1), sizeof(double));
+  if (!part) { free(slot); return -2; }
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    double* acc = part + (size_t)t * (size_t)s;
+    const int64_t u0 = n * t / T, u1 = n * (t + 1) / T;
+    for (int64_t u = u0; u < u1; ++u) {
+      const int64_t od = row_off[u + 1] - row_off[u];
+      for (int64_t e = row_off[u]; e < row_off[u + 1]; ++e) {
+        const int32_t j = slot[col[e]];
+        if (j >= 0) acc[j] += x[u] / (double)od;
+      }
+    }
+  }
+  const double un = 1.0 / (double)n;
+  for (int64_t i = 0; i < s; ++i) {
+    double sum = 0.0;
+    for (int t = 0; t < T; ++t) sum += part[(size_t)t * (size_t)s + i];
+    const double tv = tele ? tele[nodes[i]] : un;
+    out[i] = (1.0 - d) * tv + d * (sum + D * tv);
+  }
+  free(part);
+  free(slot);
+  return 0;
 }
 
 /* ---- Partition-Node Graph, from its definitions ------------------------ */

@@ -475,7 +475,7 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
   // one (residual, dangling, mass) triple per apply unit: bins applied by the
   // gather use slot p, merge units use k + unit; slots of split bins stay zero
   PCPM_TRY(dalloc(g, &g->red, 3 * (k + g->n_mg)));
-  PCPM_TRY(dalloc(g, &g->red_start, 3 * k));
+  PCPM_TRY(dalloc(g, &g->red_start, 4 * k));
   PCPM_TRY_HIP(hipMemsetAsync(g->red, 0, static_cast<size_t>(3 * (k + g->n_mg)) * sizeof(double), st));
   // per group: first partition and first merge unit (units are in partition order)
   {

@@ -33,6 +33,28 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
   }
 }
 
+// Largest of a non-negative value over the workgroup; valid in thread 0.
+template <int BS>
+__device__ __forceinline__ double block_max(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  __shared__ double sh[BS / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < BS / kWave; ++k) v = fmax(v, sh[k]);
+  return v;
+}
+
+// Fixed-point scale for sums of updates bounded by `bound` (the largest
+// iterate value): 50 - ceil(log2(bound)), so every update times 2^sh stays
+// at most 2^50, capped by `cap` (the sums' own bound) and at least 1.
+__device__ __forceinline__ int fx_shift_for(double bound, int cap) {
+  int e = 0;
+  if (bound > 0.0 && isfinite(bound)) e = static_cast<int>(ceil(log2(bound)));
+  return max(1, min(cap, 50 - e));
+}
+
 // Conversion of an FP32 update to a signed integer in units of 2^-sh,
 // rounded to nearest: v * 2^sh + 1.5*2^52 is formed by one FP64 FMA (exact
 // product, one rounding) and the integer is read from the low mantissa bits.

@@ -50,7 +50,7 @@ struct Ctl {
   int32_t nonfinite;
   int32_t fx_shift; // gather sums are kept as integers in units of 2^-fx_shift
   int32_t ngroups;
-  int32_t pad;
+  int32_t fx_cap;   // largest fx_shift the start vector's mass allows
 };
 
 // Per-group state: a group is one graph of a multi-graph handle (the whole
@@ -180,7 +180,8 @@ struct pcpm_png {
 
   // reductions and control
   double* red = nullptr;        // 3*(k + n_mg): (residual, dangling, -) partial sums per apply unit
-  double* red_start = nullptr;  // 3*k: (non-finite count, dangling, L1 mass) of the start vector per partition
+  double* red_start = nullptr;  // 4*k: (non-finite count, dangling, L1 mass) of the start vector per partition,
+                                // then the largest |value| per partition
   double* hist = nullptr;       // kMaxHist residuals (group 0)
   pcpm::Ctl* ctl = nullptr;
   pcpm::Ctl* ctl_host = nullptr;  // pinned mirror

@@ -20,10 +20,16 @@
 //               of later iterations return at once.
 //
 // Sums in the gather are kept in 64-bit fixed point: every FP32 update is
-// rounded to a multiple of 2^-fx_shift (fx_shift = 50 for a start vector of
-// unit mass, so each update moves by at most 4.4e-16) and added with LDS
-// integer atomics.  Integer addition is associative, so the ranks do not
-// depend on the order in which wavefronts add, and split bins merge exactly.
+// rounded to a multiple of 2^-fx_shift and added with LDS integer atomics.
+// Integer addition is associative, so the ranks do not depend on the order
+// in which wavefronts add, and split bins merge exactly.  The scale follows
+// the iterate: an update is at most the largest value of the vector it comes
+// from, so fx_shift = 50 - ceil(log2(max x)) keeps every converted update
+// below 2^50, and the sums (at most the vector's mass) below 2^63 when
+// fx_shift <= 61 - ceil(log2(mass)).  The first iteration takes the start
+// vector's mass as the bound; each later one the largest value of the
+// previous iterate, which the apply reports.  With ranks of a large graph
+// near 1/n, this keeps the rounding of an update far below FP32 resolution.
 #include <algorithm>
 #include <cmath>
 
@@ -53,6 +59,7 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
   const double d = ctl->d;
   const double unit = ldexp(1.0, -ctl->fx_shift);
   double sums[2] = {0.0, 0.0};  // residual, dangling mass
+  float mx = 0.0f;               // largest new value: the next fixed-point scale
   // kU nodes per thread per step, loads first, so their latencies overlap
   constexpr int kU = 4;
   for (int i = i0 + static_cast<int>(threadIdx.x); i < i1; i += kU * BS) {
@@ -75,6 +82,7 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
           const double sv = static_cast<double>(acc(ii)) * unit;
           xn = frozen ? xo[u] : static_cast<float>(fma(d, sv, base));
         }
+        mx = fmaxf(mx, fabsf(xn));
         sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
         if ((dw[u] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
         pr_out[v] = xn;
@@ -82,10 +90,11 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
     }
   }
   block_sum<BS>(sums);
+  const double vmax = block_max<BS>(static_cast<double>(mx));
   if (threadIdx.x == 0) {
     red_slot[0] = sums[0];
     red_slot[1] = sums[1];
-    red_slot[2] = 0.0;
+    red_slot[2] = vmax;
   }
 }
 
@@ -289,9 +298,12 @@ __device__ __forceinline__ void group_sums(const int32_t* __restrict__ group_slo
 // that makes the kernels of later iterations return at once.
 __global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
                                                    const int32_t* __restrict__ group_slots,
-                                                   const double* __restrict__ red, int64_t k,
+                                                   const double* __restrict__ red, int64_t k, int64_t nslots,
                                                    double* __restrict__ hist) {
   if (ctl->done) return;
+  double vmax = 0.0;  // largest value of the new iterate over all apply units
+  for (int64_t j = threadIdx.x; j < nslots; j += 1024) vmax = fmax(vmax, red[3 * j + 2]);
+  vmax = block_max<1024>(vmax);
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
@@ -328,6 +340,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* 
     ctl->iter = it + 1;
     if (bad) ctl->nonfinite = 1;
     if (bad || all_done) ctl->done = 1;
+    ctl->fx_shift = fx_shift_for(vmax, ctl->fx_cap);
   }
 }
 
@@ -350,6 +363,7 @@ __global__ __launch_bounds__(256) void k_ctl_init(Ctl* __restrict__ ctl, GCtl* _
     ctl->done = 0;
     ctl->nonfinite = 0;
     ctl->fx_shift = 50;
+    ctl->fx_cap = 61;
     ctl->ngroups = G;
   }
 }
@@ -368,7 +382,8 @@ __global__ __launch_bounds__(256) void k_fill_uniform(float* __restrict__ x, int
 }
 
 // Start vector statistics per partition: non-finite count, dangling mass and
-// L1 mass, into the partition's start slot.  Padding entries are cleared.
+// L1 mass, into the partition's start slot, and its largest |value| (after
+// the 3k slots).  Padding entries are cleared.
 __global__ __launch_bounds__(256) void k_start_parts(float* __restrict__ x, const uint32_t* __restrict__ dmask,
                                                      int64_t n, int s, const int32_t* __restrict__ part_valid,
                                                      double* __restrict__ red) {
@@ -376,6 +391,7 @@ __global__ __launch_bounds__(256) void k_start_parts(float* __restrict__ x, cons
   const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
   const int valid = part_valid[blockIdx.x];
   double sums[3] = {0.0, 0.0, 0.0};
+  float mx = 0.0f;
   for (int i = threadIdx.x; i < qn; i += 256) {
     const int64_t v = v0 + i;
     if (i >= valid) {
@@ -386,23 +402,30 @@ __global__ __launch_bounds__(256) void k_start_parts(float* __restrict__ x, cons
     if (!isfinite(xv)) sums[0] += 1.0;
     if ((dmask[v >> 5] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xv);
     sums[2] += fabs(static_cast<double>(xv));
+    mx = fmaxf(mx, fabsf(xv));
   }
   block_sum<256>(sums);
+  const double vmax = block_max<256>(static_cast<double>(mx));
   if (threadIdx.x == 0) {
     red[3 * blockIdx.x] = sums[0];
     red[3 * blockIdx.x + 1] = sums[1];
     red[3 * blockIdx.x + 2] = sums[2];
+    red[3 * gridDim.x + blockIdx.x] = vmax;
   }
 }
 
-// Per-group dangling mass and base of the start vector; the fixed-point scale
-// of the gather: every gather sum is bounded by max(1, L1 mass of the start
-// vector), which later iterates never exceed (teleport vectors are
-// non-negative and sum to one per group), so 2^fx_shift times that bound stays
-// below 2^51 and every conversion is in range.
+// Per-group dangling mass and base of the start vector, and the fixed-point
+// scale of the first gather: every gather sum is bounded by max(1, L1 mass of
+// the start vector), which later iterates never exceed (teleport vectors are
+// non-negative and sum to one per group), which caps the scale at
+// 61 - ceil(log2(that bound)); within the cap, the start vector's largest
+// value sets it.
 __global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
                                                          const int32_t* __restrict__ group_slots,
                                                          const double* __restrict__ red, int64_t k) {
+  double vmax = 0.0;  // largest |value| of the start vector
+  for (int64_t j = threadIdx.x; j < k; j += 1024) vmax = fmax(vmax, red[3 * k + j]);
+  vmax = block_max<1024>(vmax);
   __shared__ int bad;
   __shared__ double mass_w[1024 / kWave];
   if (threadIdx.x == 0) bad = 0;
@@ -429,7 +452,8 @@ __global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, 
     for (int w = 0; w < 1024 / kWave; ++w) mass += mass_w[w];
     int e = 0;
     if (isfinite(mass) && mass > 1.0) e = static_cast<int>(ceil(log2(mass)));
-    ctl->fx_shift = 50 - min(e, 1000);
+    ctl->fx_cap = 61 - min(e, 1000);
+    ctl->fx_shift = fx_shift_for(vmax, ctl->fx_cap);
     if (bad) {
       ctl->nonfinite = 1;
       ctl->done = 1;
@@ -475,7 +499,7 @@ static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hip
                 st, g->ctl, g->n, g->part_log2, g->mg_items, g->partial, in, out, g->dmask, g->red, g->k, g->gctl,
                 g->part_group, g->part_valid);
   PCPM_LAUNCH("pcpm_finalize", k_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->gctl, g->group_slots, g->red,
-              g->k, g->hist);
+              g->k, g->k + g->n_mg, g->hist);
   return PCPM_OK;
 }
 

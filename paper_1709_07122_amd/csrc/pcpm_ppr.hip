@@ -125,6 +125,7 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
   const double d = ctl->d;
   const double unit = ldexp(1.0, -ctl->fx_shift);
   double r = 0.0, dm = 0.0;
+  float mx = 0.0f;  // largest new value: the next fixed-point scale
   constexpr int kU = 4;
   constexpr int kStep = BS / KT;
   for (int node = n0 + static_cast<int>(threadIdx.x) / KT; node < n1; node += kU * kStep) {
@@ -147,6 +148,7 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
         const float xn = frozen ? xo[u] : static_cast<float>(fma(d, a, seed ? coef : 0.0));
         r += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
         if ((dw[u] >> (v & 31)) & 1u) dm += static_cast<double>(xn);
+        mx = fmaxf(mx, fabsf(xn));
         x_out[v * KT + kk] = xn;
       }
     }
@@ -156,22 +158,26 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
   for (int off = kWave / 2; off >= KT; off >>= 1) {
     r += __shfl_xor(r, off);
     dm += __shfl_xor(dm, off);
+    mx = fmaxf(mx, __shfl_xor(mx, off));
   }
-  __shared__ double sh[(BS / kWave) * KT * 2];
+  __shared__ double sh[(BS / kWave) * KT * 3];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   if (lane < KT) {
-    sh[(w * KT + lane) * 2] = r;
-    sh[(w * KT + lane) * 2 + 1] = dm;
+    sh[(w * KT + lane) * 3] = r;
+    sh[(w * KT + lane) * 3 + 1] = dm;
+    sh[(w * KT + lane) * 3 + 2] = static_cast<double>(mx);
   }
   __syncthreads();
   if (threadIdx.x < KT) {
-    double rs = 0.0, ds = 0.0;
+    double rs = 0.0, ds = 0.0, ms = 0.0;
     for (int ww = 0; ww < BS / kWave; ++ww) {
-      rs += sh[(ww * KT + threadIdx.x) * 2];
-      ds += sh[(ww * KT + threadIdx.x) * 2 + 1];
+      rs += sh[(ww * KT + threadIdx.x) * 3];
+      ds += sh[(ww * KT + threadIdx.x) * 3 + 1];
+      ms = fmax(ms, sh[(ww * KT + threadIdx.x) * 3 + 2]);
     }
-    red_slot[threadIdx.x * 2] = rs;
-    red_slot[threadIdx.x * 2 + 1] = ds;
+    red_slot[threadIdx.x * 3] = rs;
+    red_slot[threadIdx.x * 3 + 1] = ds;
+    red_slot[threadIdx.x * 3 + 2] = ms;
   }
 }
 
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
     return;
   }
   apply_ppr<KT, BS>(ctl, vctl, v0, 0, qn, [&](int i) { return static_cast<int64_t>(acc[i]); }, x_in, x_out, dmask,
-                    seedmask, red + static_cast<int64_t>(it.part) * KT * 2);
+                    seedmask, red + static_cast<int64_t>(it.part) * KT * 3);
 }
 
 template <int KT>
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__
     return sum;
   };
   apply_ppr<KT, kPprBlock>(ctl, vctl, v0, mu.node_lo, min(qn, mu.node_lo + 256), acc, x_in, x_out, dmask, seedmask,
-                           red + (red_base + blockIdx.x) * KT * 2);
+                           red + (red_base + blockIdx.x) * KT * 3);
 }
 
 // Per-vector residual, dangling mass and jump coefficient; one wavefront per
@@ -305,6 +311,9 @@ __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VC
                                                        const double* __restrict__ red, int64_t nslots,
                                                        double* __restrict__ hist) {
   if (ctl->done) return;
+  double vmax = 0.0;  // largest value of the new iterates (all vectors of the tile)
+  for (int64_t j = threadIdx.x; j < nslots * kt; j += 1024) vmax = fmax(vmax, red[3 * j + 2]);
+  vmax = block_max<1024>(vmax);
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
@@ -313,8 +322,8 @@ __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VC
   for (int kk = threadIdx.x / kWave; kk < kt; kk += 1024 / kWave) {
     double r = 0.0, dm = 0.0;
     for (int64_t sl = lane; sl < nslots; sl += kWave) {
-      r += red[(sl * kt + kk) * 2];
-      dm += red[(sl * kt + kk) * 2 + 1];
+      r += red[(sl * kt + kk) * 3];
+      dm += red[(sl * kt + kk) * 3 + 1];
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -349,6 +358,7 @@ __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VC
     ctl->iter = it + 1;
     if (bad) ctl->nonfinite = 1;
     if (bad || all_done) ctl->done = 1;
+    ctl->fx_shift = fx_shift_for(vmax, ctl->fx_cap);
   }
 }
 
@@ -409,6 +419,7 @@ __global__ void k_ppr_ctl(Ctl* ctl, double tol, double d) {
     ctl->done = 0;
     ctl->nonfinite = 0;
     ctl->fx_shift = 50;  // every vector has unit mass
+    ctl->fx_cap = 61;
     ctl->ngroups = 1;
   }
 }
@@ -455,7 +466,7 @@ static pcpm_status_t ppr_alloc(pcpm_png* g, int kt, int64_t nseeds, int k, hipSt
     PCPM_TRY(dalloc(g, &g->ppr_x[1], g->n * kt));
     PCPM_TRY(dalloc(g, &g->ppr_upd, (g->eprime + 1) * kt));
     PCPM_TRY(dalloc(g, &g->ppr_partial, static_cast<int64_t>(g->n_split_slots) * g->q * kt));
-    PCPM_TRY(dalloc(g, &g->ppr_red, (g->k + g->n_mg) * kt * 2));
+    PCPM_TRY(dalloc(g, &g->ppr_red, (g->k + g->n_mg) * kt * 3));
     PCPM_TRY(dalloc(g, &g->ppr_vctl, kt));
     PCPM_TRY(dalloc(g, &g->ppr_mask, g->n));
     g->ppr_kt = kt;
@@ -485,7 +496,7 @@ static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_i
   *all_converged = true;
   *nonfinite = false;
   // slots of split bins are never written by the gather: keep them zero
-  PCPM_TRY_HIP(hipMemsetAsync(g->ppr_red, 0, static_cast<size_t>((g->k + g->n_mg) * KT * 2) * 8, st));
+  PCPM_TRY_HIP(hipMemsetAsync(g->ppr_red, 0, static_cast<size_t>((g->k + g->n_mg) * KT * 3) * 8, st));
   for (int first = 0; first < k; first += KT) {
     const int kv = std::min(KT, k - first);
     float* a = g->ppr_x[0];

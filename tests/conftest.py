@@ -11,3 +11,4 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C-ABI library)")
     config.addinivalue_line("markers", "slow: large inputs")
+    config.addinivalue_line("markers", "full: the workloads at their full sizes (minutes; tens of GB of host memory)")

@@ -1,0 +1,156 @@
+"""Parity at the workloads' full sizes, in the configurations bench.py times.
+
+* RMAT-24 (EF 16, seed 2), random and in-degree labels, q = 16384, to L1
+  residual 1e-6: whole vectors against the FP64 oracle at the same
+  iteration count.
+* The paper-scale graphs (RMAT-26 EF 24 seed 3, random labels; uniform graph
+  of 50M nodes and 1B draws, seed 4), 20 iterations: the 20th iterate at a
+  sample of nodes against one oracle step from the GPU's 19th iterate, plus
+  properties that hold at any size (unit mass, residuals contracting by d).
+* Batched personalised PageRank on RMAT-22 (EF 16, seed 5) with 8/32/64 seed
+  sets at the autotuned partition size, and the 16-graph uneven batch.
+* The learned warm start on a held-out RMAT-24 graph.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1709_07122_amd")
+
+pytestmark = [pytest.mark.gpu, pytest.mark.full]
+
+D = 0.85
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_vector(got, ref, l1_tol=1e-5, rel_tol=1e-3):
+    got = got.astype(np.float64)
+    n = len(ref)
+    l1 = np.abs(got - ref).sum()
+    assert l1 <= l1_tol, l1
+    big = ref > 1.0 / n
+    assert big.any()
+    rel = (np.abs(got - ref)[big] / ref[big]).max()
+    assert rel <= rel_tol, rel
+
+
+@pytest.mark.parametrize("relabel", ["random", "indegree"])
+def test_rmat24_to_tolerance(relabel):
+    r, c = graphgen.rmat(24, 16, seed=2, relabel=relabel)
+    png = P.build_png(dev(r), dev(c), part_log2=14)
+    res = P.pagerank(png, d=D, tol=1e-6, max_iters=100)
+    png.close()
+    assert res.converged and res.resid < 1e-6
+    o = oracle.pagerank(r, c, d=D, iters=res.iters)
+    check_vector(res.pr.cpu().numpy(), o.x)
+    # the oracle sees the same stopping point
+    assert o.res_hist[-1] < 1.05e-6 and o.res_hist[-2] >= 0.95e-6
+
+
+def sample_nodes(r, c, count, seed):
+    """Largest in-degrees, the last nodes (ragged tail), node 0 and random ones."""
+    n = len(r) - 1
+    indeg = np.bincount(c, minlength=n)
+    top = np.argpartition(indeg, -256)[-256:]
+    rng = np.random.default_rng(seed)
+    pick = np.concatenate([top, np.arange(n - 64, n), [0], rng.choice(n, count, replace=False)])
+    return np.unique(pick)
+
+
+@pytest.mark.parametrize("kind", ["rmat26_ef24", "uniform_50m_1b"])
+def test_paper_scale_twenty_iterations(kind):
+    if kind == "rmat26_ef24":
+        r, c = graphgen.rmat(26, 24, seed=3, relabel="random")
+    else:
+        r, c = graphgen.uniform(50_000_000, 1_000_000_000, seed=4)
+    n = len(r) - 1
+    png = P.build_png(dev(r), dev(c), part_log2=14)
+    res19 = P.pagerank(png, d=D, tol=0.0, max_iters=19, want_hist=True)
+    x20, _ = P.iterate(png, res19.pr, d=D)
+    res20 = P.pagerank(png, d=D, tol=0.0, max_iters=20, want_hist=True)
+    png.close()
+    x19 = res19.pr.cpu().numpy()
+    y = x20.cpu().numpy()
+    # pcpm_pagerank's 20th iterate and pcpm_iterate from its 19th agree up to
+    # the FP32 rounding of the output (their FP64 dangling sums are formed in
+    # different orders)
+    y20 = res20.pr.cpu().numpy()
+    assert np.all(np.abs(y20.astype(np.float64) - y) <= 2.0 ** -22 * np.abs(y.astype(np.float64)))
+    nodes = sample_nodes(r, c, 20000, seed=n % 1000)
+    ref = oracle.step_at(r, c, x19.astype(np.float64), nodes, d=D)
+    rel = np.abs(y[nodes].astype(np.float64) - ref) / ref
+    assert rel.max() <= 1e-5, rel.max()
+    assert abs(y.astype(np.float64).sum() - 1.0) <= 1e-5
+    h = res20.res_hist
+    assert len(h) == 20 and np.all(np.isfinite(h))
+    assert np.all(h[1:] <= D * h[:-1] * 1.001 + 1e-7), h
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    return graphgen.rmat(22, 16, seed=5, relabel="random")
+
+
+@pytest.mark.parametrize("k", [8, 32, 64])
+def test_ppr_rmat22_autotuned(rmat22, k):
+    from paper_1709_07122_amd import autotune
+
+    r, c = rmat22
+    n = len(r) - 1
+    rt, ct = dev(r), dev(c)
+    tune = autotune.tune(rt, ct, vectors=k, cache=None)
+    png = P.build_png(rt, ct, part_log2=tune.part_log2)
+    off, seeds = graphgen.seed_sets(n, k, seed=k)
+    res = P.ppr_batch(png, off, seeds, d=D, tol=1e-6, max_iters=200)
+    png.close()
+    assert res.converged and np.all(res.resid < 1e-6)
+    x = res.pr.cpu().numpy()
+    np.testing.assert_allclose(x.astype(np.float64).sum(axis=0), 1.0, atol=1e-5)
+    for j in sorted({0, k // 2, k - 1}):
+        ref = oracle.ppr(r, c, seeds[off[j]:off[j + 1]], d=D, iters=int(res.iters[j])).x
+        check_vector(x[:, j], ref)
+
+
+@pytest.mark.parametrize("part_log2", [12, 14])
+def test_sixteen_uneven_graphs(part_log2):
+    graphs, shapes = graphgen.uneven_rmat_batch(16, seed=100)
+    r, c, off, sizes = P.union_csr(graphs, part_log2)
+    png = P.build_png(dev(r), dev(c), part_log2=part_log2, graph_node_off=off, graph_nodes=sizes)
+    res = P.pagerank(png, d=D, tol=1e-6, max_iters=200)
+    it, resid = png.graph_results()
+    png.close()
+    assert res.converged and np.all(resid < 1e-6)
+    x = res.pr.cpu().numpy()
+    for g, (rg, cg) in enumerate(graphs):
+        ref = oracle.pagerank(rg, cg, d=D, iters=int(it[g])).x
+        check_vector(x[off[g]:off[g] + sizes[g]], ref)
+        assert np.all(x[off[g] + sizes[g]:off[g + 1]] == 0.0)
+
+
+def test_warm_start_on_held_out_rmat24():
+    ws = P.warmstart
+    r, c = graphgen.rmat(24, 16, seed=2000, relabel="random")
+    png = P.build_png(dev(r), dev(c), part_log2=14)
+    pr0, fallback = ws.warm_start(png, ws.load(ws.DEFAULT_WEIGHTS), d=D)
+    assert not fallback
+    cold = P.pagerank(png, d=D, tol=1e-6, max_iters=100)
+    warm = P.pagerank(png, d=D, tol=1e-6, max_iters=100, init=pr0)
+    png.close()
+    assert cold.converged and warm.converged
+    assert warm.iters <= cold.iters - 3, (warm.iters, cold.iters)
+    star = oracle.pagerank(r, c, d=D, iters=300, tol=1e-11).x
+    for res in (cold, warm):
+        err = np.abs(res.pr.cpu().numpy().astype(np.float64) - star).sum()
+        assert err <= D * res.resid / (1 - D) + 1e-5, err

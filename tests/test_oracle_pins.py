@@ -380,3 +380,40 @@ def test_pins_catch_planted_mistakes(mistake):
     assert failed, f"no pin rejects the mistake {mistake}"
     # and the correct recurrence passes the same checks
     assert np.abs(_wrong_pagerank(r, c, d, 5, "none") - x).max() < 1e-14
+
+
+# ------------------------------------------------ one step at chosen nodes
+
+@pytest.mark.parametrize("seed,n,p,d,use_tele", [(11, 30, 0.2, 0.85, False), (12, 64, 0.07, 0.6, True),
+                                                 (13, 9, 0.4, 0.85, False)])
+def test_step_at_matches_dense_google_product(seed, n, p, d, use_tele):
+    """A step from an arbitrary (not normalised) vector, at a random subset of
+    nodes, equals rows of the dense Google matrix times that vector."""
+    r, c = random_digraph(n, p, seed)
+    rng = np.random.default_rng(seed)
+    if use_tele:
+        t = rng.random(n)
+        t[rng.random(n) < 0.5] = 0
+        t /= t.sum()
+    else:
+        t = np.full(n, 1.0 / n)
+    x = rng.random(n)
+    want = dense_google(r, c, d, t) @ x
+    # the dangling spread uses the dangling mass of x, and the jump (1-d) t
+    # weighs the mass of x in the dense form: correct that term for sum(x) != 1
+    want += (1 - d) * t * (1.0 - x.sum())
+    nodes = rng.choice(n, size=max(1, n // 3), replace=False)
+    got = oracle.step_at(r, c, x, nodes, d=d, tele=t if use_tele else None, threads=3)
+    np.testing.assert_allclose(got, want[nodes], rtol=0, atol=1e-14)
+    # all nodes, any thread count, equal one full iteration of the pull oracle
+    full = oracle.step_at(r, c, x, np.arange(n), d=d, tele=t if use_tele else None, threads=1)
+    np.testing.assert_allclose(full, want, rtol=0, atol=1e-14)
+
+
+def test_step_at_rejects_bad_node_lists():
+    r, c = random_digraph(10, 0.3, 1)
+    with pytest.raises(ValueError):
+        oracle.step_at(r, c, np.ones(10) / 10, [3, 3])
+    with pytest.raises(ValueError):
+        oracle.step_at(r, c, np.ones(10) / 10, [10])
+    assert oracle.step_at(r, c, np.ones(10) / 10, []).shape == (0,)
