@@ -41,6 +41,24 @@ def threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
+def solve_tol(args):
+    return 0.0 if args.iters > 0 else args.tol
+
+
+def solve_iters(args):
+    return args.iters if args.iters > 0 else args.max_iters
+
+
+def workload_name(args):
+    if args.graph == "uniform":
+        g = f"a uniform random directed graph of {args.nodes} nodes and {args.draws} edge draws (seed {args.seed})"
+    else:
+        g = (f"RMAT scale {args.scale}, edge factor {args.edge_factor:g} (a,b,c=.57,.19,.19, seed {args.seed}), "
+             f"random node labels")
+    stop = f"{args.iters} iterations" if args.iters > 0 else f"to L1 residual {args.tol:g}"
+    return f"PageRank d={args.d} {stop} on {g}, partition {1 << args.part_log2} nodes"
+
+
 def measure(P, torch, r, c, args, label):
     """Build the PNG, warm up, then time `steps` solves with per-kernel events."""
     from paper_1709_07122_amd import commmodel as cm
@@ -56,7 +74,7 @@ def measure(P, torch, r, c, args, label):
     info = png.info
     out = torch.empty(n, dtype=torch.float32, device="cuda")
     for _ in range(args.warmup):
-        P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters, out=out, want_hist=False)
+        P.pagerank(png, d=args.d, tol=solve_tol(args), max_iters=solve_iters(args), out=out, want_hist=False)
     log(f"[{label}] n={n} m={m} q={info['q']} k={info['k']} E'={info['eprime']} "
         f"r={m / max(info['eprime'], 1):.3f} build={build_s * 1e3:.1f} ms")
 
@@ -65,7 +83,7 @@ def measure(P, torch, r, c, args, label):
     t0 = time.perf_counter()
     iters = []
     for _ in range(args.steps):
-        res = P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters, out=out, want_hist=False)
+        res = P.pagerank(png, d=args.d, tol=solve_tol(args), max_iters=solve_iters(args), out=out, want_hist=False)
         iters.append(res.iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -243,7 +261,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--graph", choices=("rmat", "uniform"), default="rmat")
     ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--nodes", type=int, default=50_000_000, help="uniform graph: nodes")
+    ap.add_argument("--draws", type=int, default=1_000_000_000, help="uniform graph: edge draws")
+    ap.add_argument("--iters", type=int, default=0, help="fixed iteration count (0: iterate to --tol)")
+    ap.add_argument("--cpu-iters", type=int, default=0,
+                    help="oracle iterations of the CPU baseline (0: as many as the GPU solve took)")
     ap.add_argument("--edge-factor", type=float, default=16)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--part-log2", type=int, default=14)
@@ -277,19 +301,30 @@ def main():
 
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    raw_r, raw_c = graphgen.rmat(args.scale, args.edge_factor, 0.57, 0.19, 0.19, seed=args.seed)
-    n = len(raw_r) - 1
-    perm = np.empty(n, dtype=np.int32)
-    graphgen._load().gg_perm_random(n, (args.seed * 7919 + 17) & (2**64 - 1), perm.ctypes.data)
-    r, c = graphgen.apply_labels(raw_r, raw_c, perm)
-    log(f"generated RMAT-{args.scale} EF{args.edge_factor}: n={n} m={len(c)} in {time.perf_counter() - t:.1f} s")
+    if args.graph == "uniform":
+        raw_r = raw_c = None
+        r, c = graphgen.uniform(args.nodes, args.draws, seed=args.seed)
+        n = len(r) - 1
+        args.no_indegree = args.no_warm = True
+    else:
+        raw_r, raw_c = graphgen.rmat(args.scale, args.edge_factor, 0.57, 0.19, 0.19, seed=args.seed)
+        n = len(raw_r) - 1
+        perm = np.empty(n, dtype=np.int32)
+        graphgen._load().gg_perm_random(n, (args.seed * 7919 + 17) & (2**64 - 1), perm.ctypes.data)
+        r, c = graphgen.apply_labels(raw_r, raw_c, perm)
+        if args.no_indegree:
+            raw_r = raw_c = None
+    log(f"generated {args.graph}: n={n} m={len(c)} in {time.perf_counter() - t:.1f} s")
 
     main_res, x_gpu, png = measure(P, torch, r, c, args, "random")
     detail = {"random": main_res}
     warm = None
-    if not args.no_warm:
+    if not args.no_warm and args.iters == 0:
         warm = warm_detail(P, torch, png, args)
         detail["warm_start"] = warm
+    cpu_iters = args.cpu_iters if args.cpu_iters > 0 else main_res["iters"]
+    if not args.no_cpu_baseline and cpu_iters != main_res["iters"]:
+        x_gpu = P.pagerank(png, d=args.d, tol=0.0, max_iters=cpu_iters, want_hist=False).pr.cpu().numpy()
     png.close()
     if not args.no_indegree:
         ri, ci = graphgen.apply_labels(raw_r, raw_c, graphgen.indegree_labels(raw_r, raw_c))
@@ -307,7 +342,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        iters = main_res["iters"]
+        iters = cpu_iters
         t = time.perf_counter()
         o = oracle.pagerank(r, c, d=args.d, iters=iters)
         wall = time.perf_counter() - t
@@ -317,8 +352,8 @@ def main():
         rel = float((np.abs(x_gpu.astype(np.float64) - x_ref)[big] / x_ref[big]).max())
         detail["parity"] = {"l1": l1, "max_rel_above_1_over_n": rel, "iters": iters}
         cpu = {"value": len(c) / o.sec_per_iter / 1e9, "unit": "GTEPS", "cores": threads(), "kind": "oracle",
-               "sample": f"the same RMAT-{args.scale} graph (random labels), {iters} FP64 pull iterations of "
-                         f"the oracle, transpose excluded ({wall:.1f} s wall incl. transpose)",
+               "sample": f"the same graph, {iters} FP64 pull iterations of the oracle, transpose excluded "
+                         f"({wall:.1f} s wall incl. transpose)",
                "sec_per_iter": o.sec_per_iter}
         log(f"oracle: {o.sec_per_iter * 1e3:.1f} ms/iter on {threads()} threads; parity L1={l1:.2e} rel={rel:.2e}")
 
@@ -338,16 +373,15 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"PageRank d={args.d} to L1 residual {args.tol:g} on RMAT scale {args.scale}, edge factor "
-                        f"{args.edge_factor:g} (a,b,c=.57,.19,.19, seed {args.seed}), random node labels, "
-                        f"partition {1 << args.part_log2} nodes",
+            "workload": workload_name(args),
             "n": main_res["n"], "m": main_res["m"], "q": main_res["q"], "k": main_res["k"],
-            "eprime": main_res["eprime"], "tol": args.tol, "d": args.d,
+            "eprime": main_res["eprime"], "tol": solve_tol(args), "iters": main_res["iters"], "d": args.d,
         },
         "roofline": {
             "bound": "hbm", "kernel": "pcpm_gather", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": counter_traffic("pcpm::k_gather<1024>") if args.part_log2 == 14 and args.scale == 24 else None,
+            "traffic": (counter_traffic("pcpm::k_gather<1024>") if args.graph == "rmat" and args.part_log2 == 14
+                        and args.scale == 24 and args.edge_factor == 16 and args.seed == 2 else None),
             "bytes_per_launch": main_res["gather_bytes"], "avg_launch_ms": g["avg_ms"],
         },
         "cpu_baseline": cpu,

@@ -459,10 +459,33 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
     for (int64_t nl = 0; nl < qn; nl += 256) mg.push_back({static_cast<int32_t>(p), first, slot - first,
                                                            static_cast<int32_t>(nl)});
   }
-  // largest work first
+  // gather: largest work first
   auto bigger = [](const Item& x, const Item& y) { return (x.hi - x.lo) > (y.hi - y.lo); };
-  std::stable_sort(sc_items.begin(), sc_items.end(), bigger);
   std::stable_sort(ga_items.begin(), ga_items.end(), bigger);
+  // Scatter: workgroup b runs array entry xcd_block(b, n), so XCD x runs one
+  // contiguous range of the array.  With items in source-partition order,
+  // partitions p and p+1, whose segments lie next to each other in every bin,
+  // run together on one XCD and the cache lines they share fill in its L2
+  // before they are written back.  That order suits partitions of similar
+  // work; if it would load one XCD more than 10% above the mean, the array
+  // instead holds the items largest first in dispatch order.
+  {
+    const unsigned nsc = static_cast<unsigned>(sc_items.size());
+    std::vector<int64_t> xw(kXcds, 0);
+    int64_t tot = 0;
+    for (unsigned b = 0; b < nsc; ++b) {
+      const Item& it = sc_items[xcd_block(b, nsc)];
+      xw[b % kXcds] += it.hi - it.lo;
+      tot += it.hi - it.lo;
+    }
+    const int64_t worst = nsc ? *std::max_element(xw.begin(), xw.end()) : 0;
+    if (nsc && worst * 10 > 11 * ((tot + kXcds - 1) / kXcds)) {
+      std::vector<Item> lpt = sc_items;
+      std::stable_sort(lpt.begin(), lpt.end(), bigger);
+      for (unsigned b = 0; b < nsc; ++b) sc_items[xcd_block(b, nsc)] = lpt[b];
+      g->scatter_order = 1;
+    }
+  }
 
   g->n_sc = static_cast<int32_t>(sc_items.size());
   g->n_ga = static_cast<int32_t>(ga_items.size());

@@ -39,6 +39,18 @@ constexpr int kMaxLog2 = 14;       // 16384 * 8 B = 128 KB fixed-point slice in 
 constexpr int kScatterBlock = PCPM_SCATTER_BLOCK;  // threads per scatter workgroup
 constexpr int kGatherBlock = PCPM_GATHER_BLOCK;    // threads per gather / merge workgroup
 
+// MI355X has 8 XCDs (32 CUs and one L2 each), and the workgroups of a launch
+// are dealt to them in turn: workgroup b runs on XCD b % 8.  xcd_block(b, nb)
+// renumbers the workgroups so that each XCD takes one contiguous range of
+// [0, nb) (a bijection): work items that are neighbours in memory then run
+// together on one XCD and share its L2.
+constexpr unsigned kXcds = 8;
+__host__ __device__ inline unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b % kXcds, j = b / kXcds;
+  const unsigned per = nb / kXcds, rem = nb % kXcds;
+  return x * per + (x < rem ? x : rem) + j;
+}
+
 // Device control block of one handle (one solve at a time).
 struct Ctl {
   double res;       // largest residual over groups, last iteration
@@ -167,6 +179,7 @@ struct pcpm_png {
   pcpm::Item* ga_items = nullptr;
   pcpm::Merge* mg_items = nullptr;
   int32_t n_sc = 0, n_ga = 0, n_mg = 0, n_split_slots = 0, n_split_bins = 0;
+  int32_t scatter_order = 0;  // 0: source-partition order per XCD, 1: largest first
   int64_t* partial = nullptr;   // n_split_slots * q fixed-point partial sums
 
   // groups (graphs of a multi-graph handle)

@@ -6,7 +6,8 @@
 //   k_scatter   one workgroup per scatter item (a range of one source
 //               partition's PNG edges): the partition's scaled ranks
 //               PR(u)/outdeg(u) are staged in LDS, PNG edges are streamed
-//               and each writes its update to its bin slot.
+//               and each writes its update to its bin slot.  Each XCD runs
+//               one contiguous range of the item array.
 //   k_gather    one workgroup per gather item (a range of one destination
 //               bin): destination IDs and updates are streamed, the update of
 //               an ID is found from the running count of message flags, and
@@ -108,7 +109,8 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
                                                 int64_t spare) {
   if (ctl->done) return;
   extern __shared__ float spr[];
-  const Item it = items[blockIdx.x];
+  // XCD-contiguous renumbering (the build arranges the item array for it)
+  const Item it = items[xcd_block(blockIdx.x, gridDim.x)];
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
   for (int i = threadIdx.x; i < qn; i += BS) {

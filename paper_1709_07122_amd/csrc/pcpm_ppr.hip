@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict
                                                            float* __restrict__ upd, int64_t spare) {
   if (ctl->done) return;
   extern __shared__ float spr[];  // q * KT scaled values of the source partition
-  const Item it = items[blockIdx.x];
+  const Item it = items[xcd_block(blockIdx.x, gridDim.x)];  // as in the plain scatter
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
   for (int i = threadIdx.x; i < qn * KT; i += kPprBlock) {
