@@ -62,11 +62,15 @@ def scatter_bytes(n, eprime, nseg):
     return 8 * n + 4 * eprime + 4 * nseg + 4 * (eprime // TILE + 1) + 4 * eprime
 
 
-def gather_bytes(n, m, eprime):
-    """Algorithmic bytes of one gather+apply pass: destination IDs (4m), tile
-    flag prefixes (4m/1024), updates (4E'), the previous ranks for the
-    residual (4n), the new ranks (4n) and the dangling bitmask (n/8)."""
-    return 4 * m + 4 * (m // TILE + 1) + 4 * eprime + 8 * n + n // 8
+DID_BYTES = 2  # destination IDs are stored partition-local in 16 bits (flag in bit 15)
+
+
+def gather_bytes(n, m, eprime, did_bytes=DID_BYTES):
+    """Algorithmic bytes of one gather+apply pass: destination IDs
+    (did_bytes per edge), tile flag prefixes (4m/1024), updates (4E'), the
+    previous ranks for the residual (4n), the new ranks (4n) and the dangling
+    bitmask (n/8)."""
+    return did_bytes * m + 4 * (m // TILE + 1) + 4 * eprime + 8 * n + n // 8
 
 
 def iteration_bytes(n, m, eprime, nseg):

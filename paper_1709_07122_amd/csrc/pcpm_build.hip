@@ -270,7 +270,7 @@ __global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nb
                                              const int32_t* __restrict__ row_off, const int32_t* __restrict__ col,
                                              const int32_t* __restrict__ src, const int32_t* __restrict__ did_start,
                                              const int32_t* __restrict__ dwo, const int32_t* __restrict__ png_base,
-                                             const int32_t* __restrict__ png_off, uint32_t* __restrict__ did,
+                                             const int32_t* __restrict__ png_off, uint16_t* __restrict__ did,
                                              uint32_t* __restrict__ png_src) {
   extern __shared__ int32_t sh[];
   int32_t* cur_did = sh;   // absolute destination-ID position per p'
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nb
     }
     __builtin_amdgcn_wave_barrier();
     if (valid) {
-      did[cd + rank] = static_cast<uint32_t>(v) | (first ? kFlag : 0u);
+      did[cd + rank] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | (first ? kDidFlag : 0u));
       if (first) {
         const int32_t r = cr + frank;
         const int64_t pos = static_cast<int64_t>(pbase) + png_off[p * (k + 1) + pp] + r;
@@ -330,15 +330,18 @@ __global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nb
   }
 }
 
-// Number of flagged entries in each kTile tile (one wavefront per tile).
-__global__ __launch_bounds__(256) void k_tile_flags(const uint32_t* __restrict__ a, int64_t ntiles,
+// Number of flagged entries (top bit set) in each kTile tile (one wavefront
+// per tile); T = uint32_t for PNG edges, uint16_t for destination IDs.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_flags(const T* __restrict__ a, int64_t ntiles,
                                                     int32_t* __restrict__ cnt) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  constexpr int kTop = 8 * sizeof(T) - 1;
   for (int64_t t = wave; t < ntiles; t += nwaves) {
     int32_t c = 0;
-    for (int j = 0; j < kSub; ++j) c += __popcll(wave_ballot((a[t * kTile + j * kWave + lane] >> 31) != 0));
+    for (int j = 0; j < kSub; ++j) c += __popcll(wave_ballot((a[t * kTile + j * kWave + lane] >> kTop) != 0));
     if (lane == 0) cnt[t] = c;
   }
 }
@@ -622,7 +625,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(dalloc(g, &g->png_src, std::max<int64_t>(ntp, 1) * kTile));
   PCPM_TRY(dalloc(g, &g->did, std::max<int64_t>(ntd, 1) * kTile));
   PCPM_TRY_HIP(hipMemsetAsync(g->png_src, 0, std::max<int64_t>(ntp, 1) * kTile * 4, st));
-  PCPM_TRY_HIP(hipMemsetAsync(g->did, 0, std::max<int64_t>(ntd, 1) * kTile * 4, st));
+  PCPM_TRY_HIP(hipMemsetAsync(g->did, 0, std::max<int64_t>(ntd, 1) * kTile * 2, st));
   int nbits = 0;
   while ((int64_t{1} << nbits) < k) ++nbits;
   PCPM_LAUNCH("pcpm_build_fill", k_fill, dim3(kk), dim3(64), static_cast<size_t>(2 * k * 4), st, n, s,
@@ -635,13 +638,15 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(dalloc(g, &g->png_blk, ntp + 1));
   PCPM_TRY(dalloc(g, &g->did_blk, ntd + 1));
   if (ntp > 0) {
-    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags, dim3(static_cast<unsigned>(std::min<int64_t>((ntp + 3) / 4, 16384))),
-                dim3(256), 0, st, g->png_src, ntp, tcnt);
+    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags<uint32_t>,
+                dim3(static_cast<unsigned>(std::min<int64_t>((ntp + 3) / 4, 16384))), dim3(256), 0, st, g->png_src, ntp,
+                tcnt);
   }
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, g->png_blk, ntp);
   if (ntd > 0) {
-    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags, dim3(static_cast<unsigned>(std::min<int64_t>((ntd + 3) / 4, 16384))),
-                dim3(256), 0, st, g->did, ntd, tcnt);
+    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags<uint16_t>,
+                dim3(static_cast<unsigned>(std::min<int64_t>((ntd + 3) / 4, 16384))), dim3(256), 0, st, g->did, ntd,
+                tcnt);
   }
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, g->did_blk, ntd);
 
@@ -750,7 +755,18 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src, 
     PCPM_TRY_HIP(hipMemcpy(png_src, g->png_src, g->eprime * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < g->eprime; ++i) png_src[i] &= static_cast<int32_t>(kIdMask);
   }
-  if (did && g->m > 0) PCPM_TRY_HIP(hipMemcpy(did, g->did, g->m * 4, hipMemcpyDeviceToHost));
+  if (did && g->m > 0) {
+    // stored partition-local with a 16-bit flag; exported as global IDs with the top-bit flag
+    std::vector<uint16_t> loc(g->m);
+    std::vector<int32_t> ds(k + 1);
+    PCPM_TRY_HIP(hipMemcpy(loc.data(), g->did, g->m * 2, hipMemcpyDeviceToHost));
+    PCPM_TRY_HIP(hipMemcpy(ds.data(), g->did_start, (k + 1) * 4, hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < k; ++p) {
+      const uint32_t base = static_cast<uint32_t>(p * g->q);
+      for (int64_t e = ds[p]; e < ds[p + 1]; ++e)
+        did[e] = (base + (loc[e] & (kDidFlag - 1u))) | ((loc[e] & kDidFlag) ? kFlag : 0u);
+    }
+  }
   return PCPM_OK;
 }
 

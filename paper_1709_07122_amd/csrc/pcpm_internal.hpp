@@ -18,6 +18,9 @@ namespace pcpm {
 // partition segment respectively.
 constexpr uint32_t kFlag = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+// Destination IDs are stored partition-local in 16 bits: v - p'q (< q <= 2^14)
+// with bit 15 marking the first ID of each message.
+constexpr uint32_t kDidFlag = 0x8000u;
 
 // Flag-decoding tile: 16 sub-blocks of one wavefront (64 lanes) each.  The
 // running flag count before every tile is stored, so any wavefront can decode
@@ -30,6 +33,7 @@ constexpr int kMaxHist = 100000;   // residual history kept on the device
 constexpr int kMaxParts = 16384;   // k limit (LDS cursors of the fill kernel)
 constexpr int kMinLog2 = 1;
 constexpr int kMaxLog2 = 14;       // 16384 * 8 B = 128 KB fixed-point slice in LDS
+static_assert(kMaxLog2 <= 15, "partition-local destination IDs use 15 bits");
 #ifndef PCPM_SCATTER_BLOCK
 #define PCPM_SCATTER_BLOCK 512
 #endif
@@ -169,7 +173,7 @@ struct pcpm_png {
   int32_t* upd_start = nullptr; // k+1: first update slot of each bin
 
   // gather side: destination-ID bins
-  uint32_t* did = nullptr;      // ceil(m/kTile)*kTile, top bit = first of message
+  uint16_t* did = nullptr;      // ceil(m/kTile)*kTile: v - p'q, bit 15 = first of message
   int32_t* did_blk = nullptr;   // flags before each tile, ceil(m/kTile)+1
   int32_t* did_start = nullptr; // k+1
   float* upd = nullptr;         // E'+1: update bins (rewritten every iteration) + spare slot

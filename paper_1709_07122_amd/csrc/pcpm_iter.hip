@@ -173,7 +173,7 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
-                                               const Item* __restrict__ items, const uint32_t* __restrict__ did,
+                                               const Item* __restrict__ items, const uint16_t* __restrict__ did,
                                                const int32_t* __restrict__ did_blk, const float* __restrict__ upd,
                                                const float* __restrict__ pr_in, float* __restrict__ pr_out,
                                                const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
@@ -197,14 +197,14 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
   uint32_t x[kSub], xn[kSub];
   int64_t t = lo / kTile + threadIdx.x / kWave;
   if (t < t_end) {
-    const uint32_t* dt = did + t * kTile;
+    const uint16_t* dt = did + t * kTile;
 #pragma unroll
     for (int j = 0; j < kSub; ++j) x[j] = dt[j * kWave + lane];
   }
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     if (t + kNW < t_end) {  // the next tile's IDs are in flight during this tile's work
-      const uint32_t* dt = did + (t + kNW) * kTile;
+      const uint16_t* dt = did + (t + kNW) * kTile;
 #pragma unroll
       for (int j = 0; j < kSub; ++j) xn[j] = dt[j * kWave + lane];
     }
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
     uint32_t off[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
-      const bool f = static_cast<int32_t>(x[j]) < 0;
+      const bool f = (x[j] & kDidFlag) != 0u;
       const uint64_t bal = wave_ballot(f);
       // Alg. 5 update pointer (flags so far, inclusive, minus one) relative to ub
       off[j] = static_cast<uint32_t>(run + lanes_below(bal) + (f ? 1 : 0)) * 4u;

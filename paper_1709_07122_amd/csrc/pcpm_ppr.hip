@@ -189,7 +189,7 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
 template <int KT>
 __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                                 const Item* __restrict__ items,
-                                                                const uint32_t* __restrict__ did,
+                                                                const uint16_t* __restrict__ did,
                                                                 const int32_t* __restrict__ did_blk,
                                                                 const float* __restrict__ upd,
                                                                 const float* __restrict__ x_in,
@@ -218,14 +218,14 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
   uint32_t xs[kSub], xn[kSub];
   int64_t t = lo / kTile + threadIdx.x / kWave;
   if (t < t_end) {
-    const uint32_t* dt = did + t * kTile;
+    const uint16_t* dt = did + t * kTile;
 #pragma unroll
     for (int j = 0; j < kSub; ++j) xs[j] = dt[j * kWave + lane];
   }
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     if (t + kNW < t_end) {
-      const uint32_t* dt = did + (t + kNW) * kTile;
+      const uint16_t* dt = did + (t + kNW) * kTile;
 #pragma unroll
       for (int j = 0; j < kSub; ++j) xn[j] = dt[j * kWave + lane];
     }
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
     uint32_t off[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
-      const bool f = static_cast<int32_t>(xs[j]) < 0;
+      const bool f = (xs[j] & kDidFlag) != 0u;
       const uint64_t bal = wave_ballot(f);
       off[j] = static_cast<uint32_t>(run + lanes_below(bal) + (f ? 1 : 0)) * KT;
       run += __popcll(bal);

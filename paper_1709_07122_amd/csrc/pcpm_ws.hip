@@ -46,7 +46,7 @@ __device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(st
 constexpr int kCountBlock = 512;
 
 __global__ __launch_bounds__(kCountBlock) void k_ws_count(int64_t n, int s, const Item* __restrict__ items,
-                                                         const uint32_t* __restrict__ did,
+                                                         const uint16_t* __restrict__ did,
                                                          uint32_t* __restrict__ indeg) {
   extern __shared__ uint32_t cnt[];
   const Item it = items[blockIdx.x];
