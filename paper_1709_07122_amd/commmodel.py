@@ -54,12 +54,15 @@ def gteps(m, seconds_per_iteration):
 TILE = 1024  # destination IDs / PNG edges per stored flag-prefix entry
 
 
-def scatter_bytes(n, eprime, nseg):
+SRC_BYTES = 2  # PNG source IDs are stored partition-local in 16 bits (flag in bit 15)
+
+
+def scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES):
     """Algorithmic bytes of one scatter pass: ranks and out-degrees of every
-    node (8n), the PNG source IDs (4E'), one write offset per non-empty
-    (source, destination) pair (4 nseg, the k^2 d_i term of Eq. 5), the tile
-    flag prefixes (4E'/1024) and the update writes (4E')."""
-    return 8 * n + 4 * eprime + 4 * nseg + 4 * (eprime // TILE + 1) + 4 * eprime
+    node (8n), the PNG source IDs (src_bytes per PNG edge), one write offset
+    per non-empty (source, destination) pair (4 nseg, the k^2 d_i term of
+    Eq. 5), the tile flag prefixes (4E'/1024) and the update writes (4E')."""
+    return 8 * n + src_bytes * eprime + 4 * nseg + 4 * (eprime // TILE + 1) + 4 * eprime
 
 
 DID_BYTES = 2  # destination IDs are stored partition-local in 16 bits (flag in bit 15)

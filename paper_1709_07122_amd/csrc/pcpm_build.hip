@@ -271,7 +271,7 @@ __global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nb
                                              const int32_t* __restrict__ src, const int32_t* __restrict__ did_start,
                                              const int32_t* __restrict__ dwo, const int32_t* __restrict__ png_base,
                                              const int32_t* __restrict__ png_off, uint16_t* __restrict__ did,
-                                             uint32_t* __restrict__ png_src) {
+                                             uint16_t* __restrict__ png_src) {
   extern __shared__ int32_t sh[];
   int32_t* cur_did = sh;   // absolute destination-ID position per p'
   int32_t* cur_rank = sh + k;  // rank inside U(p,p') per p'
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nb
       if (first) {
         const int32_t r = cr + frank;
         const int64_t pos = static_cast<int64_t>(pbase) + png_off[p * (k + 1) + pp] + r;
-        png_src[pos] = static_cast<uint32_t>(u) | (r == 0 ? kFlag : 0u);
+        png_src[pos] = static_cast<uint16_t>((static_cast<uint32_t>(u) & ((1u << s) - 1u)) | (r == 0 ? kDidFlag : 0u));
       }
       if ((peers & below) == 0) {
         cur_did[pp] = cd + __popcll(peers);
@@ -624,7 +624,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   const int64_t ntd = (m + kTile - 1) / kTile;
   PCPM_TRY(dalloc(g, &g->png_src, std::max<int64_t>(ntp, 1) * kTile));
   PCPM_TRY(dalloc(g, &g->did, std::max<int64_t>(ntd, 1) * kTile));
-  PCPM_TRY_HIP(hipMemsetAsync(g->png_src, 0, std::max<int64_t>(ntp, 1) * kTile * 4, st));
+  PCPM_TRY_HIP(hipMemsetAsync(g->png_src, 0, std::max<int64_t>(ntp, 1) * kTile * 2, st));
   PCPM_TRY_HIP(hipMemsetAsync(g->did, 0, std::max<int64_t>(ntd, 1) * kTile * 2, st));
   int nbits = 0;
   while ((int64_t{1} << nbits) < k) ++nbits;
@@ -638,7 +638,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(dalloc(g, &g->png_blk, ntp + 1));
   PCPM_TRY(dalloc(g, &g->did_blk, ntd + 1));
   if (ntp > 0) {
-    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags<uint32_t>,
+    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags<uint16_t>,
                 dim3(static_cast<unsigned>(std::min<int64_t>((ntp + 3) / 4, 16384))), dim3(256), 0, st, g->png_src, ntp,
                 tcnt);
   }
@@ -752,8 +752,14 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src, 
     widen(t, did_start);
   }
   if (png_src && g->eprime > 0) {
-    PCPM_TRY_HIP(hipMemcpy(png_src, g->png_src, g->eprime * 4, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < g->eprime; ++i) png_src[i] &= static_cast<int32_t>(kIdMask);
+    // stored partition-local with a 16-bit flag; exported as global node IDs
+    std::vector<uint16_t> loc(g->eprime);
+    std::vector<int32_t> pb(k + 1);
+    PCPM_TRY_HIP(hipMemcpy(loc.data(), g->png_src, g->eprime * 2, hipMemcpyDeviceToHost));
+    PCPM_TRY_HIP(hipMemcpy(pb.data(), g->png_base, (k + 1) * 4, hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < k; ++p)
+      for (int64_t e = pb[p]; e < pb[p + 1]; ++e)
+        png_src[e] = static_cast<int32_t>(p * g->q + (loc[e] & (kDidFlag - 1u)));
   }
   if (did && g->m > 0) {
     // stored partition-local with a 16-bit flag; exported as global IDs with the top-bit flag

@@ -18,8 +18,9 @@ namespace pcpm {
 // partition segment respectively.
 constexpr uint32_t kFlag = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
-// Destination IDs are stored partition-local in 16 bits: v - p'q (< q <= 2^14)
-// with bit 15 marking the first ID of each message.
+// Destination IDs and PNG source IDs are stored partition-local in 16 bits:
+// v - p'q or u - pq (< q <= 2^14), with bit 15 marking the first ID of each
+// message or the first node of each segment.
 constexpr uint32_t kDidFlag = 0x8000u;
 
 // Flag-decoding tile: 16 sub-blocks of one wavefront (64 lanes) each.  The
@@ -164,7 +165,7 @@ struct pcpm_png {
   uint32_t* dmask = nullptr;    // ceil(n/32) dangling bitmask
 
   // scatter side: PNG in (source partition, destination partition, node) order
-  uint32_t* png_src = nullptr;  // ceil(E'/kTile)*kTile, top bit = segment start
+  uint16_t* png_src = nullptr;  // ceil(E'/kTile)*kTile: u - pq, bit 15 = segment start
   int32_t* png_blk = nullptr;   // flags before each tile, ceil(E'/kTile)+1
   int32_t* seg_delta = nullptr; // nseg: update slot minus PNG position per segment
   int32_t* png_base = nullptr;  // k+1: first PNG edge of each source partition

@@ -103,7 +103,7 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                 const Item* __restrict__ items, const float* __restrict__ pr,
                                                 const int32_t* __restrict__ outdeg,
-                                                const uint32_t* __restrict__ png_src,
+                                                const uint16_t* __restrict__ png_src,
                                                 const int32_t* __restrict__ png_blk,
                                                 const int32_t* __restrict__ seg_delta, float* __restrict__ upd,
                                                 int64_t spare) {
@@ -126,14 +126,14 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   uint32_t x[kSub], xn[kSub];
   int64_t t = lo / kTile + threadIdx.x / kWave;
   if (t < t_end) {
-    const uint32_t* pt = png_src + t * kTile;
+    const uint16_t* pt = png_src + t * kTile;
 #pragma unroll
     for (int j = 0; j < kSub; ++j) x[j] = pt[j * kWave + lane];
   }
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     if (t + kNW < t_end) {  // the next tile's loads overlap this tile's work
-      const uint32_t* pt = png_src + (t + kNW) * kTile;
+      const uint16_t* pt = png_src + (t + kNW) * kTile;
 #pragma unroll
       for (int j = 0; j < kSub; ++j) xn[j] = pt[j * kWave + lane];
     }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
     int32_t seg[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
-      const bool f = static_cast<int32_t>(x[j]) < 0;
+      const bool f = (x[j] & kDidFlag) != 0u;
       const uint64_t bal = wave_ballot(f);
       seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
       run += __popcll(bal);

@@ -44,7 +44,7 @@ template <int KT>
 __global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                            const Item* __restrict__ items, const float* __restrict__ x,
                                                            const int32_t* __restrict__ outdeg,
-                                                           const uint32_t* __restrict__ png_src,
+                                                           const uint16_t* __restrict__ png_src,
                                                            const int32_t* __restrict__ png_blk,
                                                            const int32_t* __restrict__ seg_delta,
                                                            float* __restrict__ upd, int64_t spare) {
@@ -66,14 +66,14 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict
   uint32_t xs[kSub], xn[kSub];
   int64_t t = lo / kTile + threadIdx.x / kWave;
   if (t < t_end) {
-    const uint32_t* pt = png_src + t * kTile;
+    const uint16_t* pt = png_src + t * kTile;
 #pragma unroll
     for (int j = 0; j < kSub; ++j) xs[j] = pt[j * kWave + lane];
   }
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     if (t + kNW < t_end) {
-      const uint32_t* pt = png_src + (t + kNW) * kTile;
+      const uint16_t* pt = png_src + (t + kNW) * kTile;
 #pragma unroll
       for (int j = 0; j < kSub; ++j) xn[j] = pt[j * kWave + lane];
     }
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict
     int32_t seg[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
-      const bool f = static_cast<int32_t>(xs[j]) < 0;
+      const bool f = (xs[j] & kDidFlag) != 0u;
       const uint64_t bal = wave_ballot(f);
       seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
       run += __popcll(bal);

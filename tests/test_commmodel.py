@@ -42,9 +42,9 @@ def test_gteps_definition():
 def test_implementation_bytes_cover_eq5():
     n, m, ep, k = 1 << 24, 263_400_000, 174_000_000, 1024
     ours = cm.iteration_bytes(n, m, ep, k * k)
-    # Eq. 5 with the destination IDs (its m d_i term) at the 2 bytes they are
-    # stored in; the PNG source IDs (m d_i / r) stay 4 bytes
-    eq5 = cm.pcpm_comm(n, m, k, m / ep) - (4 - cm.DID_BYTES) * m
+    # Eq. 5 with the destination IDs (its m d_i term) and the PNG source IDs
+    # (its m d_i / r term) at the 2 bytes they are stored in
+    eq5 = cm.pcpm_comm(n, m, k, m / ep) - (4 - cm.DID_BYTES) * m - (4 - cm.SRC_BYTES) * ep
     # the same terms plus 8 B per node (residual read, out-degrees) and the
     # tile prefixes; never less than that
     assert eq5 < ours < eq5 + 8.5 * n + 4 * (m + ep) / 1024 + 8
