@@ -239,24 +239,48 @@ __global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ 
   if (threadIdx.x == 0) out[L] = static_cast<int32_t>(tot);
 }
 
-// seg_delta[s] for the s-th non-empty segment in (p, p') order: update slot of
-// the segment's first entry minus its PNG position.  One workgroup per row.
+// The scatter walks source partitions in pairs (P = {2P', 2P'+1}): for each
+// destination p', the segments (2P', p') and (2P'+1, p') are adjacent in bin
+// p' (the write offset of the second starts where the first ends), so the pair
+// writes them as one run.  PNG edges are stored in (pair, p', node) order and
+// a "pair segment" is the union of the two.  The bins, and the canonical
+// per-partition layout that pcpm_png_export returns, are unchanged.
+__device__ __forceinline__ int32_t pair_cnt(const int32_t* __restrict__ cnt, int32_t k, int64_t pair, int32_t j) {
+  const int64_t p0 = 2 * pair, p1 = 2 * pair + 1;
+  return cnt[p0 * k + j] + (p1 < k ? cnt[p1 * k + j] : 0);
+}
+
+// Non-empty pair segments of each pair.  One workgroup per pair.
+__global__ __launch_bounds__(256) void k_pairseg(int32_t k, const int32_t* __restrict__ cnt,
+                                                 int32_t* __restrict__ pairseg) {
+  const int64_t pr = blockIdx.x;
+  int64_t nz = 0;
+  for (int32_t j = threadIdx.x; j < k; j += blockDim.x) nz += (pair_cnt(cnt, k, pr, j) > 0);
+  int64_t tot = 0;
+  (void)block_excl_scan(nz, &tot);
+  if (threadIdx.x == 0) pairseg[pr] = static_cast<int32_t>(tot);
+}
+
+// seg_delta[s] for the s-th non-empty pair segment in (pair, p') order: update
+// slot of its first entry minus its position in the pair-ordered PNG edges.
+// One workgroup per pair.
 __global__ __launch_bounds__(256) void k_segdelta(int32_t k, const int32_t* __restrict__ cnt,
                                                   const int32_t* __restrict__ wo, const int32_t* __restrict__ png_off,
                                                   const int32_t* __restrict__ upd_start,
                                                   const int32_t* __restrict__ png_base,
                                                   const int32_t* __restrict__ segbase, int32_t* __restrict__ seg_delta) {
-  const int64_t p = blockIdx.x;
+  const int64_t pr = blockIdx.x, p0 = 2 * pr, p1 = 2 * pr + 1;
   const int32_t per = (k + blockDim.x - 1) / blockDim.x;
   const int32_t j0 = min(k, static_cast<int32_t>(threadIdx.x) * per), j1 = min(k, j0 + per);
   int64_t nz = 0;
-  for (int32_t j = j0; j < j1; ++j) nz += (cnt[p * k + j] > 0);
+  for (int32_t j = j0; j < j1; ++j) nz += (pair_cnt(cnt, k, pr, j) > 0);
   int64_t tot = 0;
-  int64_t idx = segbase[p] + block_excl_scan(nz, &tot);
+  int64_t idx = segbase[pr] + block_excl_scan(nz, &tot);
   for (int32_t j = j0; j < j1; ++j) {
-    if (cnt[p * k + j] > 0) {
-      const int64_t slot = static_cast<int64_t>(upd_start[j]) + wo[p * k + j];
-      const int64_t pos = static_cast<int64_t>(png_base[p]) + png_off[p * (k + 1) + j];
+    if (pair_cnt(cnt, k, pr, j) > 0) {
+      const int64_t slot = static_cast<int64_t>(upd_start[j]) + wo[p0 * k + j];
+      const int64_t pos = static_cast<int64_t>(png_base[p0]) + png_off[p0 * (k + 1) + j] +
+                          (p1 < k ? png_off[p1 * (k + 1) + j] : 0);
       seg_delta[idx++] = static_cast<int32_t>(slot - pos);
     }
   }
@@ -285,7 +309,6 @@ __global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nb
   const int64_t u0 = p << s;
   const int64_t u1 = min(n, u0 + (int64_t{1} << s));
   const int32_t e0 = row_off[u0], e1 = row_off[u1];
-  const int32_t pbase = png_base[p];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int32_t cb = e0; cb < e1; cb += kWave) {
     const int32_t e = cb + lane;
@@ -317,9 +340,18 @@ __global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nb
     if (valid) {
       did[cd + rank] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | (first ? kDidFlag : 0u));
       if (first) {
+        // position in the pair-ordered PNG edges: after the pair's earlier
+        // pair segments and, for the odd partition, after the even one's run
         const int32_t r = cr + frank;
-        const int64_t pos = static_cast<int64_t>(pbase) + png_off[p * (k + 1) + pp] + r;
-        png_src[pos] = static_cast<uint16_t>((static_cast<uint32_t>(u) & ((1u << s) - 1u)) | (r == 0 ? kDidFlag : 0u));
+        const int64_t p0 = p & ~int64_t{1}, p1 = p0 + 1;
+        const int32_t even_off = png_off[p0 * (k + 1) + pp];
+        const int32_t even_cnt = png_off[p0 * (k + 1) + pp + 1] - even_off;
+        const int32_t odd_off = p1 < k ? png_off[p1 * (k + 1) + pp] : 0;
+        const bool odd = (p & 1) != 0;
+        const int64_t pos = static_cast<int64_t>(png_base[p0]) + even_off + odd_off + (odd ? even_cnt : 0) + r;
+        const bool seg_first = r == 0 && (!odd || even_cnt == 0);
+        // source ID local to the pair's 2q nodes, flag on the pair segment's first node
+        png_src[pos] = static_cast<uint16_t>((static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u));
       }
       if ((peers & below) == 0) {
         cur_did[pp] = cd + __popcll(peers);
@@ -435,13 +467,13 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
 
   std::vector<Item> sc_items, ga_items;
   std::vector<Merge> mg;
-  for (int64_t p = 0; p < k; ++p) {
-    const int64_t a = png_base[p], b = png_base[p + 1];
+  for (int64_t pr = 0; 2 * pr < k; ++pr) {  // scatter items: ranges of one partition pair's PNG edges
+    const int64_t a = png_base[2 * pr], b = png_base[std::min<int64_t>(2 * pr + 2, k)];
     if (b == a) continue;
-    const int64_t nch = (b - a + sc - 1) / sc;
+    const int64_t nch = (b - a + 2 * sc - 1) / (2 * sc);
     const int64_t step = (b - a + nch - 1) / nch;
     for (int64_t lo = a; lo < b; lo += step)
-      sc_items.push_back({static_cast<int32_t>(p), static_cast<int32_t>(lo),
+      sc_items.push_back({static_cast<int32_t>(pr), static_cast<int32_t>(lo),
                           static_cast<int32_t>(std::min(b, lo + step)), 0});
   }
   int32_t slot = 0;
@@ -607,17 +639,20 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, coltot, g->upd_start, k);
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, coltot_raw, g->did_start, k);
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowtot, g->png_base, k);
-  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowseg, segbase, k);
+  const int64_t npairs = (k + 1) / 2;
+  PCPM_LAUNCH("pcpm_build_pairseg", k_pairseg, dim3(static_cast<unsigned>(npairs)), dim3(256), 0, st,
+              static_cast<int32_t>(k), cnt, rowseg);
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowseg, segbase, npairs);
   int32_t tot[2] = {0, 0};
   PCPM_TRY_HIP(hipMemcpyAsync(&tot[0], g->upd_start + k, 4, hipMemcpyDeviceToHost, st));
-  PCPM_TRY_HIP(hipMemcpyAsync(&tot[1], segbase + k, 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(&tot[1], segbase + npairs, 4, hipMemcpyDeviceToHost, st));
   PCPM_TRY_HIP(hipStreamSynchronize(st));
   g->eprime = tot[0];
   g->nseg = tot[1];
 
   PCPM_TRY(dalloc(g, &g->seg_delta, g->nseg));
-  PCPM_LAUNCH("pcpm_build_segdelta", k_segdelta, dim3(kk), dim3(256), 0, st, static_cast<int32_t>(k), cnt, g->wo,
-              g->png_off, g->upd_start, g->png_base, segbase, g->seg_delta);
+  PCPM_LAUNCH("pcpm_build_segdelta", k_segdelta, dim3(static_cast<unsigned>(npairs)), dim3(256), 0, st,
+              static_cast<int32_t>(k), cnt, g->wo, g->png_off, g->upd_start, g->png_base, segbase, g->seg_delta);
 
   // ---- fill --------------------------------------------------------------------
   const int64_t ntp = (g->eprime + kTile - 1) / kTile;
@@ -755,11 +790,22 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src, 
     // stored partition-local with a 16-bit flag; exported as global node IDs
     std::vector<uint16_t> loc(g->eprime);
     std::vector<int32_t> pb(k + 1);
+    std::vector<int32_t> po(k * (k + 1));
     PCPM_TRY_HIP(hipMemcpy(loc.data(), g->png_src, g->eprime * 2, hipMemcpyDeviceToHost));
     PCPM_TRY_HIP(hipMemcpy(pb.data(), g->png_base, (k + 1) * 4, hipMemcpyDeviceToHost));
-    for (int64_t p = 0; p < k; ++p)
-      for (int64_t e = pb[p]; e < pb[p + 1]; ++e)
-        png_src[e] = static_cast<int32_t>(p * g->q + (loc[e] & (kDidFlag - 1u)));
+    PCPM_TRY_HIP(hipMemcpy(po.data(), g->png_off, po.size() * 4, hipMemcpyDeviceToHost));
+    // stored in partition-pair order (see k_segdelta); exported per partition
+    for (int64_t p = 0; p < k; ++p) {
+      const int64_t p0 = p & ~int64_t{1}, p1 = p0 + 1;
+      for (int64_t j = 0; j < k; ++j) {
+        const int64_t a = po[p * (k + 1) + j], c = po[p * (k + 1) + j + 1] - a;
+        const int64_t even_off = po[p0 * (k + 1) + j], even_cnt = po[p0 * (k + 1) + j + 1] - even_off;
+        const int64_t odd_off = p1 < k ? po[p1 * (k + 1) + j] : 0;
+        const int64_t src = pb[p0] + even_off + odd_off + ((p & 1) ? even_cnt : 0);
+        for (int64_t r = 0; r < c; ++r)
+          png_src[pb[p] + a + r] = static_cast<int32_t>(p0 * g->q + (loc[src + r] & (kDidFlag - 1u)));
+      }
+    }
   }
   if (did && g->m > 0) {
     // stored partition-local with a 16-bit flag; exported as global IDs with the top-bit flag

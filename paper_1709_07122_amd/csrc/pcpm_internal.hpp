@@ -36,7 +36,7 @@ constexpr int kMinLog2 = 1;
 constexpr int kMaxLog2 = 14;       // 16384 * 8 B = 128 KB fixed-point slice in LDS
 static_assert(kMaxLog2 <= 15, "partition-local destination IDs use 15 bits");
 #ifndef PCPM_SCATTER_BLOCK
-#define PCPM_SCATTER_BLOCK 512
+#define PCPM_SCATTER_BLOCK 1024
 #endif
 #ifndef PCPM_GATHER_BLOCK
 #define PCPM_GATHER_BLOCK 1024
@@ -165,9 +165,9 @@ struct pcpm_png {
   uint32_t* dmask = nullptr;    // ceil(n/32) dangling bitmask
 
   // scatter side: PNG in (source partition, destination partition, node) order
-  uint16_t* png_src = nullptr;  // ceil(E'/kTile)*kTile: u - pq, bit 15 = segment start
+  uint16_t* png_src = nullptr;  // ceil(E'/kTile)*kTile, in partition-pair order: u - 2Pq, bit 15 = pair segment start
   int32_t* png_blk = nullptr;   // flags before each tile, ceil(E'/kTile)+1
-  int32_t* seg_delta = nullptr; // nseg: update slot minus PNG position per segment
+  int32_t* seg_delta = nullptr; // nseg: update slot minus PNG position per non-empty pair segment
   int32_t* png_base = nullptr;  // k+1: first PNG edge of each source partition
   int32_t* png_off = nullptr;   // k*(k+1): partition-local PNG offsets
   int32_t* wo = nullptr;        // k*k: write offsets (Sec. 3.1)

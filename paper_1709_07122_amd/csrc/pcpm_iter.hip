@@ -111,15 +111,16 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   extern __shared__ float spr[];
   // XCD-contiguous renumbering (the build arranges the item array for it)
   const Item it = items[xcd_block(blockIdx.x, gridDim.x)];
-  const int64_t v0 = static_cast<int64_t>(it.part) << s;
-  const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
+  // a scatter item covers PNG edges of one partition pair: stage both slices
+  const int64_t v0 = static_cast<int64_t>(it.part) << (s + 1);
+  const int qn = static_cast<int>(min(int64_t{2} << s, n - v0));
   for (int i = threadIdx.x; i < qn; i += BS) {
     const int od = outdeg[v0 + i];
     spr[i] = od > 0 ? pr[v0 + i] / static_cast<float>(od) : 0.0f;
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t qmask = (1u << s) - 1u;
+  const uint32_t qmask = (2u << s) - 1u;  // source IDs are local to the pair
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
@@ -467,7 +468,7 @@ pcpm_status_t iter_lds_limits() {
   static bool done = false;
   if (done) return PCPM_OK;
   PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter<kScatterBlock>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 4));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (2 << kMaxLog2) * 4));
   PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
   done = true;
@@ -491,7 +492,7 @@ static pcpm_status_t reset_ctl(pcpm_png* g, double tol, double d, hipStream_t st
 static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hipStream_t st) {
   if (g->n_sc)
     PCPM_LAUNCH("pcpm_scatter", k_scatter<kScatterBlock>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kScatterBlock),
-                static_cast<size_t>(g->q) * 4, st, g->ctl, g->n, g->part_log2, g->sc_items, in, g->outdeg,
+                static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->sc_items, in, g->outdeg,
                 g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
   PCPM_LAUNCH("pcpm_gather", k_gather<kGatherBlock>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kGatherBlock),
               static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items, g->did, g->did_blk,

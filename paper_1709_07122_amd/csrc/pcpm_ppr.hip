@@ -19,7 +19,8 @@
 
 namespace pcpm {
 
-constexpr int kPprBlock = 512;         // scatter and merge workgroups
+constexpr int kPprBlock = 512;          // merge workgroups
+constexpr int kPprScatterBlock = 1024;  // scatter workgroups (a pair's slice takes up to 128 KB of LDS)
 constexpr int kPprGatherBlock = 1024;  // gather workgroups (a 128 KB slice leaves room for one per CU)
 
 template <int KT>
@@ -41,7 +42,7 @@ __device__ __forceinline__ void copy_kt(float* __restrict__ dst, const float* __
 // while this one is written.  Entries of edge tiles outside [lo, hi) write
 // to the spare slot E'.
 template <int KT>
-__global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
+__global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                            const Item* __restrict__ items, const float* __restrict__ x,
                                                            const int32_t* __restrict__ outdeg,
                                                            const uint16_t* __restrict__ png_src,
@@ -49,20 +50,20 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_scatter(const Ctl* __restrict
                                                            const int32_t* __restrict__ seg_delta,
                                                            float* __restrict__ upd, int64_t spare) {
   if (ctl->done) return;
-  extern __shared__ float spr[];  // q * KT scaled values of the source partition
+  extern __shared__ float spr[];  // 2q * KT scaled values of the source partition pair
   const Item it = items[xcd_block(blockIdx.x, gridDim.x)];  // as in the plain scatter
-  const int64_t v0 = static_cast<int64_t>(it.part) << s;
-  const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
-  for (int i = threadIdx.x; i < qn * KT; i += kPprBlock) {
+  const int64_t v0 = static_cast<int64_t>(it.part) << (s + 1);  // a partition pair
+  const int qn = static_cast<int>(min(int64_t{2} << s, n - v0));
+  for (int i = threadIdx.x; i < qn * KT; i += kPprScatterBlock) {
     const int od = outdeg[v0 + i / KT];
     spr[i] = od > 0 ? x[v0 * KT + i] / static_cast<float>(od) : 0.0f;
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t qmask = (1u << s) - 1u;
+  const uint32_t qmask = (2u << s) - 1u;
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
-  constexpr int kNW = kPprBlock / kWave;
+  constexpr int kNW = kPprScatterBlock / kWave;
   uint32_t xs[kSub], xn[kSub];
   int64_t t = lo / kTile + threadIdx.x / kWave;
   if (t < t_end) {
@@ -429,7 +430,7 @@ __global__ void k_ppr_ctl(Ctl* ctl, double tol, double d) {
 template <int KT>
 static pcpm_status_t ppr_set_lds(int s) {
   PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ppr_scatter<KT>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << s) * KT * 4));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (2 << s) * KT * 4));
   PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ppr_gather<KT>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (1 << s) * KT * 8));
   return PCPM_OK;
@@ -439,8 +440,8 @@ template <int KT>
 static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, hipStream_t st) {
   const int s = g->part_log2;
   if (g->n_sc)
-    PCPM_LAUNCH("pcpm_ppr_scatter", k_ppr_scatter<KT>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kPprBlock),
-                static_cast<size_t>(g->q) * KT * 4, st, g->ctl, g->n, s, g->sc_items, in, g->outdeg, g->png_src,
+    PCPM_LAUNCH("pcpm_ppr_scatter", k_ppr_scatter<KT>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kPprScatterBlock),
+                static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->sc_items, in, g->outdeg, g->png_src,
                 g->png_blk, g->seg_delta, g->ppr_upd, g->eprime);
   PCPM_LAUNCH("pcpm_ppr_gather", k_ppr_gather<KT>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kPprGatherBlock),
               static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->ga_items, g->did, g->did_blk, g->ppr_upd,
