@@ -61,8 +61,9 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
   const double unit = ldexp(1.0, -ctl->fx_shift);
   double sums[2] = {0.0, 0.0};  // residual, dangling mass
   float mx = 0.0f;               // largest new value: the next fixed-point scale
-  // kU nodes per thread per step, loads first, so their latencies overlap
-  constexpr int kU = 4;
+  // kU nodes per thread per step, loads first, so their latencies overlap;
+  // a 1024-thread gather covers a whole 16K-node slice in one step
+  constexpr int kU = BS >= 1024 ? 16 : 4;
   for (int i = i0 + static_cast<int>(threadIdx.x); i < i1; i += kU * BS) {
     float xo[kU];
     uint32_t dw[kU];
