@@ -127,22 +127,33 @@ __global__ __launch_bounds__(256) void k_big_rows(int64_t n, const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------------
-// Count: workgroup p histograms the destination partitions of p's edges.
-// An edge is the first of its message when it starts its row or its
+// The count and fill passes work on chunks of one source partition's edges
+// (CSR order), so that a partition with many edges (hubs under in-degree
+// labels) is spread over many workgroups.  For chunk c of partition p,
+// ccnt[c][p'] / craw[c][p'] count its first-of-message edges (the PNG edges
+// it contributes to U(p,p')) and all its edges into p'.
+
+// Partition edge bounds: pe[p] = row_off[min(n, p q)], p = 0..k.
+__global__ __launch_bounds__(256) void k_part_edges(int64_t n, int s, int32_t k, const int32_t* __restrict__ row_off,
+                                                    int32_t* __restrict__ pe) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p <= k) pe[p] = row_off[min(n, p << s)];
+}
+
+// Count: workgroup c histograms the destination partitions of chunk c's
+// edges.  An edge is the first of its message when it starts its row or its
 // destination partition differs from the previous edge's (rows are sorted).
-__global__ __launch_bounds__(1024) void k_count(int64_t n, int s, int32_t k, const int32_t* __restrict__ row_off,
+__global__ __launch_bounds__(1024) void k_count(int s, int32_t k, const Item* __restrict__ chunks,
                                                 const int32_t* __restrict__ col, const int32_t* __restrict__ src,
-                                                int32_t* __restrict__ cnt, int32_t* __restrict__ raw) {
+                                                int32_t* __restrict__ ccnt, int32_t* __restrict__ craw) {
   extern __shared__ int32_t sh[];
   int32_t* c_l = sh;
   int32_t* r_l = sh + k;
   for (int32_t i = threadIdx.x; i < 2 * k; i += blockDim.x) sh[i] = 0;
   __syncthreads();
-  const int64_t p = blockIdx.x;
-  const int64_t u0 = p << s;
-  const int64_t u1 = min(n, u0 + (int64_t{1} << s));
-  const int32_t e0 = row_off[u0], e1 = row_off[u1];
-  for (int32_t e = e0 + static_cast<int32_t>(threadIdx.x); e < e1; e += blockDim.x) {
+  const int64_t c = blockIdx.x;
+  const Item ch = chunks[c];
+  for (int32_t e = ch.lo + static_cast<int32_t>(threadIdx.x); e < ch.hi; e += blockDim.x) {
     const int32_t u = src[e];
     const int32_t pp = col[e] >> s;
     const bool first = (e == 0) || (src[e - 1] != u) || ((col[e - 1] >> s) != pp);
@@ -151,9 +162,31 @@ __global__ __launch_bounds__(1024) void k_count(int64_t n, int s, int32_t k, con
   }
   __syncthreads();
   for (int32_t i = threadIdx.x; i < k; i += blockDim.x) {
-    cnt[p * k + i] = c_l[i];
-    raw[p * k + i] = r_l[i];
+    ccnt[c * k + i] = c_l[i];
+    craw[c * k + i] = r_l[i];
   }
+}
+
+// Per partition p and destination p': exclusive prefix of the chunk counts
+// over p's chunks (in place: each chunk's starting rank and position inside
+// the (p, p') segment and its run of the bin) and the totals cnt/raw[p][p'].
+__global__ __launch_bounds__(256) void k_chunk_scan(int32_t k, const int32_t* __restrict__ cfirst,
+                                                    int32_t* __restrict__ ccnt, int32_t* __restrict__ craw,
+                                                    int32_t* __restrict__ cnt, int32_t* __restrict__ raw) {
+  const int64_t p = blockIdx.x;
+  const int32_t j = static_cast<int32_t>(blockIdx.y * blockDim.x + threadIdx.x);
+  if (j >= k) return;
+  int32_t sc = 0, sr = 0;
+  for (int64_t c = cfirst[p]; c < cfirst[p + 1]; ++c) {
+    const int64_t idx = c * k + j;
+    const int32_t a = ccnt[idx], b = craw[idx];
+    ccnt[idx] = sc;
+    craw[idx] = sr;
+    sc += a;
+    sr += b;
+  }
+  cnt[p * k + j] = sc;
+  raw[p * k + j] = sr;
 }
 
 // Column prefix over source partitions: write offsets wo[p][p'] (updates) and
@@ -286,29 +319,31 @@ __global__ __launch_bounds__(256) void k_segdelta(int32_t k, const int32_t* __re
   }
 }
 
-// Fill: one wavefront per source partition, edges in CSR order, 64 at a time.
-// Lanes with the same destination partition form a peer group (found with one
+// Fill: one wavefront per chunk, edges in CSR order, 64 at a time.  Lanes
+// with the same destination partition form a peer group (found with one
 // ballot per key bit); an edge's position in its bin is the group cursor plus
-// the number of peer lanes below it.  The lowest peer advances the cursors.
-__global__ __launch_bounds__(64) void k_fill(int64_t n, int s, int32_t k, int nbits,
-                                             const int32_t* __restrict__ row_off, const int32_t* __restrict__ col,
-                                             const int32_t* __restrict__ src, const int32_t* __restrict__ did_start,
-                                             const int32_t* __restrict__ dwo, const int32_t* __restrict__ png_base,
+// the number of peer lanes below it.  The lowest peer advances the cursors,
+// which start at the chunk's prefixes of its partition's counts.
+__global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const Item* __restrict__ chunks,
+                                             const int32_t* __restrict__ col, const int32_t* __restrict__ src,
+                                             const int32_t* __restrict__ did_start, const int32_t* __restrict__ dwo,
+                                             const int32_t* __restrict__ ccnt, const int32_t* __restrict__ craw,
+                                             const int32_t* __restrict__ png_base,
                                              const int32_t* __restrict__ png_off, uint16_t* __restrict__ did,
                                              uint16_t* __restrict__ png_src) {
   extern __shared__ int32_t sh[];
   int32_t* cur_did = sh;   // absolute destination-ID position per p'
   int32_t* cur_rank = sh + k;  // rank inside U(p,p') per p'
-  const int64_t p = blockIdx.x;
+  const int64_t c = blockIdx.x;
+  const Item ch = chunks[c];
+  const int64_t p = ch.part;
   const int lane = threadIdx.x;
   for (int32_t j = lane; j < k; j += kWave) {
-    cur_did[j] = did_start[j] + dwo[p * k + j];
-    cur_rank[j] = 0;
+    cur_did[j] = did_start[j] + dwo[p * k + j] + craw[c * k + j];
+    cur_rank[j] = ccnt[c * k + j];
   }
   __syncthreads();
-  const int64_t u0 = p << s;
-  const int64_t u1 = min(n, u0 + (int64_t{1} << s));
-  const int32_t e0 = row_off[u0], e1 = row_off[u1];
+  const int32_t e0 = ch.lo, e1 = ch.hi;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int32_t cb = e0; cb < e1; cb += kWave) {
     const int32_t e = cb + lane;
@@ -630,8 +665,40 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(dalloc(g, &g->did_start, k + 1));
   PCPM_TRY(dalloc(g, &g->png_base, k + 1));
   const unsigned kk = static_cast<unsigned>(k);
-  PCPM_LAUNCH("pcpm_build_count", k_count, dim3(kk), dim3(1024), static_cast<size_t>(2 * k * 4), st, n, s,
-              static_cast<int32_t>(k), row_off, col, src, cnt, raw);
+  // chunks of each source partition's edges, about m / max(k, 4096) edges each
+  // (at least 16384), so that skewed partitions spread over many workgroups
+  int32_t* pe_d = nullptr;
+  PCPM_TRY(dalloc(g, &pe_d, k + 1));
+  PCPM_LAUNCH("pcpm_build_chunks", k_part_edges, dim3(static_cast<unsigned>((k + 1 + 255) / 256)), dim3(256), 0, st,
+              n, s, static_cast<int32_t>(k), row_off, pe_d);
+  std::vector<int32_t> pe(k + 1), cfirst(k + 1);
+  PCPM_TRY_HIP(hipMemcpyAsync(pe.data(), pe_d, (k + 1) * 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  const int64_t chunk_len = std::max<int64_t>(16384, (m + std::max<int64_t>(k, 4096) - 1) / std::max<int64_t>(k, 4096));
+  std::vector<Item> chunks;
+  for (int64_t p = 0; p < k; ++p) {
+    cfirst[p] = static_cast<int32_t>(chunks.size());
+    const int64_t a = pe[p], b = pe[p + 1];
+    const int64_t nch = std::max<int64_t>(1, (b - a + chunk_len - 1) / chunk_len);
+    const int64_t step = std::max<int64_t>(1, (b - a + nch - 1) / nch);
+    if (b == a) chunks.push_back({static_cast<int32_t>(p), static_cast<int32_t>(a), static_cast<int32_t>(a), 0});
+    for (int64_t lo = a; lo < b; lo += step)
+      chunks.push_back({static_cast<int32_t>(p), static_cast<int32_t>(lo), static_cast<int32_t>(std::min(b, lo + step)), 0});
+  }
+  cfirst[k] = static_cast<int32_t>(chunks.size());
+  const int64_t nchunks = static_cast<int64_t>(chunks.size());
+  Item* chunks_d = nullptr;
+  int32_t *cfirst_d = nullptr, *ccnt = nullptr, *craw = nullptr;
+  PCPM_TRY(dalloc(g, &chunks_d, nchunks));
+  PCPM_TRY(dalloc(g, &cfirst_d, k + 1));
+  PCPM_TRY(dalloc(g, &ccnt, nchunks * k));
+  PCPM_TRY(dalloc(g, &craw, nchunks * k));
+  PCPM_TRY_HIP(hipMemcpyAsync(chunks_d, chunks.data(), nchunks * sizeof(Item), hipMemcpyHostToDevice, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(cfirst_d, cfirst.data(), (k + 1) * 4, hipMemcpyHostToDevice, st));
+  PCPM_LAUNCH("pcpm_build_count", k_count, dim3(static_cast<unsigned>(nchunks)), dim3(1024),
+              static_cast<size_t>(2 * k * 4), st, s, static_cast<int32_t>(k), chunks_d, col, src, ccnt, craw);
+  PCPM_LAUNCH("pcpm_build_count", k_chunk_scan, dim3(kk, static_cast<unsigned>((k + 255) / 256)), dim3(256), 0, st,
+              static_cast<int32_t>(k), cfirst_d, ccnt, craw, cnt, raw);
   PCPM_LAUNCH("pcpm_build_colscan", k_colscan, dim3((kk + 255) / 256), dim3(256), 0, st, static_cast<int32_t>(k),
               cnt, raw, g->wo, dwo, coltot, coltot_raw);
   PCPM_LAUNCH("pcpm_build_rowscan", k_rowscan, dim3(kk), dim3(256), 0, st, static_cast<int32_t>(k), cnt,
@@ -663,9 +730,9 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY_HIP(hipMemsetAsync(g->did, 0, std::max<int64_t>(ntd, 1) * kTile * 2, st));
   int nbits = 0;
   while ((int64_t{1} << nbits) < k) ++nbits;
-  PCPM_LAUNCH("pcpm_build_fill", k_fill, dim3(kk), dim3(64), static_cast<size_t>(2 * k * 4), st, n, s,
-              static_cast<int32_t>(k), nbits, row_off, col, src, g->did_start, dwo, g->png_base, g->png_off, g->did,
-              g->png_src);
+  PCPM_LAUNCH("pcpm_build_fill", k_fill, dim3(static_cast<unsigned>(nchunks)), dim3(64),
+              static_cast<size_t>(2 * k * 4), st, s, static_cast<int32_t>(k), nbits, chunks_d, col, src,
+              g->did_start, dwo, ccnt, craw, g->png_base, g->png_off, g->did, g->png_src);
 
   // ---- tile flag prefixes ----------------------------------------------------
   int32_t* tcnt = nullptr;
@@ -695,6 +762,9 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
 
   // ---- release build-only buffers ------------------------------------------------
   PCPM_TRY_HIP(hipStreamSynchronize(st));
+  for (void* p : {static_cast<void*>(pe_d), static_cast<void*>(chunks_d), static_cast<void*>(cfirst_d),
+                  static_cast<void*>(ccnt), static_cast<void*>(craw)})
+    dfree(g, p);
   for (void* p : {static_cast<void*>(src), static_cast<void*>(big), static_cast<void*>(counters),
                   static_cast<void*>(raw), static_cast<void*>(dwo), static_cast<void*>(coltot),
                   static_cast<void*>(coltot_raw), static_cast<void*>(rowtot), static_cast<void*>(rowseg),
