@@ -69,6 +69,8 @@ typedef struct {
   const int64_t* graph_nodes;    /* (host) G, required when G > 1            */
   int64_t scatter_chunk; /* PNG edges per scatter work item; 0 = automatic   */
   int64_t gather_chunk;  /* destination IDs per gather work item; 0 = auto   */
+  int64_t build_chunk;   /* CSR edges per count/fill work item of the build;
+                            0 = automatic (about m / max(k, 4096), >= 16384)  */
 } pcpm_build_opts_t;
 
 typedef struct {

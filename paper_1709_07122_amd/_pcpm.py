@@ -49,7 +49,8 @@ class PCPMError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("part_log2", ctypes.c_int32), ("num_graphs", ctypes.c_int32),
                 ("graph_node_off", ctypes.c_void_p), ("graph_nodes", ctypes.c_void_p),
-                ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64)]
+                ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64),
+                ("build_chunk", ctypes.c_int64)]
 
 
 class PngInfo(ctypes.Structure):
@@ -211,7 +212,7 @@ class PNG:
 
 
 def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_chunk: int = 0,
-              graph_node_off=None, graph_nodes=None, stream=None) -> PNG:
+              graph_node_off=None, graph_nodes=None, build_chunk: int = 0, stream=None) -> PNG:
     """pcpm_build_png on device CSR tensors (int32 row_off[n+1], col[m]).
 
     For several graphs in one handle pass the padded union (see union_csr)
@@ -225,7 +226,7 @@ def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_c
     goff = np.ascontiguousarray(graph_node_off if G else [0], dtype=np.int64)
     gn = np.ascontiguousarray(graph_nodes if G else [0], dtype=np.int64)
     opts = BuildOpts(int(part_log2), G, goff.ctypes.data if G else None, gn.ctypes.data if G else None,
-                     int(scatter_chunk), int(gather_chunk))
+                     int(scatter_chunk), int(gather_chunk), int(build_chunk))
     h = ctypes.c_void_p()
     _check(lib().pcpm_build_png(n, m, rp, cp, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return PNG(h, row_off, col)

@@ -674,7 +674,9 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   std::vector<int32_t> pe(k + 1), cfirst(k + 1);
   PCPM_TRY_HIP(hipMemcpyAsync(pe.data(), pe_d, (k + 1) * 4, hipMemcpyDeviceToHost, st));
   PCPM_TRY_HIP(hipStreamSynchronize(st));
-  const int64_t chunk_len = std::max<int64_t>(16384, (m + std::max<int64_t>(k, 4096) - 1) / std::max<int64_t>(k, 4096));
+  const int64_t chunk_len = (opts && opts->build_chunk > 0)
+                                ? opts->build_chunk
+                                : std::max<int64_t>(16384, (m + std::max<int64_t>(k, 4096) - 1) / std::max<int64_t>(k, 4096));
   std::vector<Item> chunks;
   for (int64_t p = 0; p < k; ++p) {
     cfirst[p] = static_cast<int32_t>(chunks.size());

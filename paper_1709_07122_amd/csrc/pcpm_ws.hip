@@ -32,12 +32,21 @@ static_assert(kOB3 + 1 == PCPM_WS_PARAMS, "parameter layout");
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// Round to the nearest BF16 (ties to even); returns the bits.
-__device__ __forceinline__ uint16_t bf16_bits(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+// Round to the nearest BF16 (ties to even) with gfx950's conversion
+// instruction (v_cvt_pk_bf16_f32), two values at a time where possible.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pack2(float a, float b) {
+  const float2 f = make_float2(a, b);
+  const bf16x2 h = __builtin_convertvector(*reinterpret_cast<const float __attribute__((ext_vector_type(2)))*>(&f), bf16x2);
+  return __builtin_bit_cast(uint32_t, h);
 }
-__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float(static_cast<uint32_t>(bf16_bits(f)) << 16); }
+__device__ __forceinline__ float bf16_round(float f) {
+  return __uint_as_float(static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(f))) << 16);
+}
+// four values as an MFMA operand (two packed registers)
+__device__ __forceinline__ v4s bf16_op(float a, float b, float c, float d) {
+  return __builtin_bit_cast(v4s, make_uint2(bf16_pack2(a, b), bf16_pack2(c, d)));
+}
 
 // ---- features -------------------------------------------------------------------
 // In-degrees: one workgroup per gather item counts the destination IDs of its
@@ -86,14 +95,14 @@ __global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, c
                                                      const int32_t* __restrict__ outdeg,
                                                      const uint32_t* __restrict__ dmask,
                                                      const float* __restrict__ pr1, int64_t n) {
-  const double dn = static_cast<double>(n);
+  const float fn = static_cast<float>(n);
   for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
        v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     float4 f;
     f.x = log1pf(static_cast<float>(indeg[v]));
     f.y = log1pf(static_cast<float>(outdeg[v]));
     f.z = static_cast<float>((dmask[v >> 5] >> (v & 31)) & 1u);
-    f.w = static_cast<float>(log(static_cast<double>(pr1[v]) * dn));
+    f.w = logf(pr1[v] * fn);  // FP32 is ample: the network sees the value rounded to BF16
     float4* out = reinterpret_cast<float4*>(feat + kF * v);
     out[0] = f;
     out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -123,40 +132,33 @@ __global__ __launch_bounds__(256) void k_ws_forward(const float* __restrict__ P,
   v4s a1[2], a2[2][8];
 #pragma unroll
   for (int ob = 0; ob < 2; ++ob) {
+    const float* w1 = P + kOW1 + (32 * ob + col) * kF + 4 * half;
+    a1[ob] = bf16_op(w1[0], w1[1], w1[2], w1[3]);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a1[ob][r] = static_cast<short>(bf16_bits(P[kOW1 + (32 * ob + col) * kF + 4 * half + r]));
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        a2[ob][kb][r] = static_cast<short>(bf16_bits(P[kOW2 + (32 * ob + col) * kH + 8 * kb + 4 * half + r]));
+    for (int kb = 0; kb < 8; ++kb) {
+      const float* w2 = P + kOW2 + (32 * ob + col) * kH + 8 * kb + 4 * half;
+      a2[ob][kb] = bf16_op(w2[0], w2[1], w2[2], w2[3]);
+    }
   }
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (256 / kWave);
   for (int64_t base = (static_cast<int64_t>(blockIdx.x) * (256 / kWave) + threadIdx.x / kWave) * 32; base < n;
        base += waves * 32) {
     const int64_t node = base + col;
-    v4s bx;
-    if (node < n) {
-      const float4 fv = *reinterpret_cast<const float4*>(feat + kF * node + 4 * half);
-      bx[0] = static_cast<short>(bf16_bits(fv.x));
-      bx[1] = static_cast<short>(bf16_bits(fv.y));
-      bx[2] = static_cast<short>(bf16_bits(fv.z));
-      bx[3] = static_cast<short>(bf16_bits(fv.w));
-    } else {
-      bx[0] = bx[1] = bx[2] = bx[3] = 0;
-    }
+    float4 fv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (node < n) fv = *reinterpret_cast<const float4*>(feat + kF * node + 4 * half);
+    const v4s bx = bf16_op(fv.x, fv.y, fv.z, fv.w);
     const v16f zero = {};
     v4s b2op[8];
 #pragma unroll
     for (int ob = 0; ob < 2; ++ob) {
       const v16f h1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[ob], bx, zero, 0, 0, 0);
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 32 * ob + 8 * t + 4 * half + r;
-          b2op[4 * ob + t][r] = static_cast<short>(bf16_bits(fmaxf(h1[4 * t + r] + b1s[row], 0.0f)));
-        }
+      for (int t = 0; t < 4; ++t) {
+        const int row = 32 * ob + 8 * t + 4 * half;
+        b2op[4 * ob + t] = bf16_op(fmaxf(h1[4 * t] + b1s[row], 0.0f), fmaxf(h1[4 * t + 1] + b1s[row + 1], 0.0f),
+                                   fmaxf(h1[4 * t + 2] + b1s[row + 2], 0.0f),
+                                   fmaxf(h1[4 * t + 3] + b1s[row + 3], 0.0f));
+      }
     }
     float part = 0.0f;
 #pragma unroll
@@ -165,9 +167,11 @@ __global__ __launch_bounds__(256) void k_ws_forward(const float* __restrict__ P,
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) h2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][kb], b2op[kb], h2, 0, 0, 0);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
+      for (int v = 0; v < 16; v += 2) {
         const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
-        part += w3s[row] * bf16_round(fmaxf(h2[v] + b2s[row], 0.0f));
+        const uint32_t pk = bf16_pack2(fmaxf(h2[v] + b2s[row], 0.0f), fmaxf(h2[v + 1] + b2s[row + 1], 0.0f));
+        part += w3s[row] * __uint_as_float(pk << 16);
+        part += w3s[row + 1] * __uint_as_float(pk & 0xFFFF0000u);
       }
     }
     part += __shfl_xor(part, 32);  // lanes l and l^32 hold the two halves of node col's rows

@@ -154,8 +154,7 @@ def train(specs, epochs: int = 30, batch: int = 16384, lr: float = 3e-3, seed: i
 def warm_start(png, params, d: float = 0.85):
     """Start vector predicted for this handle: (pr0, used_uniform)."""
     feat, _ = P.ws_features(png, d)
-    yhat = P.ws_forward(params, feat)
-    return P.ws_init(yhat)
+    return P.ws_init(P.ws_forward(params, feat))
 
 
 def compare(png, params, d: float = 0.85, tol: float = 1e-6, reps: int = 3):
@@ -173,8 +172,7 @@ def compare(png, params, d: float = 0.85, tol: float = 1e-6, reps: int = 3):
 
     def warm():
         f, _ = P.ws_features(png, d)
-        y = P.ws_forward(params, f)
-        pr0, fb = P.ws_init(y)
+        pr0, fb = P.ws_init(P.ws_forward(params, f))
         return P.pagerank(png, d=d, tol=tol, max_iters=500, init=pr0, out=out, want_hist=False), fb
 
     cold()

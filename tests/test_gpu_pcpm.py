@@ -94,6 +94,18 @@ def test_layout_rmat16(part_log2):
     assert_layout_equal(build(r, c, part_log2=part_log2), r, c, part_log2)
 
 
+@pytest.mark.parametrize("relabel,part_log2,chunk", [("indegree", 8, 64), ("indegree", 10, 1000),
+                                                     (None, 5, 1), ("random", 7, 333)])
+def test_layout_with_small_build_chunks(relabel, part_log2, chunk):
+    """Count and fill split every partition's edges into many chunks (the
+    paths that skewed graphs take at full size); the layout is the same."""
+    r, c = graphgen.rmat(12, 16, seed=11, relabel=relabel)
+    png = build(r, c, part_log2=part_log2, build_chunk=chunk)
+    assert_layout_equal(png, r, c, part_log2)
+    res = P.pagerank(png, tol=0.0, max_iters=12)
+    assert_ranks_close(res.pr.cpu().numpy(), oracle.pagerank(r, c, iters=12).x)
+
+
 def test_layout_ragged_and_degenerate():
     # n not a multiple of q, plus a hub row longer than one wavefront
     n = 1000
