@@ -373,7 +373,7 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
     }
     __builtin_amdgcn_wave_barrier();
     if (valid) {
-      did[cd + rank] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | (first ? kDidFlag : 0u));
+      did[tile_pos(cd + rank)] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | (first ? kDidFlag : 0u));
       if (first) {
         // position in the pair-ordered PNG edges: after the pair's earlier
         // pair segments and, for the odd partition, after the even one's run
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
         const int64_t pos = static_cast<int64_t>(png_base[p0]) + even_off + odd_off + (odd ? even_cnt : 0) + r;
         const bool seg_first = r == 0 && (!odd || even_cnt == 0);
         // source ID local to the pair's 2q nodes, flag on the pair segment's first node
-        png_src[pos] = static_cast<uint16_t>((static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u));
+        png_src[tile_pos(pos)] = static_cast<uint16_t>((static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u));
       }
       if ((peers & below) == 0) {
         cur_did[pp] = cd + __popcll(peers);
@@ -860,10 +860,11 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src, 
   }
   if (png_src && g->eprime > 0) {
     // stored partition-local with a 16-bit flag; exported as global node IDs
-    std::vector<uint16_t> loc(g->eprime);
+    // (in the tile storage order of tile_pos, up to the end of the last 128-entry block)
+    std::vector<uint16_t> loc((g->eprime + 127) / 128 * 128);
     std::vector<int32_t> pb(k + 1);
     std::vector<int32_t> po(k * (k + 1));
-    PCPM_TRY_HIP(hipMemcpy(loc.data(), g->png_src, g->eprime * 2, hipMemcpyDeviceToHost));
+    PCPM_TRY_HIP(hipMemcpy(loc.data(), g->png_src, loc.size() * 2, hipMemcpyDeviceToHost));
     PCPM_TRY_HIP(hipMemcpy(pb.data(), g->png_base, (k + 1) * 4, hipMemcpyDeviceToHost));
     PCPM_TRY_HIP(hipMemcpy(po.data(), g->png_off, po.size() * 4, hipMemcpyDeviceToHost));
     // stored in partition-pair order (see k_segdelta); exported per partition
@@ -875,20 +876,22 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src, 
         const int64_t odd_off = p1 < k ? po[p1 * (k + 1) + j] : 0;
         const int64_t src = pb[p0] + even_off + odd_off + ((p & 1) ? even_cnt : 0);
         for (int64_t r = 0; r < c; ++r)
-          png_src[pb[p] + a + r] = static_cast<int32_t>(p0 * g->q + (loc[src + r] & (kDidFlag - 1u)));
+          png_src[pb[p] + a + r] = static_cast<int32_t>(p0 * g->q + (loc[tile_pos(src + r)] & (kDidFlag - 1u)));
       }
     }
   }
   if (did && g->m > 0) {
     // stored partition-local with a 16-bit flag; exported as global IDs with the top-bit flag
-    std::vector<uint16_t> loc(g->m);
+    std::vector<uint16_t> loc((g->m + 127) / 128 * 128);
     std::vector<int32_t> ds(k + 1);
-    PCPM_TRY_HIP(hipMemcpy(loc.data(), g->did, g->m * 2, hipMemcpyDeviceToHost));
+    PCPM_TRY_HIP(hipMemcpy(loc.data(), g->did, loc.size() * 2, hipMemcpyDeviceToHost));
     PCPM_TRY_HIP(hipMemcpy(ds.data(), g->did_start, (k + 1) * 4, hipMemcpyDeviceToHost));
     for (int64_t p = 0; p < k; ++p) {
       const uint32_t base = static_cast<uint32_t>(p * g->q);
-      for (int64_t e = ds[p]; e < ds[p + 1]; ++e)
-        did[e] = (base + (loc[e] & (kDidFlag - 1u))) | ((loc[e] & kDidFlag) ? kFlag : 0u);
+      for (int64_t e = ds[p]; e < ds[p + 1]; ++e) {
+        const uint16_t x = loc[tile_pos(e)];
+        did[e] = (base + (x & (kDidFlag - 1u))) | ((x & kDidFlag) ? kFlag : 0u);
+      }
     }
   }
   return PCPM_OK;

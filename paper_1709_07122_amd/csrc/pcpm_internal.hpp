@@ -150,6 +150,30 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
+// Storage order of the 16-bit tile entries (destination IDs, PNG source IDs):
+// inside each 128-entry block, entries i and 64 + i share one 32-bit word
+// (low and high half).  A wavefront reads two 64-entry sub-blocks with one
+// 4-byte load per lane and still sees 64 consecutive entries per sub-block;
+// on MI355X 2-byte loads move about half the bytes per instruction.
+__host__ __device__ inline int64_t tile_pos(int64_t e) {
+  return (e & ~int64_t{127}) | ((e & 63) << 1) | ((e >> 6) & 1);
+}
+constexpr int kPairs = kSub / 2;
+
+// This lane's words of one tile.
+__device__ __forceinline__ void load_tile_words(const uint16_t* tile, int lane, uint32_t (&w)[kPairs]) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(tile);
+#pragma unroll
+  for (int j = 0; j < kPairs; ++j) w[j] = p[j * kWave + lane];
+}
+
+// Entry 64j + lane of the tile, j = 0..kSub-1.
+__device__ __forceinline__ void unpack_tile(const uint32_t (&w)[kPairs], uint32_t (&x)[kSub]) {
+#pragma unroll
+  for (int j = 0; j < kSub; ++j) x[j] = (j & 1) ? (w[j >> 1] >> 16) : (w[j >> 1] & 0xFFFFu);
+}
+
+
 }  // namespace pcpm
 
 // ---- the handle ------------------------------------------------------------------

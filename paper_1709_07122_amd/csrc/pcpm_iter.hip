@@ -125,20 +125,15 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
-  uint32_t x[kSub], xn[kSub];
+  uint32_t w[kPairs], wn[kPairs];
   int64_t t = lo / kTile + threadIdx.x / kWave;
-  if (t < t_end) {
-    const uint16_t* pt = png_src + t * kTile;
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = pt[j * kWave + lane];
-  }
+  if (t < t_end) load_tile_words(png_src + t * kTile, lane, w);
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    if (t + kNW < t_end) {  // the next tile's loads overlap this tile's work
-      const uint16_t* pt = png_src + (t + kNW) * kTile;
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) xn[j] = pt[j * kWave + lane];
-    }
+    // the next tile's loads overlap this tile's work
+    if (t + kNW < t_end) load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
+    uint32_t x[kSub];
+    unpack_tile(w, x);
     // Every entry of a tile has a valid segment index (entry 0 of the array
     // is flagged and padding follows the last segment), so the loads below
     // need no predicate.  A source ID masked with q-1 is its slot in the rank
@@ -169,7 +164,7 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
       }
     }
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = xn[j];
+    for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
   }
 }
 
@@ -196,20 +191,15 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
-  uint32_t x[kSub], xn[kSub];
+  uint32_t w[kPairs], wn[kPairs];
   int64_t t = lo / kTile + threadIdx.x / kWave;
-  if (t < t_end) {
-    const uint16_t* dt = did + t * kTile;
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = dt[j * kWave + lane];
-  }
+  if (t < t_end) load_tile_words(did + t * kTile, lane, w);
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    if (t + kNW < t_end) {  // the next tile's IDs are in flight during this tile's work
-      const uint16_t* dt = did + (t + kNW) * kTile;
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) xn[j] = dt[j * kWave + lane];
-    }
+    // the next tile's IDs are in flight during this tile's work
+    if (t + kNW < t_end) load_tile_words(did + (t + kNW) * kTile, lane, wn);
+    uint32_t x[kSub];
+    unpack_tile(w, x);
     // Update indices of a tile lie in [did_blk[t]-1, did_blk[t+1]-1]: the
     // loads below take a per-tile base and a 32-bit lane offset.  Every entry
     // has a valid index (entry 0 of the array is flagged and padding follows
@@ -242,7 +232,7 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
       }
     }
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) x[j] = xn[j];
+    for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
   }
   __syncthreads();
   if (it.aux >= 0) {

@@ -64,20 +64,14 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = kPprScatterBlock / kWave;
-  uint32_t xs[kSub], xn[kSub];
+  uint32_t w[kPairs], wn[kPairs];
   int64_t t = lo / kTile + threadIdx.x / kWave;
-  if (t < t_end) {
-    const uint16_t* pt = png_src + t * kTile;
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) xs[j] = pt[j * kWave + lane];
-  }
+  if (t < t_end) load_tile_words(png_src + t * kTile, lane, w);
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    if (t + kNW < t_end) {
-      const uint16_t* pt = png_src + (t + kNW) * kTile;
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) xn[j] = pt[j * kWave + lane];
-    }
+    if (t + kNW < t_end) load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
+    uint32_t xs[kSub];
+    unpack_tile(w, xs);
     // every entry of a tile has a valid segment (entry 0 is flagged and
     // padding follows the last segment): no predicate on these loads
     int32_t run = png_blk[t];
@@ -106,7 +100,7 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
       }
     }
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) xs[j] = xn[j];
+    for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
   }
 }
 
@@ -216,20 +210,14 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
   constexpr int kG = KT >= 16 ? 2 : (KT >= 8 ? 4 : (KT >= 4 ? 8 : 16));
-  uint32_t xs[kSub], xn[kSub];
+  uint32_t w[kPairs], wn[kPairs];
   int64_t t = lo / kTile + threadIdx.x / kWave;
-  if (t < t_end) {
-    const uint16_t* dt = did + t * kTile;
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) xs[j] = dt[j * kWave + lane];
-  }
+  if (t < t_end) load_tile_words(did + t * kTile, lane, w);
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    if (t + kNW < t_end) {
-      const uint16_t* dt = did + (t + kNW) * kTile;
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) xn[j] = dt[j * kWave + lane];
-    }
+    if (t + kNW < t_end) load_tile_words(did + (t + kNW) * kTile, lane, wn);
+    uint32_t xs[kSub];
+    unpack_tile(w, xs);
     // update slots of a tile lie in [did_blk[t]-1, did_blk[t+1]-1]: a per-tile
     // base and 32-bit offsets; every entry has a valid slot (no predicate)
     const float* ub = upd + (static_cast<int64_t>(did_blk[t]) - 1) * KT;
@@ -269,7 +257,7 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
       }
     }
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) xs[j] = xn[j];
+    for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
   }
   __syncthreads();
   if (it.aux >= 0) {

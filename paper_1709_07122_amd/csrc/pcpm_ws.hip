@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kCountBlock) void k_ws_count(int64_t n, int s, cons
   for (int64_t e = lo + threadIdx.x; e < hi; e += kU * kCountBlock) {
     uint32_t x[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = did[min(e + u * kCountBlock, hi - 1)];
+    for (int u = 0; u < kU; ++u) x[u] = did[tile_pos(min(e + u * kCountBlock, hi - 1))];
 #pragma unroll
     for (int u = 0; u < kU; ++u)
       if (e + u * kCountBlock < hi) atomicAdd(&cnt[x[u] & qmask], 1u);
