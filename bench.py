@@ -81,9 +81,12 @@ def measure(P, torch, r, c, args, label):
     P.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters = []
+    iters, step_s = [], []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         res = P.pagerank(png, d=args.d, tol=solve_tol(args), max_iters=solve_iters(args), out=out, want_hist=False)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
         iters.append(res.iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -102,6 +105,8 @@ def measure(P, torch, r, c, args, label):
         "n": n, "m": m, "q": info["q"], "k": info["k"], "eprime": eprime, "r": m / max(eprime, 1),
         "iters": iters[-1], "ms_per_step": total_s / args.steps * 1e3, "ms_per_iter": sec_per_iter * 1e3,
         "gteps": m / sec_per_iter / 1e9, "time_to_tol_ms": total_s / args.steps * 1e3,
+        "ms_per_step_median": sorted(step_s)[len(step_s) // 2] * 1e3,
+        "gteps_median": m * iters[-1] / sorted(step_s)[len(step_s) // 2] / 1e9,
         "alg_bytes_per_iter": it_bytes, "alg_bytes_per_edge": it_bytes / m, "eq5_bytes_per_edge": eq5 / m,
         "hbm_gbs_alg": it_bytes / sec_per_iter / 1e9, "build_ms": build_s * 1e3,
         "kernels": kernels, "gather_bytes": g_bytes, "scatter_bytes": s_bytes,
@@ -238,6 +243,39 @@ def counter_traffic(kernel):
     return None if k is None else int(k["traffic_bytes"])
 
 
+def copy_gbs(torch, nbytes=1 << 30, reps=5):
+    """Achieved bandwidth of a plain device-to-device copy (bytes read plus
+    written per second), timed with events on the current stream."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = None
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "model": model}
+
+
 def calibrate_copy(torch):
     """A plain copy kernel of known size: 2 GiB read + 2 GiB written per launch."""
     nbytes = 2 << 30
@@ -354,7 +392,7 @@ def main():
         cpu = {"value": len(c) / o.sec_per_iter / 1e9, "unit": "GTEPS", "cores": threads(), "kind": "oracle",
                "sample": f"the same graph, {iters} FP64 pull iterations of the oracle, transpose excluded "
                          f"({wall:.1f} s wall incl. transpose)",
-               "sec_per_iter": o.sec_per_iter}
+               "sec_per_iter": o.sec_per_iter, "host": host_info()}
         log(f"oracle: {o.sec_per_iter * 1e3:.1f} ms/iter on {threads()} threads; parity L1={l1:.2e} rel={rel:.2e}")
 
     g = main_res["kernels"].get("pcpm_gather", {"avg_ms": float("nan")})
@@ -386,6 +424,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "hbm_gbs_algorithmic": round(main_res["hbm_gbs_alg"], 1),
+        "copy_gbs": round(copy_gbs(torch), 1),
         "time_to_tol_ms": None if warm is None else {
             "cold": round(warm["cold_ms"], 3), "warm": round(warm["warm_ms"], 3),
             "warm_incl_indegree_count": round(warm["warm_ms_first"], 3),

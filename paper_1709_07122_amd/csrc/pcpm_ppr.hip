@@ -139,7 +139,7 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
       if (nd < n1) {
         const int64_t v = v0 + nd;
         const bool seed = (sm[u] >> kk) & 1u;
-        const double a = static_cast<double>(acc(nd * KT + kk)) * unit;
+        const double a = static_cast<double>(acc(nd, kk)) * unit;
         const float xn = frozen ? xo[u] : static_cast<float>(fma(d, a, seed ? coef : 0.0));
         r += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
         if ((dw[u] >> (v & 31)) & 1u) dm += static_cast<double>(xn);
@@ -179,7 +179,9 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
 // Gather (Alg. 5) for a tile of KT vectors: each destination ID is decoded
 // once (its update is the one of the message it belongs to: flags so far,
 // inclusive, minus one) and adds KT fixed-point values to the LDS slice
-// ([q][KT] 64-bit sums).  The next tile's IDs are loaded while this one is
+// ([KT][q] 64-bit sums: vector-major, so the 64 lanes of one add spread over
+// the banks as in the single-vector gather; node-major rows of KT sums put
+// them on 32/KT bank pairs).  The next tile's IDs are loaded while this one is
 // accumulated; the update values of kG sub-blocks are in flight together.
 template <int KT>
 __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
@@ -202,10 +204,11 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
   const FixedConv to_fixed(ctl->fx_shift);
-  for (int i = threadIdx.x; i < qn * KT; i += BS) acc[i] = 0ull;
+  for (int i = threadIdx.x; i < q * KT; i += BS) acc[i] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t qmask = static_cast<uint32_t>(q - 1);
+  const uint32_t qs = static_cast<uint32_t>(q);
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
@@ -239,20 +242,20 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
       if (full) {
 #pragma unroll
         for (int jj = 0; jj < kG; ++jj) {
-          const uint32_t li = (xs[g0 + jj] & qmask) * KT;
+          const uint32_t li = xs[g0 + jj] & qmask;
 #pragma unroll
           for (int c = 0; c < KT; ++c)
-            atomicAdd(&acc[li + c], static_cast<unsigned long long>(to_fixed(val[jj][c])));
+            atomicAdd(&acc[c * qs + li], static_cast<unsigned long long>(to_fixed(val[jj][c])));
         }
       } else {  // edge tile: entries outside [lo, hi) add nothing
 #pragma unroll
         for (int jj = 0; jj < kG; ++jj) {
           const int64_t e = tb + (g0 + jj) * kWave + lane;
           const bool in = e >= lo && e < hi;
-          const uint32_t li = in ? (xs[g0 + jj] & qmask) * KT : 0u;
+          const uint32_t li = in ? (xs[g0 + jj] & qmask) : 0u;
 #pragma unroll
           for (int c = 0; c < KT; ++c)
-            atomicAdd(&acc[li + c], static_cast<unsigned long long>(in ? to_fixed(val[jj][c]) : 0));
+            atomicAdd(&acc[c * qs + li], static_cast<unsigned long long>(in ? to_fixed(val[jj][c]) : 0));
         }
       }
     }
@@ -261,12 +264,12 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
   }
   __syncthreads();
   if (it.aux >= 0) {
-    int64_t* dst = partial + static_cast<int64_t>(it.aux) * q * KT;
-    for (int i = threadIdx.x; i < qn * KT; i += BS) dst[i] = static_cast<int64_t>(acc[i]);
+    int64_t* dst = partial + static_cast<int64_t>(it.aux) * q * KT;  // the same [KT][q] layout
+    for (int i = threadIdx.x; i < q * KT; i += BS) dst[i] = static_cast<int64_t>(acc[i]);
     return;
   }
-  apply_ppr<KT, BS>(ctl, vctl, v0, 0, qn, [&](int i) { return static_cast<int64_t>(acc[i]); }, x_in, x_out, dmask,
-                    seedmask, red + static_cast<int64_t>(it.part) * KT * 3);
+  apply_ppr<KT, BS>(ctl, vctl, v0, 0, qn, [&](int nd, int c) { return static_cast<int64_t>(acc[c * q + nd]); }, x_in,
+                    x_out, dmask, seedmask, red + static_cast<int64_t>(it.part) * KT * 3);
 }
 
 template <int KT>
@@ -285,9 +288,9 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__
   const int qn = static_cast<int>(min(q, n - v0));
   const int64_t* base = partial + static_cast<int64_t>(mu.first) * q * KT;
   const int cnt = mu.count;
-  auto acc = [&](int i) {
+  auto acc = [&](int nd, int vec) {  // partial slices are [KT][q]
     int64_t sum = 0;
-    for (int c = 0; c < cnt; ++c) sum += base[static_cast<int64_t>(c) * q * KT + i];
+    for (int c = 0; c < cnt; ++c) sum += base[static_cast<int64_t>(c) * q * KT + static_cast<int64_t>(vec) * q + nd];
     return sum;
   };
   apply_ppr<KT, kPprBlock>(ctl, vctl, v0, mu.node_lo, min(qn, mu.node_lo + 256), acc, x_in, x_out, dmask, seedmask,
