@@ -89,6 +89,20 @@ struct VCtl {
   double res;       // residual of the vector's last iteration
   int32_t iter;     // iterations the vector has run
   int32_t done;     // residual fell below tol: the vector keeps its iterate
+  int32_t vec;      // vector of the batch in this slot, -1 = idle
+  int32_t pad;
+};
+
+// Queue of the batch's vectors over the kt slots of a tile: a slot whose
+// vector has finished takes the next one.  old_vec / new_vec describe the
+// refill planned by the last iteration (-1 = none).
+struct PprQueue {
+  int32_t head;       // next vector to start
+  int32_t k;          // vectors in the batch
+  int32_t max_iters;  // iteration limit per vector
+  int32_t pending;    // a refill is planned
+  int32_t old_vec[16];
+  int32_t new_vec[16];
 };
 
 // A unit of scatter or gather work: a contiguous range [lo, hi) of PNG edges
@@ -242,6 +256,11 @@ struct pcpm_png {
   int64_t ppr_seed_cap = 0;
   int32_t* ppr_seed_off = nullptr;
   int64_t ppr_off_cap = 0;
+  pcpm::PprQueue* ppr_queue = nullptr;
+  int32_t* ppr_out_it = nullptr;         // per vector of the batch: iterations,
+  double* ppr_out_res = nullptr;         // last residual
+  int32_t* ppr_out_conv = nullptr;       // and whether it fell below tol
+  int64_t ppr_vec_cap = 0;
 
   // warm start: in-degrees (computed once per handle) and two rank vectors
   // for the first iterate from the uniform start

@@ -6,9 +6,11 @@
 // dangling mass, i.e. the recurrence of Eq. 1 with the uniform jump replaced
 // by t_j.  An update slot holds kt values (one per vector of the tile), so the
 // scatter of Alg. 3 writes kt floats per PNG edge and the gather of Alg. 5
-// decodes each destination ID once for kt accumulations.  Vectors are
-// processed in tiles of kt; a vector whose residual falls below tol keeps
-// its iterate while the rest of its tile goes on.
+// decodes each destination ID once for kt accumulations.  The kt slots of
+// the tile take the batch's vectors from a queue: a vector whose residual
+// falls below tol (or that reaches the iteration limit) is stored and its
+// slot starts the next vector at once, so slots never idle while vectors
+// wait.  A slot with no vector left keeps its last iterate.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -298,10 +300,15 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__
 }
 
 // Per-vector residual, dangling mass and jump coefficient; one wavefront per
-// vector, apply units in order.
+// slot, apply units in order.  Then the refill plan: every slot whose vector
+// finished (below tol, or at the iteration limit) records the vector's
+// iteration count, residual and convergence, and takes the next vector of the
+// queue; the batch is done when every slot is idle.
 __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VCtl* __restrict__ vctl, int kt,
                                                        const double* __restrict__ red, int64_t nslots,
-                                                       double* __restrict__ hist) {
+                                                       double* __restrict__ hist, PprQueue* __restrict__ queue,
+                                                       int32_t* __restrict__ out_it, double* __restrict__ out_res,
+                                                       int32_t* __restrict__ out_conv) {
   if (ctl->done) return;
   double vmax = 0.0;  // largest value of the new iterates (all vectors of the tile)
   for (int64_t j = threadIdx.x; j < nslots * kt; j += 1024) vmax = fmax(vmax, red[3 * j + 2]);
@@ -336,21 +343,138 @@ __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VC
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double rmax = 0.0;
-    int all_done = 1;
+    double rmax = 0.0;  // largest residual of the vectors still running
+    for (int kk = 0; kk < kt; ++kk)
+      if (vctl[kk].vec >= 0 && !vctl[kk].done) rmax = fmax(rmax, vctl[kk].res);
+    int pending = 0, any_new = 0, all_idle = 1;
     for (int kk = 0; kk < kt; ++kk) {
-      rmax = fmax(rmax, vctl[kk].res);
-      all_done &= vctl[kk].done;
+      VCtl& vc = vctl[kk];
+      queue->old_vec[kk] = -1;
+      queue->new_vec[kk] = -1;
+      if (vc.vec >= 0 && (vc.done || vc.iter >= queue->max_iters)) {
+        out_it[vc.vec] = vc.iter;
+        out_res[vc.vec] = vc.res;
+        out_conv[vc.vec] = vc.done;
+        const int nv = queue->head < queue->k ? queue->head++ : -1;
+        queue->old_vec[kk] = vc.vec;
+        queue->new_vec[kk] = nv;
+        vc.vec = nv;
+        vc.done = 1;  // keeps its column until k_ppr_refill_seeds starts the next vector
+        pending = 1;
+        any_new |= nv >= 0;
+      }
+      all_idle &= vc.vec < 0;
     }
+    queue->pending = pending;
     if (bad) rmax = NAN;
     const int32_t it = ctl->iter;
     ctl->res_prev = ctl->res;
     ctl->res = rmax;
-    hist[it] = rmax;
+    if (it < kMaxHist) hist[it] = rmax;
     ctl->iter = it + 1;
     if (bad) ctl->nonfinite = 1;
-    if (bad || all_done) ctl->done = 1;
-    ctl->fx_shift = fx_shift_for(vmax, ctl->fx_cap);
+    if (bad || all_idle) ctl->done = 1;
+    // a new vector starts with values up to 1 (a single seed)
+    ctl->fx_shift = fx_shift_for(any_new ? fmax(vmax, 1.0) : vmax, ctl->fx_cap);
+  }
+}
+
+// Refill, first part (whole grid): the finished vectors' columns go to
+// pr_out[v][vec], and the columns of slots that start a new vector are
+// cleared.  Nothing to do unless the last iteration planned a refill.
+template <int KT>
+__global__ __launch_bounds__(256) void k_ppr_refill_cols(const PprQueue* __restrict__ queue, float* __restrict__ x,
+                                                         float* __restrict__ out, int64_t n, int k) {
+  if (!queue->pending) return;
+  int ov[KT], nv[KT];
+#pragma unroll
+  for (int c = 0; c < KT; ++c) {
+    ov[c] = queue->old_vec[c];
+    nv[c] = queue->new_vec[c];
+  }
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float row[KT];
+    copy_kt<KT>(row, x + v * KT);
+    bool clear = false;
+#pragma unroll
+    for (int c = 0; c < KT; ++c) {
+      if (ov[c] >= 0) out[v * k + ov[c]] = row[c];
+      if (nv[c] >= 0) {
+        row[c] = 0.0f;
+        clear = true;
+      }
+    }
+    if (clear) copy_kt<KT>(x + v * KT, row);
+  }
+}
+
+// Refill, second part (one workgroup): seed bits of the finished vectors are
+// cleared, then each new vector gets x_0 = t_j on its seeds, its seed bits,
+// dangling mass and jump coefficient; one wavefront per slot.
+__global__ __launch_bounds__(1024) void k_ppr_refill_seeds(PprQueue* __restrict__ queue, float* __restrict__ x,
+                                                           uint32_t* __restrict__ mask,
+                                                           const int32_t* __restrict__ seeds,
+                                                           const int32_t* __restrict__ seed_off, int kt,
+                                                           VCtl* __restrict__ vctl,
+                                                           const uint32_t* __restrict__ dmask, double d) {
+  if (!queue->pending) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int kk = threadIdx.x / kWave; kk < kt; kk += 1024 / kWave) {
+    const int ov = queue->old_vec[kk];
+    if (ov >= 0)
+      for (int i = seed_off[ov] + lane; i < seed_off[ov + 1]; i += kWave) atomicAnd(&mask[seeds[i]], ~(1u << kk));
+  }
+  __threadfence();
+  __syncthreads();
+  for (int kk = threadIdx.x / kWave; kk < kt; kk += 1024 / kWave) {
+    const int nv = queue->new_vec[kk];
+    double dm = 0.0, inv = 0.0;
+    if (nv >= 0) {
+      const int a = seed_off[nv], b = seed_off[nv + 1];
+      inv = 1.0 / static_cast<double>(b - a);
+      for (int i = a + lane; i < b; i += kWave) {
+        const int v = seeds[i];
+        x[static_cast<int64_t>(v) * kt + kk] = static_cast<float>(inv);
+        atomicOr(&mask[v], 1u << kk);
+        if ((dmask[v >> 5] >> (v & 31)) & 1u) dm += inv;
+      }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) dm += __shfl_xor(dm, off);
+    if (lane == 0 && nv >= 0) {
+      VCtl& vc = vctl[kk];
+      vc.inv_s = inv;
+      vc.dmass = dm;
+      vc.coef = ((1.0 - d) + d * dm) * inv;
+      vc.res = 0.0;
+      vc.iter = 0;
+      vc.done = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) queue->pending = 0;
+}
+
+// pr_out[v][j] = x[v][j] for the first kv slots (batches that fit one tile:
+// every vector keeps its slot, and its last iterate, to the end).
+__global__ __launch_bounds__(256) void k_ppr_store(float* __restrict__ out, const float* __restrict__ x, int64_t n,
+                                                   int k, int kv, int kt) {
+  const int64_t total = n * kv;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t v = i / kv;
+    const int j = static_cast<int>(i - v * kv);
+    out[v * k + j] = x[v * kt + j];
+  }
+}
+
+__global__ void k_ppr_queue_init(PprQueue* queue, int head, int k, int max_iters) {
+  if (threadIdx.x == 0) {
+    queue->head = head;
+    queue->k = k;
+    queue->max_iters = max_iters;
+    queue->pending = 0;
   }
 }
 
@@ -385,19 +509,8 @@ __global__ __launch_bounds__(1024) void k_ppr_seed(float* __restrict__ x, uint32
       vc.res = 0.0;
       vc.iter = 0;
       vc.done = kk < kv ? 0 : 1;
+      vc.vec = kk < kv ? first + kk : -1;
     }
-  }
-}
-
-// pr_out[v][first + j] = x[v][j] for the tile's kv vectors.
-__global__ __launch_bounds__(256) void k_ppr_store(float* __restrict__ out, const float* __restrict__ x, int64_t n,
-                                                   int k, int first, int kv, int kt) {
-  const int64_t total = n * kv;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t v = i / kv;
-    const int j = static_cast<int>(i - v * kv);
-    out[v * k + first + j] = x[v * kt + j];
   }
 }
 
@@ -428,7 +541,8 @@ static pcpm_status_t ppr_set_lds(int s) {
 }
 
 template <int KT>
-static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, hipStream_t st) {
+static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, float* pr_out, int k, double d,
+                                   hipStream_t st) {
   const int s = g->part_log2;
   if (g->n_sc)
     PCPM_LAUNCH("pcpm_ppr_scatter", k_ppr_scatter<KT>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kPprScatterBlock),
@@ -442,7 +556,13 @@ static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, hip
                 g->ctl, g->n, s, g->mg_items, g->ppr_partial, in, out, g->dmask, g->ppr_mask, g->ppr_red, g->k,
                 g->ppr_vctl);
   PCPM_LAUNCH("pcpm_ppr_finalize", k_ppr_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->ppr_vctl, KT, g->ppr_red,
-              g->k + g->n_mg, g->hist);
+              g->k + g->n_mg, g->hist, g->ppr_queue, g->ppr_out_it, g->ppr_out_res, g->ppr_out_conv);
+  if (k <= KT) return PCPM_OK;  // one tile: no refill, the columns are stored at the end
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((g->n + 255) / 256, 4096));
+  PCPM_LAUNCH("pcpm_ppr_refill", k_ppr_refill_cols<KT>, dim3(blocks), dim3(256), 0, st, g->ppr_queue, out, pr_out,
+              g->n, k);
+  PCPM_LAUNCH("pcpm_ppr_refill", k_ppr_refill_seeds, dim3(1), dim3(1024), 0, st, g->ppr_queue, out, g->ppr_mask,
+              g->ppr_seeds, g->ppr_seed_off, KT, g->ppr_vctl, g->dmask, d);
   return PCPM_OK;
 }
 
@@ -475,6 +595,19 @@ static pcpm_status_t ppr_alloc(pcpm_png* g, int kt, int64_t nseeds, int k, hipSt
     PCPM_TRY(dalloc(g, &g->ppr_seed_off, k + 1));
     g->ppr_off_cap = k + 1;
   }
+  if (g->ppr_vec_cap < k) {
+    for (void* p : {static_cast<void*>(g->ppr_out_it), static_cast<void*>(g->ppr_out_res),
+                    static_cast<void*>(g->ppr_out_conv)})
+      if (p) dfree(g, p);
+    g->ppr_out_it = g->ppr_out_conv = nullptr;
+    g->ppr_out_res = nullptr;
+    g->ppr_vec_cap = 0;
+    PCPM_TRY(dalloc(g, &g->ppr_out_it, k));
+    PCPM_TRY(dalloc(g, &g->ppr_out_res, k));
+    PCPM_TRY(dalloc(g, &g->ppr_out_conv, k));
+    g->ppr_vec_cap = k;
+  }
+  if (!g->ppr_queue) PCPM_TRY(dalloc(g, &g->ppr_queue, 1));
   if (!g->ppr_vctl_host)
     PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->ppr_vctl_host), sizeof(VCtl) * 64, hipHostMallocDefault));
   return PCPM_OK;
@@ -489,48 +622,58 @@ static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_i
   *nonfinite = false;
   // slots of split bins are never written by the gather: keep them zero
   PCPM_TRY_HIP(hipMemsetAsync(g->ppr_red, 0, static_cast<size_t>((g->k + g->n_mg) * KT * 3) * 8, st));
-  for (int first = 0; first < k; first += KT) {
-    const int kv = std::min(KT, k - first);
-    float* a = g->ppr_x[0];
-    float* b = g->ppr_x[1];
-    PCPM_TRY_HIP(hipMemsetAsync(a, 0, static_cast<size_t>(n) * KT * 4, st));
-    PCPM_TRY_HIP(hipMemsetAsync(g->ppr_mask, 0, static_cast<size_t>(n) * 4, st));
-    PCPM_LAUNCH("pcpm_ppr_init", k_ppr_ctl, dim3(1), dim3(64), 0, st, g->ctl, tol, d);
-    PCPM_LAUNCH("pcpm_ppr_init", k_ppr_seed, dim3(1), dim3(1024), 0, st, a, g->ppr_mask, g->ppr_seeds,
-                g->ppr_seed_off, first, kv, KT, g->ppr_vctl, g->dmask, d);
-    int launched = 0;
-    int next = std::min(tol > 0.0 ? 4 : 64, max_iters);
-    while (launched < max_iters) {
-      for (int i = 0; i < next; ++i) {
-        const bool even = ((launched + i) % 2) == 0;
-        PCPM_TRY(ppr_iteration<KT>(g, even ? a : b, even ? b : a, st));
-      }
-      launched += next;
-      PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-      PCPM_TRY_HIP(hipStreamSynchronize(st));
-      if (g->ctl_host->done) break;
-      int want = 64;
-      if (tol > 0.0) {
-        const double res = g->ctl_host->res, prev = g->ctl_host->res_prev;
-        double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
-        rho = std::min(std::max(rho, 0.05), 0.995);
-        want = static_cast<int>(std::min(std::max(std::ceil(std::log(tol / res) / std::log(rho)), 1.0), 16.0));
-      }
-      next = std::min(want, max_iters - launched);
+  const int kv = std::min(KT, k);
+  float* a = g->ppr_x[0];
+  float* b = g->ppr_x[1];
+  PCPM_TRY_HIP(hipMemsetAsync(a, 0, static_cast<size_t>(n) * KT * 4, st));
+  PCPM_TRY_HIP(hipMemsetAsync(g->ppr_mask, 0, static_cast<size_t>(n) * 4, st));
+  PCPM_LAUNCH("pcpm_ppr_init", k_ppr_ctl, dim3(1), dim3(64), 0, st, g->ctl, tol, d);
+  PCPM_LAUNCH("pcpm_ppr_init", k_ppr_seed, dim3(1), dim3(1024), 0, st, a, g->ppr_mask, g->ppr_seeds,
+              g->ppr_seed_off, 0, kv, KT, g->ppr_vctl, g->dmask, d);
+  PCPM_LAUNCH("pcpm_ppr_init", k_ppr_queue_init, dim3(1), dim3(64), 0, st, g->ppr_queue, kv, k, max_iters);
+  // Every slot is busy while vectors wait, so the queue is empty after at
+  // most ceil(k/KT) * max_iters iterations, and the last vectors finish
+  // within max_iters more.
+  const int64_t cap = (static_cast<int64_t>(k + KT - 1) / KT + 1) * max_iters;
+  int64_t launched = 0;
+  int64_t next = std::min<int64_t>(tol > 0.0 ? 4 : 64, cap);
+  while (launched < cap) {
+    for (int64_t i = 0; i < next; ++i) {
+      const bool even = ((launched + i) % 2) == 0;
+      PCPM_TRY(ppr_iteration<KT>(g, even ? a : b, even ? b : a, pr_out, k, d, st));
     }
+    launched += next;
+    PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    PCPM_TRY_HIP(hipStreamSynchronize(st));
+    if (g->ctl_host->done) break;
+    int64_t want = 64;
+    if (tol > 0.0) {
+      const double res = g->ctl_host->res, prev = g->ctl_host->res_prev;
+      double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
+      rho = std::min(std::max(rho, 0.05), 0.995);
+      want = res > 0.0 ? static_cast<int64_t>(std::min(std::max(std::ceil(std::log(tol / res) / std::log(rho)), 1.0),
+                                                        16.0))
+                       : 1;
+    }
+    next = std::min(want, cap - launched);
+  }
+  if (!g->ctl_host->done) return set_error(PCPM_ERR_DEVICE, "personalised PageRank did not drain its queue");
+  if (k <= KT) {
     const int it_done = g->ctl_host->iter;
     const float* xr = (it_done > 0 && ((it_done - 1) % 2) == 0) ? b : a;
-    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((n * kv + 255) / 256, 8192));
-    PCPM_LAUNCH("pcpm_ppr_store", k_ppr_store, dim3(blocks), dim3(256), 0, st, pr_out, xr, n, k, first, kv, KT);
-    PCPM_TRY_HIP(hipMemcpyAsync(g->ppr_vctl_host, g->ppr_vctl, sizeof(VCtl) * KT, hipMemcpyDeviceToHost, st));
-    PCPM_TRY_HIP(hipStreamSynchronize(st));
-    for (int j = 0; j < kv; ++j) {
-      iters[first + j] = g->ppr_vctl_host[j].iter;
-      resid[first + j] = g->ppr_vctl_host[j].res;
-      if (!g->ppr_vctl_host[j].done) *all_converged = false;
-    }
-    if (g->ctl_host->nonfinite) *nonfinite = true;
+    const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((n * k + 255) / 256, 8192));
+    PCPM_LAUNCH("pcpm_ppr_store", k_ppr_store, dim3(blocks), dim3(256), 0, st, pr_out, xr, n, k, k, KT);
   }
+  std::vector<int32_t> it(k), conv(k);
+  PCPM_TRY_HIP(hipMemcpyAsync(it.data(), g->ppr_out_it, static_cast<size_t>(k) * 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(resid, g->ppr_out_res, static_cast<size_t>(k) * 8, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(conv.data(), g->ppr_out_conv, static_cast<size_t>(k) * 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < k; ++j) {
+    iters[j] = it[j];
+    if (!conv[j]) *all_converged = false;
+  }
+  if (g->ctl_host->nonfinite) *nonfinite = true;
   return PCPM_OK;
 }
 

@@ -88,3 +88,62 @@ def test_ppr_rejects_bad_seed_sets():
         with pytest.raises(P.PCPMError) as ei:
             P.ppr_batch(png, np.array(off, np.int32), np.array(seeds, np.int32))
         assert ei.value.status == P.PCPM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("k,part_log2", [(37, 12), (37, 10), (21, 11)])
+def test_ppr_queue_refill_matches_single_vectors(k, part_log2):
+    """More vectors than slots: a slot whose vector converges starts the next
+    one.  Every vector matches the oracle at its own iteration count, and that
+    count is the one it takes when run alone (up to one iteration where its
+    residual sits at tol: the tile's shared fixed-point scale rounds
+    differently)."""
+    r, c = graphgen.rmat(13, 16, seed=8, relabel="random")
+    n = len(r) - 1
+    png = P.build_png(dev(r), dev(c), part_log2=part_log2)
+    assert P.ppr_tile_width(png) < k
+    off, seeds = graphgen.seed_sets(n, k, seed=40 + k)
+    res = P.ppr_batch(png, off, seeds, tol=1e-6, max_iters=200)
+    assert res.converged and np.all(res.resid < 1e-6)
+    x = res.pr.cpu().numpy()
+    check_vectors(x, r, c, off, seeds, res.iters)
+    np.testing.assert_allclose(x.sum(axis=0), 1.0, atol=1e-4)
+    alone = np.array([P.ppr_batch(png, off[j:j + 2] - off[j], seeds[off[j]:off[j + 1]], tol=1e-6,
+                                  max_iters=200).iters[0] for j in range(k)])
+    assert np.all(np.abs(res.iters - alone) <= 1), (res.iters, alone)
+    assert np.mean(res.iters == alone) >= 0.9
+    png.close()
+
+
+def test_ppr_queue_mixes_fast_slow_and_capped_vectors():
+    """A cycle of 48 nodes plus 48 isolated (dangling) nodes.  A vector seeded
+    on isolated nodes is a fixed point after one iteration (all its mass
+    teleports back); one seeded on the cycle needs many.  With max_iters = 30
+    the cycle vectors stop unconverged while the others finish at once and
+    free their slots; all of them are stored at their own counts."""
+    nc, ni, d = 48, 48, 0.85
+    n = nc + ni
+    e = np.array([(i, (i + 1) % nc) for i in range(nc)])
+    r, c = graphgen.from_edges(n, e[:, 0], e[:, 1])
+    png = P.build_png(dev(r), dev(c), part_log2=3)
+    kt = P.ppr_tile_width(png)
+    sets = []
+    for j in range(3 * kt):
+        if j % 4 == 3:
+            sets.append([j % nc, (j + 5) % nc])          # on the cycle: slow
+        else:
+            sets.append([nc + (j % ni), nc + ((j + 7) % ni)])  # isolated: one iteration
+    off = np.concatenate([[0], np.cumsum([len(s) for s in sets])]).astype(np.int32)
+    seeds = np.concatenate(sets).astype(np.int32)
+    res = P.ppr_batch(png, off, seeds, d=d, tol=1e-9, max_iters=30)
+    assert not res.converged
+    slow = np.array([j % 4 == 3 for j in range(len(sets))])
+    assert np.all(res.iters[~slow] == 1) and np.all(res.resid[~slow] < 1e-9)
+    assert np.all(res.iters[slow] == 30) and np.all(res.resid[slow] > 1e-9)
+    x = res.pr.cpu().numpy()
+    check_vectors(x, r, c, off, seeds, res.iters, d=d)
+    for j, s in enumerate(sets):
+        if not slow[j]:
+            want = np.zeros(n)
+            want[s] = 0.5
+            np.testing.assert_allclose(x[:, j], want, atol=1e-7)
+    png.close()
