@@ -16,6 +16,10 @@ Everything here is FP64 and follows the paper's definitions directly:
                  scatter, Alg. 5 gather, Alg. 2 apply).
 * ``step_at``    one step of Eq. 1 from a given vector, at chosen nodes only
                  (for checks on graphs too large for full runs).
+* ``spmv``       the sparse matrix-vector product of Sec. 3.4 (weighted
+                 graphs): y(v) = sum over edges u->v of w(u,v) x(u).
+* ``bin_weights`` edge weights in the order of the destination-ID bins, where
+                 Sec. 3.4 stores them.
 * ``mlp``        FP64 reference of the warm-start network (see ``oracle.mlp``).
 """
 from __future__ import annotations
@@ -203,3 +207,31 @@ def pcpm_iterate(row_off, png: PNG, x, d=0.85, tele=None):
                          _p(png.upd_start), _p(np.ascontiguousarray(png.wo.reshape(-1))),
                          _p(png.did_start), _p(did), float(d), _p(tele), _p(x), _p(y), _p(res))
     return y, float(res[0])
+
+
+def _sources(row_off) -> np.ndarray:
+    row_off = np.asarray(row_off, dtype=np.int64)
+    return np.repeat(np.arange(len(row_off) - 1, dtype=np.int64), np.diff(row_off))
+
+
+def spmv(row_off, col, x, weights=None) -> np.ndarray:
+    """Sec. 3.4: y(v) = sum over edges u->v of w(u,v) * x(u) in FP64, with
+    w = 1 on every edge when ``weights`` is None (weights[e] belongs to the
+    CSR edge row -> col[e]); that is y = A^T x for the CSR matrix A."""
+    n = len(row_off) - 1
+    x = np.asarray(x, dtype=np.float64)
+    col = np.asarray(col, dtype=np.int64)
+    w = np.ones(len(col)) if weights is None else np.asarray(weights, dtype=np.float64)
+    return np.bincount(col, weights=w * x[_sources(row_off)], minlength=n).astype(np.float64)
+
+
+def bin_weights(row_off, col, weights, q: int) -> np.ndarray:
+    """Sec. 3.4: each weight is stored next to its destination ID, so the
+    weights follow the canonical order of the destination-ID bins:
+    destination partition, then source partition, source node, destination
+    node (the order of ``png_layout(...).did``)."""
+    src = _sources(row_off)
+    col = np.asarray(col, dtype=np.int64)
+    order = np.lexsort((col, src, src // q, col // q))
+    return np.asarray(weights)[order]
+
