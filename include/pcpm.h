@@ -71,6 +71,12 @@ typedef struct {
   int64_t gather_chunk;  /* destination IDs per gather work item; 0 = auto   */
   int64_t build_chunk;   /* CSR edges per count/fill work item of the build;
                             0 = automatic (about m / max(k, 4096), >= 16384)  */
+  const float* weights;  /* (device) m edge weights in CSR order (weights[e]
+                            belongs to the edge row -> col[e]), finite, any
+                            sign; NULL = unweighted.  Stored next to the
+                            destination IDs in bin order (Sec. 3.4) and read
+                            by pcpm_spmv only: PageRank always scales by
+                            1/outdeg.  The caller keeps ownership.           */
 } pcpm_build_opts_t;
 
 typedef struct {
@@ -85,6 +91,7 @@ typedef struct {
   int64_t device_bytes;  /* device memory held by the handle                  */
   int64_t num_graphs;    /* G (1 for a single graph)                          */
   double build_ms;       /* wall time of pcpm_build_png, device work included */
+  int64_t weighted;      /* 1 if the build was given edge weights             */
 } pcpm_png_info_t;
 
 /*
@@ -121,8 +128,38 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src,
                               int64_t* upd_start, int64_t* wo, int64_t* did_start,
                               uint32_t* did);
 
+/* The build's edge weights in destination-ID bin order (Sec. 3.4): w[e]
+ * (host, m floats) is the weight of the edge whose destination ID is did[e]
+ * of pcpm_png_export.  PCPM_ERR_INVALID_ARG if the handle is unweighted.
+ * Synchronises the device. */
+pcpm_status_t pcpm_png_export_weights(pcpm_png_t g, float* w /* (host) m */);
+
 /* Release a handle and its device memory (NULL is ignored). */
 void pcpm_png_free(pcpm_png_t g);
+
+/*
+ * Sparse matrix-vector product over the PNG (Sec. 3.4, the extension of PCPM
+ * to weighted graphs and SpMV):
+ *   y(v) = sum over edges u->v of w(u,v) * x(u)
+ * with w the build's weights (1 on every edge of an unweighted handle), i.e.
+ * y = A^T x for the CSR matrix A of the build.  The scatter writes x(u) once
+ * per (u, destination partition) (Alg. 3 without the 1/outdeg scaling); the
+ * gather reads each weight with its destination ID and applies it to the
+ * update before accumulating (Alg. 5).  x and y are device arrays of n floats
+ * and must not overlap.  A non-square matrix (rows R, columns C) runs on a
+ * square handle with n >= max(R, C): padded rows have no edges, x is zero
+ * past R and y past C is zero.
+ * Accuracy: each product w*x(u) is formed exactly in FP64 and rounded to a
+ * multiple of 2^-s, s = min(50 - ceil(log2(max|w| max|x|)), 62 -
+ * ceil(log2(W max|x|))) with W the largest sum over v of |w(u,v)| (a
+ * build-time statistic); the sum is exact (64-bit integers, independent of
+ * order: y is bit-reproducible), then rounded once to FP32.  So |y(v) -
+ * exact| <= indeg(v) 2^-(s+1) + FP32 rounding of y(v).  If x holds a
+ * non-finite value, y is NaN everywhere.  Asynchronous on `stream`.
+ * Works on multi-graph handles (block-diagonal).
+ */
+pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x /* (device) n */, float* y /* (device) n */,
+                        void* stream);
 
 /*
  * One PageRank iteration (Eq. 1, Sec. 2.1) carried out as PCPM scatter

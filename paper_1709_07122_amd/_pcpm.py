@@ -33,7 +33,8 @@ STATUS_NAMES = {
 EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
            "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_last_error",
            "pcpm_timing_enable", "pcpm_timing_collect", "pcpm_ws_features", "pcpm_ws_forward", "pcpm_ws_init",
-           "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_adam", "pcpm_ws_targets"]
+           "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_adam", "pcpm_ws_targets", "pcpm_spmv",
+           "pcpm_png_export_weights"]
 
 WS_FEATURES = 8
 WS_HIDDEN = 64
@@ -50,13 +51,14 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("part_log2", ctypes.c_int32), ("num_graphs", ctypes.c_int32),
                 ("graph_node_off", ctypes.c_void_p), ("graph_nodes", ctypes.c_void_p),
                 ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64),
-                ("build_chunk", ctypes.c_int64)]
+                ("build_chunk", ctypes.c_int64), ("weights", ctypes.c_void_p)]
 
 
 class PngInfo(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ("n", "m", "q", "k", "eprime", "nseg", "n_dangling", "scatter_items", "gather_items",
-                 "split_bins", "device_bytes", "num_graphs")] + [("build_ms", ctypes.c_double)]
+                 "split_bins", "device_bytes", "num_graphs")] + [("build_ms", ctypes.c_double),
+                                                                 ("weighted", ctypes.c_int64)]
 
 
 class KernelTime(ctypes.Structure):
@@ -84,6 +86,10 @@ def lib():
     L.pcpm_png_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pcpm_png_free.restype = None
     L.pcpm_png_free.argtypes = [vp]
+    L.pcpm_png_export_weights.restype = ctypes.c_int
+    L.pcpm_png_export_weights.argtypes = [vp, vp]
+    L.pcpm_spmv.restype = ctypes.c_int
+    L.pcpm_spmv.argtypes = [vp, vp, vp, vp]
     L.pcpm_iterate.restype = ctypes.c_int
     L.pcpm_iterate.argtypes = [vp, dbl, vp, vp, ctypes.POINTER(dbl), vp]
     L.pcpm_pagerank.restype = ctypes.c_int
@@ -191,6 +197,12 @@ class PNG:
         out["did"] = out["did"][:m]
         return out
 
+    def export_weights(self) -> np.ndarray:
+        """Edge weights in destination-ID bin order (see pcpm_png_export_weights)."""
+        w = np.zeros(max(self.m, 1), np.float32)
+        _check(lib().pcpm_png_export_weights(self.handle, w.ctypes.data))
+        return w[:self.m]
+
     def graph_results(self):
         """(iters[G], resid[G]) of the last pagerank call on this handle."""
         G = self.info["num_graphs"]
@@ -212,11 +224,12 @@ class PNG:
 
 
 def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_chunk: int = 0,
-              graph_node_off=None, graph_nodes=None, build_chunk: int = 0, stream=None) -> PNG:
+              graph_node_off=None, graph_nodes=None, build_chunk: int = 0, weights=None, stream=None) -> PNG:
     """pcpm_build_png on device CSR tensors (int32 row_off[n+1], col[m]).
 
     For several graphs in one handle pass the padded union (see union_csr)
-    with its graph_node_off (G+1) and graph_nodes (G)."""
+    with its graph_node_off (G+1) and graph_nodes (G).  weights: optional
+    device float32 tensor of m edge weights in CSR order (for spmv)."""
     import torch
     n = row_off.numel() - 1
     m = col.numel()
@@ -225,11 +238,38 @@ def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_c
     G = 0 if graph_node_off is None else len(graph_nodes)
     goff = np.ascontiguousarray(graph_node_off if G else [0], dtype=np.int64)
     gn = np.ascontiguousarray(graph_nodes if G else [0], dtype=np.int64)
+    wp = None if weights is None else _dev_tensor(weights, torch.float32, m, "weights")
     opts = BuildOpts(int(part_log2), G, goff.ctypes.data if G else None, gn.ctypes.data if G else None,
-                     int(scatter_chunk), int(gather_chunk), int(build_chunk))
+                     int(scatter_chunk), int(gather_chunk), int(build_chunk), wp)
     h = ctypes.c_void_p()
     _check(lib().pcpm_build_png(n, m, rp, cp, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return PNG(h, row_off, col)
+
+
+def spmv(png: PNG, x, out=None, stream=None):
+    """pcpm_spmv: y(v) = sum over edges u->v of w(u,v) x(u) (w = 1 when the
+    handle is unweighted); x and the returned y are device float32 [n]."""
+    import torch
+    n = png.n
+    xp = _dev_tensor(x, torch.float32, n, "x")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=x.device)
+    yp = _dev_tensor(out, torch.float32, n, "out")
+    _check(lib().pcpm_spmv(png.handle, xp, yp, _stream(stream)))
+    return out
+
+
+def square_csr(row_off, col, cols: int):
+    """A rows x cols CSR matrix as the CSR of a square graph on
+    n = max(rows, cols) nodes (rows past `rows` are empty), so that spmv runs
+    it: pad x with zeros to n and read y[:cols].  Host arrays in and out; only
+    offsets are appended."""
+    row_off = np.ascontiguousarray(row_off, dtype=np.int32)
+    rows = len(row_off) - 1
+    n = max(rows, int(cols))
+    if n > rows:
+        row_off = np.concatenate([row_off, np.full(n - rows, row_off[-1], np.int32)])
+    return row_off, np.ascontiguousarray(col, dtype=np.int32)
 
 
 def iterate(png: PNG, pr_in, pr_out=None, d: float = 0.85, want_resid: bool = True, stream=None):

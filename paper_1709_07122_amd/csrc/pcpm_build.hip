@@ -18,6 +18,7 @@
 #include <cstring>
 #include <vector>
 
+#include "pcpm_device.hpp"
 #include "pcpm_internal.hpp"
 
 namespace pcpm {
@@ -330,7 +331,8 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
                                              const int32_t* __restrict__ ccnt, const int32_t* __restrict__ craw,
                                              const int32_t* __restrict__ png_base,
                                              const int32_t* __restrict__ png_off, uint16_t* __restrict__ did,
-                                             uint16_t* __restrict__ png_src) {
+                                             uint16_t* __restrict__ png_src, const float* __restrict__ weights,
+                                             float* __restrict__ wbin) {
   extern __shared__ int32_t sh[];
   int32_t* cur_did = sh;   // absolute destination-ID position per p'
   int32_t* cur_rank = sh + k;  // rank inside U(p,p') per p'
@@ -374,6 +376,7 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
     __builtin_amdgcn_wave_barrier();
     if (valid) {
       did[tile_pos(cd + rank)] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | (first ? kDidFlag : 0u));
+      if (wbin) wbin[cd + rank] = weights[e];  // the weight travels with its destination ID (Sec. 3.4)
       if (first) {
         // position in the pair-ordered PNG edges: after the pair's earlier
         // pair segments and, for the odd partition, after the even one's run
@@ -394,6 +397,47 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
       }
     }
     __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Weight statistics for the SpMV's fixed-point scale, one workgroup per
+// destination bin: the largest |w| and the largest sum over v of |w(u,v)|
+// (FP64 sums in an LDS slice; 1 per edge when unweighted), as the bit
+// patterns of non-negative doubles, whose order is that of the values; out[2]
+// counts non-finite weights.
+__global__ __launch_bounds__(1024) void k_w_stats(int64_t n, int s, const int32_t* __restrict__ did_start,
+                                                  const uint16_t* __restrict__ did, const float* __restrict__ wbin,
+                                                  unsigned long long* __restrict__ out) {
+  extern __shared__ double csum[];
+  const int64_t p = blockIdx.x;
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = p << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  for (int i = threadIdx.x; i < qn; i += 1024) csum[i] = 0.0;
+  __syncthreads();
+  double wm = 0.0;
+  int bad = 0;
+  const uint32_t qmask = static_cast<uint32_t>(q - 1);
+  for (int64_t e = did_start[p] + threadIdx.x; e < did_start[p + 1]; e += 1024) {
+    const uint32_t x = did[tile_pos(e)] & qmask;
+    const float wf = wbin ? wbin[e] : 1.0f;
+    if (!isfinite(wf)) {
+      bad = 1;
+      continue;
+    }
+    const double w = fabs(static_cast<double>(wf));
+    wm = fmax(wm, w);
+    atomicAdd(&csum[x], w);
+  }
+  __syncthreads();
+  double cm = 0.0;
+  for (int i = threadIdx.x; i < qn; i += 1024) cm = fmax(cm, csum[i]);
+  cm = block_max<1024>(cm);
+  wm = block_max<1024>(wm);
+  if (bad) atomicAdd(&out[2], 1ull);
+  if (threadIdx.x == 0) {
+    atomicMax(&out[0], static_cast<unsigned long long>(__double_as_longlong(cm)));
+    atomicMax(&out[1], static_cast<unsigned long long>(__double_as_longlong(wm)));
   }
 }
 
@@ -732,9 +776,32 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY_HIP(hipMemsetAsync(g->did, 0, std::max<int64_t>(ntd, 1) * kTile * 2, st));
   int nbits = 0;
   while ((int64_t{1} << nbits) < k) ++nbits;
+  const float* weights = opts ? opts->weights : nullptr;
+  if (weights) {
+    if (!is_device_ptr(weights)) return set_error(PCPM_ERR_INVALID_ARG, "weights must be a device pointer");
+    // padded to whole tiles (zeros): the gather reads a tile's weights without a predicate
+    PCPM_TRY(dalloc(g, &g->wbin, std::max<int64_t>(ntd, 1) * kTile));
+    PCPM_TRY_HIP(hipMemsetAsync(g->wbin, 0, std::max<int64_t>(ntd, 1) * kTile * 4, st));
+  }
   PCPM_LAUNCH("pcpm_build_fill", k_fill, dim3(static_cast<unsigned>(nchunks)), dim3(64),
               static_cast<size_t>(2 * k * 4), st, s, static_cast<int32_t>(k), nbits, chunks_d, col, src,
-              g->did_start, dwo, ccnt, craw, g->png_base, g->png_off, g->did, g->png_src);
+              g->did_start, dwo, ccnt, craw, g->png_base, g->png_off, g->did, g->png_src, weights, g->wbin);
+
+  // ---- weight statistics (scale of pcpm_spmv) -----------------------------------
+  unsigned long long* wst = nullptr;
+  PCPM_TRY(dalloc(g, &wst, 3));
+  PCPM_TRY_HIP(hipMemsetAsync(wst, 0, 3 * sizeof(unsigned long long), st));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_w_stats),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g->q * 8)));
+  PCPM_LAUNCH("pcpm_build_wstats", k_w_stats, dim3(static_cast<unsigned>(k)), dim3(1024),
+              static_cast<size_t>(g->q * 8), st, n, s, g->did_start, g->did, g->wbin, wst);
+  unsigned long long wst_h[3] = {0, 0, 0};
+  PCPM_TRY_HIP(hipMemcpyAsync(wst_h, wst, sizeof(wst_h), hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  dfree(g, wst);
+  if (wst_h[2]) return set_error(PCPM_ERR_INVALID_ARG, "weights hold %llu non-finite values", wst_h[2]);
+  std::memcpy(&g->w_colmax, &wst_h[0], 8);
+  std::memcpy(&g->w_absmax, &wst_h[1], 8);
 
   // ---- tile flag prefixes ----------------------------------------------------
   int32_t* tcnt = nullptr;
@@ -825,6 +892,17 @@ pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out) {
   out->device_bytes = g->device_bytes;
   out->num_graphs = g->ngroups;
   out->build_ms = g->build_ms;
+  out->weighted = g->wbin ? 1 : 0;
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_png_export_weights(pcpm_png_t g, float* w) {
+  using namespace pcpm;
+  if (!g || !w) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or output");
+  if (!g->wbin) return set_error(PCPM_ERR_INVALID_ARG, "the handle has no edge weights");
+  PCPM_TRY_HIP(hipSetDevice(g->device));
+  PCPM_TRY_HIP(hipDeviceSynchronize());
+  if (g->m > 0) PCPM_TRY_HIP(hipMemcpy(w, g->wbin, static_cast<size_t>(g->m) * 4, hipMemcpyDeviceToHost));
   return PCPM_OK;
 }
 

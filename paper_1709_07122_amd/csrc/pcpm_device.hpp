@@ -68,6 +68,12 @@ struct FixedConv {
     const double y = fma(static_cast<double>(v), scale, kMagic);
     return __double_as_longlong(y) - __double_as_longlong(kMagic);
   }
+  // the same for an FP64 value (an exact product of two FP32 values)
+  __device__ __forceinline__ int64_t operator()(double v) const {
+    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+    const double y = fma(v, scale, kMagic);
+    return __double_as_longlong(y) - __double_as_longlong(kMagic);
+  }
 };
 
 }  // namespace pcpm

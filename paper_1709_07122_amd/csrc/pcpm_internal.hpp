@@ -213,6 +213,10 @@ struct pcpm_png {
 
   // gather side: destination-ID bins
   uint16_t* did = nullptr;      // ceil(m/kTile)*kTile: v - p'q, bit 15 = first of message
+  float* wbin = nullptr;        // m edge weights in bin order (weighted handles only)
+  double w_absmax = 0.0;        // max |w| (1 if unweighted, 0 without edges)
+  double w_colmax = 0.0;        // max over v of sum_{u->v} |w(u,v)|
+  float* spmv_blockmax = nullptr;  // per-block max |x| of pcpm_spmv
   int32_t* did_blk = nullptr;   // flags before each tile, ceil(m/kTile)+1
   int32_t* did_start = nullptr; // k+1
   float* upd = nullptr;         // E'+1: update bins (rewritten every iteration) + spare slot

@@ -100,7 +100,8 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
   }
 }
 
-template <int BS>
+// kScale: stage PR(u)/outdeg(u) (PageRank); otherwise x(u) itself (SpMV).
+template <int BS, bool kScale = true>
 __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                 const Item* __restrict__ items, const float* __restrict__ pr,
                                                 const int32_t* __restrict__ outdeg,
@@ -116,8 +117,12 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   const int64_t v0 = static_cast<int64_t>(it.part) << (s + 1);
   const int qn = static_cast<int>(min(int64_t{2} << s, n - v0));
   for (int i = threadIdx.x; i < qn; i += BS) {
-    const int od = outdeg[v0 + i];
-    spr[i] = od > 0 ? pr[v0 + i] / static_cast<float>(od) : 0.0f;
+    if constexpr (kScale) {
+      const int od = outdeg[v0 + i];
+      spr[i] = od > 0 ? pr[v0 + i] / static_cast<float>(od) : 0.0f;
+    } else {
+      spr[i] = pr[v0 + i];
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
@@ -168,7 +173,10 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   }
 }
 
-template <int BS>
+// kMode 0: PageRank (apply, residual, dangling mass); 1: SpMV, y(v) = sum of
+// the updates; 2: SpMV with the edge weight stored beside each destination ID
+// applied to its update (Sec. 3.4).  In SpMV modes pr_out receives y.
+template <int BS, int kMode = 0>
 __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                const Item* __restrict__ items, const uint16_t* __restrict__ did,
                                                const int32_t* __restrict__ did_blk, const float* __restrict__ upd,
@@ -176,7 +184,8 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
                                                const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
                                                double* __restrict__ red, const GCtl* __restrict__ gctl,
                                                const int32_t* __restrict__ part_group,
-                                               const int32_t* __restrict__ part_valid) {
+                                               const int32_t* __restrict__ part_valid,
+                                               const float* __restrict__ wbin) {
   if (ctl->done) return;
   extern __shared__ unsigned long long acc[];
   const Item it = items[blockIdx.x];
@@ -219,16 +228,26 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
     float val[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) val[j] = *reinterpret_cast<const float*>(ub + off[j]);
+    // weights are stored in bin order, padded to whole tiles
+    float wv[kMode == 2 ? kSub : 1];
+    if constexpr (kMode == 2) {
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) wv[j] = wbin[tb + j * kWave + lane];
+    }
+    // the update (times its weight, formed exactly in FP64) as a fixed-point integer
+    auto fixed = [&](int j) -> int64_t {
+      if constexpr (kMode == 2) return to_fixed(static_cast<double>(wv[j]) * static_cast<double>(val[j]));
+      else return to_fixed(val[j]);
+    };
     if (tb >= lo && tb + kTile <= hi) {
 #pragma unroll
-      for (int j = 0; j < kSub; ++j)
-        atomicAdd(&acc[x[j] & qmask], static_cast<unsigned long long>(to_fixed(val[j])));
+      for (int j = 0; j < kSub; ++j) atomicAdd(&acc[x[j] & qmask], static_cast<unsigned long long>(fixed(j)));
     } else {  // edge tile: entries outside [lo, hi) add nothing
 #pragma unroll
       for (int j = 0; j < kSub; ++j) {
         const int64_t e = tb + j * kWave + lane;
         const bool in = e >= lo && e < hi;
-        atomicAdd(&acc[in ? (x[j] & qmask) : 0u], static_cast<unsigned long long>(in ? to_fixed(val[j]) : 0));
+        atomicAdd(&acc[in ? (x[j] & qmask) : 0u], static_cast<unsigned long long>(in ? fixed(j) : 0));
       }
     }
 #pragma unroll
@@ -238,6 +257,13 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
   if (it.aux >= 0) {
     int64_t* dst = partial + static_cast<int64_t>(it.aux) * q;
     for (int i = threadIdx.x; i < qn; i += BS) dst[i] = static_cast<int64_t>(acc[i]);
+    return;
+  }
+  if constexpr (kMode != 0) {
+    const double unit = ldexp(1.0, -ctl->fx_shift);
+    const bool bad = ctl->nonfinite != 0;
+    for (int i = threadIdx.x; i < qn; i += BS)
+      pr_out[v0 + i] = bad ? __builtin_nanf("") : static_cast<float>(static_cast<double>(static_cast<int64_t>(acc[i])) * unit);
     return;
   }
   apply_nodes<BS>(ctl, gctl, part_group, part_valid, it.part, v0, 0, qn,
@@ -335,6 +361,59 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* 
     if (bad) ctl->nonfinite = 1;
     if (bad || all_done) ctl->done = 1;
     ctl->fx_shift = fx_shift_for(vmax, ctl->fx_cap);
+  }
+}
+
+// ---- SpMV (Sec. 3.4) -----------------------------------------------------------------
+// Split bins of an SpMV: y = the sum of the item slices, in slot order.
+__global__ __launch_bounds__(kMergeNodes) void k_spmv_merge(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                           const Merge* __restrict__ mg,
+                                                           const int64_t* __restrict__ partial, float* __restrict__ y) {
+  const Merge mu = mg[blockIdx.x];
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  const int i = mu.node_lo + static_cast<int>(threadIdx.x);
+  if (i >= qn) return;
+  const int64_t* base = partial + static_cast<int64_t>(mu.first) * q;
+  int64_t sum = 0;
+  for (int c = 0; c < mu.count; ++c) sum += base[static_cast<int64_t>(c) * q + i];
+  y[v0 + i] = ctl->nonfinite ? __builtin_nanf("")
+                             : static_cast<float>(static_cast<double>(sum) * ldexp(1.0, -ctl->fx_shift));
+}
+
+// Largest |x| per workgroup (+inf if x holds a non-finite value).
+__global__ __launch_bounds__(256) void k_spmv_absmax(const float* __restrict__ x, int64_t n,
+                                                      float* __restrict__ blockmax) {
+  float m = 0.0f;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * 256) {
+    const float a = fabsf(x[v]);
+    m = fmaxf(m, isfinite(a) ? a : __builtin_inff());
+  }
+  const double bm = block_max<256>(static_cast<double>(m));
+  if (threadIdx.x == 0) blockmax[blockIdx.x] = static_cast<float>(bm);
+}
+
+// Fixed-point scale of one SpMV: every product w*x(u) is at most
+// wabs * max|x| (kept below 2^50 units) and every sum, partial or whole, at
+// most wcol * max|x| (kept below 2^62 units).
+__global__ __launch_bounds__(1024) void k_spmv_scale(Ctl* __restrict__ ctl, const float* __restrict__ blockmax,
+                                                      int nb, double wabs, double wcol) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 1024) m = fmax(m, static_cast<double>(blockmax[b]));
+  m = block_max<1024>(m);
+  if (threadIdx.x == 0) {
+    int sh = 0;
+    const bool bad = !isfinite(m);
+    if (!bad && m > 0.0 && wabs > 0.0 && wcol > 0.0) {
+      const int e1 = static_cast<int>(ceil(log2(wabs * m)));
+      const int e2 = static_cast<int>(ceil(log2(wcol * m)));
+      sh = min(50 - e1, 62 - e2);
+    }
+    ctl->done = 0;
+    ctl->nonfinite = bad ? 1 : 0;
+    ctl->fx_shift = sh;
   }
 }
 
@@ -462,6 +541,12 @@ pcpm_status_t iter_lds_limits() {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (2 << kMaxLog2) * 4));
   PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter<kScatterBlock, false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (2 << kMaxLog2) * 4));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock, 1>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock, 2>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
   done = true;
   return PCPM_OK;
 }
@@ -487,7 +572,7 @@ static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hip
                 g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
   PCPM_LAUNCH("pcpm_gather", k_gather<kGatherBlock>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kGatherBlock),
               static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items, g->did, g->did_blk,
-              g->upd, in, out, g->dmask, g->partial, g->red, g->gctl, g->part_group, g->part_valid);
+              g->upd, in, out, g->dmask, g->partial, g->red, g->gctl, g->part_group, g->part_valid, nullptr);
   if (g->n_mg)
     PCPM_LAUNCH("pcpm_merge", k_merge<kMergeNodes>, dim3(static_cast<unsigned>(g->n_mg)), dim3(kMergeNodes), 0,
                 st, g->ctl, g->n, g->part_log2, g->mg_items, g->partial, in, out, g->dmask, g->red, g->k, g->gctl,
@@ -527,6 +612,38 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
     *resid = g->ctl_host->res;
     if (g->ctl_host->nonfinite) return set_error(PCPM_ERR_NUMERIC, "non-finite rank, residual or dangling mass");
   }
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x, float* y, void* stream) {
+  using namespace pcpm;
+  if (!g || !x || !y) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or vector");
+  if (x < y + g->n && y < x + g->n) return set_error(PCPM_ERR_INVALID_ARG, "x and y must not overlap");
+  PCPM_TRY(check_device(g));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  constexpr int kMaxBlocks = 1024;
+  if (!g->spmv_blockmax) PCPM_TRY(dalloc(g, &g->spmv_blockmax, kMaxBlocks));
+  const int nb = static_cast<int>(std::min<int64_t>((g->n + 255) / 256, kMaxBlocks));
+  PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_absmax, dim3(nb), dim3(256), 0, st, x, g->n, g->spmv_blockmax);
+  PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_scale, dim3(1), dim3(1024), 0, st, g->ctl, g->spmv_blockmax, nb, g->w_absmax,
+              g->w_colmax);
+  if (g->n_sc)
+    PCPM_LAUNCH("pcpm_spmv_scatter", (k_scatter<kScatterBlock, false>), dim3(static_cast<unsigned>(g->n_sc)),
+                dim3(kScatterBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->sc_items, x,
+                g->outdeg, g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
+  if (g->wbin)
+    PCPM_LAUNCH("pcpm_spmv_gather", (k_gather<kGatherBlock, 2>), dim3(static_cast<unsigned>(g->n_ga)),
+                dim3(kGatherBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items,
+                g->did, g->did_blk, g->upd, x, y, g->dmask, g->partial, g->red, g->gctl, g->part_group,
+                g->part_valid, g->wbin);
+  else
+    PCPM_LAUNCH("pcpm_spmv_gather", (k_gather<kGatherBlock, 1>), dim3(static_cast<unsigned>(g->n_ga)),
+                dim3(kGatherBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items,
+                g->did, g->did_blk, g->upd, x, y, g->dmask, g->partial, g->red, g->gctl, g->part_group,
+                g->part_valid, nullptr);
+  if (g->n_mg)
+    PCPM_LAUNCH("pcpm_spmv_merge", k_spmv_merge, dim3(static_cast<unsigned>(g->n_mg)), dim3(kMergeNodes), 0, st,
+                g->ctl, g->n, g->part_log2, g->mg_items, g->partial, y);
   return PCPM_OK;
 }
 

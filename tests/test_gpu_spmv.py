@@ -1,0 +1,195 @@
+"""pcpm_spmv (Sec. 3.4: weighted graphs and SpMV over the PNG) against the
+FP64 oracle.  Bound per element: every product is rounded to a multiple of
+2^-s (s from max|w| max|x| and the largest weighted in-degree, as the header
+states), the sum is exact, and y is rounded to FP32:
+    |y - y*| <= indeg(v) 2^-s + 2^-23 |y*| + 2^-150 (subnormal y)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1709_07122_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def scale_bits(r, c, x, w):
+    """The s of the header, from the inputs (one lower, to allow for the last
+    bit of the FP64 weighted in-degree the GPU forms)."""
+    n = len(r) - 1
+    aw = np.ones(len(c)) if w is None else np.abs(w.astype(np.float64))
+    xmax = float(np.abs(x.astype(np.float64)).max()) if n else 0.0
+    if len(c) == 0 or xmax == 0.0 or aw.max() == 0.0:
+        return 60
+    wcol = np.bincount(c, weights=aw, minlength=n).max()
+    return min(50 - int(np.ceil(np.log2(aw.max() * xmax))), 62 - int(np.ceil(np.log2(wcol * xmax)))) - 1
+
+
+def check(y, r, c, x, w):
+    ref = oracle.spmv(r, c, x.astype(np.float64), None if w is None else w.astype(np.float64))
+    indeg = np.bincount(c, minlength=len(r) - 1)
+    s = scale_bits(r, c, x, w)
+    # FP32 rounding of y: relative 2^-24 (2^-23 for margin), absolute 2^-150 for subnormal results
+    bound = indeg * 2.0 ** -s + 2.0 ** -23 * np.abs(ref) + 2.0 ** -150
+    err = np.abs(y.astype(np.float64) - ref)
+    assert np.all(err <= bound), (err / bound).max()
+    return ref
+
+
+@pytest.mark.parametrize("scale,relabel,part_log2", [(12, "random", 8), (12, "random", 14), (13, "indegree", 10),
+                                                     (11, None, 5)])
+def test_weighted_spmv_matches_oracle(scale, relabel, part_log2):
+    r, c = graphgen.rmat(scale, 16, seed=scale + part_log2, relabel=relabel)
+    n = len(r) - 1
+    rng = np.random.default_rng(part_log2)
+    w = rng.standard_normal(len(c)).astype(np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=part_log2, weights=dev(w))
+    assert png.info["weighted"] == 1
+    y = P.spmv(png, dev(x)).cpu().numpy()
+    check(y, r, c, x, w)
+    y2 = P.spmv(png, dev(x)).cpu().numpy()
+    assert np.array_equal(y.view(np.uint32), y2.view(np.uint32))  # exact integer sums: bit-reproducible
+    np.testing.assert_array_equal(png.export_weights(), oracle.bin_weights(r, c, w, 1 << part_log2))
+    png.close()
+
+
+@pytest.mark.parametrize("graph", ["split_bins", "ragged"])
+def test_split_bins_and_ragged_tail(graph):
+    if graph == "split_bins":  # generator labels: hub partitions, bins split over several items
+        r, c = graphgen.rmat(14, 16, seed=6)
+        kw = dict(part_log2=10, gather_chunk=8192, scatter_chunk=4096)
+    else:  # n not a multiple of q
+        r, c = graphgen.uniform(15001, 300000, seed=3)
+        kw = dict(part_log2=10)
+    n = len(r) - 1
+    rng = np.random.default_rng(9)
+    w = rng.uniform(-2, 2, len(c)).astype(np.float32)
+    x = rng.uniform(-1, 1, n).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), weights=dev(w), **kw)
+    if graph == "split_bins":
+        assert png.info["split_bins"] > 0
+    check(P.spmv(png, dev(x)).cpu().numpy(), r, c, x, w)
+    png.close()
+
+
+def test_unweighted_integer_vector_is_exact():
+    """With w = 1 and small integers every product and sum is an integer the
+    fixed-point format holds exactly, and |y| < 2^24: y equals A^T x."""
+    r, c = graphgen.rmat(13, 8, seed=3, relabel="random")
+    n = len(r) - 1
+    x = np.random.default_rng(2).integers(-50, 51, n).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=11)
+    assert png.info["weighted"] == 0
+    y = P.spmv(png, dev(x)).cpu().numpy()
+    np.testing.assert_array_equal(y.astype(np.float64), oracle.spmv(r, c, x))
+    with pytest.raises(P.PCPMError):
+        png.export_weights()
+    png.close()
+
+
+def test_inverse_out_degree_weights_give_a_pagerank_step():
+    r, c = graphgen.rmat(12, 16, seed=4, relabel="random")
+    n = len(r) - 1
+    outdeg = np.diff(r)
+    w = (1.0 / np.repeat(outdeg, outdeg)).astype(np.float32)
+    x = np.random.default_rng(5).random(n).astype(np.float32)
+    x /= x.sum()
+    png = P.build_png(dev(r), dev(c), part_log2=9, weights=dev(w))
+    y = P.spmv(png, dev(x)).cpu().numpy().astype(np.float64)
+    d = 0.85
+    dang = x[outdeg == 0].astype(np.float64).sum()
+    step = d * y + (1 - d) / n + d * dang / n
+    it, _ = P.iterate(png, dev(x), d=d)
+    np.testing.assert_allclose(step, it.cpu().numpy(), rtol=1e-5, atol=1e-12)
+    png.close()
+
+
+def test_zero_nonfinite_and_extreme_magnitudes():
+    r, c = graphgen.rmat(11, 8, seed=7, relabel="random")
+    n = len(r) - 1
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal(len(c)).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=8, weights=dev(w))
+    assert np.all(P.spmv(png, dev(np.zeros(n, np.float32))).cpu().numpy() == 0.0)
+    x = rng.standard_normal(n).astype(np.float32)
+    for f in (1e30, 1e-30, 3e-38):
+        xs = (x * np.float32(f)).astype(np.float32)
+        check(P.spmv(png, dev(xs)).cpu().numpy(), r, c, xs, w)
+    xb = x.copy()
+    xb[17] = np.nan
+    assert np.all(np.isnan(P.spmv(png, dev(xb)).cpu().numpy()))
+    xb[17] = np.inf
+    assert np.all(np.isnan(P.spmv(png, dev(xb)).cpu().numpy()))
+    # a finite vector afterwards is unaffected
+    check(P.spmv(png, dev(x)).cpu().numpy(), r, c, x, w)
+    png.close()
+
+
+def test_rejects_bad_weights_and_overlap():
+    r, c = graphgen.rmat(9, 8, seed=1)
+    w = np.ones(len(c), np.float32)
+    w[5] = np.inf
+    with pytest.raises(P.PCPMError) as ei:
+        P.build_png(dev(r), dev(c), part_log2=6, weights=dev(w))
+    assert ei.value.status == P.PCPM_ERR_INVALID_ARG
+    png = P.build_png(dev(r), dev(c), part_log2=6)
+    n = png.n
+    buf = torch.zeros(2 * n, dtype=torch.float32, device="cuda")
+    with pytest.raises(P.PCPMError) as ei:
+        P.spmv(png, buf[:n], out=buf[3:3 + n])
+    assert ei.value.status == P.PCPM_ERR_INVALID_ARG
+    png.close()
+
+
+def test_rectangular_matrix_on_a_square_handle():
+    rows, cols = 700, 2000
+    rng = np.random.default_rng(13)
+    src = rng.integers(0, rows, 9000)
+    dst = rng.integers(0, cols, 9000)
+    keep = np.ones(len(src), bool)
+    r0, c0 = graphgen.from_edges(max(rows, cols), src[keep], dst[keep])  # canonical (dedup, no self loops)
+    r0 = r0[:rows + 1]  # rows past `rows` are empty anyway
+    r, c = P.square_csr(r0, c0, cols)
+    w = rng.standard_normal(len(c)).astype(np.float32)
+    x = np.zeros(len(r) - 1, np.float32)
+    x[:rows] = rng.standard_normal(rows).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=8, weights=dev(w))
+    y = P.spmv(png, dev(x)).cpu().numpy()[:cols]
+    A = np.zeros((rows, cols))
+    for u in range(rows):
+        for e in range(r[u], r[u + 1]):
+            A[u, c[e]] += w[e]
+    np.testing.assert_allclose(y, A.T @ x[:rows].astype(np.float64), rtol=1e-5, atol=1e-6)
+    png.close()
+
+
+def test_multi_graph_handle():
+    graphs = [graphgen.rmat(s, 8, seed=20 + s, relabel="random") for s in (9, 11, 8)]
+    r, c, off, sizes = P.union_csr(graphs, 9)
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal(len(c)).astype(np.float32)
+    x = rng.standard_normal(len(r) - 1).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=9, graph_node_off=off, graph_nodes=sizes, weights=dev(w))
+    check(P.spmv(png, dev(x)).cpu().numpy(), r, c, x, w)
+    png.close()
+
+
+def test_graph_without_edges():
+    r = np.zeros(100, np.int32)
+    c = np.zeros(0, np.int32)
+    png = P.build_png(dev(r), dev(np.zeros(1, np.int32))[:0], part_log2=5)
+    assert np.all(P.spmv(png, dev(np.ones(99, np.float32))).cpu().numpy() == 0.0)
+    png.close()
