@@ -9,7 +9,9 @@ A step is one solve from the uniform vector; the graph and its partition-node
 graph are resident in HBM before the timed region starts.  The same graph with
 in-degree-sorted labels is measured as well and reported under "indegree".
 
-Further legs (in "detail"): the learned warm start against the uniform start
+Further legs (in "detail"): the sparse matrix-vector product over the PNG
+with random edge weights on the main graph (Sec. 3.4), the learned warm
+start against the uniform start
 on the main graph (network weights shipped with the package, trained on other
 RMAT graphs), batched personalised PageRank on RMAT-22 with 8/32/64 seed sets
 against one vector at a time, and 16 RMAT graphs of uneven size in one handle
@@ -118,6 +120,63 @@ def measure(P, torch, r, c, args, label):
     for k, v in sorted(kernels.items()):
         log(f"    {k:16s} launches={v['launches']:5d} avg={v['avg_ms'] * 1e3:9.1f} us")
     return result, out.cpu().numpy(), png
+
+
+def spmv_detail(P, torch, r, c, args, reps=20):
+    """SpMV over the PNG (Sec. 3.4) on the main graph with seeded random edge
+    weights (uniform in [-1, 1)) and x uniform in [-1, 1): per-kernel event
+    times of `reps` calls, the weighted gather against the HBM roofline, and
+    y against the FP64 oracle within the bound of pcpm_spmv."""
+    import numpy as np
+    from paper_1709_07122_amd import commmodel as cm
+
+    n, m = len(r) - 1, len(c)
+    rng = np.random.default_rng(args.seed + 1000)
+    w = rng.uniform(-1.0, 1.0, m).astype(np.float32)
+    x = rng.uniform(-1.0, 1.0, n).astype(np.float32)
+    rt, ct, wt, xt = (torch.from_numpy(a).cuda() for a in (r, c, w, x))
+    png = P.build_png(rt, ct, part_log2=args.part_log2, weights=wt)
+    info = png.info
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        P.spmv(png, xt, out=y)
+    torch.cuda.synchronize()
+    P.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.spmv(png, xt, out=y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    P.timing_enable(False)
+    kt = P.timing_collect()
+    kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in kt.items()}
+    ep, nseg = info["eprime"], info["nseg"]
+    g_bytes = cm.spmv_gather_bytes(n, m, ep)
+    total = cm.spmv_bytes(n, m, ep, nseg)
+    g_ms = kernels.get("pcpm_spmv_gather", {"avg_ms": float("nan")})["avg_ms"]
+    res = {"graph": "the main graph, weights uniform in [-1, 1)", "ms_per_call": dt * 1e3, "gteps": m / dt / 1e9,
+           "alg_bytes_per_call": total, "hbm_gbs_alg": total / dt / 1e9, "kernels": kernels,
+           "gather_bytes": g_bytes, "gather_gbs": g_bytes / (g_ms * 1e-3) / 1e9,
+           "gather_frac_of_peak": g_bytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ref = oracle.spmv(r, c, x, w)
+        got = y.cpu().numpy().astype(np.float64)
+        indeg = np.bincount(c, minlength=n)
+        aw = np.abs(w.astype(np.float64))
+        xmax = float(np.abs(x).max())
+        wcol = float(np.bincount(c, weights=aw, minlength=n).max())
+        sbits = min(50 - int(np.ceil(np.log2(aw.max() * xmax))), 62 - int(np.ceil(np.log2(wcol * xmax))))
+        ratio = float((np.abs(got - ref) / (indeg * 2.0 ** -(sbits - 1) + 2.0 ** -23 * np.abs(ref) + 2.0 ** -150)).max())
+        res["parity"] = {"max_err_over_bound": ratio, "max_abs_err": float(np.abs(got - ref).max())}
+    png.close()
+    log(f"[spmv] {dt * 1e3:.3f} ms/call, {res['gteps']:.1f} GTEPS, weighted gather {res['gather_gbs']:.0f} GB/s "
+        f"({res['gather_frac_of_peak']:.3f} of peak)" + (f", error/bound {res['parity']['max_err_over_bound']:.3f}"
+                                                          if "parity" in res else ""))
+    for k, v in sorted(kernels.items()):
+        log(f"    {k:18s} launches={v['launches']:5d} avg={v['avg_ms'] * 1e3:9.1f} us")
+    return res
 
 
 def warm_detail(P, torch, png, args):
@@ -316,6 +375,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the personalised and multi-graph legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start leg")
+    ap.add_argument("--no-spmv", action="store_true", help="skip the weighted SpMV leg")
     ap.add_argument("--ppr-seed", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy (reference for HBM byte counters)")
@@ -372,6 +432,8 @@ def main():
         del ri, ci
     del raw_r, raw_c
 
+    if not args.no_spmv:
+        detail["spmv"] = spmv_detail(P, torch, r, c, args)
     if not args.no_batched:
         detail["ppr"] = ppr_detail(P, torch, args)
         detail["multigraph"] = multigraph_detail(P, torch, args)
@@ -418,7 +480,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "pcpm_gather", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (counter_traffic("pcpm::k_gather<1024>") if args.graph == "rmat" and args.part_log2 == 14
+            "traffic": (counter_traffic("pcpm::k_gather<1024, 0>") if args.graph == "rmat" and args.part_log2 == 14
                         and args.scale == 24 and args.edge_factor == 16 and args.seed == 2 else None),
             "bytes_per_launch": main_res["gather_bytes"], "avg_launch_ms": g["avg_ms"],
         },

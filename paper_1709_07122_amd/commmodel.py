@@ -78,3 +78,23 @@ def gather_bytes(n, m, eprime, did_bytes=DID_BYTES):
 
 def iteration_bytes(n, m, eprime, nseg):
     return scatter_bytes(n, eprime, nseg) + gather_bytes(n, m, eprime)
+
+
+# ---- SpMV over the PNG (Sec. 3.4) -------------------------------------------
+
+def spmv_scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES):
+    """Scatter of one SpMV: x (4n, no out-degrees), PNG source IDs, write
+    offsets, tile flag prefixes and the update writes."""
+    return 4 * n + src_bytes * eprime + 4 * nseg + 4 * (eprime // TILE + 1) + 4 * eprime
+
+
+def spmv_gather_bytes(n, m, eprime, weighted=True, did_bytes=DID_BYTES):
+    """Gather of one SpMV: destination IDs, their weights (4m when weighted,
+    stored beside the IDs, Sec. 3.4), tile flag prefixes, updates and y (4n);
+    no residual, no dangling mask."""
+    return did_bytes * m + (4 * m if weighted else 0) + 4 * (m // TILE + 1) + 4 * eprime + 4 * n
+
+
+def spmv_bytes(n, m, eprime, nseg, weighted=True):
+    """Whole SpMV: the scale pass reads x once (4n), then scatter and gather."""
+    return 4 * n + spmv_scatter_bytes(n, eprime, nseg) + spmv_gather_bytes(n, m, eprime, weighted)

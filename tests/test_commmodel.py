@@ -49,3 +49,13 @@ def test_implementation_bytes_cover_eq5():
     # tile prefixes; never less than that
     assert eq5 < ours < eq5 + 8.5 * n + 4 * (m + ep) / 1024 + 8
     assert cm.gather_bytes(n, m, ep, did_bytes=4) - cm.gather_bytes(n, m, ep) == 2 * m
+
+
+def test_spmv_bytes_add_up():
+    n, m, ep, nseg = 1000, 16000, 9000, 300
+    s = cm.spmv_scatter_bytes(n, ep, nseg)
+    g = cm.spmv_gather_bytes(n, m, ep)
+    assert s == 4 * n + 2 * ep + 4 * nseg + 4 * (ep // 1024 + 1) + 4 * ep
+    assert g == 2 * m + 4 * m + 4 * (m // 1024 + 1) + 4 * ep + 4 * n
+    assert cm.spmv_gather_bytes(n, m, ep, weighted=False) == g - 4 * m
+    assert cm.spmv_bytes(n, m, ep, nseg) == 4 * n + s + g
