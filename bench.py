@@ -161,7 +161,12 @@ def spmv_detail(P, torch, r, c, args, reps=20):
     if not args.no_cpu_baseline:
         import oracle
 
+        tc = time.perf_counter()
         ref = oracle.spmv(r, c, x, w)
+        cpu_s = time.perf_counter() - tc
+        res["cpu_baseline"] = {"value": m / cpu_s / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                               "sample": "one FP64 SpMV of the oracle (numpy, one thread) on the same graph",
+                               "sec_per_call": cpu_s}
         got = y.cpu().numpy().astype(np.float64)
         indeg = np.bincount(c, minlength=n)
         aw = np.abs(w.astype(np.float64))
@@ -172,7 +177,8 @@ def spmv_detail(P, torch, r, c, args, reps=20):
         res["parity"] = {"max_err_over_bound": ratio, "max_abs_err": float(np.abs(got - ref).max())}
     png.close()
     log(f"[spmv] {dt * 1e3:.3f} ms/call, {res['gteps']:.1f} GTEPS, weighted gather {res['gather_gbs']:.0f} GB/s "
-        f"({res['gather_frac_of_peak']:.3f} of peak)" + (f", error/bound {res['parity']['max_err_over_bound']:.3f}"
+        f"({res['gather_frac_of_peak']:.3f} of peak)" + (f", error/bound {res['parity']['max_err_over_bound']:.3f}, "
+                                                          f"oracle {res['cpu_baseline']['sec_per_call'] * 1e3:.0f} ms"
                                                           if "parity" in res else ""))
     for k, v in sorted(kernels.items()):
         log(f"    {k:18s} launches={v['launches']:5d} avg={v['avg_ms'] * 1e3:9.1f} us")
