@@ -77,6 +77,14 @@ typedef struct {
                             destination IDs in bin order (Sec. 3.4) and read
                             by pcpm_spmv only: PageRank always scales by
                             1/outdeg.  The caller keeps ownership.           */
+  int64_t update_order;  /* storage order of the updates: 1 = bin order (the
+                            bins of Sec. 3.1: the scatter writes one run per
+                            (pair, bin) segment, the gather reads its bin in
+                            sequence), 2 = PNG order (update e belongs to PNG
+                            edge e: sequential scatter writes, the gather
+                            reads one run per segment), 0 = automatic: PNG
+                            order when the average non-empty segment holds
+                            fewer than 300 updates.  Results are identical.  */
 } pcpm_build_opts_t;
 
 typedef struct {
@@ -92,6 +100,7 @@ typedef struct {
   int64_t num_graphs;    /* G (1 for a single graph)                          */
   double build_ms;       /* wall time of pcpm_build_png, device work included */
   int64_t weighted;      /* 1 if the build was given edge weights             */
+  int64_t update_order;  /* 1 = bin order, 2 = PNG order (see the build opts) */
 } pcpm_png_info_t;
 
 /*

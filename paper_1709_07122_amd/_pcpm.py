@@ -51,14 +51,15 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("part_log2", ctypes.c_int32), ("num_graphs", ctypes.c_int32),
                 ("graph_node_off", ctypes.c_void_p), ("graph_nodes", ctypes.c_void_p),
                 ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64),
-                ("build_chunk", ctypes.c_int64), ("weights", ctypes.c_void_p)]
+                ("build_chunk", ctypes.c_int64), ("weights", ctypes.c_void_p), ("update_order", ctypes.c_int64)]
 
 
 class PngInfo(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ("n", "m", "q", "k", "eprime", "nseg", "n_dangling", "scatter_items", "gather_items",
                  "split_bins", "device_bytes", "num_graphs")] + [("build_ms", ctypes.c_double),
-                                                                 ("weighted", ctypes.c_int64)]
+                                                                 ("weighted", ctypes.c_int64),
+                                                                 ("update_order", ctypes.c_int64)]
 
 
 class KernelTime(ctypes.Structure):
@@ -224,12 +225,14 @@ class PNG:
 
 
 def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_chunk: int = 0,
-              graph_node_off=None, graph_nodes=None, build_chunk: int = 0, weights=None, stream=None) -> PNG:
+              graph_node_off=None, graph_nodes=None, build_chunk: int = 0, weights=None, update_order: int = 0,
+              stream=None) -> PNG:
     """pcpm_build_png on device CSR tensors (int32 row_off[n+1], col[m]).
 
     For several graphs in one handle pass the padded union (see union_csr)
     with its graph_node_off (G+1) and graph_nodes (G).  weights: optional
-    device float32 tensor of m edge weights in CSR order (for spmv)."""
+    device float32 tensor of m edge weights in CSR order (for spmv).
+    update_order: 0 automatic, 1 bin order, 2 PNG order (see pcpm_build_opts_t)."""
     import torch
     n = row_off.numel() - 1
     m = col.numel()
@@ -240,7 +243,7 @@ def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_c
     gn = np.ascontiguousarray(graph_nodes if G else [0], dtype=np.int64)
     wp = None if weights is None else _dev_tensor(weights, torch.float32, m, "weights")
     opts = BuildOpts(int(part_log2), G, goff.ctypes.data if G else None, gn.ctypes.data if G else None,
-                     int(scatter_chunk), int(gather_chunk), int(build_chunk), wp)
+                     int(scatter_chunk), int(gather_chunk), int(build_chunk), wp, int(update_order))
     h = ctypes.c_void_p()
     _check(lib().pcpm_build_png(n, m, rp, cp, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return PNG(h, row_off, col)

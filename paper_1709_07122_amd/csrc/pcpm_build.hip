@@ -284,6 +284,50 @@ __device__ __forceinline__ int32_t pair_cnt(const int32_t* __restrict__ cnt, int
   return cnt[p0 * k + j] + (p1 < k ? cnt[p1 * k + j] : 0);
 }
 
+// Non-empty (bin, source pair) segments of each destination bin.  One
+// workgroup per bin.
+__global__ __launch_bounds__(256) void k_binseg(int32_t k, const int32_t* __restrict__ cnt,
+                                                int32_t* __restrict__ binseg) {
+  const int32_t j = blockIdx.x;
+  const int64_t npairs = (k + 1) / 2;
+  int64_t nz = 0;
+  for (int64_t pr = threadIdx.x; pr < npairs; pr += blockDim.x) nz += (pair_cnt(cnt, k, pr, j) > 0);
+  int64_t tot = 0;
+  (void)block_excl_scan(nz, &tot);
+  if (threadIdx.x == 0) binseg[j] = static_cast<int32_t>(tot);
+}
+
+// PNG order of the updates: seg_delta[s] for the s-th non-empty segment in
+// (bin p', pair) order: the
+// PNG position of the pair segment's first update minus the bin-order index
+// of its first message.  The updates of one segment are consecutive in both
+// orders (U(2P', p') then U(2P'+1, p'), nodes ascending), so a message's
+// update sits at its bin-order index plus its segment's delta.  One
+// workgroup per bin.
+__global__ __launch_bounds__(256) void k_segdelta_bins(int32_t k, const int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ wo, const int32_t* __restrict__ png_off,
+                                                  const int32_t* __restrict__ upd_start,
+                                                  const int32_t* __restrict__ png_base,
+                                                  const int32_t* __restrict__ segbase, int32_t* __restrict__ seg_delta) {
+  const int32_t j = blockIdx.x;
+  const int64_t npairs = (k + 1) / 2;
+  const int64_t per = (npairs + blockDim.x - 1) / blockDim.x;
+  const int64_t q0 = min(npairs, static_cast<int64_t>(threadIdx.x) * per), q1 = min(npairs, q0 + per);
+  int64_t nz = 0;
+  for (int64_t pr = q0; pr < q1; ++pr) nz += (pair_cnt(cnt, k, pr, j) > 0);
+  int64_t tot = 0;
+  int64_t idx = segbase[j] + block_excl_scan(nz, &tot);
+  for (int64_t pr = q0; pr < q1; ++pr) {
+    if (pair_cnt(cnt, k, pr, j) > 0) {
+      const int64_t p0 = 2 * pr, p1 = 2 * pr + 1;
+      const int64_t msg = static_cast<int64_t>(upd_start[j]) + wo[p0 * k + j];
+      const int64_t pos = static_cast<int64_t>(png_base[p0]) + png_off[p0 * (k + 1) + j] +
+                          (p1 < k ? png_off[p1 * (k + 1) + j] : 0);
+      seg_delta[idx++] = static_cast<int32_t>(pos - msg);
+    }
+  }
+}
+
 // Non-empty pair segments of each pair.  One workgroup per pair.
 __global__ __launch_bounds__(256) void k_pairseg(int32_t k, const int32_t* __restrict__ cnt,
                                                  int32_t* __restrict__ pairseg) {
@@ -295,10 +339,10 @@ __global__ __launch_bounds__(256) void k_pairseg(int32_t k, const int32_t* __res
   if (threadIdx.x == 0) pairseg[pr] = static_cast<int32_t>(tot);
 }
 
-// seg_delta[s] for the s-th non-empty pair segment in (pair, p') order: update
-// slot of its first entry minus its position in the pair-ordered PNG edges.
-// One workgroup per pair.
-__global__ __launch_bounds__(256) void k_segdelta(int32_t k, const int32_t* __restrict__ cnt,
+// Bin order of the updates: seg_delta[s] for the s-th non-empty pair segment
+// in (pair, p') order, the update slot of its first entry minus its position
+// in the pair-ordered PNG edges.  One workgroup per pair.
+__global__ __launch_bounds__(256) void k_segdelta_pairs(int32_t k, const int32_t* __restrict__ cnt,
                                                   const int32_t* __restrict__ wo, const int32_t* __restrict__ png_off,
                                                   const int32_t* __restrict__ upd_start,
                                                   const int32_t* __restrict__ png_base,
@@ -375,7 +419,7 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
     }
     __builtin_amdgcn_wave_barrier();
     if (valid) {
-      did[tile_pos(cd + rank)] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | (first ? kDidFlag : 0u));
+      uint32_t flags = first ? kDidFlag : 0u;
       if (wbin) wbin[cd + rank] = weights[e];  // the weight travels with its destination ID (Sec. 3.4)
       if (first) {
         // position in the pair-ordered PNG edges: after the pair's earlier
@@ -390,7 +434,10 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
         const bool seg_first = r == 0 && (!odd || even_cnt == 0);
         // source ID local to the pair's 2q nodes, flag on the pair segment's first node
         png_src[tile_pos(pos)] = static_cast<uint16_t>((static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u));
+        // in bin p', the same edge starts the (p', pair) segment of destination IDs
+        if (seg_first) flags |= kSegFlag;
       }
+      did[tile_pos(cd + rank)] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | flags);
       if ((peers & below) == 0) {
         cur_did[pp] = cd + __popcll(peers);
         cur_rank[pp] = cr + __popcll(fpeers);
@@ -441,18 +488,17 @@ __global__ __launch_bounds__(1024) void k_w_stats(int64_t n, int s, const int32_
   }
 }
 
-// Number of flagged entries (top bit set) in each kTile tile (one wavefront
-// per tile); T = uint32_t for PNG edges, uint16_t for destination IDs.
-template <typename T>
-__global__ __launch_bounds__(256) void k_tile_flags(const T* __restrict__ a, int64_t ntiles,
+// Number of entries with a flag bit (`flag`) set in each kTile tile of
+// destination IDs (one wavefront per tile; the count does not depend on the
+// storage order inside a tile).
+__global__ __launch_bounds__(256) void k_tile_flags(const uint16_t* __restrict__ a, int64_t ntiles, uint32_t flag,
                                                     int32_t* __restrict__ cnt) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-  constexpr int kTop = 8 * sizeof(T) - 1;
   for (int64_t t = wave; t < ntiles; t += nwaves) {
     int32_t c = 0;
-    for (int j = 0; j < kSub; ++j) c += __popcll(wave_ballot((a[t * kTile + j * kWave + lane] >> kTop) != 0));
+    for (int j = 0; j < kSub; ++j) c += __popcll(wave_ballot((a[t * kTile + j * kWave + lane] & flag) != 0));
     if (lane == 0) cnt[t] = c;
   }
 }
@@ -752,20 +798,32 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, coltot, g->upd_start, k);
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, coltot_raw, g->did_start, k);
   PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowtot, g->png_base, k);
-  const int64_t npairs = (k + 1) / 2;
-  PCPM_LAUNCH("pcpm_build_pairseg", k_pairseg, dim3(static_cast<unsigned>(npairs)), dim3(256), 0, st,
-              static_cast<int32_t>(k), cnt, rowseg);
-  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowseg, segbase, npairs);
+  PCPM_LAUNCH("pcpm_build_pairseg", k_binseg, dim3(kk), dim3(256), 0, st, static_cast<int32_t>(k), cnt, rowseg);
+  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowseg, segbase, k);
   int32_t tot[2] = {0, 0};
   PCPM_TRY_HIP(hipMemcpyAsync(&tot[0], g->upd_start + k, 4, hipMemcpyDeviceToHost, st));
-  PCPM_TRY_HIP(hipMemcpyAsync(&tot[1], segbase + npairs, 4, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(&tot[1], segbase + k, 4, hipMemcpyDeviceToHost, st));
   PCPM_TRY_HIP(hipStreamSynchronize(st));
   g->eprime = tot[0];
   g->nseg = tot[1];
 
+  // Update order: PNG order when (pair, bin) segments are short on average
+  // (the scatter's writes then break into many partial runs), else bin order.
+  const int64_t order = opts ? opts->update_order : 0;
+  if (order < 0 || order > 2) return set_error(PCPM_ERR_INVALID_ARG, "update_order must be 0, 1 or 2");
+  g->png_order = order == 2 || (order == 0 && g->eprime < kPngOrderRun * g->nseg);
   PCPM_TRY(dalloc(g, &g->seg_delta, g->nseg));
-  PCPM_LAUNCH("pcpm_build_segdelta", k_segdelta, dim3(static_cast<unsigned>(npairs)), dim3(256), 0, st,
-              static_cast<int32_t>(k), cnt, g->wo, g->png_off, g->upd_start, g->png_base, segbase, g->seg_delta);
+  if (g->png_order) {
+    PCPM_LAUNCH("pcpm_build_segdelta", k_segdelta_bins, dim3(kk), dim3(256), 0, st, static_cast<int32_t>(k), cnt,
+                g->wo, g->png_off, g->upd_start, g->png_base, segbase, g->seg_delta);
+  } else {
+    const int64_t npairs = (k + 1) / 2;
+    PCPM_LAUNCH("pcpm_build_pairseg", k_pairseg, dim3(static_cast<unsigned>(npairs)), dim3(256), 0, st,
+                static_cast<int32_t>(k), cnt, rowseg);
+    PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, rowseg, segbase, npairs);
+    PCPM_LAUNCH("pcpm_build_segdelta", k_segdelta_pairs, dim3(static_cast<unsigned>(npairs)), dim3(256), 0, st,
+                static_cast<int32_t>(k), cnt, g->wo, g->png_off, g->upd_start, g->png_base, segbase, g->seg_delta);
+  }
 
   // ---- fill --------------------------------------------------------------------
   const int64_t ntp = (g->eprime + kTile - 1) / kTile;
@@ -804,22 +862,23 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   std::memcpy(&g->w_absmax, &wst_h[1], 8);
 
   // ---- tile flag prefixes ----------------------------------------------------
+  // Messages (bit 15) before every tile of destination IDs; with PNG-ordered
+  // updates also (bin, pair) segments (bit 14), with bin-ordered updates the
+  // pair segments (bit 15) before every tile of PNG edges.
   int32_t* tcnt = nullptr;
-  PCPM_TRY(dalloc(g, &tcnt, std::max(ntp, ntd) + 1));
-  PCPM_TRY(dalloc(g, &g->png_blk, ntp + 1));
+  PCPM_TRY(dalloc(g, &tcnt, std::max(ntd, ntp) + 1));
   PCPM_TRY(dalloc(g, &g->did_blk, ntd + 1));
-  if (ntp > 0) {
-    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags<uint16_t>,
-                dim3(static_cast<unsigned>(std::min<int64_t>((ntp + 3) / 4, 16384))), dim3(256), 0, st, g->png_src, ntp,
-                tcnt);
+  if (g->png_order) PCPM_TRY(dalloc(g, &g->did_sblk, ntd + 1));
+  else PCPM_TRY(dalloc(g, &g->png_blk, ntp + 1));
+  for (int f = 0; f < 2; ++f) {
+    const uint16_t* a = (f == 0 || g->png_order) ? g->did : g->png_src;
+    const int64_t nt = (f == 0 || g->png_order) ? ntd : ntp;
+    int32_t* out = f == 0 ? g->did_blk : (g->png_order ? g->did_sblk : g->png_blk);
+    if (nt > 0)
+      PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags, dim3(static_cast<unsigned>(std::min<int64_t>((nt + 3) / 4, 16384))),
+                  dim3(256), 0, st, a, nt, (f == 1 && g->png_order) ? kSegFlag : kDidFlag, tcnt);
+    PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, out, nt);
   }
-  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, g->png_blk, ntp);
-  if (ntd > 0) {
-    PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags<uint16_t>,
-                dim3(static_cast<unsigned>(std::min<int64_t>((ntd + 3) / 4, 16384))), dim3(256), 0, st, g->did, ntd,
-                tcnt);
-  }
-  PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, g->did_blk, ntd);
 
   // ---- iteration buffers -----------------------------------------------------------
   PCPM_TRY(dalloc(g, &g->upd, g->eprime + 1));  // + spare slot for masked stores
@@ -893,6 +952,7 @@ pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out) {
   out->num_graphs = g->ngroups;
   out->build_ms = g->build_ms;
   out->weighted = g->wbin ? 1 : 0;
+  out->update_order = g->png_order ? 2 : 1;
   return PCPM_OK;
 }
 
@@ -968,7 +1028,7 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src, 
       const uint32_t base = static_cast<uint32_t>(p * g->q);
       for (int64_t e = ds[p]; e < ds[p + 1]; ++e) {
         const uint16_t x = loc[tile_pos(e)];
-        did[e] = (base + (x & (kDidFlag - 1u))) | ((x & kDidFlag) ? kFlag : 0u);
+        did[e] = (base + (x & (kSegFlag - 1u))) | ((x & kDidFlag) ? kFlag : 0u);
       }
     }
   }

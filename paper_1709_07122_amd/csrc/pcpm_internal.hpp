@@ -22,6 +22,10 @@ constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 // v - p'q or u - pq (< q <= 2^14), with bit 15 marking the first ID of each
 // message or the first node of each segment.
 constexpr uint32_t kDidFlag = 0x8000u;
+// Bit 14 of a destination ID marks the first ID of each (destination bin,
+// source pair) segment: the gather finds an update's position in the
+// PNG-ordered update array from its message index and its segment.
+constexpr uint32_t kSegFlag = 0x4000u;
 
 // Flag-decoding tile: 16 sub-blocks of one wavefront (64 lanes) each.  The
 // running flag count before every tile is stored, so any wavefront can decode
@@ -31,10 +35,14 @@ constexpr int kSub = 16;
 constexpr int kTile = kWave * kSub;
 
 constexpr int kMaxHist = 100000;   // residual history kept on the device
+// Updates go in PNG order when the average non-empty (pair, bin) segment is
+// shorter than this many updates (measured crossover on MI355X: RMAT with
+// random labels at 2^24 nodes, 333 per segment, runs as fast either way).
+constexpr int64_t kPngOrderRun = 300;
 constexpr int kMaxParts = 16384;   // k limit (LDS cursors of the fill kernel)
 constexpr int kMinLog2 = 1;
 constexpr int kMaxLog2 = 14;       // 16384 * 8 B = 128 KB fixed-point slice in LDS
-static_assert(kMaxLog2 <= 15, "partition-local destination IDs use 15 bits");
+static_assert(kMaxLog2 <= 14, "partition-local destination IDs use 14 bits (bits 14, 15 are flags)");
 #ifndef PCPM_SCATTER_BLOCK
 #define PCPM_SCATTER_BLOCK 1024
 #endif
@@ -202,24 +210,28 @@ struct pcpm_png {
   int32_t* outdeg = nullptr;    // n
   uint32_t* dmask = nullptr;    // ceil(n/32) dangling bitmask
 
-  // scatter side: PNG in (source partition, destination partition, node) order
+  // scatter side: PNG in (source pair, destination partition, source partition, node) order
   uint16_t* png_src = nullptr;  // ceil(E'/kTile)*kTile, in partition-pair order: u - 2Pq, bit 15 = pair segment start
-  int32_t* png_blk = nullptr;   // flags before each tile, ceil(E'/kTile)+1
-  int32_t* seg_delta = nullptr; // nseg: update slot minus PNG position per non-empty pair segment
+  int32_t* png_blk = nullptr;   // bin order: pair-segment flags before each PNG tile, ceil(E'/kTile)+1
+  int32_t* seg_delta = nullptr; // nseg, one per non-empty (pair, bin) segment.  Bin order: update slot minus PNG
+                                // position, segments in (pair, bin) order.  PNG order: PNG position minus
+                                // message index, segments in (bin, pair) order
+  bool png_order = false;       // updates stored in PNG order (else bin order)
   int32_t* png_base = nullptr;  // k+1: first PNG edge of each source partition
   int32_t* png_off = nullptr;   // k*(k+1): partition-local PNG offsets
   int32_t* wo = nullptr;        // k*k: write offsets (Sec. 3.1)
   int32_t* upd_start = nullptr; // k+1: first update slot of each bin
 
   // gather side: destination-ID bins
-  uint16_t* did = nullptr;      // ceil(m/kTile)*kTile: v - p'q, bit 15 = first of message
+  uint16_t* did = nullptr;      // ceil(m/kTile)*kTile: v - p'q, bit 15 = first of message, bit 14 = first of segment
+  int32_t* did_sblk = nullptr;  // segment flags before each tile, ceil(m/kTile)+1
   float* wbin = nullptr;        // m edge weights in bin order (weighted handles only)
   double w_absmax = 0.0;        // max |w| (1 if unweighted, 0 without edges)
   double w_colmax = 0.0;        // max over v of sum_{u->v} |w(u,v)|
   float* spmv_blockmax = nullptr;  // per-block max |x| of pcpm_spmv
   int32_t* did_blk = nullptr;   // flags before each tile, ceil(m/kTile)+1
   int32_t* did_start = nullptr; // k+1
-  float* upd = nullptr;         // E'+1: update bins (rewritten every iteration) + spare slot
+  float* upd = nullptr;         // E'+1: updates in bin or PNG order (rewritten every iteration) + spare slot
 
   // work lists
   pcpm::Item* sc_items = nullptr;

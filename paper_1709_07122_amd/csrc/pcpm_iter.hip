@@ -4,14 +4,26 @@
 //
 // Per iteration, on the caller's stream:
 //   k_scatter   one workgroup per scatter item (a range of one source
-//               partition's PNG edges): the partition's scaled ranks
-//               PR(u)/outdeg(u) are staged in LDS, PNG edges are streamed
-//               and each writes its update to its bin slot.  Each XCD runs
-//               one contiguous range of the item array.
+//               partition pair's PNG edges): the pair's scaled ranks
+//               PR(u)/outdeg(u) are staged in LDS and PNG edges are streamed.
+//               Each XCD runs one contiguous range of the item array.
 //   k_gather    one workgroup per gather item (a range of one destination
-//               bin): destination IDs and updates are streamed, the update of
-//               an ID is found from the running count of message flags, and
-//               sums build up in an LDS slice of the destination partition.
+//               bin): destination IDs are streamed, the update of an ID is
+//               found from the running count of message flags, and sums
+//               build up in an LDS slice of the destination partition.
+//
+// Updates are stored in one of two orders, chosen per handle at build time:
+//   bin order   (Sec. 3.1) the updates of bin p' are contiguous, in message
+//               order; the scatter writes one run per (pair, bin) segment at
+//               the segment's write offset, and the gather reads its bin's
+//               updates in sequence.
+//   PNG order   update e belongs to PNG edge e: the scatter's stores are one
+//               contiguous stream, and the gather reads one run per (bin,
+//               pair) segment, locating an ID's update as its message index
+//               plus its segment's delta (segment flags on the IDs).
+// Short segments make the scatter's runs of writes costly on HBM (partial
+// lines, scattered rows), while runs of reads cost less; the build takes PNG
+// order when the average segment is short.
 //               A whole bin is applied in place; a split bin stores its
 //               partial slice for k_merge.
 //   k_merge     applies split bins, adding their partial slices in order;
@@ -101,7 +113,8 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
 }
 
 // kScale: stage PR(u)/outdeg(u) (PageRank); otherwise x(u) itself (SpMV).
-template <int BS, bool kScale = true>
+// kPng: updates in PNG order, else in bin order.
+template <int BS, bool kScale, bool kPng>
 __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                 const Item* __restrict__ items, const float* __restrict__ pr,
                                                 const int32_t* __restrict__ outdeg,
@@ -139,33 +152,49 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
     if (t + kNW < t_end) load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
     uint32_t x[kSub];
     unpack_tile(w, x);
-    // Every entry of a tile has a valid segment index (entry 0 of the array
-    // is flagged and padding follows the last segment), so the loads below
-    // need no predicate.  A source ID masked with q-1 is its slot in the rank
-    // slice (entries of other partitions, in edge tiles, only read a stale
-    // slot and store to the spare update slot E').
-    int32_t run = png_blk[t];
-    int32_t seg[kSub];
+    if constexpr (kPng) {
+      // PNG edge e writes upd[e]: a tile's stores are one contiguous run.  A
+      // source ID masked with 2q-1 is its slot in the pair's rank slice.
+      if (tb >= lo && tb + kTile <= hi) {
+        float* ut = upd + tb;
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const bool f = (x[j] & kDidFlag) != 0u;
-      const uint64_t bal = wave_ballot(f);
-      seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
-      run += __popcll(bal);
-    }
-    int32_t dl[kSub];
+        for (int j = 0; j < kSub; ++j) ut[j * kWave + lane] = spr[x[j] & qmask];
+      } else {
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
-    if (tb >= lo && tb + kTile <= hi) {
-      float* ut = upd + tb;
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) ut[static_cast<int64_t>(j * kWave + lane + dl[j])] = spr[x[j] & qmask];
+        for (int j = 0; j < kSub; ++j) {
+          const int64_t e = tb + j * kWave + lane;
+          if (e >= lo && e < hi) upd[e] = spr[x[j] & qmask];
+        }
+      }
     } else {
-#pragma unroll
+      // Every entry of a tile has a valid segment index (entry 0 of the array
+      // is flagged and padding follows the last segment), so the loads below
+      // need no predicate.  A source ID masked with q-1 is its slot in the rank
+      // slice (entries of other partitions, in edge tiles, only read a stale
+      // slot and store to the spare update slot E').
+      int32_t run = png_blk[t];
+      int32_t seg[kSub];
+  #pragma unroll
       for (int j = 0; j < kSub; ++j) {
-        const int64_t e = tb + j * kWave + lane;
-        const bool in = e >= lo && e < hi;
-        upd[in ? e + dl[j] : spare] = spr[x[j] & qmask];
+        const bool f = (x[j] & kDidFlag) != 0u;
+        const uint64_t bal = wave_ballot(f);
+        seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
+        run += __popcll(bal);
+      }
+      int32_t dl[kSub];
+  #pragma unroll
+      for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
+      if (tb >= lo && tb + kTile <= hi) {
+        float* ut = upd + tb;
+  #pragma unroll
+        for (int j = 0; j < kSub; ++j) ut[static_cast<int64_t>(j * kWave + lane + dl[j])] = spr[x[j] & qmask];
+      } else {
+  #pragma unroll
+        for (int j = 0; j < kSub; ++j) {
+          const int64_t e = tb + j * kWave + lane;
+          const bool in = e >= lo && e < hi;
+          upd[in ? e + dl[j] : spare] = spr[x[j] & qmask];
+        }
       }
     }
 #pragma unroll
@@ -176,10 +205,14 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
 // kMode 0: PageRank (apply, residual, dangling mass); 1: SpMV, y(v) = sum of
 // the updates; 2: SpMV with the edge weight stored beside each destination ID
 // applied to its update (Sec. 3.4).  In SpMV modes pr_out receives y.
-template <int BS, int kMode = 0>
+// kPng: updates in PNG order (an ID's update is at its message index plus
+// its segment's delta), else in bin order (at its message index).
+template <int BS, int kMode, bool kPng>
 __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                const Item* __restrict__ items, const uint16_t* __restrict__ did,
-                                               const int32_t* __restrict__ did_blk, const float* __restrict__ upd,
+                                               const int32_t* __restrict__ did_blk,
+                                               const int32_t* __restrict__ did_sblk,
+                                               const int32_t* __restrict__ seg_delta, const float* __restrict__ upd,
                                                const float* __restrict__ pr_in, float* __restrict__ pr_out,
                                                const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
                                                double* __restrict__ red, const GCtl* __restrict__ gctl,
@@ -209,25 +242,45 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
     if (t + kNW < t_end) load_tile_words(did + (t + kNW) * kTile, lane, wn);
     uint32_t x[kSub];
     unpack_tile(w, x);
-    // Update indices of a tile lie in [did_blk[t]-1, did_blk[t+1]-1]: the
-    // loads below take a per-tile base and a 32-bit lane offset.  Every entry
-    // has a valid index (entry 0 of the array is flagged and padding follows
-    // the last message), so update loads need no predicate.
-    const int32_t ubase = did_blk[t];
-    const char* ub = reinterpret_cast<const char*>(upd) + (static_cast<int64_t>(ubase) - 1) * 4;
-    int32_t run = 0;  // flags in the earlier sub-blocks of this tile
-    uint32_t off[kSub];
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const bool f = (x[j] & kDidFlag) != 0u;
-      const uint64_t bal = wave_ballot(f);
-      // Alg. 5 update pointer (flags so far, inclusive, minus one) relative to ub
-      off[j] = static_cast<uint32_t>(run + lanes_below(bal) + (f ? 1 : 0)) * 4u;
-      run += __popcll(bal);
-    }
+    // Alg. 5 update pointer: an ID's message index in bin order is the number
+    // of message flags so far (inclusive) minus one.  Every entry has a valid
+    // index (entry 0 of the array carries every flag and padding follows the
+    // last message), so the update loads need no predicate.
     float val[kSub];
+    if constexpr (kPng) {
+      // plus its (bin, source pair) segment's delta, the segment index
+      // counting segment flags the same way
+      int32_t run = did_blk[t] - 1, srun = did_sblk[t] - 1;  // counts before this tile, minus one
+      int32_t msg[kSub], seg[kSub];
 #pragma unroll
-    for (int j = 0; j < kSub; ++j) val[j] = *reinterpret_cast<const float*>(ub + off[j]);
+      for (int j = 0; j < kSub; ++j) {
+        const bool f = (x[j] & kDidFlag) != 0u, sf = (x[j] & kSegFlag) != 0u;
+        const uint64_t bal = wave_ballot(f), sbal = wave_ballot(sf);
+        msg[j] = run + lanes_below(bal) + (f ? 1 : 0);
+        seg[j] = srun + lanes_below(sbal) + (sf ? 1 : 0);
+        run += __popcll(bal);
+        srun += __popcll(sbal);
+      }
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) msg[j] += seg_delta[seg[j]];
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) val[j] = upd[msg[j]];
+    } else {
+      // a tile's updates lie in [did_blk[t]-1, did_blk[t+1]-1]: a per-tile
+      // base and 32-bit lane offsets
+      const char* ub = reinterpret_cast<const char*>(upd) + (static_cast<int64_t>(did_blk[t]) - 1) * 4;
+      int32_t run = 0;  // flags in the earlier sub-blocks of this tile
+      uint32_t off[kSub];
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) {
+        const bool f = (x[j] & kDidFlag) != 0u;
+        const uint64_t bal = wave_ballot(f);
+        off[j] = static_cast<uint32_t>(run + lanes_below(bal) + (f ? 1 : 0)) * 4u;
+        run += __popcll(bal);
+      }
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) val[j] = *reinterpret_cast<const float*>(ub + off[j]);
+    }
     // weights are stored in bin order, padded to whole tiles
     float wv[kMode == 2 ? kSub : 1];
     if constexpr (kMode == 2) {
@@ -534,19 +587,25 @@ __global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, 
   }
 }
 
+template <bool kPng>
+static pcpm_status_t iter_lds_limits_for() {
+  const void* scat[] = {reinterpret_cast<const void*>(k_scatter<kScatterBlock, true, kPng>),
+                        reinterpret_cast<const void*>(k_scatter<kScatterBlock, false, kPng>)};
+  const void* gath[] = {reinterpret_cast<const void*>(k_gather<kGatherBlock, 0, kPng>),
+                        reinterpret_cast<const void*>(k_gather<kGatherBlock, 1, kPng>),
+                        reinterpret_cast<const void*>(k_gather<kGatherBlock, 2, kPng>)};
+  for (const void* f : scat)
+    PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (2 << kMaxLog2) * 4));
+  for (const void* f : gath)
+    PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
+  return PCPM_OK;
+}
+
 pcpm_status_t iter_lds_limits() {
   static bool done = false;
   if (done) return PCPM_OK;
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter<kScatterBlock>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (2 << kMaxLog2) * 4));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter<kScatterBlock, false>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (2 << kMaxLog2) * 4));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock, 1>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_gather<kGatherBlock, 2>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
+  PCPM_TRY(iter_lds_limits_for<false>());
+  PCPM_TRY(iter_lds_limits_for<true>());
   done = true;
   return PCPM_OK;
 }
@@ -565,14 +624,31 @@ static pcpm_status_t reset_ctl(pcpm_png* g, double tol, double d, hipStream_t st
   return PCPM_OK;
 }
 
-static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hipStream_t st) {
+// Scatter and gather of one pass in the handle's update order; kScale and
+// kMode as in k_scatter / k_gather.
+template <bool kScale, int kMode, bool kPng>
+static pcpm_status_t scatter_gather(pcpm_png* g, const float* in, float* out, const char* sname, const char* gname,
+                                    hipStream_t st) {
   if (g->n_sc)
-    PCPM_LAUNCH("pcpm_scatter", k_scatter<kScatterBlock>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kScatterBlock),
-                static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->sc_items, in, g->outdeg,
-                g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
-  PCPM_LAUNCH("pcpm_gather", k_gather<kGatherBlock>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kGatherBlock),
+    PCPM_LAUNCH(sname, (k_scatter<kScatterBlock, kScale, kPng>), dim3(static_cast<unsigned>(g->n_sc)),
+                dim3(kScatterBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->sc_items, in,
+                g->outdeg, g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
+  PCPM_LAUNCH(gname, (k_gather<kGatherBlock, kMode, kPng>), dim3(static_cast<unsigned>(g->n_ga)), dim3(kGatherBlock),
               static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items, g->did, g->did_blk,
-              g->upd, in, out, g->dmask, g->partial, g->red, g->gctl, g->part_group, g->part_valid, nullptr);
+              g->did_sblk, g->seg_delta, g->upd, in, out, g->dmask, g->partial, g->red, g->gctl, g->part_group,
+              g->part_valid, g->wbin);
+  return PCPM_OK;
+}
+
+template <bool kScale, int kMode>
+static pcpm_status_t scatter_gather(pcpm_png* g, const float* in, float* out, const char* sname, const char* gname,
+                                    hipStream_t st) {
+  return g->png_order ? scatter_gather<kScale, kMode, true>(g, in, out, sname, gname, st)
+                      : scatter_gather<kScale, kMode, false>(g, in, out, sname, gname, st);
+}
+
+static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hipStream_t st) {
+  PCPM_TRY((scatter_gather<true, 0>(g, in, out, "pcpm_scatter", "pcpm_gather", st)));
   if (g->n_mg)
     PCPM_LAUNCH("pcpm_merge", k_merge<kMergeNodes>, dim3(static_cast<unsigned>(g->n_mg)), dim3(kMergeNodes), 0,
                 st, g->ctl, g->n, g->part_log2, g->mg_items, g->partial, in, out, g->dmask, g->red, g->k, g->gctl,
@@ -627,20 +703,10 @@ pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x, float* y, void* stream) {
   PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_absmax, dim3(nb), dim3(256), 0, st, x, g->n, g->spmv_blockmax);
   PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_scale, dim3(1), dim3(1024), 0, st, g->ctl, g->spmv_blockmax, nb, g->w_absmax,
               g->w_colmax);
-  if (g->n_sc)
-    PCPM_LAUNCH("pcpm_spmv_scatter", (k_scatter<kScatterBlock, false>), dim3(static_cast<unsigned>(g->n_sc)),
-                dim3(kScatterBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->sc_items, x,
-                g->outdeg, g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
   if (g->wbin)
-    PCPM_LAUNCH("pcpm_spmv_gather", (k_gather<kGatherBlock, 2>), dim3(static_cast<unsigned>(g->n_ga)),
-                dim3(kGatherBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items,
-                g->did, g->did_blk, g->upd, x, y, g->dmask, g->partial, g->red, g->gctl, g->part_group,
-                g->part_valid, g->wbin);
+    PCPM_TRY((scatter_gather<false, 2>(g, x, y, "pcpm_spmv_scatter", "pcpm_spmv_gather", st)));
   else
-    PCPM_LAUNCH("pcpm_spmv_gather", (k_gather<kGatherBlock, 1>), dim3(static_cast<unsigned>(g->n_ga)),
-                dim3(kGatherBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items,
-                g->did, g->did_blk, g->upd, x, y, g->dmask, g->partial, g->red, g->gctl, g->part_group,
-                g->part_valid, nullptr);
+    PCPM_TRY((scatter_gather<false, 1>(g, x, y, "pcpm_spmv_scatter", "pcpm_spmv_gather", st)));
   if (g->n_mg)
     PCPM_LAUNCH("pcpm_spmv_merge", k_spmv_merge, dim3(static_cast<unsigned>(g->n_mg)), dim3(kMergeNodes), 0, st,
                 g->ctl, g->n, g->part_log2, g->mg_items, g->partial, y);

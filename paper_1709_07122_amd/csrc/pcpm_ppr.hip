@@ -37,13 +37,13 @@ __device__ __forceinline__ void copy_kt(float* __restrict__ dst, const float* __
   }
 }
 
-// Scatter (Alg. 3) for a tile of KT vectors: the source partition's scaled
-// values x(u, j)/outdeg(u) are staged in LDS ([q][KT]); every PNG edge copies
-// its node's KT values to its update slot.  Tiles of 1024 PNG edges are
-// decoded with a ballot per 64 entries; the next tile's source IDs are loaded
-// while this one is written.  Entries of edge tiles outside [lo, hi) write
-// to the spare slot E'.
-template <int KT>
+// Scatter (Alg. 3) for a tile of KT vectors: the source pair's scaled values
+// x(u, j)/outdeg(u) are staged in LDS ([2q][KT]); every PNG edge copies its
+// node's KT values to its update slot: slot e in PNG order (kPng; a tile of
+// 1024 PNG edges writes one contiguous run), else the slot its pair segment's
+// delta gives, with a ballot per 64 entries decoding the segments.  The next
+// tile's source IDs are loaded while this one is written.
+template <int KT, bool kPng>
 __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                            const Item* __restrict__ items, const float* __restrict__ x,
                                                            const int32_t* __restrict__ outdeg,
@@ -74,31 +74,46 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
     if (t + kNW < t_end) load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
     uint32_t xs[kSub];
     unpack_tile(w, xs);
-    // every entry of a tile has a valid segment (entry 0 is flagged and
-    // padding follows the last segment): no predicate on these loads
-    int32_t run = png_blk[t];
-    int32_t seg[kSub];
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const bool f = (xs[j] & kDidFlag) != 0u;
-      const uint64_t bal = wave_ballot(f);
-      seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
-      run += __popcll(bal);
-    }
-    int32_t dl[kSub];
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
-    if (tb >= lo && tb + kTile <= hi) {
-      float* ut = upd + tb * KT;
-#pragma unroll
-      for (int j = 0; j < kSub; ++j)
-        copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane + dl[j]) * KT, spr + (xs[j] & qmask) * KT);
+    if constexpr (kPng) {
+      if (tb >= lo && tb + kTile <= hi) {
+        float* ut = upd + tb * KT;
+  #pragma unroll
+        for (int j = 0; j < kSub; ++j)
+          copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane) * KT, spr + (xs[j] & qmask) * KT);
+      } else {
+  #pragma unroll
+        for (int j = 0; j < kSub; ++j) {
+          const int64_t e = tb + j * kWave + lane;
+          if (e >= lo && e < hi) copy_kt<KT>(upd + e * KT, spr + (xs[j] & qmask) * KT);
+        }
+      }
     } else {
-#pragma unroll
+      // every entry of a tile has a valid segment (entry 0 is flagged and
+      // padding follows the last segment): no predicate on these loads
+      int32_t run = png_blk[t];
+      int32_t seg[kSub];
+  #pragma unroll
       for (int j = 0; j < kSub; ++j) {
-        const int64_t e = tb + j * kWave + lane;
-        const bool in = e >= lo && e < hi;
-        copy_kt<KT>(upd + (in ? e + dl[j] : spare) * KT, spr + (xs[j] & qmask) * KT);
+        const bool f = (xs[j] & kDidFlag) != 0u;
+        const uint64_t bal = wave_ballot(f);
+        seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
+        run += __popcll(bal);
+      }
+      int32_t dl[kSub];
+  #pragma unroll
+      for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
+      if (tb >= lo && tb + kTile <= hi) {
+        float* ut = upd + tb * KT;
+  #pragma unroll
+        for (int j = 0; j < kSub; ++j)
+          copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane + dl[j]) * KT, spr + (xs[j] & qmask) * KT);
+      } else {
+  #pragma unroll
+        for (int j = 0; j < kSub; ++j) {
+          const int64_t e = tb + j * kWave + lane;
+          const bool in = e >= lo && e < hi;
+          copy_kt<KT>(upd + (in ? e + dl[j] : spare) * KT, spr + (xs[j] & qmask) * KT);
+        }
       }
     }
 #pragma unroll
@@ -185,11 +200,13 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
 // the banks as in the single-vector gather; node-major rows of KT sums put
 // them on 32/KT bank pairs).  The next tile's IDs are loaded while this one is
 // accumulated; the update values of kG sub-blocks are in flight together.
-template <int KT>
+template <int KT, bool kPng>
 __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                                 const Item* __restrict__ items,
                                                                 const uint16_t* __restrict__ did,
                                                                 const int32_t* __restrict__ did_blk,
+                                                                const int32_t* __restrict__ did_sblk,
+                                                                const int32_t* __restrict__ seg_delta,
                                                                 const float* __restrict__ upd,
                                                                 const float* __restrict__ x_in,
                                                                 float* __restrict__ x_out,
@@ -223,24 +240,34 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
     if (t + kNW < t_end) load_tile_words(did + (t + kNW) * kTile, lane, wn);
     uint32_t xs[kSub];
     unpack_tile(w, xs);
-    // update slots of a tile lie in [did_blk[t]-1, did_blk[t+1]-1]: a per-tile
-    // base and 32-bit offsets; every entry has a valid slot (no predicate)
-    const float* ub = upd + (static_cast<int64_t>(did_blk[t]) - 1) * KT;
-    int32_t run = 0;
-    uint32_t off[kSub];
+    // an ID's update slot: its message index in bin order (message flags so
+    // far, inclusive, minus one), plus, for PNG-ordered updates, its (bin,
+    // source pair) segment's delta; every entry has a valid slot
+    int32_t run = did_blk[t] - 1, srun = kPng ? did_sblk[t] - 1 : 0;
+    int32_t slot[kSub], seg[kSub];
 #pragma unroll
     for (int j = 0; j < kSub; ++j) {
       const bool f = (xs[j] & kDidFlag) != 0u;
       const uint64_t bal = wave_ballot(f);
-      off[j] = static_cast<uint32_t>(run + lanes_below(bal) + (f ? 1 : 0)) * KT;
+      slot[j] = run + lanes_below(bal) + (f ? 1 : 0);
       run += __popcll(bal);
+      if constexpr (kPng) {
+        const bool sf = (xs[j] & kSegFlag) != 0u;
+        const uint64_t sbal = wave_ballot(sf);
+        seg[j] = srun + lanes_below(sbal) + (sf ? 1 : 0);
+        srun += __popcll(sbal);
+      }
+    }
+    if constexpr (kPng) {
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) slot[j] += seg_delta[seg[j]];
     }
     const bool full = tb >= lo && tb + kTile <= hi;
 #pragma unroll
     for (int g0 = 0; g0 < kSub; g0 += kG) {
       float val[kG][KT];
 #pragma unroll
-      for (int jj = 0; jj < kG; ++jj) copy_kt<KT>(val[jj], ub + off[g0 + jj]);
+      for (int jj = 0; jj < kG; ++jj) copy_kt<KT>(val[jj], upd + static_cast<int64_t>(slot[g0 + jj]) * KT);
       if (full) {
 #pragma unroll
         for (int jj = 0; jj < kG; ++jj) {
@@ -533,10 +560,27 @@ __global__ void k_ppr_ctl(Ctl* ctl, double tol, double d) {
 
 template <int KT>
 static pcpm_status_t ppr_set_lds(int s) {
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ppr_scatter<KT>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (2 << s) * KT * 4));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ppr_gather<KT>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << s) * KT * 8));
+  for (const void* f : {reinterpret_cast<const void*>(k_ppr_scatter<KT, false>),
+                        reinterpret_cast<const void*>(k_ppr_scatter<KT, true>)})
+    PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (2 << s) * KT * 4));
+  for (const void* f : {reinterpret_cast<const void*>(k_ppr_gather<KT, false>),
+                        reinterpret_cast<const void*>(k_ppr_gather<KT, true>)})
+    PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (1 << s) * KT * 8));
+  return PCPM_OK;
+}
+
+// Scatter and gather of one iteration in the handle's update order.
+template <int KT, bool kPng>
+static pcpm_status_t ppr_scatter_gather(pcpm_png* g, const float* in, float* out, hipStream_t st) {
+  const int s = g->part_log2;
+  if (g->n_sc)
+    PCPM_LAUNCH("pcpm_ppr_scatter", (k_ppr_scatter<KT, kPng>), dim3(static_cast<unsigned>(g->n_sc)),
+                dim3(kPprScatterBlock), static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->sc_items, in,
+                g->outdeg, g->png_src, g->png_blk, g->seg_delta, g->ppr_upd, g->eprime);
+  PCPM_LAUNCH("pcpm_ppr_gather", (k_ppr_gather<KT, kPng>), dim3(static_cast<unsigned>(g->n_ga)),
+              dim3(kPprGatherBlock), static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->ga_items, g->did,
+              g->did_blk, g->did_sblk, g->seg_delta, g->ppr_upd, in, out, g->dmask, g->ppr_mask, g->ppr_partial,
+              g->ppr_red, g->ppr_vctl);
   return PCPM_OK;
 }
 
@@ -544,13 +588,7 @@ template <int KT>
 static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, float* pr_out, int k, double d,
                                    hipStream_t st) {
   const int s = g->part_log2;
-  if (g->n_sc)
-    PCPM_LAUNCH("pcpm_ppr_scatter", k_ppr_scatter<KT>, dim3(static_cast<unsigned>(g->n_sc)), dim3(kPprScatterBlock),
-                static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->sc_items, in, g->outdeg, g->png_src,
-                g->png_blk, g->seg_delta, g->ppr_upd, g->eprime);
-  PCPM_LAUNCH("pcpm_ppr_gather", k_ppr_gather<KT>, dim3(static_cast<unsigned>(g->n_ga)), dim3(kPprGatherBlock),
-              static_cast<size_t>(g->q) * KT * 8, st, g->ctl, g->n, s, g->ga_items, g->did, g->did_blk, g->ppr_upd,
-              in, out, g->dmask, g->ppr_mask, g->ppr_partial, g->ppr_red, g->ppr_vctl);
+  PCPM_TRY(g->png_order ? (ppr_scatter_gather<KT, true>(g, in, out, st)) : (ppr_scatter_gather<KT, false>(g, in, out, st)));
   if (g->n_mg)
     PCPM_LAUNCH("pcpm_ppr_merge", k_ppr_merge<KT>, dim3(static_cast<unsigned>(g->n_mg)), dim3(kPprBlock), 0, st,
                 g->ctl, g->n, s, g->mg_items, g->ppr_partial, in, out, g->dmask, g->ppr_mask, g->ppr_red, g->k,

@@ -1,0 +1,90 @@
+"""The two storage orders of the updates (bin order, PNG order) are two
+layouts of the same values: every result is bit-identical between them, and
+the automatic choice follows the average segment length."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1709_07122_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+CASES = {
+    "rmat_random": lambda: (graphgen.rmat(12, 16, seed=31, relabel="random"), dict(part_log2=8)),
+    "rmat_indegree": lambda: (graphgen.rmat(13, 16, seed=32, relabel="indegree"), dict(part_log2=10)),
+    "uniform_ragged": lambda: (graphgen.uniform(9001, 120000, seed=33), dict(part_log2=9)),
+    "split_bins": lambda: (graphgen.rmat(14, 16, seed=6), dict(part_log2=10, gather_chunk=8192, scatter_chunk=4096)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_orders_give_identical_results(case):
+    (r, c), kw = CASES[case]()
+    n = len(r) - 1
+    rng = np.random.default_rng(7)
+    w = rng.standard_normal(len(c)).astype(np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    off, seeds = graphgen.seed_sets(n, 21, seed=5)
+    out = {}
+    for order in (1, 2):
+        png = P.build_png(dev(r), dev(c), weights=dev(w), update_order=order, **kw)
+        assert png.info["update_order"] == order
+        res = P.pagerank(png, tol=0.0, max_iters=12)
+        it, _ = P.iterate(png, res.pr)
+        ppr = P.ppr_batch(png, off, seeds, tol=1e-6, max_iters=100)
+        ppr1 = P.ppr_batch(png, off[:3], seeds[:off[2]], tol=0.0, max_iters=9)
+        y = P.spmv(png, dev(x))
+        out[order] = dict(pr=bits(res.pr), it=bits(it), ppr=bits(ppr.pr), ppr_iters=ppr.iters.copy(),
+                          ppr1=bits(ppr1.pr), y=bits(y), layout=png.export(), wb=png.export_weights())
+        png.close()
+    a, b = out[1], out[2]
+    for key in ("pr", "it", "ppr", "ppr1", "y", "wb"):
+        np.testing.assert_array_equal(a[key], b[key], err_msg=key)
+    np.testing.assert_array_equal(a["ppr_iters"], b["ppr_iters"])
+    for key in a["layout"]:
+        np.testing.assert_array_equal(a["layout"][key], b["layout"][key], err_msg=key)
+    # and the common result is the oracle's
+    ref = oracle.pagerank(r, c, iters=12).x
+    assert np.abs(a["pr"].view(np.float32).astype(np.float64) - ref).sum() < 1e-5
+
+
+def test_multi_graph_handle_in_both_orders():
+    graphs = [graphgen.rmat(s, 8, seed=40 + s, relabel="random") for s in (9, 11, 8)]
+    r, c, goff, sizes = P.union_csr(graphs, 9)
+    res = {}
+    for order in (1, 2):
+        png = P.build_png(dev(r), dev(c), part_log2=9, graph_node_off=goff, graph_nodes=sizes, update_order=order)
+        res[order] = bits(P.pagerank(png, tol=1e-7, max_iters=100).pr)
+        png.close()
+    np.testing.assert_array_equal(res[1], res[2])
+
+
+@pytest.mark.parametrize("scale,relabel,part_log2", [(12, "random", 6), (12, "indegree", 12), (13, None, 9)])
+def test_automatic_order_follows_segment_length(scale, relabel, part_log2):
+    r, c = graphgen.rmat(scale, 16, seed=scale, relabel=relabel)
+    png = P.build_png(dev(r), dev(c), part_log2=part_log2)
+    info = png.info
+    want = 2 if info["eprime"] < 300 * info["nseg"] else 1
+    assert info["update_order"] == want
+    png.close()
+    with pytest.raises(P.PCPMError) as ei:
+        P.build_png(dev(r), dev(c), part_log2=part_log2, update_order=3)
+    assert ei.value.status == P.PCPM_ERR_INVALID_ARG
