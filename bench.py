@@ -78,7 +78,8 @@ def measure(P, torch, r, c, args, label):
     for _ in range(args.warmup):
         P.pagerank(png, d=args.d, tol=solve_tol(args), max_iters=solve_iters(args), out=out, want_hist=False)
     log(f"[{label}] n={n} m={m} q={info['q']} k={info['k']} E'={info['eprime']} "
-        f"r={m / max(info['eprime'], 1):.3f} build={build_s * 1e3:.1f} ms")
+        f"r={m / max(info['eprime'], 1):.3f} updates in {'PNG' if info['update_order'] == 2 else 'bin'} order "
+        f"build={build_s * 1e3:.1f} ms")
 
     P.timing_enable(True)
     torch.cuda.synchronize()
@@ -99,8 +100,9 @@ def measure(P, torch, r, c, args, label):
     sec_per_iter = total_s / tot_iters
     eprime, nseg = info["eprime"], info["nseg"]
     kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in kt.items()}
-    g_bytes = cm.gather_bytes(n, m, eprime)
-    s_bytes = cm.scatter_bytes(n, eprime, nseg)
+    png_order = info["update_order"] == 2
+    g_bytes = cm.gather_bytes(n, m, eprime, nseg=nseg, png_order=png_order)
+    s_bytes = cm.scatter_bytes(n, eprime, nseg, png_order=png_order)
     it_bytes = g_bytes + s_bytes
     eq5 = cm.pcpm_comm(n, m, info["k"], m / max(eprime, 1))
     result = {
@@ -112,6 +114,7 @@ def measure(P, torch, r, c, args, label):
         "alg_bytes_per_iter": it_bytes, "alg_bytes_per_edge": it_bytes / m, "eq5_bytes_per_edge": eq5 / m,
         "hbm_gbs_alg": it_bytes / sec_per_iter / 1e9, "build_ms": build_s * 1e3,
         "kernels": kernels, "gather_bytes": g_bytes, "scatter_bytes": s_bytes,
+        "update_order": "png" if png_order else "bin",
         "split_bins": info["split_bins"], "gather_items": info["gather_items"],
         "scatter_items": info["scatter_items"],
     }
@@ -151,8 +154,9 @@ def spmv_detail(P, torch, r, c, args, reps=20):
     kt = P.timing_collect()
     kernels = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in kt.items()}
     ep, nseg = info["eprime"], info["nseg"]
-    g_bytes = cm.spmv_gather_bytes(n, m, ep)
-    total = cm.spmv_bytes(n, m, ep, nseg)
+    po = info["update_order"] == 2
+    g_bytes = cm.spmv_gather_bytes(n, m, ep, nseg=nseg, png_order=po)
+    total = cm.spmv_bytes(n, m, ep, nseg, png_order=po)
     g_ms = kernels.get("pcpm_spmv_gather", {"avg_ms": float("nan")})["avg_ms"]
     res = {"graph": "the main graph, weights uniform in [-1, 1)", "ms_per_call": dt * 1e3, "gteps": m / dt / 1e9,
            "alg_bytes_per_call": total, "hbm_gbs_alg": total / dt / 1e9, "kernels": kernels,
@@ -486,7 +490,8 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "pcpm_gather", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (counter_traffic("pcpm::k_gather<1024, 0>") if args.graph == "rmat" and args.part_log2 == 14
+            "traffic": (counter_traffic("pcpm::k_gather<1024, 0, %s>" % (
+                "true" if main_res["update_order"] == "png" else "false")) if args.graph == "rmat" and args.part_log2 == 14
                         and args.scale == 24 and args.edge_factor == 16 and args.seed == 2 else None),
             "bytes_per_launch": main_res["gather_bytes"], "avg_launch_ms": g["avg_ms"],
         },

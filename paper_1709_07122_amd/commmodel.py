@@ -57,44 +57,52 @@ TILE = 1024  # destination IDs / PNG edges per stored flag-prefix entry
 SRC_BYTES = 2  # PNG source IDs are stored partition-local in 16 bits (flag in bit 15)
 
 
-def scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES):
+def scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES, png_order=False):
     """Algorithmic bytes of one scatter pass: ranks and out-degrees of every
-    node (8n), the PNG source IDs (src_bytes per PNG edge), one write offset
-    per non-empty (source, destination) pair (4 nseg, the k^2 d_i term of
-    Eq. 5), the tile flag prefixes (4E'/1024) and the update writes (4E')."""
-    return 8 * n + src_bytes * eprime + 4 * nseg + 4 * (eprime // TILE + 1) + 4 * eprime
+    node (8n), the PNG source IDs (src_bytes per PNG edge) and the update
+    writes (4E').  With updates in bin order also one write offset per
+    non-empty (pair, bin) segment (4 nseg, the k^2 d_i term of Eq. 5) and the
+    tile flag prefixes (4E'/1024); in PNG order the writes need neither."""
+    extra = 0 if png_order else 4 * nseg + 4 * (eprime // TILE + 1)
+    return 8 * n + src_bytes * eprime + extra + 4 * eprime
 
 
 DID_BYTES = 2  # destination IDs are stored partition-local in 16 bits (flag in bit 15)
 
 
-def gather_bytes(n, m, eprime, did_bytes=DID_BYTES):
+def gather_bytes(n, m, eprime, did_bytes=DID_BYTES, nseg=0, png_order=False):
     """Algorithmic bytes of one gather+apply pass: destination IDs
     (did_bytes per edge), tile flag prefixes (4m/1024), updates (4E'), the
     previous ranks for the residual (4n), the new ranks (4n) and the dangling
-    bitmask (n/8)."""
-    return did_bytes * m + 4 * (m // TILE + 1) + 4 * eprime + 8 * n + n // 8
+    bitmask (n/8).  With updates in PNG order also the segment deltas
+    (4 nseg) and the segment-flag prefixes (4m/1024)."""
+    extra = 4 * nseg + 4 * (m // TILE + 1) if png_order else 0
+    return did_bytes * m + 4 * (m // TILE + 1) + 4 * eprime + 8 * n + n // 8 + extra
 
 
-def iteration_bytes(n, m, eprime, nseg):
-    return scatter_bytes(n, eprime, nseg) + gather_bytes(n, m, eprime)
+def iteration_bytes(n, m, eprime, nseg, png_order=False):
+    return (scatter_bytes(n, eprime, nseg, png_order=png_order)
+            + gather_bytes(n, m, eprime, nseg=nseg, png_order=png_order))
 
 
 # ---- SpMV over the PNG (Sec. 3.4) -------------------------------------------
 
-def spmv_scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES):
-    """Scatter of one SpMV: x (4n, no out-degrees), PNG source IDs, write
-    offsets, tile flag prefixes and the update writes."""
-    return 4 * n + src_bytes * eprime + 4 * nseg + 4 * (eprime // TILE + 1) + 4 * eprime
+def spmv_scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES, png_order=False):
+    """Scatter of one SpMV: x (4n, no out-degrees), PNG source IDs, the update
+    writes, and in bin order the write offsets and tile flag prefixes."""
+    return scatter_bytes(n, eprime, nseg, src_bytes, png_order) - 4 * n
 
 
-def spmv_gather_bytes(n, m, eprime, weighted=True, did_bytes=DID_BYTES):
+def spmv_gather_bytes(n, m, eprime, weighted=True, did_bytes=DID_BYTES, nseg=0, png_order=False):
     """Gather of one SpMV: destination IDs, their weights (4m when weighted,
     stored beside the IDs, Sec. 3.4), tile flag prefixes, updates and y (4n);
-    no residual, no dangling mask."""
-    return did_bytes * m + (4 * m if weighted else 0) + 4 * (m // TILE + 1) + 4 * eprime + 4 * n
+    no residual, no dangling mask; in PNG order also the segment deltas and
+    segment-flag prefixes."""
+    extra = 4 * nseg + 4 * (m // TILE + 1) if png_order else 0
+    return did_bytes * m + (4 * m if weighted else 0) + 4 * (m // TILE + 1) + 4 * eprime + 4 * n + extra
 
 
-def spmv_bytes(n, m, eprime, nseg, weighted=True):
+def spmv_bytes(n, m, eprime, nseg, weighted=True, png_order=False):
     """Whole SpMV: the scale pass reads x once (4n), then scatter and gather."""
-    return 4 * n + spmv_scatter_bytes(n, eprime, nseg) + spmv_gather_bytes(n, m, eprime, weighted)
+    return (4 * n + spmv_scatter_bytes(n, eprime, nseg, png_order=png_order)
+            + spmv_gather_bytes(n, m, eprime, weighted, nseg=nseg, png_order=png_order))

@@ -447,25 +447,27 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const 
   }
 }
 
-// Weight statistics for the SpMV's fixed-point scale, one workgroup per
-// destination bin: the largest |w| and the largest sum over v of |w(u,v)|
-// (FP64 sums in an LDS slice; 1 per edge when unweighted), as the bit
-// patterns of non-negative doubles, whose order is that of the values; out[2]
-// counts non-finite weights.
-__global__ __launch_bounds__(1024) void k_w_stats(int64_t n, int s, const int32_t* __restrict__ did_start,
+// Weight statistics for the SpMV's fixed-point scale: the largest |w| and
+// the largest sum over v of |w(u,v)| (1 per edge when unweighted), as the
+// bit patterns of non-negative doubles, whose order is that of the values;
+// out[2] counts non-finite weights.  One workgroup per gather item (big bins
+// are split over several): FP64 sums in an LDS slice; a whole bin takes its
+// largest sum at once, the items of a split bin store their slices (as
+// doubles in the partial-sum buffer) for k_w_stats_merge.
+__global__ __launch_bounds__(1024) void k_w_stats(int64_t n, int s, const Item* __restrict__ items,
                                                   const uint16_t* __restrict__ did, const float* __restrict__ wbin,
-                                                  unsigned long long* __restrict__ out) {
+                                                  int64_t* __restrict__ partial, unsigned long long* __restrict__ out) {
   extern __shared__ double csum[];
-  const int64_t p = blockIdx.x;
+  const Item it = items[blockIdx.x];
   const int64_t q = int64_t{1} << s;
-  const int64_t v0 = p << s;
+  const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
   for (int i = threadIdx.x; i < qn; i += 1024) csum[i] = 0.0;
   __syncthreads();
   double wm = 0.0;
   int bad = 0;
   const uint32_t qmask = static_cast<uint32_t>(q - 1);
-  for (int64_t e = did_start[p] + threadIdx.x; e < did_start[p + 1]; e += 1024) {
+  for (int64_t e = it.lo + threadIdx.x; e < it.hi; e += 1024) {
     const uint32_t x = did[tile_pos(e)] & qmask;
     const float wf = wbin ? wbin[e] : 1.0f;
     if (!isfinite(wf)) {
@@ -478,7 +480,12 @@ __global__ __launch_bounds__(1024) void k_w_stats(int64_t n, int s, const int32_
   }
   __syncthreads();
   double cm = 0.0;
-  for (int i = threadIdx.x; i < qn; i += 1024) cm = fmax(cm, csum[i]);
+  if (it.aux >= 0) {
+    double* dst = reinterpret_cast<double*>(partial + static_cast<int64_t>(it.aux) * q);
+    for (int i = threadIdx.x; i < qn; i += 1024) dst[i] = csum[i];
+  } else {
+    for (int i = threadIdx.x; i < qn; i += 1024) cm = fmax(cm, csum[i]);
+  }
   cm = block_max<1024>(cm);
   wm = block_max<1024>(wm);
   if (bad) atomicAdd(&out[2], 1ull);
@@ -486,6 +493,25 @@ __global__ __launch_bounds__(1024) void k_w_stats(int64_t n, int s, const int32_
     atomicMax(&out[0], static_cast<unsigned long long>(__double_as_longlong(cm)));
     atomicMax(&out[1], static_cast<unsigned long long>(__double_as_longlong(wm)));
   }
+}
+
+// Split bins: the sums of the items' slices, node by node, in slot order;
+// one workgroup per merge unit (256 nodes).
+__global__ __launch_bounds__(256) void k_w_stats_merge(int64_t n, int s, const Merge* __restrict__ mg,
+                                                       const int64_t* __restrict__ partial,
+                                                       unsigned long long* __restrict__ out) {
+  const Merge mu = mg[blockIdx.x];
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  const int i = mu.node_lo + static_cast<int>(threadIdx.x);
+  double sum = 0.0;
+  if (i < qn) {
+    const double* base = reinterpret_cast<const double*>(partial + static_cast<int64_t>(mu.first) * q);
+    for (int c = 0; c < mu.count; ++c) sum += base[static_cast<int64_t>(c) * q + i];
+  }
+  const double cm = block_max<256>(sum);
+  if (threadIdx.x == 0) atomicMax(&out[0], static_cast<unsigned long long>(__double_as_longlong(cm)));
 }
 
 // Number of entries with a flag bit (`flag`) set in each kTile tile of
@@ -845,22 +871,6 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
               static_cast<size_t>(2 * k * 4), st, s, static_cast<int32_t>(k), nbits, chunks_d, col, src,
               g->did_start, dwo, ccnt, craw, g->png_base, g->png_off, g->did, g->png_src, weights, g->wbin);
 
-  // ---- weight statistics (scale of pcpm_spmv) -----------------------------------
-  unsigned long long* wst = nullptr;
-  PCPM_TRY(dalloc(g, &wst, 3));
-  PCPM_TRY_HIP(hipMemsetAsync(wst, 0, 3 * sizeof(unsigned long long), st));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_w_stats),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g->q * 8)));
-  PCPM_LAUNCH("pcpm_build_wstats", k_w_stats, dim3(static_cast<unsigned>(k)), dim3(1024),
-              static_cast<size_t>(g->q * 8), st, n, s, g->did_start, g->did, g->wbin, wst);
-  unsigned long long wst_h[3] = {0, 0, 0};
-  PCPM_TRY_HIP(hipMemcpyAsync(wst_h, wst, sizeof(wst_h), hipMemcpyDeviceToHost, st));
-  PCPM_TRY_HIP(hipStreamSynchronize(st));
-  dfree(g, wst);
-  if (wst_h[2]) return set_error(PCPM_ERR_INVALID_ARG, "weights hold %llu non-finite values", wst_h[2]);
-  std::memcpy(&g->w_colmax, &wst_h[0], 8);
-  std::memcpy(&g->w_absmax, &wst_h[1], 8);
-
   // ---- tile flag prefixes ----------------------------------------------------
   // Messages (bit 15) before every tile of destination IDs; with PNG-ordered
   // updates also (bin, pair) segments (bit 14), with bin-ordered updates the
@@ -887,6 +897,26 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(dalloc(g, &g->tmp_pr, n));
   PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->ctl_host), sizeof(Ctl), hipHostMallocDefault));
   PCPM_TRY(build_items(g, opts, st));
+
+  // ---- weight statistics (scale of pcpm_spmv) -----------------------------------
+  unsigned long long* wst = nullptr;
+  PCPM_TRY(dalloc(g, &wst, 3));
+  PCPM_TRY_HIP(hipMemsetAsync(wst, 0, 3 * sizeof(unsigned long long), st));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_w_stats),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g->q * 8)));
+  if (g->n_ga)
+    PCPM_LAUNCH("pcpm_build_wstats", k_w_stats, dim3(static_cast<unsigned>(g->n_ga)), dim3(1024),
+                static_cast<size_t>(g->q * 8), st, n, s, g->ga_items, g->did, g->wbin, g->partial, wst);
+  if (g->n_mg)
+    PCPM_LAUNCH("pcpm_build_wstats", k_w_stats_merge, dim3(static_cast<unsigned>(g->n_mg)), dim3(256), 0, st, n, s,
+                g->mg_items, g->partial, wst);
+  unsigned long long wst_h[3] = {0, 0, 0};
+  PCPM_TRY_HIP(hipMemcpyAsync(wst_h, wst, sizeof(wst_h), hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  dfree(g, wst);
+  if (wst_h[2]) return set_error(PCPM_ERR_INVALID_ARG, "weights hold %llu non-finite values", wst_h[2]);
+  std::memcpy(&g->w_colmax, &wst_h[0], 8);
+  std::memcpy(&g->w_absmax, &wst_h[1], 8);
 
   // ---- release build-only buffers ------------------------------------------------
   PCPM_TRY_HIP(hipStreamSynchronize(st));

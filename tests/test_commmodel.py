@@ -59,3 +59,11 @@ def test_spmv_bytes_add_up():
     assert g == 2 * m + 4 * m + 4 * (m // 1024 + 1) + 4 * ep + 4 * n
     assert cm.spmv_gather_bytes(n, m, ep, weighted=False) == g - 4 * m
     assert cm.spmv_bytes(n, m, ep, nseg) == 4 * n + s + g
+
+
+def test_png_order_moves_the_offsets_to_the_gather():
+    n, m, ep, nseg = 1000, 16000, 9000, 300
+    assert cm.scatter_bytes(n, ep, nseg) - cm.scatter_bytes(n, ep, nseg, png_order=True) == 4 * nseg + 4 * (ep // 1024 + 1)
+    assert cm.gather_bytes(n, m, ep, nseg=nseg, png_order=True) - cm.gather_bytes(n, m, ep) == 4 * nseg + 4 * (m // 1024 + 1)
+    assert cm.iteration_bytes(n, m, ep, nseg, png_order=True) == (cm.scatter_bytes(n, ep, nseg, png_order=True)
+                                                                  + cm.gather_bytes(n, m, ep, nseg=nseg, png_order=True))
