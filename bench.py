@@ -70,7 +70,7 @@ def measure(P, torch, r, c, args, label):
     ct = torch.from_numpy(c).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    png = P.build_png(rt, ct, part_log2=args.part_log2)
+    png = P.build_png(rt, ct, part_log2=args.part_log2, update_order=args.update_order)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = png.info
@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the personalised and multi-graph legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start leg")
     ap.add_argument("--no-spmv", action="store_true", help="skip the weighted SpMV leg")
+    ap.add_argument("--update-order", type=int, default=0, choices=(0, 1, 2),
+                    help="storage order of the updates: 0 automatic, 1 bin order, 2 PNG order")
     ap.add_argument("--ppr-seed", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy (reference for HBM byte counters)")

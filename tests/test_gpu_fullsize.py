@@ -10,6 +10,7 @@
 * Batched personalised PageRank on RMAT-22 (EF 16, seed 5) with 8/32/64 seed
   sets at the autotuned partition size, and the 16-graph uneven batch.
 * The learned warm start on a held-out RMAT-24 graph.
+* The weighted SpMV on RMAT-24 in both update orders.
 """
 import numpy as np
 import pytest
@@ -154,3 +155,25 @@ def test_warm_start_on_held_out_rmat24():
     for res in (cold, warm):
         err = np.abs(res.pr.cpu().numpy().astype(np.float64) - star).sum()
         assert err <= D * res.resid / (1 - D) + 1e-5, err
+
+
+@pytest.mark.parametrize("update_order", [1, 2])
+def test_weighted_spmv_rmat24(update_order):
+    """SpMV (Sec. 3.4) on RMAT-24 with weights uniform in [-1, 1), in both
+    update orders, against the FP64 oracle within the bound of pcpm_spmv."""
+    r, c = graphgen.rmat(24, 16, seed=2, relabel="random")
+    n = len(r) - 1
+    rng = np.random.default_rng(1002)
+    w = rng.uniform(-1.0, 1.0, len(c)).astype(np.float32)
+    x = rng.uniform(-1.0, 1.0, n).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=14, weights=dev(w), update_order=update_order)
+    y = P.spmv(png, dev(x)).cpu().numpy().astype(np.float64)
+    png.close()
+    ref = oracle.spmv(r, c, x, w)
+    aw = np.abs(w.astype(np.float64))
+    xmax = float(np.abs(x).max())
+    indeg = np.bincount(c, minlength=n)
+    wcol = float(np.bincount(c, weights=aw, minlength=n).max())
+    s = min(50 - int(np.ceil(np.log2(aw.max() * xmax))), 62 - int(np.ceil(np.log2(wcol * xmax)))) - 1
+    bound = indeg * 2.0 ** -s + 2.0 ** -23 * np.abs(ref) + 2.0 ** -150
+    assert np.all(np.abs(y - ref) <= bound)
