@@ -209,10 +209,12 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
  * from x_0 = t_j:
  *   x'(v) = (1-d) t_j(v) + d * ( sum_{u->v} x(u)/outdeg(u) + D_j t_j(v) ).
  * S_j = seeds[seed_off[j] .. seed_off[j+1]) (host arrays; every set non-empty,
- * nodes in [0, n), no node twice in a set).  Vectors run in tiles of
- * pcpm_ppr_tile_width(g) that share every PNG edge and destination ID of the
- * scatter and gather; a vector whose FP64 L1 residual falls below tol keeps
- * that iterate.  pr_out (device) receives the ranks as [n][k] row-major;
+ * nodes in [0, n), no node twice in a set).  pcpm_ppr_tile_width(g) vectors
+ * share every PNG edge and destination ID of the scatter and gather, one per
+ * slot of an update; a vector whose FP64 L1 residual falls below tol (or
+ * that has run max_iters iterations) is stored with that iterate and its
+ * slot starts the next waiting vector, so each vector runs its own number of
+ * iterations, the same as when it runs alone.  pr_out (device) receives the ranks as [n][k] row-major;
  * iters and resid (host, k each) every vector's iteration count and last
  * residual.  tol <= 0 runs exactly max_iters iterations.  Returns
  * PCPM_ERR_NOT_CONVERGED (outputs valid) when some vector stays above tol.

@@ -169,12 +169,12 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
     } else {
       // Every entry of a tile has a valid segment index (entry 0 of the array
       // is flagged and padding follows the last segment), so the loads below
-      // need no predicate.  A source ID masked with q-1 is its slot in the rank
-      // slice (entries of other partitions, in edge tiles, only read a stale
-      // slot and store to the spare update slot E').
+      // need no predicate.  A source ID masked with 2q-1 is its slot in the
+      // pair's rank slice (entries of other pairs, in edge tiles, only read a
+      // stale slot and store to the spare update slot E').
       int32_t run = png_blk[t];
       int32_t seg[kSub];
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < kSub; ++j) {
         const bool f = (x[j] & kDidFlag) != 0u;
         const uint64_t bal = wave_ballot(f);
@@ -182,14 +182,14 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
         run += __popcll(bal);
       }
       int32_t dl[kSub];
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
       if (tb >= lo && tb + kTile <= hi) {
         float* ut = upd + tb;
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < kSub; ++j) ut[static_cast<int64_t>(j * kWave + lane + dl[j])] = spr[x[j] & qmask];
       } else {
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < kSub; ++j) {
           const int64_t e = tb + j * kWave + lane;
           const bool in = e >= lo && e < hi;
@@ -694,7 +694,11 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
 pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x, float* y, void* stream) {
   using namespace pcpm;
   if (!g || !x || !y) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or vector");
-  if (x < y + g->n && y < x + g->n) return set_error(PCPM_ERR_INVALID_ARG, "x and y must not overlap");
+  {
+    const uintptr_t xa = reinterpret_cast<uintptr_t>(x), ya = reinterpret_cast<uintptr_t>(y);
+    const uintptr_t bytes = static_cast<uintptr_t>(g->n) * sizeof(float);
+    if (xa < ya + bytes && ya < xa + bytes) return set_error(PCPM_ERR_INVALID_ARG, "x and y must not overlap");
+  }
   PCPM_TRY(check_device(g));
   hipStream_t st = static_cast<hipStream_t>(stream);
   constexpr int kMaxBlocks = 1024;

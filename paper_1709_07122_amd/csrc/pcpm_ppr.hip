@@ -77,11 +77,11 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
     if constexpr (kPng) {
       if (tb >= lo && tb + kTile <= hi) {
         float* ut = upd + tb * KT;
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < kSub; ++j)
           copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane) * KT, spr + (xs[j] & qmask) * KT);
       } else {
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < kSub; ++j) {
           const int64_t e = tb + j * kWave + lane;
           if (e >= lo && e < hi) copy_kt<KT>(upd + e * KT, spr + (xs[j] & qmask) * KT);
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
       // padding follows the last segment): no predicate on these loads
       int32_t run = png_blk[t];
       int32_t seg[kSub];
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < kSub; ++j) {
         const bool f = (xs[j] & kDidFlag) != 0u;
         const uint64_t bal = wave_ballot(f);
@@ -100,15 +100,15 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
         run += __popcll(bal);
       }
       int32_t dl[kSub];
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
       if (tb >= lo && tb + kTile <= hi) {
         float* ut = upd + tb * KT;
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < kSub; ++j)
           copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane + dl[j]) * KT, spr + (xs[j] & qmask) * KT);
       } else {
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < kSub; ++j) {
           const int64_t e = tb + j * kWave + lane;
           const bool in = e >= lo && e < hi;
