@@ -224,11 +224,11 @@ def ppr_detail(P, torch, args):
     n, m = len(r) - 1, len(c)
     rt, ct = torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()
     one = autotune.tune(rt, ct, vectors=1, cache=None)
-    png1 = P.build_png(rt, ct, part_log2=one.part_log2)
+    png1 = P.build_png(rt, ct, part_log2=one.part_log2, update_order=one.update_order)
     rows = []
     for k in (8, 32, 64):
         tune = autotune.tune(rt, ct, vectors=k, cache=None)
-        png = P.build_png(rt, ct, part_log2=tune.part_log2)
+        png = P.build_png(rt, ct, part_log2=tune.part_log2, update_order=tune.update_order)
         off, seeds = graphgen.seed_sets(n, k, seed=k)
         reps = max(1, args.steps // 2)
         b_ms, res = _timed(torch, lambda: P.ppr_batch(png, off, seeds, tol=args.tol, max_iters=args.max_iters), reps)
@@ -239,13 +239,16 @@ def ppr_detail(P, torch, args):
 
         s_ms, sres = _timed(torch, one_by_one, 1)
         vec_iters = int(res.iters.sum())
-        rows.append({"k": k, "part_log2": tune.part_log2, "tile_width": tune.tile_width, "batched_ms": b_ms,
+        rows.append({"k": k, "part_log2": tune.part_log2, "update_order": tune.update_order,
+                     "tile_width": tune.tile_width, "batched_ms": b_ms,
                      "one_at_a_time_ms": s_ms, "one_at_a_time_part_log2": one.part_log2,
+                     "one_at_a_time_update_order": one.update_order,
                      "speedup": s_ms / b_ms, "iters_mean": float(res.iters.mean()), "iters_max": int(res.iters.max()),
                      "converged": bool(res.converged), "vector_gteps": m * vec_iters / (b_ms * 1e-3) / 1e9,
                      "single_iters_mean": float(np.mean([x.iters[0] for x in sres]))})
-        log(f"[ppr] k={k} q=2^{tune.part_log2} width {tune.tile_width}: {b_ms:.2f} ms batched vs {s_ms:.2f} ms one at "
-            f"a time ({s_ms / b_ms:.2f}x), {rows[-1]['vector_gteps']:.1f} vector-GTEPS")
+        log(f"[ppr] k={k} q=2^{tune.part_log2} order {tune.update_order} width {tune.tile_width}: {b_ms:.2f} ms batched "
+            f"vs {s_ms:.2f} ms one at a time (q=2^{one.part_log2} order {one.update_order}, {s_ms / b_ms:.2f}x), "
+            f"{rows[-1]['vector_gteps']:.1f} vector-GTEPS")
         png.close()
     png1.close()
     return {"graph": f"RMAT-22 EF16 seed {args.ppr_seed} random labels", "n": n, "m": m, "tol": args.tol, "rows": rows}

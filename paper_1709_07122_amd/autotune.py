@@ -1,11 +1,13 @@
-"""Measured choice of the partition size q (and, for batched personalised
-PageRank, of the vector tile width that q implies).
+"""Measured choice of the partition size q and of the update storage order
+(and, for batched personalised PageRank, of the vector tile width that q
+implies).
 
 The paper picks its partition size by a sweep of execution time against
 partition size (Sec. 5.4, Figs. 11-14); this does the same sweep on the GPU:
-for each candidate q it builds the PNG, runs a few iterations through the
-library and keeps the fastest time per iteration (per vector for batched
-personalised PageRank).  PNG build time is reported beside it, not mixed in.
+for each candidate q and each update order (bin order, PNG order) it builds
+the PNG, runs a few iterations through the library and keeps the fastest time
+per iteration (per vector for batched personalised PageRank).  PNG build
+time is reported beside it, not mixed in.
 Results are cached in a JSON file keyed by (n, m, vectors, device).
 """
 from __future__ import annotations
@@ -30,6 +32,7 @@ class TuneResult:
     build_ms: float
     table: list = field(default_factory=list)  # every candidate measured
     cached: bool = False
+    update_order: int = 0        # 1 bin order, 2 PNG order (0: entries cached before the order was tuned)
 
 
 def _device_name():
@@ -75,7 +78,7 @@ def _time_solve(fn, iters, reps):
 
 
 def tune(row_off, col, vectors: int = 1, candidates=(12, 13, 14), iters: int = 6, reps: int = 2,
-         cache: str | None = DEFAULT_CACHE, seed: int = 0, force: bool = False) -> TuneResult:
+         cache: str | None = DEFAULT_CACHE, seed: int = 0, force: bool = False, orders=(1, 2)) -> TuneResult:
     """Pick part_log2 for PageRank (vectors = 1) or for batched personalised
     PageRank with `vectors` right-hand sides, on device CSR tensors."""
     n, m = row_off.numel() - 1, col.numel()
@@ -86,11 +89,12 @@ def tune(row_off, col, vectors: int = 1, candidates=(12, 13, 14), iters: int = 6
             hit["cached"] = True
             return TuneResult(**hit)
     rows = []
-    for pl in candidates:
+    cands = [(pl, order) for pl in candidates for order in orders]
+    for pl, order in cands:
         if pl < 1 or pl > 14 or (n + (1 << pl) - 1) >> pl > 16384:
             continue
         t0 = time.perf_counter()
-        png = P.build_png(row_off, col, part_log2=pl)
+        png = P.build_png(row_off, col, part_log2=pl, update_order=order)
         build_ms = (time.perf_counter() - t0) * 1e3
         width = P.ppr_tile_width(png)
         if vectors <= 1:
@@ -104,13 +108,14 @@ def tune(row_off, col, vectors: int = 1, candidates=(12, 13, 14), iters: int = 6
             ms = _time_solve(lambda it: P.ppr_batch(png, off, seeds.astype(np.int32), tol=0.0, max_iters=it),
                              iters, reps)
             per = ms / k
-        rows.append({"part_log2": pl, "tile_width": width, "ms_per_iter": per, "build_ms": build_ms,
-                     "eprime": png.info["eprime"]})
+        rows.append({"part_log2": pl, "update_order": order, "tile_width": width, "ms_per_iter": per,
+                     "build_ms": build_ms, "eprime": png.info["eprime"], "nseg": png.info["nseg"]})
         png.close()
     if not rows:
         raise ValueError("no candidate partition size fits this graph")
     best = min(rows, key=lambda r: r["ms_per_iter"])
-    res = TuneResult(best["part_log2"], best["tile_width"], best["ms_per_iter"], best["build_ms"], rows)
+    res = TuneResult(best["part_log2"], best["tile_width"], best["ms_per_iter"], best["build_ms"], rows,
+                     update_order=best["update_order"])
     if cache:
         _store(cache, key, res)
     return res

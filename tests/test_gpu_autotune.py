@@ -22,10 +22,11 @@ def test_tune_pagerank_and_cache(tmp_path):
     cache = str(tmp_path / "tune.json")
     res = P.autotune.tune(rt, ct, candidates=(8, 10, 12), iters=3, reps=1, cache=cache)
     assert res.part_log2 in (8, 10, 12) and not res.cached
-    assert len(res.table) == 3
+    assert len(res.table) == 6 and res.update_order in (1, 2)
+    assert {(row["part_log2"], row["update_order"]) for row in res.table} == {(p, o) for p in (8, 10, 12) for o in (1, 2)}
     assert res.ms_per_iter == min(row["ms_per_iter"] for row in res.table)
     again = P.autotune.tune(rt, ct, candidates=(8, 10, 12), cache=cache)
-    assert again.cached and again.part_log2 == res.part_log2
+    assert again.cached and again.part_log2 == res.part_log2 and again.update_order == res.update_order
 
 
 def test_tune_batched_ppr(tmp_path):

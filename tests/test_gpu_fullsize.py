@@ -112,7 +112,7 @@ def test_ppr_rmat22_autotuned(rmat22, k):
     n = len(r) - 1
     rt, ct = dev(r), dev(c)
     tune = autotune.tune(rt, ct, vectors=k, cache=None)
-    png = P.build_png(rt, ct, part_log2=tune.part_log2)
+    png = P.build_png(rt, ct, part_log2=tune.part_log2, update_order=tune.update_order)
     off, seeds = graphgen.seed_sets(n, k, seed=k)
     res = P.ppr_batch(png, off, seeds, d=D, tol=1e-6, max_iters=200)
     png.close()
