@@ -3,6 +3,7 @@
 //
 // Pipeline (all on the caller's stream):
 //   node pass    validate rows, out-degrees, dangling bitmask, edge -> source
+//                (node-parallel marks, then edge-parallel tiles)
 //   count        per source partition p (one workgroup, LDS histograms):
 //                |U(p,p')| and raw edges p -> p' for every p'
 //   scans        write offsets (column prefix over source partitions),
@@ -33,11 +34,11 @@ enum : int32_t {
   kErrGraphs = 64,   // an edge leaves its graph, or a padding node has edges
 };
 
-constexpr int kBigRow = 64;  // rows longer than this are validated by a workgroup
-
-// ---------------------------------------------------------------------------------
-// Node pass: one lane per node.  Short rows are validated and expanded by their
-// lane; long rows are queued for k_big_rows.
+// Node pass, in two kernels.  Nodes (one lane per node, coalesced):
+// out-degree, dangling bit, offset checks, and a mark at the first edge of
+// every non-empty row (src[row_off[u]] = u; src starts at -1).  Edges (one
+// wavefront per 1024-edge tile): each edge's source node, then the edge
+// checks.
 // Edge u -> c stays inside u's graph and avoids padding nodes.
 __device__ __forceinline__ bool same_graph(int64_t u, int32_t c, int s, const int32_t* __restrict__ part_group,
                                            const int32_t* __restrict__ part_valid) {
@@ -47,11 +48,9 @@ __device__ __forceinline__ bool same_graph(int64_t u, int32_t c, int s, const in
 }
 
 __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
-                                                   const int32_t* __restrict__ col, int32_t* __restrict__ outdeg,
-                                                   uint32_t* __restrict__ dmask, int32_t* __restrict__ src,
-                                                   int32_t* __restrict__ big, int64_t big_cap,
-                                                   int32_t* __restrict__ counters /* [0]=err [1]=nbig [2]=ndang */,
-                                                   int s, const int32_t* __restrict__ part_group,
+                                                   int32_t* __restrict__ outdeg, uint32_t* __restrict__ dmask,
+                                                   int32_t* __restrict__ src,
+                                                   int32_t* __restrict__ counters /* [0]=err [2]=ndang */, int s,
                                                    const int32_t* __restrict__ part_valid) {
   const int64_t nwords = (n + 31) >> 5;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -67,22 +66,9 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
       } else {
         outdeg[u] = hi - lo;
         dang = (hi == lo);
-        if (hi > lo && (u & ((int64_t{1} << s) - 1)) >= part_valid[u >> s]) err |= kErrGraphs;
-        if (hi - lo > kBigRow) {
-          const int32_t idx = atomicAdd(&counters[1], 1);
-          if (idx < big_cap) big[idx] = static_cast<int32_t>(u);
-          else err |= kErrInternal;
-        } else {
-          int32_t prev = -1;
-          for (int32_t j = lo; j < hi; ++j) {
-            const int32_t c = col[j];
-            if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
-            else if (!same_graph(u, c, s, part_group, part_valid)) err |= kErrGraphs;
-            if (c == u) err |= kErrSelfLoop;
-            if (c <= prev) err |= kErrOrder;
-            prev = c;
-            src[j] = static_cast<int32_t>(u);
-          }
+        if (hi > lo) {
+          if ((u & ((int64_t{1} << s) - 1)) >= part_valid[u >> s]) err |= kErrGraphs;
+          src[lo] = static_cast<int32_t>(u);  // first edge of the row
         }
       }
     }
@@ -102,29 +88,52 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
   }
 }
 
-// Long rows: one workgroup per queued row.
-__global__ __launch_bounds__(256) void k_big_rows(int64_t n, const int32_t* __restrict__ row_off,
-                                                  const int32_t* __restrict__ col, int32_t* __restrict__ src,
-                                                  const int32_t* __restrict__ big, int64_t big_cap,
-                                                  int32_t* __restrict__ counters, int s,
-                                                  const int32_t* __restrict__ part_group,
-                                                  const int32_t* __restrict__ part_valid) {
-  const int64_t nbig = min(static_cast<int64_t>(counters[1]), big_cap);
-  for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
-    const int32_t u = big[i];
-    const int32_t lo = row_off[u], hi = row_off[u + 1];
-    int32_t err = 0;
-    for (int32_t j = lo + static_cast<int32_t>(threadIdx.x); j < hi; j += blockDim.x) {
-      const int32_t c = col[j];
-      const int32_t prev = (j > lo) ? col[j - 1] : -1;
-      if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
-      else if (!same_graph(u, c, s, part_group, part_valid)) err |= kErrGraphs;
-      if (c == u) err |= kErrSelfLoop;
-      if (c <= prev) err |= kErrOrder;
-      src[j] = u;
+// The row holding a tile's first edge e0 is the largest u with
+// row_off[u] <= e0 (binary search); wavefront max-scans over the row marks
+// carry it through the tile.  Every index stays in range whatever the
+// offsets: rows found are in [0, n), marks were written for valid rows only.
+__global__ __launch_bounds__(256) void k_edge_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
+                                                   const int32_t* __restrict__ col, int32_t* __restrict__ src,
+                                                   int32_t* __restrict__ counters, int s,
+                                                   const int32_t* __restrict__ part_group,
+                                                   const int32_t* __restrict__ part_valid) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  int32_t err = 0;
+  for (int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave; t < ntiles; t += nwaves) {
+    const int64_t e0 = t * kTile;
+    int64_t lo = 0, hi = n;  // search [0, n)
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (static_cast<int64_t>(row_off[mid]) <= e0) lo = mid;
+      else hi = mid;
     }
-    if (err) atomicOr(&counters[0], err);
+    int32_t carry = static_cast<int32_t>(lo);
+    for (int j = 0; j < kSub; ++j) {
+      const int64_t e = e0 + j * kWave + lane;
+      const bool in = e < m;
+      const int32_t mk = in ? src[e] : -1;
+      int32_t v = mk;  // inclusive max-scan over the wavefront
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t o = __shfl_up(v, off);
+        if (lane >= off) v = max(v, o);
+      }
+      const int32_t u = max(v, carry);
+      carry = __shfl(u, kWave - 1);
+      if (in) {
+        src[e] = u;
+        const int32_t c = col[e];
+        const int32_t prev = (mk >= 0 || e == 0) ? -1 : col[e - 1];  // first edge of its row: no predecessor
+        if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
+        else if (!same_graph(u, c, s, part_group, part_valid)) err |= kErrGraphs;
+        if (c == u) err |= kErrSelfLoop;
+        if (c <= prev) err |= kErrOrder;
+      }
+    }
   }
+  if (err) atomicOr(&counters[0], err);
 }
 
 // ---------------------------------------------------------------------------------
@@ -733,21 +742,21 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
 
   // ---- node pass -------------------------------------------------------------
   int32_t* src = nullptr;
-  int32_t* big = nullptr;
   int32_t* counters = nullptr;
-  const int64_t big_cap = m / kBigRow + 1;
   PCPM_TRY(dalloc(g, &g->outdeg, n));
   PCPM_TRY(dalloc(g, &g->dmask, (n + 31) / 32));
   PCPM_TRY(dalloc(g, &src, m));
-  PCPM_TRY(dalloc(g, &big, big_cap));
   PCPM_TRY(dalloc(g, &counters, 4));
   PCPM_TRY_HIP(hipMemsetAsync(counters, 0, 16, st));
+  PCPM_TRY_HIP(hipMemsetAsync(src, 0xFF, static_cast<size_t>(std::max<int64_t>(m, 1)) * 4, st));  // -1: no mark
   {
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
     PCPM_LAUNCH("pcpm_build_nodes", k_node_pass, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, n, m,
-                row_off, col, g->outdeg, g->dmask, src, big, big_cap, counters, s, g->part_group, g->part_valid);
-    PCPM_LAUNCH("pcpm_build_bigrows", k_big_rows, dim3(1024), dim3(256), 0, st, n, row_off, col, src, big,
-                big_cap, counters, s, g->part_group, g->part_valid);
+                row_off, g->outdeg, g->dmask, src, counters, s, g->part_valid);
+    const int64_t eblocks = std::min<int64_t>(((m + kTile - 1) / kTile + 3) / 4, 65536);
+    if (m > 0)
+      PCPM_LAUNCH("pcpm_build_nodes", k_edge_pass, dim3(static_cast<unsigned>(eblocks)), dim3(256), 0, st, n, m,
+                  row_off, col, src, counters, s, g->part_group, g->part_valid);
   }
   int32_t hc[4] = {0, 0, 0, 0};
   PCPM_TRY_HIP(hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
@@ -923,7 +932,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   for (void* p : {static_cast<void*>(pe_d), static_cast<void*>(chunks_d), static_cast<void*>(cfirst_d),
                   static_cast<void*>(ccnt), static_cast<void*>(craw)})
     dfree(g, p);
-  for (void* p : {static_cast<void*>(src), static_cast<void*>(big), static_cast<void*>(counters),
+  for (void* p : {static_cast<void*>(src), static_cast<void*>(counters),
                   static_cast<void*>(raw), static_cast<void*>(dwo), static_cast<void*>(coltot),
                   static_cast<void*>(coltot_raw), static_cast<void*>(rowtot), static_cast<void*>(rowseg),
                   static_cast<void*>(segbase), static_cast<void*>(tcnt), static_cast<void*>(cnt)})
