@@ -8,11 +8,12 @@
 //                |U(p,p')| and raw edges p -> p' for every p'
 //   scans        write offsets (column prefix over source partitions),
 //                partition-local PNG offsets (row prefix), bin starts
-//   fill         per source partition, one wavefront walks p's edges in CSR
-//                order; a ballot multisplit ranks each edge among the edges of
-//                the same destination partition, so every bin is written in
-//                the canonical (p, u, v) order without atomics and the PNG in
-//                (p, p', u) order
+//   fill         per chunk of a source partition's edges, one wavefront walks
+//                them in CSR order; a ballot multisplit ranks each edge among
+//                the edges of the same destination partition, so every bin is
+//                written in the canonical (p, u, v) order without atomics and
+//                the PNG in (p, p', u) order; records go first to at most 64
+//                buckets of destination partitions, then to their slots
 //   tile flags   flags before every 1024-entry tile of both arrays
 #include <algorithm>
 #include <chrono>
@@ -373,86 +374,176 @@ __global__ __launch_bounds__(256) void k_segdelta_pairs(int32_t k, const int32_t
   }
 }
 
-// Fill: one wavefront per chunk, edges in CSR order, 64 at a time.  Lanes
-// with the same destination partition form a peer group (found with one
-// ballot per key bit); an edge's position in its bin is the group cursor plus
-// the number of peer lanes below it.  The lowest peer advances the cursors,
-// which start at the chunk's prefixes of its partition's counts.
-__global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, const Item* __restrict__ chunks,
+// Fill, in two passes that write each bin and PNG region in long runs.  A
+// direct fill stores every edge's 2-byte ID into one of k bins; with
+// thousands of wavefronts each holding k half-written cache lines, the lines
+// leave L2 before they are complete and every store costs a partial-line
+// write to memory.
+//
+// Pass 1 (k_fill): one wavefront per chunk, edges in CSR order, 64 at a time.
+// Lanes with the same destination partition form a peer group (one ballot
+// per key bit, high bits first); an edge's destination-ID slot is its group's
+// cursor plus the number of peer lanes below it (a stable multisplit, no
+// atomics), and likewise its rank inside U(p, p') for a message's first
+// edge.  The lowest peer advances the cursors, which start at the chunk's
+// prefixes of its partition's counts.  The edge's record (ID slot and value;
+// PNG slot and value for a message's first edge; weight) goes to the region
+// of its bucket, the 2^bbits destination partitions that share their high
+// bits (64 buckets at most).  A bucket's region is the bucket's span of the
+// ID array, so its cursor is the same prefix summed over the bucket's bins,
+// and the records of a bucket lie in CSR order.
+constexpr int kFillSets = 4;      // 64-edge sets whose loads are issued together
+constexpr int kFillBuckets = 64;  // most buckets of pass 1
+__global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bbits, const Item* __restrict__ chunks,
                                              const int32_t* __restrict__ col, const int32_t* __restrict__ src,
                                              const int32_t* __restrict__ did_start, const int32_t* __restrict__ dwo,
                                              const int32_t* __restrict__ ccnt, const int32_t* __restrict__ craw,
                                              const int32_t* __restrict__ png_base,
-                                             const int32_t* __restrict__ png_off, uint16_t* __restrict__ did,
-                                             uint16_t* __restrict__ png_src, const float* __restrict__ weights,
-                                             float* __restrict__ wbin) {
+                                             const int32_t* __restrict__ png_off, const float* __restrict__ weights,
+                                             uint64_t* __restrict__ rec, uint32_t* __restrict__ rpng,
+                                             float* __restrict__ rw) {
   extern __shared__ int32_t sh[];
-  int32_t* cur_did = sh;   // absolute destination-ID position per p'
+  int32_t* cur_did = sh;       // absolute destination-ID slot per p'
   int32_t* cur_rank = sh + k;  // rank inside U(p,p') per p'
+  int32_t* bcur = sh + 2 * k;  // record slot per bucket
+  const int32_t nb = ((k - 1) >> bbits) + 1;
   const int64_t c = blockIdx.x;
   const Item ch = chunks[c];
   const int64_t p = ch.part;
   const int lane = threadIdx.x;
+  for (int32_t j = lane; j < nb; j += kWave) bcur[j] = 0;
+  __syncthreads();
   for (int32_t j = lane; j < k; j += kWave) {
-    cur_did[j] = did_start[j] + dwo[p * k + j] + craw[c * k + j];
+    const int32_t before = dwo[p * k + j] + craw[c * k + j];  // earlier edges into p' in CSR order
+    cur_did[j] = did_start[j] + before;
     cur_rank[j] = ccnt[c * k + j];
+    atomicAdd(&bcur[j >> bbits], before);
   }
+  __syncthreads();
+  for (int32_t j = lane; j < nb; j += kWave) bcur[j] += did_start[j << bbits];
   __syncthreads();
   const int32_t e0 = ch.lo, e1 = ch.hi;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int32_t cb = e0; cb < e1; cb += kWave) {
-    const int32_t e = cb + lane;
-    const bool valid = e < e1;
-    int32_t u = 0, v = 0, pp = 0;
-    bool first = false;
-    if (valid) {
-      u = src[e];
-      v = col[e];
-      pp = v >> s;
-      first = (e == 0) || (src[e - 1] != u) || ((col[e - 1] >> s) != pp);
+  const uint32_t lmask = (1u << s) - 1u;
+  // the edge before the current set; a source of -1 makes the next edge a
+  // message start
+  int32_t cu = -1, cv = 0;
+  if (e0 > 0) {
+    cu = src[e0 - 1];
+    cv = col[e0 - 1];
+  }
+  for (int32_t cb = e0; cb < e1; cb += kFillSets * kWave) {
+    int32_t us[kFillSets], vs[kFillSets];
+#pragma unroll
+    for (int t = 0; t < kFillSets; ++t) {
+      const int32_t e = cb + t * kWave + lane;
+      us[t] = e < e1 ? src[e] : 0;
+      vs[t] = e < e1 ? col[e] : 0;
     }
-    uint64_t peers = wave_ballot(valid);
-    const uint64_t fmask = wave_ballot(first);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (pp >> b) & 1;
-      const uint64_t bb = wave_ballot(bit);
-      peers &= bit ? bb : ~bb;
-    }
-    const uint64_t fpeers = peers & fmask;
-    const int rank = __popcll(peers & below);
-    const int frank = __popcll(fpeers & below);
-    int32_t cd = 0, cr = 0;
-    if (valid) {
-      cd = cur_did[pp];
-      cr = cur_rank[pp];
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (valid) {
-      uint32_t flags = first ? kDidFlag : 0u;
-      if (wbin) wbin[cd + rank] = weights[e];  // the weight travels with its destination ID (Sec. 3.4)
-      if (first) {
-        // position in the pair-ordered PNG edges: after the pair's earlier
-        // pair segments and, for the odd partition, after the even one's run
-        const int32_t r = cr + frank;
-        const int64_t p0 = p & ~int64_t{1}, p1 = p0 + 1;
-        const int32_t even_off = png_off[p0 * (k + 1) + pp];
-        const int32_t even_cnt = png_off[p0 * (k + 1) + pp + 1] - even_off;
-        const int32_t odd_off = p1 < k ? png_off[p1 * (k + 1) + pp] : 0;
-        const bool odd = (p & 1) != 0;
-        const int64_t pos = static_cast<int64_t>(png_base[p0]) + even_off + odd_off + (odd ? even_cnt : 0) + r;
-        const bool seg_first = r == 0 && (!odd || even_cnt == 0);
-        // source ID local to the pair's 2q nodes, flag on the pair segment's first node
-        png_src[tile_pos(pos)] = static_cast<uint16_t>((static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u));
-        // in bin p', the same edge starts the (p', pair) segment of destination IDs
-        if (seg_first) flags |= kSegFlag;
+#pragma unroll
+    for (int t = 0; t < kFillSets; ++t) {
+      if (cb + t * kWave >= e1) break;
+      const int32_t e = cb + t * kWave + lane;
+      const bool valid = e < e1;
+      const int32_t u = us[t], v = vs[t];
+      int32_t pu = __shfl_up(u, 1), pv = __shfl_up(v, 1);
+      if (lane == 0) {
+        pu = cu;
+        pv = cv;
       }
-      did[tile_pos(cd + rank)] = static_cast<uint16_t>((static_cast<uint32_t>(v) & ((1u << s) - 1u)) | flags);
-      if ((peers & below) == 0) {
-        cur_did[pp] = cd + __popcll(peers);
-        cur_rank[pp] = cr + __popcll(fpeers);
+      cu = __builtin_amdgcn_readlane(u, 63);
+      cv = __builtin_amdgcn_readlane(v, 63);
+      const int32_t pp = v >> s;
+      const bool first = valid && (pu != u || (pv >> s) != pp);
+      uint64_t peers = wave_ballot(valid);
+      const uint64_t fmask = wave_ballot(first);
+      for (int b = nbits - 1; b >= bbits; --b) {
+        const bool bit = (pp >> b) & 1;
+        const uint64_t bb = wave_ballot(bit);
+        peers &= bit ? bb : ~bb;
       }
+      const uint64_t bpeers = peers;  // same bucket
+      for (int b = bbits - 1; b >= 0; --b) {
+        const bool bit = (pp >> b) & 1;
+        const uint64_t bb = wave_ballot(bit);
+        peers &= bit ? bb : ~bb;
+      }
+      const uint64_t fpeers = peers & fmask;
+      const int32_t hb = pp >> bbits;
+      int32_t cd = 0, cr = 0, bc = 0;
+      if (valid) {
+        cd = cur_did[pp];
+        cr = cur_rank[pp];
+        bc = bcur[hb];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (valid) {
+        const int32_t ri = bc + __popcll(bpeers & below);
+        uint32_t flags = first ? kDidFlag : 0u;
+        uint32_t pval = 0;
+        if (first) {
+          // slot in the pair-ordered PNG edges: after the pair's earlier pair
+          // segments and, for the odd partition, after the even one's run
+          const int32_t r = cr + __popcll(fpeers & below);
+          const int64_t p0 = p & ~int64_t{1}, p1 = p0 + 1;
+          const int32_t even_off = png_off[p0 * (k + 1) + pp];
+          const int32_t even_cnt = png_off[p0 * (k + 1) + pp + 1] - even_off;
+          const int32_t odd_off = p1 < k ? png_off[p1 * (k + 1) + pp] : 0;
+          const bool odd = (p & 1) != 0;
+          const int64_t pos = static_cast<int64_t>(png_base[p0]) + even_off + odd_off + (odd ? even_cnt : 0) + r;
+          const bool seg_first = r == 0 && (!odd || even_cnt == 0);
+          // source ID local to the pair's 2q nodes, flag on the pair segment's first node
+          pval = (static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u);
+          rpng[ri] = static_cast<uint32_t>(pos);
+          // in bin p', the same edge starts the (p', pair) segment of destination IDs
+          if (seg_first) flags |= kSegFlag;
+        }
+        const uint32_t dval = (static_cast<uint32_t>(v) & lmask) | flags;
+        rec[ri] = static_cast<uint64_t>(static_cast<uint32_t>(cd + __popcll(peers & below))) |
+                  (static_cast<uint64_t>(dval) << 32) | (static_cast<uint64_t>(pval) << 48);
+        if (rw) rw[ri] = weights[e];  // the weight travels with its destination ID (Sec. 3.4)
+        if ((peers & below) == 0) {
+          cur_did[pp] = cd + __popcll(peers);
+          cur_rank[pp] = cr + __popcll(fpeers);
+        }
+        if ((bpeers & below) == 0) bcur[hb] = bc + __popcll(bpeers);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Pass 2 (k_place): workgroups take consecutive runs of records and store
+// each ID (and PNG source ID, and weight) at its slot.  A run lies in one or
+// two buckets, so its stores fall on at most 2 * 2^bbits bins, a long
+// stretch of each; workgroups of neighbouring runs share an XCD (xcd_block),
+// so the lines that two runs share fill in one L2.
+constexpr int kPlaceBlock = 1024;
+constexpr int kPlaceRecs = 16;  // records per thread
+__global__ __launch_bounds__(kPlaceBlock) void k_place(int64_t m, const uint64_t* __restrict__ rec,
+                                                       const uint32_t* __restrict__ rpng,
+                                                       const float* __restrict__ rw, uint16_t* __restrict__ did,
+                                                       uint16_t* __restrict__ png_src, float* __restrict__ wbin) {
+  const int64_t base = static_cast<int64_t>(xcd_block(blockIdx.x, gridDim.x)) * (kPlaceBlock * kPlaceRecs) +
+                       threadIdx.x;
+  uint64_t r[kPlaceRecs];
+  uint32_t pp[kPlaceRecs];
+#pragma unroll
+  for (int j = 0; j < kPlaceRecs; ++j) {
+    const int64_t i = base + static_cast<int64_t>(j) * kPlaceBlock;
+    r[j] = i < m ? rec[i] : 0;
+    pp[j] = i < m ? rpng[i] : 0;  // read for every record; used for a message's first edge only
+  }
+#pragma unroll
+  for (int j = 0; j < kPlaceRecs; ++j) {
+    const int64_t i = base + static_cast<int64_t>(j) * kPlaceBlock;
+    if (i < m) {
+      const uint32_t dpos = static_cast<uint32_t>(r[j]);
+      const uint32_t dval = static_cast<uint32_t>(r[j] >> 32) & 0xFFFFu;
+      did[tile_pos(dpos)] = static_cast<uint16_t>(dval);
+      if (dval & kDidFlag) png_src[tile_pos(pp[j])] = static_cast<uint16_t>(r[j] >> 48);
+      if (wbin) wbin[dpos] = rw[i];
+    }
   }
 }
 
@@ -544,7 +635,7 @@ pcpm_status_t set_lds_limits() {
   PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_count),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kMaxParts * 4));
   PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fill),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kMaxParts * 4));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (2 * kMaxParts + kFillBuckets) * 4));
   done = true;
   return PCPM_OK;
 }
@@ -869,6 +960,9 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY_HIP(hipMemsetAsync(g->did, 0, std::max<int64_t>(ntd, 1) * kTile * 2, st));
   int nbits = 0;
   while ((int64_t{1} << nbits) < k) ++nbits;
+  int bbits = 0;  // destination partitions per bucket: 2^bbits, at most kFillBuckets buckets
+  while ((int64_t{1} << (nbits - bbits)) > kFillBuckets) ++bbits;
+  const int64_t nbuckets = ((k - 1) >> bbits) + 1;
   const float* weights = opts ? opts->weights : nullptr;
   if (weights) {
     if (!is_device_ptr(weights)) return set_error(PCPM_ERR_INVALID_ARG, "weights must be a device pointer");
@@ -876,9 +970,24 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
     PCPM_TRY(dalloc(g, &g->wbin, std::max<int64_t>(ntd, 1) * kTile));
     PCPM_TRY_HIP(hipMemsetAsync(g->wbin, 0, std::max<int64_t>(ntd, 1) * kTile * 4, st));
   }
-  PCPM_LAUNCH("pcpm_build_fill", k_fill, dim3(static_cast<unsigned>(nchunks)), dim3(64),
-              static_cast<size_t>(2 * k * 4), st, s, static_cast<int32_t>(k), nbits, chunks_d, col, src,
-              g->did_start, dwo, ccnt, craw, g->png_base, g->png_off, g->did, g->png_src, weights, g->wbin);
+  if (m > 0) {
+    uint64_t* rec = nullptr;
+    uint32_t* rpng = nullptr;
+    float* rw = nullptr;
+    PCPM_TRY(dalloc(g, &rec, m));
+    PCPM_TRY(dalloc(g, &rpng, m));
+    if (weights) PCPM_TRY(dalloc(g, &rw, m));
+    PCPM_LAUNCH("pcpm_build_fill", k_fill, dim3(static_cast<unsigned>(nchunks)), dim3(64),
+                static_cast<size_t>((2 * k + nbuckets) * 4), st, s, static_cast<int32_t>(k), nbits, bbits, chunks_d,
+                col, src, g->did_start, dwo, ccnt, craw, g->png_base, g->png_off, weights, rec, rpng, rw);
+    const int64_t per = int64_t{kPlaceBlock} * kPlaceRecs;
+    PCPM_LAUNCH("pcpm_build_place", k_place, dim3(static_cast<unsigned>((m + per - 1) / per)), dim3(kPlaceBlock), 0,
+                st, m, rec, rpng, rw, g->did, g->png_src, g->wbin);
+    PCPM_TRY_HIP(hipStreamSynchronize(st));
+    dfree(g, rec);
+    dfree(g, rpng);
+    if (rw) dfree(g, rw);
+  }
 
   // ---- tile flag prefixes ----------------------------------------------------
   // Messages (bit 15) before every tile of destination IDs; with PNG-ordered
