@@ -384,16 +384,21 @@ __global__ __launch_bounds__(256) void k_segdelta_pairs(int32_t k, const int32_t
 // Lanes with the same destination partition form a peer group (one ballot
 // per key bit, high bits first); an edge's destination-ID slot is its group's
 // cursor plus the number of peer lanes below it (a stable multisplit, no
-// atomics), and likewise its rank inside U(p, p') for a message's first
-// edge.  The lowest peer advances the cursors, which start at the chunk's
-// prefixes of its partition's counts.  The edge's record (ID slot and value;
+// atomics), and likewise its PNG slot for a message's first edge.  The
+// lowest peer advances the cursors, which start at the chunk's prefixes of
+// its partition's counts (the PNG cursor holds the absolute slot in the
+// pair-ordered PNG edges, and in its top bit whether the next message
+// starts the (pair, p') segment).  The edge's record (ID slot and value;
 // PNG slot and value for a message's first edge; weight) goes to the region
 // of its bucket, the 2^bbits destination partitions that share their high
 // bits (64 buckets at most).  A bucket's region is the bucket's span of the
 // ID array, so its cursor is the same prefix summed over the bucket's bins,
 // and the records of a bucket lie in CSR order.
-constexpr int kFillSets = 4;      // 64-edge sets whose loads are issued together
-constexpr int kFillBuckets = 64;  // most buckets of pass 1
+constexpr int kFillSets = 4;  // 64-edge sets whose loads are issued together
+#ifndef PCPM_FILL_BUCKETS
+#define PCPM_FILL_BUCKETS 64
+#endif
+constexpr int kFillBuckets = PCPM_FILL_BUCKETS;  // most buckets of pass 1
 __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bbits, const Item* __restrict__ chunks,
                                              const int32_t* __restrict__ col, const int32_t* __restrict__ src,
                                              const int32_t* __restrict__ did_start, const int32_t* __restrict__ dwo,
@@ -403,9 +408,9 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
                                              uint64_t* __restrict__ rec, uint32_t* __restrict__ rpng,
                                              float* __restrict__ rw) {
   extern __shared__ int32_t sh[];
-  int32_t* cur_did = sh;       // absolute destination-ID slot per p'
-  int32_t* cur_rank = sh + k;  // rank inside U(p,p') per p'
-  int32_t* bcur = sh + 2 * k;  // record slot per bucket
+  int32_t* cur_did = sh;                                     // absolute destination-ID slot per p'
+  uint32_t* cur_png = reinterpret_cast<uint32_t*>(sh + k);  // PNG slot per p' | segment-start bit
+  int32_t* bcur = sh + 2 * k;                                // record slot per bucket
   const int32_t nb = ((k - 1) >> bbits) + 1;
   const int64_t c = blockIdx.x;
   const Item ch = chunks[c];
@@ -413,11 +418,22 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
   const int lane = threadIdx.x;
   for (int32_t j = lane; j < nb; j += kWave) bcur[j] = 0;
   __syncthreads();
+  // PNG slots: the pair's earlier pair segments, for the odd partition the
+  // even one's run, then the chunk's rank inside U(p, p')
+  const int64_t p0 = p & ~int64_t{1}, p1 = p0 + 1;
+  const bool odd = (p & 1) != 0;
+  const int32_t pbase = png_base[p0];
   for (int32_t j = lane; j < k; j += kWave) {
     const int32_t before = dwo[p * k + j] + craw[c * k + j];  // earlier edges into p' in CSR order
     cur_did[j] = did_start[j] + before;
-    cur_rank[j] = ccnt[c * k + j];
     atomicAdd(&bcur[j >> bbits], before);
+    const int32_t rank = ccnt[c * k + j];
+    const int32_t even_off = png_off[p0 * (k + 1) + j];
+    const int32_t even_cnt = png_off[p0 * (k + 1) + j + 1] - even_off;
+    const int32_t odd_off = p1 < k ? png_off[p1 * (k + 1) + j] : 0;
+    const uint32_t slot = static_cast<uint32_t>(pbase + even_off + odd_off + (odd ? even_cnt : 0) + rank);
+    const bool seg_open = rank == 0 && (!odd || even_cnt == 0);
+    cur_png[j] = slot | (seg_open ? kFlag : 0u);
   }
   __syncthreads();
   for (int32_t j = lane; j < nb; j += kWave) bcur[j] += did_start[j << bbits];
@@ -434,11 +450,13 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
   }
   for (int32_t cb = e0; cb < e1; cb += kFillSets * kWave) {
     int32_t us[kFillSets], vs[kFillSets];
+    float ws[kFillSets];
 #pragma unroll
     for (int t = 0; t < kFillSets; ++t) {
       const int32_t e = cb + t * kWave + lane;
       us[t] = e < e1 ? src[e] : 0;
       vs[t] = e < e1 ? col[e] : 0;
+      ws[t] = (rw && e < e1) ? weights[e] : 0.0f;
     }
 #pragma unroll
     for (int t = 0; t < kFillSets; ++t) {
@@ -470,10 +488,11 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
       }
       const uint64_t fpeers = peers & fmask;
       const int32_t hb = pp >> bbits;
-      int32_t cd = 0, cr = 0, bc = 0;
+      int32_t cd = 0, bc = 0;
+      uint32_t cp = 0;
       if (valid) {
         cd = cur_did[pp];
-        cr = cur_rank[pp];
+        cp = cur_png[pp];
         bc = bcur[hb];
       }
       __builtin_amdgcn_wave_barrier();
@@ -482,29 +501,22 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
         uint32_t flags = first ? kDidFlag : 0u;
         uint32_t pval = 0;
         if (first) {
-          // slot in the pair-ordered PNG edges: after the pair's earlier pair
-          // segments and, for the odd partition, after the even one's run
-          const int32_t r = cr + __popcll(fpeers & below);
-          const int64_t p0 = p & ~int64_t{1}, p1 = p0 + 1;
-          const int32_t even_off = png_off[p0 * (k + 1) + pp];
-          const int32_t even_cnt = png_off[p0 * (k + 1) + pp + 1] - even_off;
-          const int32_t odd_off = p1 < k ? png_off[p1 * (k + 1) + pp] : 0;
-          const bool odd = (p & 1) != 0;
-          const int64_t pos = static_cast<int64_t>(png_base[p0]) + even_off + odd_off + (odd ? even_cnt : 0) + r;
-          const bool seg_first = r == 0 && (!odd || even_cnt == 0);
+          const int frank = __popcll(fpeers & below);
+          const bool seg_first = (cp & kFlag) && frank == 0;
           // source ID local to the pair's 2q nodes, flag on the pair segment's first node
           pval = (static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u);
-          rpng[ri] = static_cast<uint32_t>(pos);
+          rpng[ri] = (cp & kIdMask) + static_cast<uint32_t>(frank);
           // in bin p', the same edge starts the (p', pair) segment of destination IDs
           if (seg_first) flags |= kSegFlag;
         }
         const uint32_t dval = (static_cast<uint32_t>(v) & lmask) | flags;
         rec[ri] = static_cast<uint64_t>(static_cast<uint32_t>(cd + __popcll(peers & below))) |
                   (static_cast<uint64_t>(dval) << 32) | (static_cast<uint64_t>(pval) << 48);
-        if (rw) rw[ri] = weights[e];  // the weight travels with its destination ID (Sec. 3.4)
+        if (rw) rw[ri] = ws[t];  // the weight travels with its destination ID (Sec. 3.4)
         if ((peers & below) == 0) {
           cur_did[pp] = cd + __popcll(peers);
-          cur_rank[pp] = cr + __popcll(fpeers);
+          const int nf = __popcll(fpeers);
+          if (nf) cur_png[pp] = (cp & kIdMask) + static_cast<uint32_t>(nf);
         }
         if ((bpeers & below) == 0) bcur[hb] = bc + __popcll(bpeers);
       }
