@@ -3,7 +3,8 @@
 //
 // Pipeline (all on the caller's stream):
 //   node pass    validate rows, out-degrees, dangling bitmask, edge -> source
-//                (node-parallel marks, then edge-parallel tiles)
+//                (node-parallel: the row of each tile's first edge; then
+//                edge-parallel tiles with row marks in LDS)
 //   count        per source partition p (one workgroup, LDS histograms):
 //                |U(p,p')| and raw edges p -> p' for every p'
 //   scans        write offsets (column prefix over source partitions),
@@ -36,10 +37,12 @@ enum : int32_t {
 };
 
 // Node pass, in two kernels.  Nodes (one lane per node, coalesced):
-// out-degree, dangling bit, offset checks, and a mark at the first edge of
-// every non-empty row (src[row_off[u]] = u; src starts at -1).  Edges (one
-// wavefront per 1024-edge tile): each edge's source node, then the edge
-// checks.
+// out-degree, dangling bit, offset checks, and for every 1024-edge tile the
+// row holding its first edge (tile_row[t]; only rows that contain a tile
+// start write, about one per tile).  Edges (one wavefront per tile): the
+// rows from tile_row[t] to tile_row[t + 1] put a mark at their first edge in
+// LDS, a wavefront max-scan over the marks gives every edge its source, then
+// the edge checks.
 // Edge u -> c stays inside u's graph and avoids padding nodes.
 __device__ __forceinline__ bool same_graph(int64_t u, int32_t c, int s, const int32_t* __restrict__ part_group,
                                            const int32_t* __restrict__ part_valid) {
@@ -50,11 +53,13 @@ __device__ __forceinline__ bool same_graph(int64_t u, int32_t c, int s, const in
 
 __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
                                                    int32_t* __restrict__ outdeg, uint32_t* __restrict__ dmask,
-                                                   int32_t* __restrict__ src,
+                                                   int32_t* __restrict__ tile_row,
                                                    int32_t* __restrict__ counters /* [0]=err [2]=ndang */, int s,
                                                    const int32_t* __restrict__ part_valid) {
+  __shared__ int32_t wdang[256 / kWave];
   const int64_t nwords = (n + 31) >> 5;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int32_t ndang = 0;  // dangling nodes seen by this wavefront (lane 0)
   for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < n; base += stride) {
     const int64_t u = base + threadIdx.x;
     bool dang = false;
@@ -67,11 +72,12 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
       } else {
         outdeg[u] = hi - lo;
         dang = (hi == lo);
-        if (hi > lo) {
-          if ((u & ((int64_t{1} << s) - 1)) >= part_valid[u >> s]) err |= kErrGraphs;
-          src[lo] = static_cast<int32_t>(u);  // first edge of the row
-        }
+        if (hi > lo && (u & ((int64_t{1} << s) - 1)) >= part_valid[u >> s]) err |= kErrGraphs;
+        // tiles whose first edge lies in [lo, hi): all below ceil(m / kTile)
+        for (int64_t t = (static_cast<int64_t>(lo) + kTile - 1) / kTile; t * kTile < hi; ++t)
+          tile_row[t] = static_cast<int32_t>(u);
       }
+      if (u == n - 1) tile_row[(m + kTile - 1) / kTile] = static_cast<int32_t>(u);  // end of the last tile's rows
     }
     if (err) atomicOr(&counters[0], err);
     const uint64_t bal = wave_ballot(dang);
@@ -81,40 +87,58 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
       const int64_t w = first >> 5;
       dmask[w] = static_cast<uint32_t>(bal);
       if (w + 1 < nwords) dmask[w + 1] = static_cast<uint32_t>(bal >> 32);
-      if (bal) atomicAdd(&counters[2], __popcll(bal));
+      ndang += __popcll(bal);
     }
+  }
+  // one atomic per workgroup (one per wavefront on a single counter serialised the pass)
+  if ((threadIdx.x & (kWave - 1)) == 0) wdang[threadIdx.x / kWave] = ndang;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t b = 0;
+    for (int i = 0; i < static_cast<int>(blockDim.x) / kWave; ++i) b += wdang[i];
+    if (b) atomicAdd(&counters[2], b);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (row_off[0] != 0 || static_cast<int64_t>(row_off[n]) != m) atomicOr(&counters[0], kErrEnds);
   }
 }
 
-// The row holding a tile's first edge e0 is the largest u with
-// row_off[u] <= e0 (binary search); wavefront max-scans over the row marks
-// carry it through the tile.  Every index stays in range whatever the
-// offsets: rows found are in [0, n), marks were written for valid rows only.
-__global__ __launch_bounds__(256) void k_edge_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
-                                                   const int32_t* __restrict__ col, int32_t* __restrict__ src,
-                                                   int32_t* __restrict__ counters, int s,
-                                                   const int32_t* __restrict__ part_group,
-                                                   const int32_t* __restrict__ part_valid) {
+// With valid offsets (non-decreasing in [0, m], which the node pass checked
+// on the same stream; otherwise this kernel returns at once) the rows of
+// tile t are tile_row[t] .. tile_row[t + 1]: the first holds the tile's first
+// edge, the others start inside the tile or at its end.  A row's mark is
+// kept with an LDS max, so among empty rows that share an offset the
+// non-empty row after them wins.  Rows visited over all tiles: n + ntiles.
+constexpr int kEdgeBlock = 256;
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
+                                                          const int32_t* __restrict__ col, int32_t* __restrict__ src,
+                                                          const int32_t* __restrict__ tile_row,
+                                                          int32_t* __restrict__ counters, int s,
+                                                          const int32_t* __restrict__ part_group,
+                                                          const int32_t* __restrict__ part_valid) {
+  __shared__ int32_t marks[kEdgeBlock / kWave][kTile];
+  if (counters[0] != 0) return;  // invalid offsets: the build fails, src is not used
   const int lane = threadIdx.x & (kWave - 1);
+  int32_t* mk_l = marks[threadIdx.x / kWave];
   const int64_t ntiles = (m + kTile - 1) / kTile;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
   int32_t err = 0;
   for (int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave; t < ntiles; t += nwaves) {
-    const int64_t e0 = t * kTile;
-    int64_t lo = 0, hi = n;  // search [0, n)
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (static_cast<int64_t>(row_off[mid]) <= e0) lo = mid;
-      else hi = mid;
+    const int64_t e0 = t * kTile, e_end = min(m, e0 + kTile);
+    const int32_t r0 = tile_row[t], r1 = tile_row[t + 1];
+    const int64_t lo0 = row_off[r0];  // the first row's start: at or before e0
+    for (int j = 0; j < kSub; ++j) mk_l[j * kWave + lane] = -1;
+    __builtin_amdgcn_wave_barrier();
+    for (int64_t u = static_cast<int64_t>(r0) + 1 + lane; u <= r1; u += kWave) {
+      const int64_t lo = row_off[u];
+      if (lo >= e0 && lo < e_end) atomicMax(&mk_l[lo - e0], static_cast<int32_t>(u));
     }
-    int32_t carry = static_cast<int32_t>(lo);
+    __builtin_amdgcn_wave_barrier();
+    int32_t carry = r0;
     for (int j = 0; j < kSub; ++j) {
       const int64_t e = e0 + j * kWave + lane;
       const bool in = e < m;
-      const int32_t mk = in ? src[e] : -1;
+      const int32_t mk = mk_l[j * kWave + lane];
       int32_t v = mk;  // inclusive max-scan over the wavefront
 #pragma unroll
       for (int off = 1; off < kWave; off <<= 1) {
@@ -126,13 +150,16 @@ __global__ __launch_bounds__(256) void k_edge_pass(int64_t n, int64_t m, const i
       if (in) {
         src[e] = u;
         const int32_t c = col[e];
-        const int32_t prev = (mk >= 0 || e == 0) ? -1 : col[e - 1];  // first edge of its row: no predecessor
+        // first edge of its row (a mark, or the tile's first row starting here): no predecessor
+        const bool row_start = mk >= 0 || e == lo0;
+        const int32_t prev = row_start ? -1 : col[e - 1];
         if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
         else if (!same_graph(u, c, s, part_group, part_valid)) err |= kErrGraphs;
         if (c == u) err |= kErrSelfLoop;
         if (c <= prev) err |= kErrOrder;
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
   if (err) atomicOr(&counters[0], err);
 }
@@ -236,6 +263,39 @@ __device__ int64_t block_excl_scan(int64_t v, int64_t* total) {
   *total = sh[blockDim.x - 1];
   __syncthreads();
   return incl - v;
+}
+
+// Exclusive scan of long arrays (the tile flag counts) in three launches:
+// every workgroup sums kScanSpan values, one workgroup scans the sums
+// (k_scan_excl), every workgroup scans its values from its offset, 1024 at a
+// time with coalesced loads.  out[L] = total.
+constexpr int kScanSpan = 8192;
+__global__ __launch_bounds__(1024) void k_scan_sums(const int32_t* __restrict__ in, int64_t L,
+                                                    int32_t* __restrict__ bsum) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanSpan + threadIdx.x;
+  int64_t sum = 0;
+  for (int j = 0; j < kScanSpan / 1024; ++j) {
+    const int64_t i = base + j * 1024;
+    if (i < L) sum += in[i];
+  }
+  int64_t tot = 0;
+  (void)block_excl_scan(sum, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = static_cast<int32_t>(tot);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* __restrict__ in, int64_t L,
+                                                     const int32_t* __restrict__ boff, int32_t* __restrict__ out) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanSpan + threadIdx.x;
+  int64_t carry = boff[blockIdx.x];
+  for (int j = 0; j < kScanSpan / 1024; ++j) {
+    const int64_t i = base + j * 1024;
+    const int64_t v = i < L ? in[i] : 0;
+    int64_t tot = 0;
+    const int64_t ex = block_excl_scan(v, &tot);
+    if (i < L) out[i] = static_cast<int32_t>(carry + ex);
+    carry += tot;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[L] = static_cast<int32_t>(carry);
 }
 
 // Row prefix over destination partitions: png_off[p][0..k], row totals and the
@@ -449,7 +509,7 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
     cv = col[e0 - 1];
   }
   for (int32_t cb = e0; cb < e1; cb += kFillSets * kWave) {
-    int32_t us[kFillSets], vs[kFillSets];
+    int32_t us[kFillSets], vs[kFillSets], pps[kFillSets];
     float ws[kFillSets];
 #pragma unroll
     for (int t = 0; t < kFillSets; ++t) {
@@ -458,35 +518,49 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
       vs[t] = e < e1 ? col[e] : 0;
       ws[t] = (rw && e < e1) ? weights[e] : 0.0f;
     }
+    // message starts and peer groups of all sets first (independent work,
+    // one ballot per key bit and set), then the cursor updates in order
+    bool firsts[kFillSets];
+    uint64_t peers[kFillSets], bpeers[kFillSets], fmask[kFillSets];
 #pragma unroll
     for (int t = 0; t < kFillSets; ++t) {
-      if (cb + t * kWave >= e1) break;
-      const int32_t e = cb + t * kWave + lane;
-      const bool valid = e < e1;
-      const int32_t u = us[t], v = vs[t];
-      int32_t pu = __shfl_up(u, 1), pv = __shfl_up(v, 1);
+      const bool valid = cb + t * kWave + lane < e1;
+      int32_t pu = __shfl_up(us[t], 1), pv = __shfl_up(vs[t], 1);
       if (lane == 0) {
         pu = cu;
         pv = cv;
       }
-      cu = __builtin_amdgcn_readlane(u, 63);
-      cv = __builtin_amdgcn_readlane(v, 63);
-      const int32_t pp = v >> s;
-      const bool first = valid && (pu != u || (pv >> s) != pp);
-      uint64_t peers = wave_ballot(valid);
-      const uint64_t fmask = wave_ballot(first);
-      for (int b = nbits - 1; b >= bbits; --b) {
-        const bool bit = (pp >> b) & 1;
+      cu = __builtin_amdgcn_readlane(us[t], 63);
+      cv = __builtin_amdgcn_readlane(vs[t], 63);
+      pps[t] = vs[t] >> s;
+      firsts[t] = valid && (pu != us[t] || (pv >> s) != pps[t]);
+      peers[t] = wave_ballot(valid);
+      fmask[t] = wave_ballot(firsts[t]);
+    }
+    for (int b = nbits - 1; b >= bbits; --b) {
+#pragma unroll
+      for (int t = 0; t < kFillSets; ++t) {
+        const bool bit = (pps[t] >> b) & 1;
         const uint64_t bb = wave_ballot(bit);
-        peers &= bit ? bb : ~bb;
+        peers[t] &= bit ? bb : ~bb;
       }
-      const uint64_t bpeers = peers;  // same bucket
-      for (int b = bbits - 1; b >= 0; --b) {
-        const bool bit = (pp >> b) & 1;
+    }
+#pragma unroll
+    for (int t = 0; t < kFillSets; ++t) bpeers[t] = peers[t];  // same bucket
+    for (int b = bbits - 1; b >= 0; --b) {
+#pragma unroll
+      for (int t = 0; t < kFillSets; ++t) {
+        const bool bit = (pps[t] >> b) & 1;
         const uint64_t bb = wave_ballot(bit);
-        peers &= bit ? bb : ~bb;
+        peers[t] &= bit ? bb : ~bb;
       }
-      const uint64_t fpeers = peers & fmask;
+    }
+#pragma unroll
+    for (int t = 0; t < kFillSets; ++t) {
+      if (cb + t * kWave >= e1) break;
+      const bool valid = cb + t * kWave + lane < e1;
+      const int32_t pp = pps[t];
+      const uint64_t fpeers = peers[t] & fmask[t];
       const int32_t hb = pp >> bbits;
       int32_t cd = 0, bc = 0;
       uint32_t cp = 0;
@@ -497,28 +571,28 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
       }
       __builtin_amdgcn_wave_barrier();
       if (valid) {
-        const int32_t ri = bc + __popcll(bpeers & below);
-        uint32_t flags = first ? kDidFlag : 0u;
+        const int32_t ri = bc + __popcll(bpeers[t] & below);
+        uint32_t flags = firsts[t] ? kDidFlag : 0u;
         uint32_t pval = 0;
-        if (first) {
+        if (firsts[t]) {
           const int frank = __popcll(fpeers & below);
           const bool seg_first = (cp & kFlag) && frank == 0;
           // source ID local to the pair's 2q nodes, flag on the pair segment's first node
-          pval = (static_cast<uint32_t>(u) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u);
+          pval = (static_cast<uint32_t>(us[t]) & ((2u << s) - 1u)) | (seg_first ? kDidFlag : 0u);
           rpng[ri] = (cp & kIdMask) + static_cast<uint32_t>(frank);
           // in bin p', the same edge starts the (p', pair) segment of destination IDs
           if (seg_first) flags |= kSegFlag;
         }
-        const uint32_t dval = (static_cast<uint32_t>(v) & lmask) | flags;
-        rec[ri] = static_cast<uint64_t>(static_cast<uint32_t>(cd + __popcll(peers & below))) |
+        const uint32_t dval = (static_cast<uint32_t>(vs[t]) & lmask) | flags;
+        rec[ri] = static_cast<uint64_t>(static_cast<uint32_t>(cd + __popcll(peers[t] & below))) |
                   (static_cast<uint64_t>(dval) << 32) | (static_cast<uint64_t>(pval) << 48);
         if (rw) rw[ri] = ws[t];  // the weight travels with its destination ID (Sec. 3.4)
-        if ((peers & below) == 0) {
-          cur_did[pp] = cd + __popcll(peers);
+        if ((peers[t] & below) == 0) {
+          cur_did[pp] = cd + __popcll(peers[t]);
           const int nf = __popcll(fpeers);
           if (nf) cur_png[pp] = (cp & kIdMask) + static_cast<uint32_t>(nf);
         }
-        if ((bpeers & below) == 0) bcur[hb] = bc + __popcll(bpeers);
+        if ((bpeers[t] & below) == 0) bcur[hb] = bc + __popcll(bpeers[t]);
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -846,20 +920,23 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   // ---- node pass -------------------------------------------------------------
   int32_t* src = nullptr;
   int32_t* counters = nullptr;
+  int32_t* tile_row = nullptr;
+  const int64_t ntiles_e = (m + kTile - 1) / kTile;
   PCPM_TRY(dalloc(g, &g->outdeg, n));
   PCPM_TRY(dalloc(g, &g->dmask, (n + 31) / 32));
   PCPM_TRY(dalloc(g, &src, m));
   PCPM_TRY(dalloc(g, &counters, 4));
+  PCPM_TRY(dalloc(g, &tile_row, ntiles_e + 1));
   PCPM_TRY_HIP(hipMemsetAsync(counters, 0, 16, st));
-  PCPM_TRY_HIP(hipMemsetAsync(src, 0xFF, static_cast<size_t>(std::max<int64_t>(m, 1)) * 4, st));  // -1: no mark
+  PCPM_TRY_HIP(hipMemsetAsync(tile_row, 0, static_cast<size_t>(ntiles_e + 1) * 4, st));
   {
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
     PCPM_LAUNCH("pcpm_build_nodes", k_node_pass, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, n, m,
-                row_off, g->outdeg, g->dmask, src, counters, s, g->part_valid);
-    const int64_t eblocks = std::min<int64_t>(((m + kTile - 1) / kTile + 3) / 4, 65536);
+                row_off, g->outdeg, g->dmask, tile_row, counters, s, g->part_valid);
+    const int64_t eblocks = std::min<int64_t>((ntiles_e + kEdgeBlock / kWave - 1) / (kEdgeBlock / kWave), 65536);
     if (m > 0)
-      PCPM_LAUNCH("pcpm_build_nodes", k_edge_pass, dim3(static_cast<unsigned>(eblocks)), dim3(256), 0, st, n, m,
-                  row_off, col, src, counters, s, g->part_group, g->part_valid);
+      PCPM_LAUNCH("pcpm_build_nodes", k_edge_pass, dim3(static_cast<unsigned>(eblocks)), dim3(kEdgeBlock), 0, st, n,
+                  m, row_off, col, src, tile_row, counters, s, g->part_group, g->part_valid);
   }
   int32_t hc[4] = {0, 0, 0, 0};
   PCPM_TRY_HIP(hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
@@ -1006,7 +1083,9 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   // updates also (bin, pair) segments (bit 14), with bin-ordered updates the
   // pair segments (bit 15) before every tile of PNG edges.
   int32_t* tcnt = nullptr;
+  int32_t* tsum = nullptr;  // per-workgroup sums of the long scans, then their offsets
   PCPM_TRY(dalloc(g, &tcnt, std::max(ntd, ntp) + 1));
+  PCPM_TRY(dalloc(g, &tsum, 2 * ((std::max(ntd, ntp) + kScanSpan - 1) / kScanSpan + 1)));
   PCPM_TRY(dalloc(g, &g->did_blk, ntd + 1));
   if (g->png_order) PCPM_TRY(dalloc(g, &g->did_sblk, ntd + 1));
   else PCPM_TRY(dalloc(g, &g->png_blk, ntp + 1));
@@ -1017,7 +1096,17 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
     if (nt > 0)
       PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags, dim3(static_cast<unsigned>(std::min<int64_t>((nt + 3) / 4, 16384))),
                   dim3(256), 0, st, a, nt, (f == 1 && g->png_order) ? kSegFlag : kDidFlag, tcnt);
-    PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, out, nt);
+    if (nt <= kScanSpan) {
+      PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, out, nt);
+    } else {
+      const int64_t nblk = (nt + kScanSpan - 1) / kScanSpan;
+      int32_t* boff = tsum + nblk + 1;
+      PCPM_LAUNCH("pcpm_build_scan", k_scan_sums, dim3(static_cast<unsigned>(nblk)), dim3(1024), 0, st, tcnt, nt,
+                  tsum);
+      PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tsum, boff, nblk);
+      PCPM_LAUNCH("pcpm_build_scan", k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(1024), 0, st, tcnt, nt,
+                  boff, out);
+    }
   }
 
   // ---- iteration buffers -----------------------------------------------------------
@@ -1053,10 +1142,11 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   for (void* p : {static_cast<void*>(pe_d), static_cast<void*>(chunks_d), static_cast<void*>(cfirst_d),
                   static_cast<void*>(ccnt), static_cast<void*>(craw)})
     dfree(g, p);
-  for (void* p : {static_cast<void*>(src), static_cast<void*>(counters),
+  for (void* p : {static_cast<void*>(src), static_cast<void*>(counters), static_cast<void*>(tile_row),
                   static_cast<void*>(raw), static_cast<void*>(dwo), static_cast<void*>(coltot),
                   static_cast<void*>(coltot_raw), static_cast<void*>(rowtot), static_cast<void*>(rowseg),
-                  static_cast<void*>(segbase), static_cast<void*>(tcnt), static_cast<void*>(cnt)})
+                  static_cast<void*>(segbase), static_cast<void*>(tcnt), static_cast<void*>(tsum),
+                  static_cast<void*>(cnt)})
     dfree(g, p);
   return PCPM_OK;
 }

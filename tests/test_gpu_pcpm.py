@@ -147,6 +147,21 @@ def test_rmat16_twenty_iterations(relabel):
     assert abs(float(res.pr.double().sum()) - 1.0) < 1e-5
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_rmat20_multi_workgroup_tile_scans(order):
+    """RMAT-20 (16.8M edge draws): over 8192 tiles of destination IDs, so the
+    flag prefixes before each tile come from the multi-workgroup scan; exact
+    layout and 20 iterations against the oracle, in both update orders."""
+    r, c = graphgen.rmat(20, 16, seed=4, relabel="random")
+    png = build(r, c, update_order=order)
+    assert len(c) > 8192 * 1024 and png.info["update_order"] == order
+    assert_layout_equal(png, r, c, 14)
+    res = P.pagerank(png, d=0.85, tol=0.0, max_iters=20)
+    o = oracle.pagerank(r, c, d=0.85, iters=20)
+    assert_ranks_close(res.pr.cpu().numpy(), o.x)
+    np.testing.assert_allclose(res.res_hist, o.res_hist, rtol=0.05, atol=2e-7)
+
+
 @pytest.mark.parametrize("part_log2,sc,gc", [(14, 0, 0), (10, 4096, 4096), (12, 0, 65536), (6, 512, 300)])
 def test_to_tolerance_with_split_work(part_log2, sc, gc):
     """Convergence to L1 residual 1e-6; small chunk sizes force split scatter
