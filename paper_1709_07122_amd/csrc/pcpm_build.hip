@@ -454,7 +454,10 @@ __global__ __launch_bounds__(256) void k_segdelta_pairs(int32_t k, const int32_t
 // bits (64 buckets at most).  A bucket's region is the bucket's span of the
 // ID array, so its cursor is the same prefix summed over the bucket's bins,
 // and the records of a bucket lie in CSR order.
-constexpr int kFillSets = 4;  // 64-edge sets whose loads are issued together
+#ifndef PCPM_FILL_SETS
+#define PCPM_FILL_SETS 4
+#endif
+constexpr int kFillSets = PCPM_FILL_SETS;  // 64-edge sets whose loads are issued together
 #ifndef PCPM_FILL_BUCKETS
 #define PCPM_FILL_BUCKETS 64
 #endif
@@ -508,15 +511,33 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
     cu = src[e0 - 1];
     cv = col[e0 - 1];
   }
+  // the next batch's loads are in flight while a batch is processed
+  int32_t nu[kFillSets], nv[kFillSets];
+  float nw[kFillSets];
+#pragma unroll
+  for (int t = 0; t < kFillSets; ++t) {
+    const int32_t e = e0 + t * kWave + lane;
+    nu[t] = e < e1 ? src[e] : 0;
+    nv[t] = e < e1 ? col[e] : 0;
+    nw[t] = (rw && e < e1) ? weights[e] : 0.0f;
+  }
   for (int32_t cb = e0; cb < e1; cb += kFillSets * kWave) {
     int32_t us[kFillSets], vs[kFillSets], pps[kFillSets];
     float ws[kFillSets];
 #pragma unroll
     for (int t = 0; t < kFillSets; ++t) {
-      const int32_t e = cb + t * kWave + lane;
-      us[t] = e < e1 ? src[e] : 0;
-      vs[t] = e < e1 ? col[e] : 0;
-      ws[t] = (rw && e < e1) ? weights[e] : 0.0f;
+      us[t] = nu[t];
+      vs[t] = nv[t];
+      ws[t] = nw[t];
+    }
+    if (cb + kFillSets * kWave < e1) {
+#pragma unroll
+      for (int t = 0; t < kFillSets; ++t) {
+        const int32_t e = cb + (kFillSets + t) * kWave + lane;
+        nu[t] = e < e1 ? src[e] : 0;
+        nv[t] = e < e1 ? col[e] : 0;
+        nw[t] = (rw && e < e1) ? weights[e] : 0.0f;
+      }
     }
     // message starts and peer groups of all sets first (independent work,
     // one ballot per key bit and set), then the cursor updates in order
