@@ -20,6 +20,9 @@ Everything here is FP64 and follows the paper's definitions directly:
                  graphs): y(v) = sum over edges u->v of w(u,v) x(u).
 * ``bin_weights`` edge weights in the order of the destination-ID bins, where
                  Sec. 3.4 stores them.
+* ``relabel``    a degree-ordered node labelling and the relabelled CSR
+                 (Sec. 5.3.1, Table 6: the compression ratio r, and with it
+                 the traffic of Sec. 4, rises with a locality-aware labelling).
 * ``mlp``        FP64 reference of the warm-start network (see ``oracle.mlp``).
 """
 from __future__ import annotations
@@ -113,7 +116,8 @@ def pagerank(row_off, col, d=0.85, iters=20, tol=0.0, tele=None, x0=None, thread
     hist = np.zeros(max(iters, 1), dtype=np.float64)
     it = np.zeros(1, dtype=np.int32)
     spi = np.zeros(1, dtype=np.float64)
-    rc = lib.orc_pagerank(n, _p(row_off), _p(_col(col)), float(d), _p(tele), _p(x0), int(iters),
+    colc = _col(col)  # held here: a temporary's buffer could be freed before the call
+    rc = lib.orc_pagerank(n, _p(row_off), _p(colc), float(d), _p(tele), _p(x0), int(iters),
                           float(tol), _threads(threads), _p(x), _p(hist), _p(it), _p(spi))
     if rc < 0:
         raise ValueError("oracle rejected its input")
@@ -131,7 +135,8 @@ def step_at(row_off, col, x, nodes, d=0.85, tele=None, threads=None) -> np.ndarr
     if len(x) != n:
         raise ValueError("x must have n entries")
     out = np.empty(len(nodes), dtype=np.float64)
-    rc = lib.orc_step_at(n, _p(row_off), _p(_col(col)), float(d), _p(tele), _p(x), _p(nodes) if len(nodes) else None,
+    colc = _col(col)  # held here: a temporary's buffer could be freed before the call
+    rc = lib.orc_step_at(n, _p(row_off), _p(colc), float(d), _p(tele), _p(x), _p(nodes) if len(nodes) else None,
                          len(nodes), _threads(threads), _p(out))
     if rc < 0:
         raise ValueError("oracle rejected its input")
@@ -235,3 +240,29 @@ def bin_weights(row_off, col, weights, q: int) -> np.ndarray:
     order = np.lexsort((col, src, src // q, col // q))
     return np.asarray(weights)[order]
 
+
+def relabel(row_off, col, key: str = "in"):
+    """Degree-ordered relabelling (Sec. 5.3.1, Table 6: a labelling that puts
+    related nodes close raises r).  New label i goes to the node of i-th
+    largest in-degree (``key="in"``) or out-degree (``key="out"``), equal
+    degrees in increasing old ID.  Returns (perm, row_off2, col2): perm[old]
+    = new label; the relabelled CSR holds edge perm[u] -> perm[v] for every
+    edge u -> v, rows in ascending column order."""
+    row_off = np.asarray(row_off, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    n = len(row_off) - 1
+    if key == "in":
+        deg = np.bincount(col, minlength=n)
+    elif key == "out":
+        deg = np.diff(row_off)
+    else:
+        raise ValueError(f"unknown key {key!r}")
+    order = np.lexsort((np.arange(n), -deg))  # largest degree first, then old ID
+    perm = np.empty(n, dtype=np.int64)
+    perm[order] = np.arange(n)
+    nu = perm[_sources(row_off)]
+    nv = perm[col]
+    idx = np.lexsort((nv, nu))
+    row_off2 = np.zeros(n + 1, dtype=np.int64)
+    row_off2[1:] = np.cumsum(np.bincount(nu, minlength=n))
+    return perm, row_off2, nv[idx]
