@@ -171,6 +171,26 @@ pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x /* (device) n */, float* y 
                         void* stream);
 
 /*
+ * Degree-ordered relabelling of a CSR graph (Sec. 5.3.1 and Table 6: a node
+ * labelling with more locality raises the compression ratio r of the PNG,
+ * and with it lowers the traffic of Sec. 4).  New label i goes to the node of
+ * i-th largest degree -- in-degree for key 0, out-degree for key 1 -- with
+ * equal degrees in increasing old ID.  Outputs (device, caller-owned):
+ * perm[old] = new label (n), and the relabelled CSR row_off_out (n + 1),
+ * col_out (m): edge perm[u] -> perm[v] for every input edge u -> v, every row
+ * in ascending column order.  Input: row_off (n + 1) non-decreasing from 0
+ * to m, col (m) in [0, n) (PCPM_ERR_GRAPH otherwise); row order, self-loops
+ * and duplicates are not checked and are carried over (pcpm_build_png
+ * rejects them).  Outputs must not overlap inputs or each other.  Allocates
+ * about 16 max(n, m) + m/4 bytes of device memory for the call.  Synchronises
+ * `stream`.
+ */
+pcpm_status_t pcpm_relabel(int64_t n, int64_t m, const int32_t* row_off /* (device) n+1 */,
+                           const int32_t* col /* (device) m */, int32_t key,
+                           int32_t* perm /* (device) n */, int32_t* row_off_out /* (device) n+1 */,
+                           int32_t* col_out /* (device) m */, void* stream);
+
+/*
  * One PageRank iteration (Eq. 1, Sec. 2.1) carried out as PCPM scatter
  * (Alg. 3 over the PNG), gather (Alg. 5, branch-free) and apply (Alg. 2):
  *   pr_out(v) = (1-d)/n + d * ( sum_{u->v} pr_in(u)/outdeg(u) + D/n )

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpcpm.so")
-SOURCES = ["pcpm_runtime.hip", "pcpm_build.hip", "pcpm_iter.hip", "pcpm_ppr.hip", "pcpm_ws.hip"]
+SOURCES = ["pcpm_runtime.hip", "pcpm_build.hip", "pcpm_iter.hip", "pcpm_ppr.hip", "pcpm_ws.hip", "pcpm_relabel.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

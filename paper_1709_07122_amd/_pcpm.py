@@ -34,7 +34,7 @@ EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free"
            "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_last_error",
            "pcpm_timing_enable", "pcpm_timing_collect", "pcpm_ws_features", "pcpm_ws_forward", "pcpm_ws_init",
            "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_adam", "pcpm_ws_targets", "pcpm_spmv",
-           "pcpm_png_export_weights"]
+           "pcpm_png_export_weights", "pcpm_relabel"]
 
 WS_FEATURES = 8
 WS_HIDDEN = 64
@@ -91,6 +91,8 @@ def lib():
     L.pcpm_png_export_weights.argtypes = [vp, vp]
     L.pcpm_spmv.restype = ctypes.c_int
     L.pcpm_spmv.argtypes = [vp, vp, vp, vp]
+    L.pcpm_relabel.restype = ctypes.c_int
+    L.pcpm_relabel.argtypes = [i64, i64, vp, vp, i32, vp, vp, vp, vp]
     L.pcpm_iterate.restype = ctypes.c_int
     L.pcpm_iterate.argtypes = [vp, dbl, vp, vp, ctypes.POINTER(dbl), vp]
     L.pcpm_pagerank.restype = ctypes.c_int
@@ -260,6 +262,30 @@ def spmv(png: PNG, x, out=None, stream=None):
     yp = _dev_tensor(out, torch.float32, n, "out")
     _check(lib().pcpm_spmv(png.handle, xp, yp, _stream(stream)))
     return out
+
+
+RELABEL_KEYS = {"in": 0, "out": 1}
+
+
+def relabel(row_off, col, key: str = "in", stream=None):
+    """pcpm_relabel: degree-ordered labelling (largest in- or out-degree
+    first, ties by old ID).  row_off (n+1) and col (m) are device int32
+    tensors; returns device int32 tensors (perm, row_off_out, col_out) with
+    perm[old] = new label and the relabelled CSR."""
+    import torch
+    if key not in RELABEL_KEYS:
+        raise ValueError(f"key must be one of {sorted(RELABEL_KEYS)}")
+    n = row_off.numel() - 1
+    m = col.numel()
+    rp = _dev_tensor(row_off, torch.int32, n + 1, "row_off")
+    cp = _dev_tensor(col, torch.int32, m, "col") if m else ctypes.c_void_p(None)
+    perm = torch.empty(n, dtype=torch.int32, device=row_off.device)
+    ro2 = torch.empty(n + 1, dtype=torch.int32, device=row_off.device)
+    c2 = torch.empty(max(m, 1), dtype=torch.int32, device=row_off.device)[:m]
+    _check(lib().pcpm_relabel(n, m, rp, cp, RELABEL_KEYS[key], ctypes.c_void_p(perm.data_ptr()),
+                              ctypes.c_void_p(ro2.data_ptr()),
+                              ctypes.c_void_p(c2.data_ptr()) if m else ctypes.c_void_p(None), _stream(stream)))
+    return perm, ro2, c2
 
 
 def square_csr(row_off, col, cols: int):

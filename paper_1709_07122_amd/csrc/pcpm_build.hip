@@ -747,6 +747,24 @@ pcpm_status_t set_lds_limits() {
   return PCPM_OK;
 }
 
+// Exclusive scan of L int32 values: out[0..L), out[L] = total (in == out is
+// allowed).  One workgroup up to kScanSpan values, else three launches;
+// tmp holds scan_tmp_ints(L) ints.
+int64_t scan_tmp_ints(int64_t L) { return 2 * ((L + kScanSpan - 1) / kScanSpan + 1); }
+
+pcpm_status_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t L, int32_t* tmp, hipStream_t st) {
+  if (L <= kScanSpan) {
+    PCPM_LAUNCH("pcpm_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, in, out, L);
+    return PCPM_OK;
+  }
+  const int64_t nblk = (L + kScanSpan - 1) / kScanSpan;
+  int32_t* boff = tmp + nblk + 1;
+  PCPM_LAUNCH("pcpm_scan", k_scan_sums, dim3(static_cast<unsigned>(nblk)), dim3(1024), 0, st, in, L, tmp);
+  PCPM_LAUNCH("pcpm_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tmp, boff, nblk);
+  PCPM_LAUNCH("pcpm_scan", k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(1024), 0, st, in, L, boff, out);
+  return PCPM_OK;
+}
+
 pcpm_status_t iter_lds_limits();  // pcpm_iter.hip
 
 static bool is_device_ptr(const void* p) {
@@ -1106,7 +1124,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   int32_t* tcnt = nullptr;
   int32_t* tsum = nullptr;  // per-workgroup sums of the long scans, then their offsets
   PCPM_TRY(dalloc(g, &tcnt, std::max(ntd, ntp) + 1));
-  PCPM_TRY(dalloc(g, &tsum, 2 * ((std::max(ntd, ntp) + kScanSpan - 1) / kScanSpan + 1)));
+  PCPM_TRY(dalloc(g, &tsum, scan_tmp_ints(std::max(ntd, ntp))));
   PCPM_TRY(dalloc(g, &g->did_blk, ntd + 1));
   if (g->png_order) PCPM_TRY(dalloc(g, &g->did_sblk, ntd + 1));
   else PCPM_TRY(dalloc(g, &g->png_blk, ntp + 1));
@@ -1117,17 +1135,7 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
     if (nt > 0)
       PCPM_LAUNCH("pcpm_build_tiles", k_tile_flags, dim3(static_cast<unsigned>(std::min<int64_t>((nt + 3) / 4, 16384))),
                   dim3(256), 0, st, a, nt, (f == 1 && g->png_order) ? kSegFlag : kDidFlag, tcnt);
-    if (nt <= kScanSpan) {
-      PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tcnt, out, nt);
-    } else {
-      const int64_t nblk = (nt + kScanSpan - 1) / kScanSpan;
-      int32_t* boff = tsum + nblk + 1;
-      PCPM_LAUNCH("pcpm_build_scan", k_scan_sums, dim3(static_cast<unsigned>(nblk)), dim3(1024), 0, st, tcnt, nt,
-                  tsum);
-      PCPM_LAUNCH("pcpm_build_scan", k_scan_excl, dim3(1), dim3(1024), 0, st, tsum, boff, nblk);
-      PCPM_LAUNCH("pcpm_build_scan", k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(1024), 0, st, tcnt, nt,
-                  boff, out);
-    }
+    PCPM_TRY(scan_excl_i32(tcnt, out, nt, tsum, st));
   }
 
   // ---- iteration buffers -----------------------------------------------------------

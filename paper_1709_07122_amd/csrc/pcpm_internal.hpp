@@ -309,4 +309,8 @@ pcpm_status_t dalloc(pcpm_png* g, T** p, int64_t count) {
 void dfree(pcpm_png* g, void* p);
 void free_handle(pcpm_png* g);
 pcpm_status_t set_lds_limits();
+// Exclusive scan of L int32 values into out[0..L] (out[L] = total) on st;
+// tmp holds scan_tmp_ints(L) ints (pcpm_build.hip).
+int64_t scan_tmp_ints(int64_t L);
+pcpm_status_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t L, int32_t* tmp, hipStream_t st);
 }  // namespace pcpm
