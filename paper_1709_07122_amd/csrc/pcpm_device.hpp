@@ -76,4 +76,18 @@ struct FixedConv {
   }
 };
 
+// Sum of the cnt fixed-point values base[c * stride], c = 0..cnt-1, with
+// eight loads in flight (the partial slices of a split bin).  Integer
+// addition modulo 2^64, so the result does not depend on the grouping.
+__device__ __forceinline__ int64_t sum_slices(const int64_t* __restrict__ base, int cnt, int64_t stride) {
+  uint64_t s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (; c + 8 <= cnt; c += 8) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += static_cast<uint64_t>(base[static_cast<int64_t>(c + j) * stride]);
+  }
+  for (; c < cnt; ++c) s[0] += static_cast<uint64_t>(base[static_cast<int64_t>(c) * stride]);
+  return static_cast<int64_t>(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
+}
+
 }  // namespace pcpm

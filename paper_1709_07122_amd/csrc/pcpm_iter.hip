@@ -338,11 +338,7 @@ __global__ __launch_bounds__(BS) void k_merge(const Ctl* __restrict__ ctl, int64
   const int qn = static_cast<int>(min(q, n - v0));
   const int64_t* base = partial + static_cast<int64_t>(mu.first) * q;
   const int cnt = mu.count;
-  auto acc = [&](int i) {
-    int64_t sum = 0;
-    for (int c = 0; c < cnt; ++c) sum += base[static_cast<int64_t>(c) * q + i];
-    return sum;
-  };
+  auto acc = [&](int i) { return sum_slices(base + i, cnt, q); };
   apply_nodes<BS>(ctl, gctl, part_group, part_valid, mu.part, v0, mu.node_lo, min(qn, mu.node_lo + kMergeNodes),
                   acc, pr_in, pr_out, dmask, red + 3 * (red_base + blockIdx.x));
 }
@@ -429,8 +425,7 @@ __global__ __launch_bounds__(kMergeNodes) void k_spmv_merge(const Ctl* __restric
   const int i = mu.node_lo + static_cast<int>(threadIdx.x);
   if (i >= qn) return;
   const int64_t* base = partial + static_cast<int64_t>(mu.first) * q;
-  int64_t sum = 0;
-  for (int c = 0; c < mu.count; ++c) sum += base[static_cast<int64_t>(c) * q + i];
+  const int64_t sum = sum_slices(base + i, mu.count, q);
   y[v0 + i] = ctl->nonfinite ? __builtin_nanf("")
                              : static_cast<float>(static_cast<double>(sum) * ldexp(1.0, -ctl->fx_shift));
 }

@@ -318,9 +318,7 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__
   const int64_t* base = partial + static_cast<int64_t>(mu.first) * q * KT;
   const int cnt = mu.count;
   auto acc = [&](int nd, int vec) {  // partial slices are [KT][q]
-    int64_t sum = 0;
-    for (int c = 0; c < cnt; ++c) sum += base[static_cast<int64_t>(c) * q * KT + static_cast<int64_t>(vec) * q + nd];
-    return sum;
+    return sum_slices(base + static_cast<int64_t>(vec) * q + nd, cnt, q * KT);
   };
   apply_ppr<KT, kPprBlock>(ctl, vctl, v0, mu.node_lo, min(qn, mu.node_lo + 256), acc, x_in, x_out, dmask, seedmask,
                            red + (red_base + blockIdx.x) * KT * 3);
