@@ -362,6 +362,22 @@ __device__ __forceinline__ void group_sums(const int32_t* __restrict__ group_slo
     for (int c = 0; c < 3; ++c) s[c] += __shfl_xor(s[c], off);
 }
 
+// The same sums over the whole workgroup (for few groups): a fixed strided
+// assignment and a fixed reduction order, so the result is reproducible;
+// valid in thread 0.
+__device__ __forceinline__ void group_sums_block(const int32_t* __restrict__ group_slots,
+                                                 const double* __restrict__ red, int64_t k, int grp,
+                                                 double (&s)[3]) {
+  s[0] = s[1] = s[2] = 0.0;
+  const int p0 = group_slots[2 * grp], p1 = group_slots[2 * grp + 2];
+  for (int j = p0 + static_cast<int>(threadIdx.x); j < p1; j += 1024)
+    for (int c = 0; c < 3; ++c) s[c] += red[3 * j + c];
+  const int u0 = group_slots[2 * grp + 1], u1 = group_slots[2 * grp + 3];
+  for (int j = u0 + static_cast<int>(threadIdx.x); j < u1; j += 1024)
+    for (int c = 0; c < 3; ++c) s[c] += red[3 * (k + j) + c];
+  block_sum<1024, 3>(s);
+}
+
 // End of an iteration: per-group residual, next dangling mass and base, group
 // convergence; then the largest residual, the iteration count and the flag
 // that makes the kernels of later iterations return at once.
@@ -378,19 +394,29 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* 
   __syncthreads();
   const int G = ctl->ngroups;
   const double d = ctl->d, tol = ctl->tol;
-  for (int grp = threadIdx.x / kWave; grp < G; grp += 1024 / kWave) {
-    double sm[3];
-    group_sums(group_slots, red, k, grp, true, sm);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-      GCtl& gc = gctl[grp];
-      if (!gc.done) {
-        gc.res = sm[0];
-        gc.iter += 1;
-        gc.dmass = sm[1];
-        gc.base = (1.0 - d) * gc.inv_n + d * sm[1] * gc.inv_n;
-        if (!isfinite(sm[0]) || !isfinite(sm[1])) atomicOr(&bad, 1);
-        else if (tol > 0.0 && sm[0] < tol) gc.done = 1;
-      }
+  auto update = [&](int grp, const double (&sm)[3]) {
+    GCtl& gc = gctl[grp];
+    if (!gc.done) {
+      gc.res = sm[0];
+      gc.iter += 1;
+      gc.dmass = sm[1];
+      gc.base = (1.0 - d) * gc.inv_n + d * sm[1] * gc.inv_n;
+      if (!isfinite(sm[0]) || !isfinite(sm[1])) atomicOr(&bad, 1);
+      else if (tol > 0.0 && sm[0] < tol) gc.done = 1;
+    }
+  };
+  if (G < 1024 / kWave) {  // few groups: the whole workgroup sums each one
+    for (int grp = 0; grp < G; ++grp) {
+      double sm[3];
+      group_sums_block(group_slots, red, k, grp, sm);
+      if (threadIdx.x == 0) update(grp, sm);
+      __syncthreads();
+    }
+  } else {  // one wavefront per group
+    for (int grp = threadIdx.x / kWave; grp < G; grp += 1024 / kWave) {
+      double sm[3];
+      group_sums(group_slots, red, k, grp, true, sm);
+      if ((threadIdx.x & (kWave - 1)) == 0) update(grp, sm);
     }
   }
   __syncthreads();
