@@ -603,7 +603,7 @@ static pcpm_status_t ppr_iteration(pcpm_png* g, const float* in, float* out, flo
 }
 
 // Working set for tiles of kt vectors (kept in the handle, grown on demand).
-static pcpm_status_t ppr_alloc(pcpm_png* g, int kt, int64_t nseeds, int k, hipStream_t st) {
+static pcpm_status_t ppr_alloc(pcpm_png* g, int kt, int64_t nseeds, int k) {
   if (g->ppr_kt < kt) {
     for (void* p : {static_cast<void*>(g->ppr_x[0]), static_cast<void*>(g->ppr_x[1]),
                     static_cast<void*>(g->ppr_upd), static_cast<void*>(g->ppr_partial),
@@ -756,7 +756,7 @@ pcpm_status_t pcpm_ppr_batch(pcpm_png_t g, double d, int32_t k, const int32_t* s
   int kt = 1;
   while (kt < k && kt < kt_max) kt <<= 1;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  PCPM_TRY(ppr_alloc(g, kt, seed_off[k], k, st));
+  PCPM_TRY(ppr_alloc(g, kt, seed_off[k], k));
   PCPM_TRY_HIP(hipMemcpyAsync(g->ppr_seeds, seeds, static_cast<size_t>(seed_off[k]) * 4, hipMemcpyHostToDevice, st));
   PCPM_TRY_HIP(hipMemcpyAsync(g->ppr_seed_off, seed_off, static_cast<size_t>(k + 1) * 4, hipMemcpyHostToDevice, st));
   bool conv = true, bad = false;
