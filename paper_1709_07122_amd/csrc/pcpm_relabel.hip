@@ -6,7 +6,8 @@
 // Pipeline (caller's stream):
 //   nodes      offset checks, out-degrees, the row of every 1024-edge tile's
 //              first edge
-//   columns    range check, in-degrees (global atomics)
+//   columns    range check; in-degrees as run lengths of the sorted columns
+//              (a 32-bit radix sort: no atomics)
 //   node sort  keys (maxdeg - deg) << idbits | id, LSD radix sort over the
 //              degree bits only: the IDs are already in order, so equal
 //              degrees keep increasing old ID
@@ -57,7 +58,8 @@ __device__ int32_t block256_excl_scan(int32_t v, int32_t* wtot /* kRsWaves */) {
   return before + x - v;
 }
 
-__global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t L, int shift,
+template <class K>
+__global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K* __restrict__ keys, int64_t L, int shift,
                                                       int64_t nblk, int32_t* __restrict__ hist) {
   __shared__ int32_t h[kRsDigits];
   h[threadIdx.x] = 0;
@@ -74,10 +76,11 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint64_t* __restrict
 
 // off: exclusive scan of the digit-major histogram (keys of smaller digits,
 // then of the same digit in earlier tiles).
-__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+template <class K>
+__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const K* __restrict__ in, K* __restrict__ out,
                                                          int64_t L, int shift, int64_t nblk,
                                                          const int32_t* __restrict__ off) {
-  __shared__ uint64_t sk[kRsTile];              // the tile in digit order
+  __shared__ K sk[kRsTile];                     // the tile in digit order
   __shared__ int32_t lstart[kRsDigits];         // tile-local start of each digit
   __shared__ int32_t cur[kRsDigits];            // next tile-local slot of each digit
   __shared__ int32_t cnt[kRsWaves][kRsDigits];  // keys of each digit in a wavefront's 64
@@ -90,11 +93,11 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restr
 #pragma unroll
   for (int i = 0; i < kRsWaves; ++i) cnt[i][tid] = 0;
   __syncthreads();
-  uint64_t k[kRsPer];
+  K k[kRsPer];
 #pragma unroll
   for (int j = 0; j < kRsPer; ++j) {
     const int64_t i = t0 + static_cast<int64_t>(j) * kRsBlock + tid;
-    k[j] = i < L ? in[i] : 0;
+    k[j] = i < L ? in[i] : K{0};
     if (i < L) atomicAdd(&cur[(k[j] >> shift) & (kRsDigits - 1)], 1);
   }
   __syncthreads();
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint64_t* __restr
   for (int j = 0; j < kRsPer; ++j) {
     const int i = j * kRsBlock + tid;
     if (i < nvalid) {
-      const uint64_t key = sk[i];
+      const K key = sk[i];
       const int d = static_cast<int>((key >> shift) & (kRsDigits - 1));
       out[static_cast<int64_t>(off[static_cast<int64_t>(d) * nblk + blockIdx.x]) + (i - lstart[d])] = key;
     }
@@ -168,17 +171,37 @@ __global__ __launch_bounds__(256) void k_rl_nodes(int64_t n, int64_t m, const in
   if (err) atomicOr(flags, err);
 }
 
-// Column range check; in-degrees when indeg is given.
+// Column range check; a copy of the columns as sort keys when ckeys is given.
 __global__ __launch_bounds__(256) void k_rl_cols(int64_t n, int64_t m, const int32_t* __restrict__ col,
-                                                 int32_t* __restrict__ indeg, int32_t* __restrict__ flags) {
+                                                 uint32_t* __restrict__ ckeys, int32_t* __restrict__ flags) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   int32_t err = 0;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m; e += stride) {
     const int32_t c = col[e];
     if (c < 0 || static_cast<int64_t>(c) >= n) err = kRlErrRange;
-    else if (indeg) atomicAdd(&indeg[c], 1);
+    if (ckeys) ckeys[e] = static_cast<uint32_t>(c);
   }
   if (err) atomicOr(flags, err);
+}
+
+// In-degrees from the sorted columns: node v's entries are one run, whose
+// first and last index are stored by the entries at the run's two ends
+// (rstart and rend start at 0, so a node without in-edges gets 0).
+__global__ __launch_bounds__(256) void k_rl_runs(int64_t m, const uint32_t* __restrict__ sc,
+                                                 int32_t* __restrict__ rstart, int32_t* __restrict__ rend) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint32_t v = sc[i];
+    if (i == 0 || sc[i - 1] != v) rstart[v] = static_cast<int32_t>(i);
+    if (i == m - 1 || sc[i + 1] != v) rend[v] = static_cast<int32_t>(i + 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rl_indeg(int64_t n, const int32_t* __restrict__ rstart,
+                                                  int32_t* __restrict__ rend_indeg) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n; v += stride)
+    rend_indeg[v] -= rstart[v];
 }
 
 __global__ __launch_bounds__(256) void k_rl_max(int64_t n, const int32_t* __restrict__ deg, int32_t* __restrict__ mx) {
@@ -285,14 +308,15 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = 65536) {
 
 // Stable LSD sort of a[0..L) by bits [lo, hi); b is the second buffer.
 // *result is the buffer holding the sorted keys.
-pcpm_status_t radix_sort(uint64_t* a, uint64_t* b, int64_t L, int lo, int hi, int32_t* hist, int32_t* tmp,
-                         hipStream_t st, uint64_t** result) {
+template <class K>
+pcpm_status_t radix_sort(K* a, K* b, int64_t L, int lo, int hi, int32_t* hist, int32_t* tmp, hipStream_t st,
+                         K** result) {
   const int64_t nblk = (L + kRsTile - 1) / kRsTile;
   for (int shift = lo; shift < hi && L > 0; shift += kRsBits) {
-    PCPM_LAUNCH("pcpm_relabel_sort", k_rs_hist, dim3(static_cast<unsigned>(nblk)), dim3(kRsBlock), 0, st, a, L,
+    PCPM_LAUNCH("pcpm_relabel_sort", k_rs_hist<K>, dim3(static_cast<unsigned>(nblk)), dim3(kRsBlock), 0, st, a, L,
                 shift, nblk, hist);
     PCPM_TRY(scan_excl_i32(hist, hist, kRsDigits * nblk, tmp, st));
-    PCPM_LAUNCH("pcpm_relabel_sort", k_rs_scatter, dim3(static_cast<unsigned>(nblk)), dim3(kRsBlock), 0, st, a, b,
+    PCPM_LAUNCH("pcpm_relabel_sort", k_rs_scatter<K>, dim3(static_cast<unsigned>(nblk)), dim3(kRsBlock), 0, st, a, b,
                 L, shift, nblk, hist);
     std::swap(a, b);
   }
@@ -343,44 +367,63 @@ extern "C" pcpm_status_t pcpm_relabel(int64_t n, int64_t m, const int32_t* row_o
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   Scratch sc;
+  int idbits = 1;
+  while ((int64_t{1} << idbits) < n) ++idbits;
+  const uint64_t idmask = (uint64_t{1} << idbits) - 1;
   const int64_t ntiles = (m + kTile - 1) / kTile;
-  int32_t *outdeg, *indeg = nullptr, *tile_row, *flags, *newdeg, *tmp;
+  const int64_t nk = std::max(n, m);
+  const int64_t nh = kRsDigits * ((nk + kRsTile - 1) / kRsTile) + 1;
+  int32_t *outdeg, *indeg = nullptr, *rstart = nullptr, *tile_row, *flags, *newdeg, *tmp, *hist;
+  uint64_t *ka, *kb, *sorted;
   PCPM_TRY(sc.get(&outdeg, n));
   PCPM_TRY(sc.get(&tile_row, ntiles + 1));
   PCPM_TRY(sc.get(&flags, 2));
   PCPM_TRY(sc.get(&newdeg, n));
-  if (key == 0) PCPM_TRY(sc.get(&indeg, n));
+  PCPM_TRY(sc.get(&ka, nk));
+  PCPM_TRY(sc.get(&kb, nk));
+  PCPM_TRY(sc.get(&hist, nh));
+  PCPM_TRY(sc.get(&tmp, scan_tmp_ints(std::max(nh, n))));
+  if (key == 0) {
+    PCPM_TRY(sc.get(&indeg, n));
+    PCPM_TRY(sc.get(&rstart, n));
+  }
+  // in-degrees: the columns (as 32-bit keys in the first key buffer) sorted,
+  // then each node's run length
+  uint32_t* ca = key == 0 && m > 0 ? reinterpret_cast<uint32_t*>(ka) : nullptr;
+  uint32_t* cb = reinterpret_cast<uint32_t*>(kb);
   PCPM_TRY_HIP(hipMemsetAsync(flags, 0, 8, st));
   PCPM_TRY_HIP(hipMemsetAsync(tile_row, 0, static_cast<size_t>(ntiles + 1) * 4, st));
-  if (indeg) PCPM_TRY_HIP(hipMemsetAsync(indeg, 0, static_cast<size_t>(n) * 4, st));
   PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_nodes, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, m, row_off,
               outdeg, tile_row, flags);
   if (m > 0)
-    PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_cols, dim3(grid_for(m, 256 * 16, 8192)), dim3(256), 0, st, n, m, col,
-                indeg, flags);
-  const int32_t* deg = indeg ? indeg : outdeg;
-  PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_max, dim3(grid_for(n, 256 * 16, 4096)), dim3(256), 0, st, n, deg,
-              flags + 1);
+    PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_cols, dim3(grid_for(m, 256 * 16, 8192)), dim3(256), 0, st, n, m, col, ca,
+                flags);
   int32_t hf[2] = {0, 0};
   PCPM_TRY_HIP(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, st));
   PCPM_TRY_HIP(hipStreamSynchronize(st));
   if (hf[0] & kRlErrOffsets) return set_error(PCPM_ERR_GRAPH, "invalid CSR: row offsets");
   if (hf[0] & kRlErrRange) return set_error(PCPM_ERR_GRAPH, "invalid CSR: column index outside [0, n)");
+  if (indeg) {
+    PCPM_TRY_HIP(hipMemsetAsync(indeg, 0, static_cast<size_t>(n) * 4, st));
+    PCPM_TRY_HIP(hipMemsetAsync(rstart, 0, static_cast<size_t>(n) * 4, st));
+    if (m > 0) {
+      uint32_t* sc_sorted = nullptr;
+      PCPM_TRY(radix_sort<uint32_t>(ca, cb, m, 0, idbits, hist, tmp, st, &sc_sorted));
+      PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_runs, dim3(grid_for(m, 256 * 16, 8192)), dim3(256), 0, st, m, sc_sorted,
+                  rstart, indeg);
+      PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_indeg, dim3(grid_for(n, 256 * 4, 8192)), dim3(256), 0, st, n, rstart,
+                  indeg);
+    }
+  }
+  const int32_t* deg = indeg ? indeg : outdeg;
+  PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_max, dim3(grid_for(n, 256 * 16, 4096)), dim3(256), 0, st, n, deg,
+              flags + 1);
+  PCPM_TRY_HIP(hipMemcpyAsync(hf, flags, 8, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
   const int32_t maxdeg = hf[1];
-  int idbits = 1;
-  while ((int64_t{1} << idbits) < n) ++idbits;
   int degbits = 0;
   while ((int64_t{1} << degbits) <= maxdeg) ++degbits;
-  const uint64_t idmask = (uint64_t{1} << idbits) - 1;
 
-  const int64_t nk = std::max(n, m);
-  uint64_t *ka, *kb, *sorted;
-  int32_t* hist;
-  const int64_t nh = kRsDigits * ((nk + kRsTile - 1) / kRsTile) + 1;
-  PCPM_TRY(sc.get(&ka, nk));
-  PCPM_TRY(sc.get(&kb, nk));
-  PCPM_TRY(sc.get(&hist, nh));
-  PCPM_TRY(sc.get(&tmp, scan_tmp_ints(std::max(nh, n))));
   // nodes: largest degree first, equal degrees in old-ID order
   PCPM_LAUNCH("pcpm_relabel_nodes", k_rl_node_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, n, deg, maxdeg, idbits,
               ka);
