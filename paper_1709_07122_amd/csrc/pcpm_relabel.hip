@@ -16,7 +16,7 @@
 //              per tile), LSD radix sort over 2 idbits bits: rows in new
 //              order, columns ascending
 //
-// The radix sort is stable and 8 bits per pass: a histogram per 4096-key
+// The radix sort is stable and 8 bits per pass: a histogram per 2048-key
 // tile (digit-major, so one exclusive scan gives every tile's start in
 // every digit), then each tile ranks its keys in LDS (one ballot per digit
 // bit gives the lanes of a wavefront with the same digit; per-wavefront
@@ -34,7 +34,10 @@ namespace pcpm {
 namespace {
 
 constexpr int kRsBlock = 256;                 // threads per radix workgroup (= digits)
-constexpr int kRsPer = 16;                    // keys per thread
+#ifndef PCPM_RS_PER
+#define PCPM_RS_PER 8
+#endif
+constexpr int kRsPer = PCPM_RS_PER;           // keys per thread
 constexpr int kRsTile = kRsBlock * kRsPer;    // keys per workgroup
 constexpr int kRsBits = 8;
 constexpr int kRsDigits = 1 << kRsBits;
