@@ -182,7 +182,7 @@ pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x /* (device) n */, float* y 
  * to m, col (m) in [0, n) (PCPM_ERR_GRAPH otherwise); row order, self-loops
  * and duplicates are not checked and are carried over (pcpm_build_png
  * rejects them).  Outputs must not overlap inputs or each other.  Allocates
- * about 16 max(n, m) + m/4 bytes of device memory for the call.  Synchronises
+ * about 16.5 max(n, m) + 16 n bytes of device memory for the call.  Synchronises
  * `stream`.
  */
 pcpm_status_t pcpm_relabel(int64_t n, int64_t m, const int32_t* row_off /* (device) n+1 */,
