@@ -66,6 +66,25 @@ def test_weighted_spmv_matches_oracle(scale, relabel, part_log2):
     png.close()
 
 
+@pytest.mark.parametrize("part_log2,chunk,order", [(8, 64, 1), (10, 333, 2), (6, 1, 1), (12, 5000, 2)])
+def test_weights_and_layout_with_small_build_chunks(part_log2, chunk, order):
+    """Many build chunks per source partition (down to one edge each): the
+    fill's per-chunk cursors place IDs, PNG sources and weights exactly."""
+    r, c = graphgen.rmat(12, 16, seed=21, relabel="indegree")
+    n = len(r) - 1
+    rng = np.random.default_rng(chunk)
+    w = rng.standard_normal(len(c)).astype(np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=part_log2, build_chunk=chunk, weights=dev(w), update_order=order)
+    got = png.export()
+    want = oracle.png_layout(r, c, 1 << part_log2)
+    for key in ("png_off", "upd_start", "wo", "did_start", "png_src", "did"):
+        np.testing.assert_array_equal(got[key], getattr(want, key))
+    np.testing.assert_array_equal(png.export_weights(), oracle.bin_weights(r, c, w, 1 << part_log2))
+    check(P.spmv(png, dev(x)).cpu().numpy(), r, c, x, w)
+    png.close()
+
+
 @pytest.mark.parametrize("graph", ["split_bins", "ragged"])
 def test_split_bins_and_ragged_tail(graph):
     if graph == "split_bins":  # generator labels: hub partitions, bins split over several items
