@@ -160,8 +160,9 @@ void pcpm_png_free(pcpm_png_t g);
  * past R and y past C is zero.
  * Accuracy: each product w*x(u) is formed exactly in FP64 and rounded to a
  * multiple of 2^-s, s = min(50 - ceil(log2(max|w| max|x|)), 62 -
- * ceil(log2(W max|x|))) with W the largest sum over v of |w(u,v)| (a
- * build-time statistic); the sum is exact (64-bit integers, independent of
+ * ceil(log2(W max|x|))) with W the largest sum over v of |w(u,v)| (computed
+ * once per handle: by the build when it has weights, by the first call
+ * otherwise, on `stream`); the sum is exact (64-bit integers, independent of
  * order: y is bit-reproducible), then rounded once to FP32.  So |y(v) -
  * exact| <= indeg(v) 2^-(s+1) + FP32 rounding of y(v).  If x holds a
  * non-finite value, y is NaN everywhere.  Asynchronous on `stream`.

@@ -765,6 +765,22 @@ pcpm_status_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t L, int32_t*
   return PCPM_OK;
 }
 
+pcpm_status_t weight_stats(pcpm_png* g, hipStream_t st) {
+  if (!g->wstats) PCPM_TRY(dalloc(g, &g->wstats, 3));
+  PCPM_TRY_HIP(hipMemsetAsync(g->wstats, 0, 3 * sizeof(unsigned long long), st));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_w_stats),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g->q * 8)));
+  if (g->n_ga)
+    PCPM_LAUNCH("pcpm_wstats", k_w_stats, dim3(static_cast<unsigned>(g->n_ga)), dim3(1024),
+                static_cast<size_t>(g->q * 8), st, g->n, g->part_log2, g->ga_items, g->did, g->wbin, g->partial,
+                g->wstats);
+  if (g->n_mg)
+    PCPM_LAUNCH("pcpm_wstats", k_w_stats_merge, dim3(static_cast<unsigned>(g->n_mg)), dim3(256), 0, st, g->n,
+                g->part_log2, g->mg_items, g->partial, g->wstats);
+  g->wstats_ready = true;
+  return PCPM_OK;
+}
+
 pcpm_status_t iter_lds_limits();  // pcpm_iter.hip
 
 static bool is_device_ptr(const void* p) {
@@ -1147,24 +1163,15 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(build_items(g, opts, st));
 
   // ---- weight statistics (scale of pcpm_spmv) -----------------------------------
-  unsigned long long* wst = nullptr;
-  PCPM_TRY(dalloc(g, &wst, 3));
-  PCPM_TRY_HIP(hipMemsetAsync(wst, 0, 3 * sizeof(unsigned long long), st));
-  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_w_stats),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g->q * 8)));
-  if (g->n_ga)
-    PCPM_LAUNCH("pcpm_build_wstats", k_w_stats, dim3(static_cast<unsigned>(g->n_ga)), dim3(1024),
-                static_cast<size_t>(g->q * 8), st, n, s, g->ga_items, g->did, g->wbin, g->partial, wst);
-  if (g->n_mg)
-    PCPM_LAUNCH("pcpm_build_wstats", k_w_stats_merge, dim3(static_cast<unsigned>(g->n_mg)), dim3(256), 0, st, n, s,
-                g->mg_items, g->partial, wst);
-  unsigned long long wst_h[3] = {0, 0, 0};
-  PCPM_TRY_HIP(hipMemcpyAsync(wst_h, wst, sizeof(wst_h), hipMemcpyDeviceToHost, st));
-  PCPM_TRY_HIP(hipStreamSynchronize(st));
-  dfree(g, wst);
-  if (wst_h[2]) return set_error(PCPM_ERR_INVALID_ARG, "weights hold %llu non-finite values", wst_h[2]);
-  std::memcpy(&g->w_colmax, &wst_h[0], 8);
-  std::memcpy(&g->w_absmax, &wst_h[1], 8);
+  // weighted handles: now, to reject non-finite weights; unweighted ones on
+  // their first pcpm_spmv (PageRank does not use them)
+  if (g->wbin) {
+    PCPM_TRY(weight_stats(g, st));
+    unsigned long long bad = 0;
+    PCPM_TRY_HIP(hipMemcpyAsync(&bad, g->wstats + 2, sizeof(bad), hipMemcpyDeviceToHost, st));
+    PCPM_TRY_HIP(hipStreamSynchronize(st));
+    if (bad) return set_error(PCPM_ERR_INVALID_ARG, "weights hold %llu non-finite values", bad);
+  }
 
   // ---- release build-only buffers ------------------------------------------------
   PCPM_TRY_HIP(hipStreamSynchronize(st));

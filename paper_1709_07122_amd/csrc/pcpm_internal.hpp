@@ -226,8 +226,12 @@ struct pcpm_png {
   uint16_t* did = nullptr;      // ceil(m/kTile)*kTile: v - p'q, bit 15 = first of message, bit 14 = first of segment
   int32_t* did_sblk = nullptr;  // segment flags before each tile, ceil(m/kTile)+1
   float* wbin = nullptr;        // m edge weights in bin order (weighted handles only)
-  double w_absmax = 0.0;        // max |w| (1 if unweighted, 0 without edges)
-  double w_colmax = 0.0;        // max over v of sum_{u->v} |w(u,v)|
+  // weight statistics of the SpMV scale, as bit patterns of non-negative
+  // doubles: max over v of sum_{u->v} |w(u,v)|, max |w| (1 if unweighted, 0
+  // without edges), then the count of non-finite weights; computed at build
+  // for weighted handles, on the first pcpm_spmv for unweighted ones
+  unsigned long long* wstats = nullptr;
+  bool wstats_ready = false;
   float* spmv_blockmax = nullptr;  // per-block max |x| of pcpm_spmv
   int32_t* did_blk = nullptr;   // flags before each tile, ceil(m/kTile)+1
   int32_t* did_start = nullptr; // k+1
@@ -312,5 +316,7 @@ pcpm_status_t set_lds_limits();
 // Exclusive scan of L int32 values into out[0..L] (out[L] = total) on st;
 // tmp holds scan_tmp_ints(L) ints (pcpm_build.hip).
 int64_t scan_tmp_ints(int64_t L);
+// Queue the weight statistics into g->wstats on st (pcpm_build.hip).
+pcpm_status_t weight_stats(pcpm_png* g, hipStream_t st);
 pcpm_status_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t L, int32_t* tmp, hipStream_t st);
 }  // namespace pcpm

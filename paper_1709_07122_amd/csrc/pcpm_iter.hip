@@ -475,7 +475,9 @@ __global__ __launch_bounds__(256) void k_spmv_absmax(const float* __restrict__ x
 // wabs * max|x| (kept below 2^50 units) and every sum, partial or whole, at
 // most wcol * max|x| (kept below 2^62 units).
 __global__ __launch_bounds__(1024) void k_spmv_scale(Ctl* __restrict__ ctl, const float* __restrict__ blockmax,
-                                                      int nb, double wabs, double wcol) {
+                                                      int nb, const unsigned long long* __restrict__ wstats) {
+  const double wcol = __longlong_as_double(static_cast<long long>(wstats[0]));
+  const double wabs = __longlong_as_double(static_cast<long long>(wstats[1]));
   double m = 0.0;
   for (int b = threadIdx.x; b < nb; b += 1024) m = fmax(m, static_cast<double>(blockmax[b]));
   m = block_max<1024>(m);
@@ -728,8 +730,8 @@ pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x, float* y, void* stream) {
   if (!g->spmv_blockmax) PCPM_TRY(dalloc(g, &g->spmv_blockmax, kMaxBlocks));
   const int nb = static_cast<int>(std::min<int64_t>((g->n + 255) / 256, kMaxBlocks));
   PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_absmax, dim3(nb), dim3(256), 0, st, x, g->n, g->spmv_blockmax);
-  PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_scale, dim3(1), dim3(1024), 0, st, g->ctl, g->spmv_blockmax, nb, g->w_absmax,
-              g->w_colmax);
+  if (!g->wstats_ready) PCPM_TRY(weight_stats(g, st));  // unweighted handle, first call
+  PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_scale, dim3(1), dim3(1024), 0, st, g->ctl, g->spmv_blockmax, nb, g->wstats);
   if (g->wbin)
     PCPM_TRY((scatter_gather<false, 2>(g, x, y, "pcpm_spmv_scatter", "pcpm_spmv_gather", st)));
   else
