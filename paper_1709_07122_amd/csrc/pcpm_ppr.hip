@@ -25,15 +25,25 @@ constexpr int kPprBlock = 512;          // merge workgroups
 constexpr int kPprScatterBlock = 1024;  // scatter workgroups (a pair's slice takes up to 128 KB of LDS)
 constexpr int kPprGatherBlock = 1024;  // gather workgroups (a 128 KB slice leaves room for one per CU)
 
-template <int KT>
+// Copy of a slot's KT values; kNt: non-temporal stores (the PNG-ordered
+// update stream, one contiguous run per tile: the batch ran ~5% faster on
+// RMAT-22 with them).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int KT, bool kNt = false>
 __device__ __forceinline__ void copy_kt(float* __restrict__ dst, const float* __restrict__ src) {
   if constexpr (KT % 4 == 0) {
 #pragma unroll
-    for (int c = 0; c < KT; c += 4)
-      *reinterpret_cast<float4*>(dst + c) = *reinterpret_cast<const float4*>(src + c);
+    for (int c = 0; c < KT; c += 4) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(src + c);
+      if constexpr (kNt) __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + c));
+      else *reinterpret_cast<f32x4*>(dst + c) = v;
+    }
   } else {
 #pragma unroll
-    for (int c = 0; c < KT; ++c) dst[c] = src[c];
+    for (int c = 0; c < KT; ++c) {
+      if constexpr (kNt) __builtin_nontemporal_store(src[c], dst + c);
+      else dst[c] = src[c];
+    }
   }
 }
 
@@ -79,12 +89,12 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
         float* ut = upd + tb * KT;
 #pragma unroll
         for (int j = 0; j < kSub; ++j)
-          copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane) * KT, spr + (xs[j] & qmask) * KT);
+          copy_kt<KT, true>(ut + static_cast<int64_t>(j * kWave + lane) * KT, spr + (xs[j] & qmask) * KT);
       } else {
 #pragma unroll
         for (int j = 0; j < kSub; ++j) {
           const int64_t e = tb + j * kWave + lane;
-          if (e >= lo && e < hi) copy_kt<KT>(upd + e * KT, spr + (xs[j] & qmask) * KT);
+          if (e >= lo && e < hi) copy_kt<KT, true>(upd + e * KT, spr + (xs[j] & qmask) * KT);
         }
       }
     } else {
