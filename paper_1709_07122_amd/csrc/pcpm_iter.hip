@@ -99,7 +99,7 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
         mx = fmaxf(mx, fabsf(xn));
         sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
         if ((dw[u] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
-        pr_out[v] = xn;
+        __builtin_nontemporal_store(xn, pr_out + v);  // read by the next scatter, not this kernel
       }
     }
   }
@@ -318,7 +318,9 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
     const double unit = ldexp(1.0, -ctl->fx_shift);
     const bool bad = ctl->nonfinite != 0;
     for (int i = threadIdx.x; i < qn; i += BS)
-      pr_out[v0 + i] = bad ? __builtin_nanf("") : static_cast<float>(static_cast<double>(static_cast<int64_t>(acc[i])) * unit);
+      __builtin_nontemporal_store(
+          bad ? __builtin_nanf("") : static_cast<float>(static_cast<double>(static_cast<int64_t>(acc[i])) * unit),
+          pr_out + v0 + i);
     return;
   }
   apply_nodes<BS>(ctl, gctl, part_group, part_valid, it.part, v0, 0, qn,
@@ -454,8 +456,9 @@ __global__ __launch_bounds__(kMergeNodes) void k_spmv_merge(const Ctl* __restric
   if (i >= qn) return;
   const int64_t* base = partial + static_cast<int64_t>(mu.first) * q;
   const int64_t sum = sum_slices(base + i, mu.count, q);
-  y[v0 + i] = ctl->nonfinite ? __builtin_nanf("")
-                             : static_cast<float>(static_cast<double>(sum) * ldexp(1.0, -ctl->fx_shift));
+  __builtin_nontemporal_store(
+      ctl->nonfinite ? __builtin_nanf("") : static_cast<float>(static_cast<double>(sum) * ldexp(1.0, -ctl->fx_shift)),
+      y + v0 + i);
 }
 
 // Largest |x| per workgroup (+inf if x holds a non-finite value).
