@@ -8,8 +8,8 @@ arithmetic -- features, forward, backward, Adam -- runs in the library's
 kernels.  Python only draws the graphs and the random minibatch indices.
 
 Plain uniform initialisation stays both the fallback (non-finite
-prediction) and the judge: every warm solve is still certified by the FP64
-residual of pcpm_pagerank.
+prediction) and the reference the warm start is measured against; every
+warm solve is still certified by the FP64 residual of pcpm_pagerank.
 
 Command line:
   python -m paper_1709_07122_amd.warmstart train --graphs 200 --out weights.npy

@@ -85,7 +85,7 @@ def test_in_star_closed_form(n):
     bound = d * res.resid / (1 - d) + 1e-15
     assert abs(x[0] - xc) <= bound
     assert np.max(np.abs(x[1:] - xl)) <= bound
-    if n == 5:  # the numbers the survey tabulates
+    if n == 5:  # the closed form's values at n = 5, d = 0.85
         assert round(xc, 7) == 0.5238095 and round(xl, 7) == 0.1190476
 
 
