@@ -5,7 +5,8 @@ Methodology of Lakhotia, Kannan and Prasanna (arXiv 1709.07122) as
 hand-written HIP kernels.  This package only marshals arguments; PyTorch
 provides device memory and streams.
 """
-from ._pcpm import (EXPORTS, LIB_PATH, PCPM_ERR_GRAPH, PCPM_ERR_INVALID_ARG, PCPM_ERR_NOT_CONVERGED,
+from ._pcpm import (EXPORTS, LIB_PATH, PCPM_ERR_DEVICE, PCPM_ERR_GRAPH, PCPM_ERR_INVALID_ARG,
+                    PCPM_ERR_NOT_CONVERGED, PCPM_ERR_OOM,
                     PCPM_ERR_NUMERIC, PCPM_ERR_OVERFLOW, PCPM_OK, PNG, PCPMError, PagerankResult, build_png,
                     WS_FEATURES, WS_HIDDEN, WS_PARAMS, iterate, last_error, lib, pagerank, ppr_batch, ppr_tile_width,
                     relabel, spmv, square_csr, timing_collect, timing_enable, union_csr, ws_adam, ws_backward, ws_features,
@@ -16,5 +17,5 @@ __all__ = ["EXPORTS", "LIB_PATH", "PNG", "PCPMError", "PagerankResult", "build_p
            "last_error", "lib", "relabel", "spmv", "square_csr", "timing_enable", "timing_collect", "union_csr", "autotune", "commmodel", "warmstart",
            "ws_features", "ws_forward", "ws_init", "ws_backward", "ws_adam", "ws_targets", "WS_FEATURES",
            "WS_HIDDEN", "WS_PARAMS", "PCPM_OK",
-           "PCPM_ERR_GRAPH", "PCPM_ERR_INVALID_ARG", "PCPM_ERR_NOT_CONVERGED", "PCPM_ERR_NUMERIC",
+           "PCPM_ERR_DEVICE", "PCPM_ERR_GRAPH", "PCPM_ERR_INVALID_ARG", "PCPM_ERR_NOT_CONVERGED", "PCPM_ERR_NUMERIC", "PCPM_ERR_OOM",
            "PCPM_ERR_OVERFLOW"]
