@@ -10,13 +10,19 @@ graph are resident in HBM before the timed region starts.  The same graph with
 in-degree-sorted labels (relabelled on the GPU by pcpm_relabel, whose time is
 reported) is measured as well and reported under "indegree".
 
+The timed region holds the solves only; per-kernel averages (and the
+roofline figure taken from them) come from a separate pass of solves with a
+HIP event pair around every launch.
+
 Further legs (in "detail"): the sparse matrix-vector product over the PNG
-with random edge weights on the main graph (Sec. 3.4), the learned warm
+with random edge weights on the main graph (Sec. 3.5), the learned warm
 start against the uniform start
 on the main graph (network weights shipped with the package, trained on other
 RMAT graphs), batched personalised PageRank on RMAT-22 with 8/32/64 seed sets
-against one vector at a time, and 16 RMAT graphs of uneven size in one handle
-against one handle per graph.
+against one vector at a time, 16 RMAT graphs of uneven size in one handle
+against one handle per graph, and the paper's scale of graph (RMAT-26 EF 24
+with 1.58B edges, and a uniform graph of 50M nodes and 1B edge draws) for
+20 iterations each, as in the paper's Table 5 protocol.
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
@@ -83,41 +89,57 @@ def relabel_detail(P, torch, r, c, reps=3):
     return ri, ci, rl_ms
 
 
-def measure(P, torch, r, c, args, label):
-    """Build the PNG, warm up, then time `steps` solves with per-kernel events."""
+def measure(P, torch, r, c, args, label, tol=None, max_iters=None, update_order=None):
+    """Build the PNG, warm up, time `steps` solves with nothing but the solves
+    in the timed region, then run a separate pass of solves with per-launch
+    HIP events for the per-kernel averages."""
     from paper_1709_07122_amd import commmodel as cm
 
+    tol = solve_tol(args) if tol is None else tol
+    max_iters = solve_iters(args) if max_iters is None else max_iters
+    update_order = args.update_order if update_order is None else update_order
     n, m = len(r) - 1, len(c)
     rt = torch.from_numpy(r).cuda()
     ct = torch.from_numpy(c).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    png = P.build_png(rt, ct, part_log2=args.part_log2, update_order=args.update_order)
+    png = P.build_png(rt, ct, part_log2=args.part_log2, update_order=update_order)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    del rt, ct
     info = png.info
     out = torch.empty(n, dtype=torch.float32, device="cuda")
     for _ in range(args.warmup):
-        P.pagerank(png, d=args.d, tol=solve_tol(args), max_iters=solve_iters(args), out=out, want_hist=False)
+        P.pagerank(png, d=args.d, tol=tol, max_iters=max_iters, out=out, want_hist=False)
     log(f"[{label}] n={n} m={m} q={info['q']} k={info['k']} E'={info['eprime']} "
         f"r={m / max(info['eprime'], 1):.3f} updates in {'PNG' if info['update_order'] == 2 else 'bin'} order "
         f"build={build_s * 1e3:.1f} ms")
 
-    P.timing_enable(True)
+    # timed region: the solves only (no per-launch events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, step_s = [], []
     for _ in range(args.steps):
         ts = time.perf_counter()
-        res = P.pagerank(png, d=args.d, tol=solve_tol(args), max_iters=solve_iters(args), out=out, want_hist=False)
+        res = P.pagerank(png, d=args.d, tol=tol, max_iters=max_iters, out=out, want_hist=False)
         torch.cuda.synchronize()
         step_s.append(time.perf_counter() - ts)
         iters.append(res.iters)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    total_s = time.perf_counter() - t0
+
+    # separate pass for the per-kernel table: events around every launch
+    ev_steps = max(2, args.steps // 4)
+    P.timing_enable(True)
+    te = time.perf_counter()
+    ev_iters = 0
+    for _ in range(ev_steps):
+        ev_iters += P.pagerank(png, d=args.d, tol=tol, max_iters=max_iters, out=out, want_hist=False).iters
+    torch.cuda.synchronize()
+    ev_ms = (time.perf_counter() - te) / ev_steps * 1e3
     P.timing_enable(False)
     kt = P.timing_collect()
-    total_s = t1 - t0
+
     tot_iters = sum(iters)
     sec_per_iter = total_s / tot_iters
     eprime, nseg = info["eprime"], info["nseg"]
@@ -127,6 +149,9 @@ def measure(P, torch, r, c, args, label):
     s_bytes = cm.scatter_bytes(n, eprime, nseg, png_order=png_order)
     it_bytes = g_bytes + s_bytes
     eq5 = cm.pcpm_comm(n, m, info["k"], m / max(eprime, 1))
+    kern_iter_ms = sum(v[1] for name, v in kt.items() if name != "pcpm_init") / max(ev_iters, 1)
+    g_ms = kernels.get("pcpm_gather", {"avg_ms": float("nan")})["avg_ms"]
+    s_ms = kernels.get("pcpm_scatter", {"avg_ms": float("nan")})["avg_ms"]
     result = {
         "n": n, "m": m, "q": info["q"], "k": info["k"], "eprime": eprime, "r": m / max(eprime, 1),
         "iters": iters[-1], "ms_per_step": total_s / args.steps * 1e3, "ms_per_iter": sec_per_iter * 1e3,
@@ -134,21 +159,51 @@ def measure(P, torch, r, c, args, label):
         "ms_per_step_median": sorted(step_s)[len(step_s) // 2] * 1e3,
         "gteps_median": m * iters[-1] / sorted(step_s)[len(step_s) // 2] / 1e9,
         "alg_bytes_per_iter": it_bytes, "alg_bytes_per_edge": it_bytes / m, "eq5_bytes_per_edge": eq5 / m,
-        "hbm_gbs_alg": it_bytes / sec_per_iter / 1e9, "build_ms": build_s * 1e3,
-        "kernels": kernels, "gather_bytes": g_bytes, "scatter_bytes": s_bytes,
+        "hbm_gbs_alg": it_bytes / sec_per_iter / 1e9,
+        "iteration_frac_of_peak": it_bytes / sec_per_iter / 1e9 / HBM_PEAK_GBS,
+        "build_ms": build_s * 1e3,
+        "kernels": kernels, "kernel_pass": {"solves": ev_steps, "ms_per_step_with_events": ev_ms,
+                                            "kernel_ms_per_iter": kern_iter_ms},
+        "gather_bytes": g_bytes, "scatter_bytes": s_bytes,
+        "gather_frac_of_peak": g_bytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "scatter_frac_of_peak": s_bytes / (s_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "update_order": "png" if png_order else "bin",
         "split_bins": info["split_bins"], "gather_items": info["gather_items"],
         "scatter_items": info["scatter_items"],
     }
     log(f"[{label}] iters={iters} {result['ms_per_step']:.3f} ms/solve, {result['gteps']:.1f} GTEPS, "
-        f"{result['hbm_gbs_alg']:.0f} GB/s (algorithmic)")
+        f"{result['hbm_gbs_alg']:.0f} GB/s (algorithmic, {result['iteration_frac_of_peak']:.3f} of peak); "
+        f"with events {ev_ms:.3f} ms/solve")
     for k, v in sorted(kernels.items()):
         log(f"    {k:16s} launches={v['launches']:5d} avg={v['avg_ms'] * 1e3:9.1f} us")
     return result, out.cpu().numpy(), png
 
 
+def paper_scale_detail(P, torch, args, kind):
+    """The paper's protocol on its scale of graph: 20 iterations from the
+    uniform start, q = 16384, automatic update order (Table 5's GTEPS =
+    edges / one iteration's time)."""
+    import graphgen
+
+    t = time.perf_counter()
+    if kind == "rmat26":
+        r, c = graphgen.rmat(26, 24, seed=3, relabel="random")
+        name = "RMAT scale 26, edge factor 24 (a,b,c=.57,.19,.19, seed 3), random node labels"
+    else:
+        r, c = graphgen.uniform(50_000_000, 1_000_000_000, seed=4)
+        name = "uniform random directed graph, 50M nodes, 1B edge draws (seed 4)"
+    log(f"generated {kind}: n={len(r) - 1} m={len(c)} in {time.perf_counter() - t:.1f} s")
+    res, _, png = measure(P, torch, r, c, args, kind, tol=0.0, max_iters=20, update_order=0)
+    png.close()
+    del r, c
+    torch.cuda.empty_cache()
+    res["graph"] = name
+    res["protocol"] = "20 iterations from the uniform start, q = 16384"
+    return res
+
+
 def spmv_detail(P, torch, r, c, args, reps=20):
-    """SpMV over the PNG (Sec. 3.4) on the main graph with seeded random edge
+    """SpMV over the PNG (Sec. 3.5) on the main graph with seeded random edge
     weights (uniform in [-1, 1)) and x uniform in [-1, 1): per-kernel event
     times of `reps` calls, the weighted gather against the HBM roofline, and
     y against the FP64 oracle within the bound of pcpm_spmv."""
@@ -411,6 +466,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the personalised and multi-graph legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start leg")
     ap.add_argument("--no-spmv", action="store_true", help="skip the weighted SpMV leg")
+    ap.add_argument("--no-paper-scale", action="store_true",
+                    help="skip the 20-iteration legs on RMAT-26 EF24 and the uniform 50M/1B graph")
     ap.add_argument("--update-order", type=int, default=0, choices=(0, 1, 2),
                     help="storage order of the updates: 0 automatic, 1 bin order, 2 PNG order")
     ap.add_argument("--ppr-seed", type=int, default=5)
@@ -472,6 +529,9 @@ def main():
     if not args.no_batched:
         detail["ppr"] = ppr_detail(P, torch, args)
         detail["multigraph"] = multigraph_detail(P, torch, args)
+    if not args.no_paper_scale and args.graph == "rmat" and args.scale < 26:
+        detail["rmat26"] = paper_scale_detail(P, torch, args, "rmat26")
+        detail["uniform"] = paper_scale_detail(P, torch, args, "uniform")
 
     cpu = None
     if not args.no_cpu_baseline:

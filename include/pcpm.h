@@ -74,7 +74,7 @@ typedef struct {
   const float* weights;  /* (device) m edge weights in CSR order (weights[e]
                             belongs to the edge row -> col[e]), finite, any
                             sign; NULL = unweighted.  Stored next to the
-                            destination IDs in bin order (Sec. 3.4) and read
+                            destination IDs in bin order (Sec. 3.5) and read
                             by pcpm_spmv only: PageRank always scales by
                             1/outdeg.  The caller keeps ownership.           */
   int64_t update_order;  /* storage order of the updates: 1 = bin order (the
@@ -137,7 +137,7 @@ pcpm_status_t pcpm_png_export(pcpm_png_t g, int64_t* png_off, int32_t* png_src,
                               int64_t* upd_start, int64_t* wo, int64_t* did_start,
                               uint32_t* did);
 
-/* The build's edge weights in destination-ID bin order (Sec. 3.4): w[e]
+/* The build's edge weights in destination-ID bin order (Sec. 3.5): w[e]
  * (host, m floats) is the weight of the edge whose destination ID is did[e]
  * of pcpm_png_export.  PCPM_ERR_INVALID_ARG if the handle is unweighted.
  * Synchronises the device. */
@@ -147,7 +147,7 @@ pcpm_status_t pcpm_png_export_weights(pcpm_png_t g, float* w /* (host) m */);
 void pcpm_png_free(pcpm_png_t g);
 
 /*
- * Sparse matrix-vector product over the PNG (Sec. 3.4, the extension of PCPM
+ * Sparse matrix-vector product over the PNG (Sec. 3.5, the extension of PCPM
  * to weighted graphs and SpMV):
  *   y(v) = sum over edges u->v of w(u,v) * x(u)
  * with w the build's weights (1 on every edge of an unweighted handle), i.e.
@@ -198,7 +198,11 @@ pcpm_status_t pcpm_relabel(int64_t n, int64_t m, const int32_t* row_off /* (devi
  * with D the FP64 sum of pr_in over dangling nodes (their mass is spread
  * uniformly).  pr_in and pr_out (n floats each) must not overlap.  If resid
  * is non-NULL the FP64 L1 distance sum_v |pr_out(v) - pr_in(v)| is written
- * there and the call synchronises `stream`.  0 <= d < 1.
+ * there and the call synchronises `stream`; a non-finite value in pr_in then
+ * returns PCPM_ERR_NUMERIC.  With resid NULL the call does not synchronise,
+ * and a non-finite pr_in makes pr_out NaN everywhere.  pr_in may hold any
+ * finite values (the fixed-point scale of the gather follows its largest
+ * value and its L1 mass).  0 <= d < 1.
  */
 pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr_out,
                            double* resid /* (host) nullable */, void* stream);
@@ -215,8 +219,9 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
  * For a handle of G > 1 graphs every graph runs Eq. 1 with its own n_g
  * (1/n_g start, jump and dangling spread on its own nodes, 0 on padding);
  * a graph whose residual falls below tol keeps that iterate while the others
- * go on; *iters and *resid are the largest over graphs, res_hist is graph 0's,
- * and pcpm_graph_results gives every graph's.
+ * go on; *iters and *resid are the largest over graphs, res_hist[i] is the
+ * largest residual over graphs in iteration i (a graph that has converged
+ * contributes its last residual), and pcpm_graph_results gives every graph's.
  */
 pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iters,
                             const float* init /* nullable */, float* pr_out,

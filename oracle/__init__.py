@@ -16,10 +16,10 @@ Everything here is FP64 and follows the paper's definitions directly:
                  scatter, Alg. 5 gather, Alg. 2 apply).
 * ``step_at``    one step of Eq. 1 from a given vector, at chosen nodes only
                  (for checks on graphs too large for full runs).
-* ``spmv``       the sparse matrix-vector product of Sec. 3.4 (weighted
+* ``spmv``       the sparse matrix-vector product of Sec. 3.5 (weighted
                  graphs): y(v) = sum over edges u->v of w(u,v) x(u).
 * ``bin_weights`` edge weights in the order of the destination-ID bins, where
-                 Sec. 3.4 stores them.
+                 Sec. 3.5 stores them.
 * ``relabel``    a degree-ordered node labelling and the relabelled CSR
                  (Sec. 5.3.1, Table 6: the compression ratio r, and with it
                  the traffic of Sec. 4, rises with a locality-aware labelling).
@@ -59,6 +59,11 @@ def _load():
     lib.orc_pagerank.restype = ctypes.c_int
     lib.orc_pagerank.argtypes = [i64, vp, vp, ctypes.c_double, vp, vp, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
+    lib.orc_pagerank_csc.restype = ctypes.c_int
+    lib.orc_pagerank_csc.argtypes = [i64, vp, vp, vp, ctypes.c_double, vp, vp, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
+    lib.orc_transpose_into.restype = ctypes.c_int
+    lib.orc_transpose_into.argtypes = [i64, vp, vp, vp, vp]
     lib.orc_png_sizes.restype = ctypes.c_int
     lib.orc_png_sizes.argtypes = [i64, vp, vp, i64, vp, vp]
     lib.orc_png_layout.restype = ctypes.c_int
@@ -103,10 +108,32 @@ class Result:
         return float(self.res_hist[self.iters - 1]) if self.iters else float("nan")
 
 
-def pagerank(row_off, col, d=0.85, iters=20, tol=0.0, tele=None, x0=None, threads=None) -> Result:
+class Transposed:
+    """The transposed adjacency of a CSR graph (in-neighbour lists, sources
+    ascending), formed once for many oracle runs on the same graph."""
+
+    def __init__(self, row_off, col):
+        lib = _load()
+        self.row_off = np.ascontiguousarray(row_off, dtype=np.int32)
+        n = len(self.row_off) - 1
+        m = int(self.row_off[-1])
+        colc = _col(col)
+        self.in_off = np.empty(n + 2, dtype=np.int64)
+        self.in_src = np.empty(max(m, 1), dtype=np.int32)
+        if lib.orc_transpose_into(n, _p(self.row_off), _p(colc), _p(self.in_off), _p(self.in_src)) != 0:
+            raise ValueError("oracle rejected its input")
+
+
+def transpose(row_off, col) -> Transposed:
+    return Transposed(row_off, col)
+
+
+def pagerank(row_off, col, d=0.85, iters=20, tol=0.0, tele=None, x0=None, threads=None,
+             transposed: Transposed | None = None) -> Result:
     """FP64 PageRank of Eq. 1.  ``tol > 0`` stops at the first iteration whose
     L1 residual is below ``tol`` (at most ``iters``); otherwise runs exactly
-    ``iters`` iterations."""
+    ``iters`` iterations.  ``transposed`` (from ``transpose(row_off, col)``)
+    skips forming the in-neighbour lists again."""
     lib = _load()
     row_off = np.ascontiguousarray(row_off, dtype=np.int32)
     n = len(row_off) - 1
@@ -116,9 +143,16 @@ def pagerank(row_off, col, d=0.85, iters=20, tol=0.0, tele=None, x0=None, thread
     hist = np.zeros(max(iters, 1), dtype=np.float64)
     it = np.zeros(1, dtype=np.int32)
     spi = np.zeros(1, dtype=np.float64)
-    colc = _col(col)  # held here: a temporary's buffer could be freed before the call
-    rc = lib.orc_pagerank(n, _p(row_off), _p(colc), float(d), _p(tele), _p(x0), int(iters),
-                          float(tol), _threads(threads), _p(x), _p(hist), _p(it), _p(spi))
+    if transposed is not None:
+        if not np.array_equal(transposed.row_off, row_off):
+            raise ValueError("transposed adjacency of another graph")
+        rc = lib.orc_pagerank_csc(n, _p(row_off), _p(transposed.in_off), _p(transposed.in_src), float(d),
+                                  _p(tele), _p(x0), int(iters), float(tol), _threads(threads), _p(x), _p(hist),
+                                  _p(it), _p(spi))
+    else:
+        colc = _col(col)  # held here: a temporary's buffer could be freed before the call
+        rc = lib.orc_pagerank(n, _p(row_off), _p(colc), float(d), _p(tele), _p(x0), int(iters),
+                              float(tol), _threads(threads), _p(x), _p(hist), _p(it), _p(spi))
     if rc < 0:
         raise ValueError("oracle rejected its input")
     return Result(x, int(it[0]), hist[: int(it[0])], rc == 0, float(spi[0]))
@@ -151,13 +185,15 @@ def teleport_from_seeds(n, seeds) -> np.ndarray:
     return t
 
 
-def ppr(row_off, col, seeds, d=0.85, iters=100, tol=0.0, threads=None) -> Result:
+def ppr(row_off, col, seeds, d=0.85, iters=100, tol=0.0, threads=None,
+        transposed: Transposed | None = None) -> Result:
     """Personalised PageRank: the recurrence of Eq. 1 with the uniform jump
     and the dangling redistribution both replaced by t = uniform on ``seeds``;
     starts from x_0 = t."""
     n = len(row_off) - 1
     t = teleport_from_seeds(n, seeds)
-    return pagerank(row_off, col, d=d, iters=iters, tol=tol, tele=t, x0=t, threads=threads)
+    return pagerank(row_off, col, d=d, iters=iters, tol=tol, tele=t, x0=t, threads=threads,
+                    transposed=transposed)
 
 
 class PNG:
@@ -220,7 +256,7 @@ def _sources(row_off) -> np.ndarray:
 
 
 def spmv(row_off, col, x, weights=None) -> np.ndarray:
-    """Sec. 3.4: y(v) = sum over edges u->v of w(u,v) * x(u) in FP64, with
+    """Sec. 3.5: y(v) = sum over edges u->v of w(u,v) * x(u) in FP64, with
     w = 1 on every edge when ``weights`` is None (weights[e] belongs to the
     CSR edge row -> col[e]); that is y = A^T x for the CSR matrix A."""
     n = len(row_off) - 1
@@ -231,7 +267,7 @@ def spmv(row_off, col, x, weights=None) -> np.ndarray:
 
 
 def bin_weights(row_off, col, weights, q: int) -> np.ndarray:
-    """Sec. 3.4: each weight is stored next to its destination ID, so the
+    """Sec. 3.5: each weight is stored next to its destination ID, so the
     weights follow the canonical order of the destination-ID bins:
     destination partition, then source partition, source node, destination
     node (the order of ``png_layout(...).did``)."""

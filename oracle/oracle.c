@@ -16,6 +16,9 @@
  *                     with the mass of dangling nodes redistributed by the
  *                     teleport vector.  Plain PageRank uses t(v) = 1/|V|;
  *                     personalised PageRank passes its own t.
+ *                     orc_pagerank_csc takes the transposed adjacency from
+ *                     orc_transpose_into, so many runs on one graph (the
+ *                     vectors of a personalised batch) transpose it once.
  *   orc_png_sizes,    The Partition-Node Graph layout of Sec. 3.1 and 3.3,
  *   orc_png_layout    written from its set definitions (equisized index
  *                     partitions of any size q, one update per (node, destination
@@ -79,19 +82,28 @@ static double orc_l1_term(int64_t v, const void* c) {
   return fabs(k->y[v] - k->x[v]);
 }
 
-/* Transposed adjacency: in_off[n+1], in_src[m], sources ascending per node. */
+/* Transposed adjacency into caller arrays: in_off[n+2], in_src[m]; afterwards
+ * in_off[v] .. in_off[v+1] is v's list of in-neighbours, sources ascending. */
+int orc_transpose_into(int64_t n, const int32_t* row_off, const int32_t* col, int64_t* in_off, int32_t* in_src) {
+  if (n <= 0) return -1;
+  const int64_t m = row_off[n];
+  memset(in_off, 0, ((size_t)n + 2) * sizeof(int64_t));
+  for (int64_t e = 0; e < m; ++e) in_off[(int64_t)col[e] + 2]++;
+  for (int64_t v = 0; v < n; ++v) in_off[v + 2] += in_off[v + 1];
+  /* in_off[v+1] is now the start of v's list; advance it while filling */
+  for (int64_t u = 0; u < n; ++u)
+    for (int64_t e = row_off[u]; e < row_off[u + 1]; ++e) in_src[in_off[(int64_t)col[e] + 1]++] = (int32_t)u;
+  return 0;
+}
+
 static int orc_transpose(int64_t n, const int32_t* row_off, const int32_t* col, int64_t** in_off_out,
                          int32_t** in_src_out) {
   const int64_t m = row_off[n];
   int64_t* in_off = (int64_t*)calloc((size_t)n + 2, sizeof(int64_t));
   int32_t* in_src = (int32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
   if (!in_off || !in_src) { free(in_off); free(in_src); return -1; }
-  for (int64_t e = 0; e < m; ++e) in_off[(int64_t)col[e] + 2]++;
-  for (int64_t v = 0; v < n; ++v) in_off[v + 2] += in_off[v + 1];
-  /* in_off[v+1] is now the start of v's list; advance it while filling */
-  for (int64_t u = 0; u < n; ++u)
-    for (int64_t e = row_off[u]; e < row_off[u + 1]; ++e) in_src[in_off[(int64_t)col[e] + 1]++] = (int32_t)u;
-  *in_off_out = in_off; /* in_off[v] .. in_off[v+1] is v's list */
+  orc_transpose_into(n, row_off, col, in_off, in_src);
+  *in_off_out = in_off;
   *in_src_out = in_src;
   return 0;
 }
@@ -105,14 +117,11 @@ static int orc_transpose(int64_t n, const int32_t* row_off, const int32_t* col, 
  * Runs until res_i < tol (tol > 0) or max_iters iterations.
  * Returns 0, 1 when tol > 0 was never reached, negative on bad input.
  */
-int orc_pagerank(int64_t n, const int32_t* row_off, const int32_t* col, double d, const double* tele,
-                 const double* x0, int max_iters, double tol, int nthreads, double* x_out,
-                 double* res_hist, int32_t* iters_out, double* sec_per_iter) {
+int orc_pagerank_csc(int64_t n, const int32_t* row_off, const int64_t* in_off, const int32_t* in_src, double d,
+                     const double* tele, const double* x0, int max_iters, double tol, int nthreads, double* x_out,
+                     double* res_hist, int32_t* iters_out, double* sec_per_iter) {
   orc_threads(nthreads);
   if (n <= 0 || max_iters < 0) return -1;
-  int64_t* in_off = NULL;
-  int32_t* in_src = NULL;
-  if (orc_transpose(n, row_off, col, &in_off, &in_src) != 0) return -2;
   double* x = (double*)malloc((size_t)n * sizeof(double));
   double* y = (double*)malloc((size_t)n * sizeof(double));
   double* spr = (double*)malloc((size_t)n * sizeof(double));
@@ -149,7 +158,21 @@ int orc_pagerank(int64_t n, const int32_t* row_off, const int32_t* col, double d
   if (sec_per_iter) *sec_per_iter = it > 0 ? (t1 - t0) / it : 0.0;
   memcpy(x_out, x, (size_t)n * sizeof(double));
   if (iters_out) *iters_out = it;
-  free(x); free(y); free(spr); free(in_off); free(in_src);
+  free(x); free(y); free(spr);
+  return rc;
+}
+
+/* The same with the transposed adjacency formed here from the CSR. */
+int orc_pagerank(int64_t n, const int32_t* row_off, const int32_t* col, double d, const double* tele,
+                 const double* x0, int max_iters, double tol, int nthreads, double* x_out,
+                 double* res_hist, int32_t* iters_out, double* sec_per_iter) {
+  if (n <= 0 || max_iters < 0) return -1;
+  int64_t* in_off = NULL;
+  int32_t* in_src = NULL;
+  if (orc_transpose(n, row_off, col, &in_off, &in_src) != 0) return -2;
+  const int rc = orc_pagerank_csc(n, row_off, in_off, in_src, d, tele, x0, max_iters, tol, nthreads, x_out,
+                                  res_hist, iters_out, sec_per_iter);
+  free(in_off); free(in_src);
   return rc;
 }
 

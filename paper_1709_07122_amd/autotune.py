@@ -3,7 +3,7 @@
 implies).
 
 The paper picks its partition size by a sweep of execution time against
-partition size (Sec. 5.4, Figs. 11-14); this does the same sweep on the GPU:
+partition size (Sec. 5.3.2, Figs. 11-14); this does the same sweep on the GPU:
 for each candidate q and each update order (bin order, PNG order) it builds
 the PNG, runs a few iterations through the library and keeps the fastest time
 per iteration (per vector for batched personalised PageRank).  PNG build

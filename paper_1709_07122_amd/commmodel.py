@@ -85,7 +85,7 @@ def iteration_bytes(n, m, eprime, nseg, png_order=False):
             + gather_bytes(n, m, eprime, nseg=nseg, png_order=png_order))
 
 
-# ---- SpMV over the PNG (Sec. 3.4) -------------------------------------------
+# ---- SpMV over the PNG (Sec. 3.5) -------------------------------------------
 
 def spmv_scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES, png_order=False):
     """Scatter of one SpMV: x (4n, no out-degrees), PNG source IDs, the update
@@ -95,7 +95,7 @@ def spmv_scatter_bytes(n, eprime, nseg, src_bytes=SRC_BYTES, png_order=False):
 
 def spmv_gather_bytes(n, m, eprime, weighted=True, did_bytes=DID_BYTES, nseg=0, png_order=False):
     """Gather of one SpMV: destination IDs, their weights (4m when weighted,
-    stored beside the IDs, Sec. 3.4), tile flag prefixes, updates and y (4n);
+    stored beside the IDs, Sec. 3.5), tile flag prefixes, updates and y (4n);
     no residual, no dangling mask; in PNG order also the segment deltas and
     segment-flag prefixes."""
     extra = 4 * nseg + 4 * (m // TILE + 1) if png_order else 0

@@ -607,7 +607,7 @@ __global__ __launch_bounds__(64) void k_fill(int s, int32_t k, int nbits, int bb
         const uint32_t dval = (static_cast<uint32_t>(vs[t]) & lmask) | flags;
         rec[ri] = static_cast<uint64_t>(static_cast<uint32_t>(cd + __popcll(peers[t] & below))) |
                   (static_cast<uint64_t>(dval) << 32) | (static_cast<uint64_t>(pval) << 48);
-        if (rw) rw[ri] = ws[t];  // the weight travels with its destination ID (Sec. 3.4)
+        if (rw) rw[ri] = ws[t];  // the weight travels with its destination ID (Sec. 3.5)
         if ((peers[t] & below) == 0) {
           cur_did[pp] = cd + __popcll(peers[t]);
           const int nf = __popcll(fpeers);

@@ -48,11 +48,12 @@ __device__ __forceinline__ double block_max(double v) {
 
 // Fixed-point scale for sums of updates bounded by `bound` (the largest
 // iterate value): 50 - ceil(log2(bound)), so every update times 2^sh stays
-// at most 2^50, capped by `cap` (the sums' own bound) and at least 1.
+// at most 2^50, capped by `cap` (the sums' own bound).  Zero and negative
+// shifts are valid (units of 2^-sh >= 1 for vectors of large values).
 __device__ __forceinline__ int fx_shift_for(double bound, int cap) {
   int e = 0;
   if (bound > 0.0 && isfinite(bound)) e = static_cast<int>(ceil(log2(bound)));
-  return max(1, min(cap, 50 - e));
+  return min(cap, 50 - e);
 }
 
 // Conversion of an FP32 update to a signed integer in units of 2^-sh,

@@ -258,7 +258,7 @@ struct pcpm_png {
   double* red = nullptr;        // 3*(k + n_mg): (residual, dangling, -) partial sums per apply unit
   double* red_start = nullptr;  // 4*k: (non-finite count, dangling, L1 mass) of the start vector per partition,
                                 // then the largest |value| per partition
-  double* hist = nullptr;       // kMaxHist residuals (group 0)
+  double* hist = nullptr;       // kMaxHist residuals (largest over groups)
   pcpm::Ctl* ctl = nullptr;
   pcpm::Ctl* ctl_host = nullptr;  // pinned mirror
   float* tmp_pr = nullptr;      // n: second rank buffer

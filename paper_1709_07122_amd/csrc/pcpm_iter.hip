@@ -206,7 +206,7 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
 
 // kMode 0: PageRank (apply, residual, dangling mass); 1: SpMV, y(v) = sum of
 // the updates; 2: SpMV with the edge weight stored beside each destination ID
-// applied to its update (Sec. 3.4).  In SpMV modes pr_out receives y.
+// applied to its update (Sec. 3.5).  In SpMV modes pr_out receives y.
 // kPng: updates in PNG order (an ID's update is at its message index plus
 // its segment's delta), else in bin order (at its message index).
 template <int BS, int kMode, bool kPng>
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* 
   }
 }
 
-// ---- SpMV (Sec. 3.4) -----------------------------------------------------------------
+// ---- SpMV (Sec. 3.5) -----------------------------------------------------------------
 // Split bins of an SpMV: y = the sum of the item slices, in slot order.
 __global__ __launch_bounds__(kMergeNodes) void k_spmv_merge(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                            const Merge* __restrict__ mg,
@@ -615,6 +615,16 @@ __global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, 
   }
 }
 
+// NaN everywhere in x when the solve met a non-finite value (the kernels of
+// an iteration return at once then, leaving x unwritten).
+__global__ __launch_bounds__(256) void k_nan_if_nonfinite(const Ctl* __restrict__ ctl, float* __restrict__ x,
+                                                          int64_t n) {
+  if (!ctl->nonfinite) return;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * 256)
+    x[v] = __builtin_nanf("");
+}
+
 template <bool kPng>
 static pcpm_status_t iter_lds_limits_for() {
   const void* scat[] = {reinterpret_cast<const void*>(k_scatter<kScatterBlock, true, kPng>),
@@ -710,7 +720,10 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
   PCPM_TRY(reset_ctl(g, 0.0, d, st));
   PCPM_TRY(start_solve(g, 0.0, d, g->tmp_pr, st));
   PCPM_TRY(run_iteration(g, g->tmp_pr, pr_out, st));
-  if (resid) {
+  if (!resid) {
+    const unsigned nb = static_cast<unsigned>(std::min<int64_t>((g->n + 255) / 256, 1024));
+    PCPM_LAUNCH("pcpm_init", k_nan_if_nonfinite, dim3(nb), dim3(256), 0, st, g->ctl, pr_out, g->n);
+  } else {
     PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     PCPM_TRY_HIP(hipStreamSynchronize(st));
     *resid = g->ctl_host->res;

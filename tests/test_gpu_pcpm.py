@@ -255,3 +255,44 @@ def test_poisoned_init_is_reported():
     with pytest.raises(P.PCPMError) as ei:
         P.pagerank(png, init=bad, tol=1e-6, max_iters=10)
     assert ei.value.status == P.PCPM_ERR_NUMERIC
+
+
+def test_poisoned_input_without_resid_gives_nan():
+    """pcpm_iterate with resid NULL does not synchronise; a non-finite input
+    makes the whole output NaN instead of leaving it unwritten."""
+    r, c = graphgen.rmat(10, 8, seed=3)
+    n = len(r) - 1
+    png = build(r, c, part_log2=6)
+    bad = torch.full((n,), 1.0 / n, device="cuda")
+    bad[7] = float("inf")
+    out = torch.zeros(n, device="cuda")
+    P.iterate(png, bad, pr_out=out, want_resid=False)
+    assert torch.isnan(out).all().item()
+    with pytest.raises(P.PCPMError) as ei:
+        P.iterate(png, bad, pr_out=out, want_resid=True)
+    assert ei.value.status == P.PCPM_ERR_NUMERIC
+    # a finite input afterwards is computed normally
+    good = torch.full((n,), 1.0 / n, device="cuda")
+    y, _ = P.iterate(png, good, pr_out=out, want_resid=False)
+    assert_ranks_close(y.cpu().numpy(), oracle.pagerank(r, c, iters=1).x)
+
+
+@pytest.mark.parametrize("scale", [1e20, 1e30])
+def test_start_vector_of_large_values(scale):
+    """A start vector of L1 mass far above 2^60 (the fixed-point scale goes
+    below one unit) iterates as the oracle does from the same vector, used as
+    given."""
+    r, c = graphgen.rmat(12, 8, seed=13, relabel="random")
+    n = len(r) - 1
+    png = build(r, c, part_log2=8)
+    rng = np.random.default_rng(5)
+    x0 = (rng.random(n) * (2.0 * scale / n)).astype(np.float32)
+    assert np.isfinite(x0).all()
+    res = P.pagerank(png, tol=0.0, max_iters=4, init=torch.from_numpy(x0).cuda())
+    o = oracle.pagerank(r, c, iters=4, x0=x0.astype(np.float64))
+    got = res.pr.cpu().numpy().astype(np.float64)
+    mass = np.abs(o.x).sum()
+    assert np.abs(got - o.x).sum() <= 1e-5 * mass
+    big = o.x > mass / n
+    assert (np.abs(got - o.x)[big] / o.x[big]).max() <= 1e-3
+    np.testing.assert_allclose(res.res_hist, o.res_hist, rtol=1e-4)

@@ -1,4 +1,4 @@
-"""pcpm_spmv (Sec. 3.4: weighted graphs and SpMV over the PNG) against the
+"""pcpm_spmv (Sec. 3.5: weighted graphs and SpMV over the PNG) against the
 FP64 oracle.  Bound per element: every product is rounded to a multiple of
 2^-s (s from max|w| max|x| and the largest weighted in-degree, as the header
 states), the sum is exact, and y is rounded to FP32:

@@ -54,6 +54,33 @@ def test_adam_first_step_moves_by_lr_sign():
     assert p[3] == 0.0
 
 
+def test_adam_constant_gradient_moves_by_lr_every_step():
+    """With bias correction, a constant gradient g gives m_t / (1 - b1^t) = g
+    and v_t / (1 - b2^t) = g^2 at every step t, so each step moves by
+    lr * sign(g) (eps = 0)."""
+    g = np.array([2.0, -0.25])
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    for t in range(1, 6):
+        p, m, v = mlp.adam_step(p, g, m, v, t, 0.1, eps=0.0)
+        np.testing.assert_allclose(p, -0.1 * t * np.sign(g), rtol=1e-13)
+
+
+def test_adam_second_step_by_hand():
+    """Gradient +1 then -1, lr 0.1, b1 0.9, b2 0.999, eps 0, worked by hand:
+    step 1: m = 0.1, v = 0.001, corrected 1 and 1, p = -0.1;
+    step 2: m = 0.09 - 0.1 = -0.01, corrected -0.01 / 0.19; v = 0.000999 +
+    0.001 = 0.001999, corrected 0.001999 / 0.001999 = 1; p = -0.1 + 0.1 *
+    0.01 / 0.19 = -0.0947368421052631...  With b1 and b2 swapped the second
+    step would give -0.1 + 0.1 * 1e-6 / 0.001999 instead."""
+    p, m, v = mlp.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, 0.1, eps=0.0)
+    np.testing.assert_allclose(p, [-0.1], rtol=1e-15)
+    p, m, v = mlp.adam_step(p, -np.ones(1), m, v, 2, 0.1, eps=0.0)
+    np.testing.assert_allclose(m, [-0.01], rtol=1e-12)
+    np.testing.assert_allclose(v, [0.001999], rtol=1e-12)
+    np.testing.assert_allclose(p, [-0.1 + 0.001 / 0.19], rtol=1e-13)
+    np.testing.assert_allclose(p, [-0.09473684210526316], rtol=1e-13)
+
+
 def test_features_from_definitions():
     """Feature 3 is log(n PR_1) of the first PageRank iterate from 1/n."""
     r, c = graphgen.rmat(10, 8, seed=2, relabel="random")

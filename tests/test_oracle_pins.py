@@ -217,6 +217,28 @@ def test_ppr_on_all_nodes_is_plain_pagerank():
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-16)
 
 
+def test_transposed_adjacency_is_the_in_neighbour_lists():
+    """transpose() gives every node its in-neighbours, sources ascending
+    (brute force over the edge list), and runs on it equal runs that form
+    the lists themselves, for plain and personalised PageRank."""
+    r, c = graphgen.rmat(10, 8, seed=8)
+    n = len(r) - 1
+    T = oracle.transpose(r, c)
+    src = np.repeat(np.arange(n), np.diff(r))
+    for v in range(0, n, 37):
+        want = np.sort(src[c == v])
+        np.testing.assert_array_equal(T.in_src[T.in_off[v]:T.in_off[v + 1]], want)
+    assert T.in_off[n] == len(c)
+    a, b = oracle.pagerank(r, c, iters=9), oracle.pagerank(r, c, iters=9, transposed=T)
+    np.testing.assert_array_equal(a.x, b.x)
+    np.testing.assert_array_equal(a.res_hist, b.res_hist)
+    seeds = np.array([3, 70, 500])
+    np.testing.assert_array_equal(oracle.ppr(r, c, seeds, iters=7).x, oracle.ppr(r, c, seeds, iters=7, transposed=T).x)
+    r2, c2 = graphgen.rmat(10, 8, seed=9)
+    with pytest.raises(ValueError):
+        oracle.pagerank(r2, c2, iters=2, transposed=T)
+
+
 # ---------------------------------------------------------------- PNG layout
 
 def brute_png(row_off, col, q):

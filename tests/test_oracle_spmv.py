@@ -1,4 +1,4 @@
-"""Pins of the oracle's SpMV (Sec. 3.4): independent computations of the
+"""Pins of the oracle's SpMV (Sec. 3.5): independent computations of the
 same product, closed forms, and the bin order of the weights against the
 C oracle's PNG layout."""
 import numpy as np
