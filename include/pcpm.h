@@ -302,6 +302,19 @@ pcpm_status_t pcpm_ws_backward(const float* params, const float* feat, const flo
                                const int64_t* idx, int64_t b, float* grad, float* work, double* loss /* (host) */,
                                void* stream);
 
+/* pcpm_ws_backward without a workspace argument and without allocating,
+ * for callers that cannot allocate device memory (tight training loops,
+ * harnesses that forbid hipMalloc).  The workspace is a fixed array of the
+ * library in device memory (4.9 MB per GPU, held until the process ends),
+ * so the minibatch is limited to b <= 16384 samples; a larger b returns
+ * PCPM_ERR_INVALID_ARG before any device work.  Results are bit-identical to
+ * pcpm_ws_backward's for the same inputs.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other threads, other streams)
+ * race and must be serialised by the caller.  Synchronises `stream`. */
+pcpm_status_t pcpm_ws_backward_noalloc(const float* params, const float* feat, const float* target, int64_t rows,
+                                       const int64_t* idx, int64_t b, float* grad, double* loss /* (host) */,
+                                       void* stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step
  * >= 1) on the FP32 master parameters, moments m and v (device). */
 pcpm_status_t pcpm_ws_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr,

@@ -33,7 +33,7 @@ STATUS_NAMES = {
 EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
            "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_last_error",
            "pcpm_timing_enable", "pcpm_timing_collect", "pcpm_ws_features", "pcpm_ws_forward", "pcpm_ws_init",
-           "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_adam", "pcpm_ws_targets", "pcpm_spmv",
+           "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_backward_noalloc", "pcpm_ws_adam", "pcpm_ws_targets", "pcpm_spmv",
            "pcpm_png_export_weights", "pcpm_relabel"]
 
 WS_FEATURES = 8
@@ -111,6 +111,8 @@ def lib():
     L.pcpm_ws_work_floats.argtypes = [i64]
     L.pcpm_ws_backward.restype = ctypes.c_int
     L.pcpm_ws_backward.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, ctypes.POINTER(dbl), vp]
+    L.pcpm_ws_backward_noalloc.restype = ctypes.c_int
+    L.pcpm_ws_backward_noalloc.argtypes = [vp, vp, vp, i64, vp, i64, vp, ctypes.POINTER(dbl), vp]
     L.pcpm_ws_adam.restype = ctypes.c_int
     L.pcpm_ws_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp]
     L.pcpm_ws_targets.restype = ctypes.c_int
@@ -468,6 +470,22 @@ def ws_backward(params, feat, target, idx, grad=None, work=None, stream=None):
                                   _dev_tensor(grad, torch.float32, WS_PARAMS, "grad"),
                                   _dev_tensor(work, torch.float32, name="work"), ctypes.byref(loss),
                                   _stream(stream)))
+    return grad, loss.value
+
+
+def ws_backward_noalloc(params, feat, target, idx, grad, stream=None):
+    """pcpm_ws_backward_noalloc: the same gradient with the library's fixed
+    scratch (minibatches of at most 16384); returns (grad, loss)."""
+    import torch
+    b = idx.numel()
+    rows = feat.shape[0]
+    loss = ctypes.c_double(0.0)
+    _check(lib().pcpm_ws_backward_noalloc(_dev_tensor(params, torch.float32, WS_PARAMS, "params"),
+                                          _dev_tensor(feat, torch.float32, rows * WS_FEATURES, "feat"),
+                                          _dev_tensor(target, torch.float32, rows, "target"), rows,
+                                          _dev_tensor(idx, torch.int64, b, "idx"), b,
+                                          _dev_tensor(grad, torch.float32, WS_PARAMS, "grad"), ctypes.byref(loss),
+                                          _stream(stream)))
     return grad, loss.value
 
 

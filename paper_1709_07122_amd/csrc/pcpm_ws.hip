@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "pcpm_device.hpp"
@@ -422,6 +423,65 @@ static pcpm_status_t ws_check_device_ptr(const void* p, const char* what) {
   return PCPM_OK;
 }
 
+// Minibatch gradient (k_ws_grad + k_ws_grad_reduce) with the caller's or
+// the fixed scratch as `work`: 2 (parts + 1) doubles (per-workgroup loss and
+// bad-index count, then the totals), then parts * PARAMS floats of
+// per-workgroup partial gradients.  Every entry the kernels read is written
+// by them first in the same call, so nothing needs clearing between calls.
+static pcpm_status_t ws_backward(const float* params, const float* feat, const float* target, int64_t rows,
+                                 const int64_t* idx, int64_t b, float* grad, float* work, double* loss,
+                                 hipStream_t st) {
+  PCPM_TRY(ws_check_device_ptr(params, "params"));
+  PCPM_TRY(ws_check_device_ptr(feat, "feat"));
+  PCPM_TRY(ws_check_device_ptr(target, "target"));
+  PCPM_TRY(ws_check_device_ptr(idx, "idx"));
+  PCPM_TRY(ws_check_device_ptr(grad, "grad"));
+  const int parts = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((b + kChunk - 1) / kChunk, 1024)));
+  double* lpart = reinterpret_cast<double*>(work);
+  double* ldev = lpart + 2 * parts;
+  float* part = work + 4 * (parts + 1);
+  PCPM_LAUNCH("pcpm_ws_backward", k_ws_grad, dim3(parts), dim3(kGradBlock), 0, st, params, feat, target, rows, idx,
+              b, 1.0f / static_cast<float>(b), part, lpart);
+  PCPM_LAUNCH("pcpm_ws_backward", k_ws_grad_reduce, dim3((PCPM_WS_PARAMS + 255) / 256), dim3(256), 0, st, part,
+              parts, lpart, grad, ldev);
+  double tot[2] = {0.0, 0.0};
+  PCPM_TRY_HIP(hipMemcpyAsync(tot, ldev, 16, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  if (tot[1] != 0.0)
+    return set_error(PCPM_ERR_INVALID_ARG, "%.0f minibatch indices outside [0, %lld)", tot[1],
+                     static_cast<long long>(rows));
+  *loss = tot[0] / static_cast<double>(b);
+  return PCPM_OK;
+}
+
+// Fixed scratch of pcpm_ws_backward_noalloc: the workspace of
+// pcpm_ws_backward for up to kNoAllocParts workgroups, i.e. minibatches of
+// up to kNoAllocParts * kChunk samples (4.9 MB).  Every GPU the library runs
+// on holds its own copy until the process ends.  On the host, `scratch`
+// names a host-side stand-in, not device memory: kernels get the device
+// address that hipGetSymbolAddress returns, looked up once per device.
+constexpr int kNoAllocParts = 256;
+constexpr int64_t kNoAllocMaxBatch = int64_t{kNoAllocParts} * kChunk;
+constexpr int64_t kNoAllocFloats = int64_t{kNoAllocParts} * PCPM_WS_PARAMS + 4 * (kNoAllocParts + 1);
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+static pcpm_status_t noalloc_scratch(float** out) {
+  static std::mutex mu;
+  static std::vector<float*> per_device;
+  int dev = -1;
+  PCPM_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<int>(per_device.size()) <= dev) per_device.resize(static_cast<size_t>(dev) + 1, nullptr);
+  if (!per_device[dev]) {
+    void* ptr = nullptr;
+    PCPM_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return set_error(PCPM_ERR_DEVICE, "no device address for the fixed scratch on device %d", dev);
+    per_device[dev] = static_cast<float*>(ptr);
+  }
+  *out = per_device[dev];
+  return PCPM_OK;
+}
+
 }  // namespace pcpm
 
 extern "C" {
@@ -484,31 +544,22 @@ pcpm_status_t pcpm_ws_backward(const float* params, const float* feat, const flo
                                const int64_t* idx, int64_t b, float* grad, float* work, double* loss, void* stream) {
   using namespace pcpm;
   if (b < 1 || rows < 1 || !loss) return set_error(PCPM_ERR_INVALID_ARG, "empty minibatch, no rows or NULL loss");
-  PCPM_TRY(ws_check_device_ptr(params, "params"));
-  PCPM_TRY(ws_check_device_ptr(feat, "feat"));
-  PCPM_TRY(ws_check_device_ptr(target, "target"));
-  PCPM_TRY(ws_check_device_ptr(idx, "idx"));
-  PCPM_TRY(ws_check_device_ptr(grad, "grad"));
   PCPM_TRY(ws_check_device_ptr(work, "work"));
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int parts = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((b + kChunk - 1) / kChunk, 1024)));
-  // work: 2 (parts + 1) doubles (per-workgroup loss and bad-index count,
-  // then the totals), then parts * PARAMS floats
-  double* lpart = reinterpret_cast<double*>(work);
-  double* ldev = lpart + 2 * parts;
-  float* part = work + 4 * (parts + 1);
-  PCPM_LAUNCH("pcpm_ws_backward", k_ws_grad, dim3(parts), dim3(kGradBlock), 0, st, params, feat, target, rows, idx,
-              b, 1.0f / static_cast<float>(b), part, lpart);
-  PCPM_LAUNCH("pcpm_ws_backward", k_ws_grad_reduce, dim3((PCPM_WS_PARAMS + 255) / 256), dim3(256), 0, st, part,
-              parts, lpart, grad, ldev);
-  double tot[2] = {0.0, 0.0};
-  PCPM_TRY_HIP(hipMemcpyAsync(tot, ldev, 16, hipMemcpyDeviceToHost, st));
-  PCPM_TRY_HIP(hipStreamSynchronize(st));
-  if (tot[1] != 0.0)
-    return set_error(PCPM_ERR_INVALID_ARG, "%.0f minibatch indices outside [0, %lld)", tot[1],
-                     static_cast<long long>(rows));
-  *loss = tot[0] / static_cast<double>(b);
-  return PCPM_OK;
+  return ws_backward(params, feat, target, rows, idx, b, grad, work, loss, static_cast<hipStream_t>(stream));
+}
+
+pcpm_status_t pcpm_ws_backward_noalloc(const float* params, const float* feat, const float* target, int64_t rows,
+                                       const int64_t* idx, int64_t b, float* grad, double* loss, void* stream) {
+  using namespace pcpm;
+  if (b < 1 || rows < 1 || !loss) return set_error(PCPM_ERR_INVALID_ARG, "empty minibatch, no rows or NULL loss");
+  if (b > kNoAllocMaxBatch)
+    return set_error(PCPM_ERR_INVALID_ARG,
+                     "minibatch of %lld samples exceeds the %lld that the fixed scratch of "
+                     "pcpm_ws_backward_noalloc holds (use pcpm_ws_backward with a workspace)",
+                     static_cast<long long>(b), static_cast<long long>(kNoAllocMaxBatch));
+  float* work = nullptr;
+  PCPM_TRY(noalloc_scratch(&work));
+  return ws_backward(params, feat, target, rows, idx, b, grad, work, loss, static_cast<hipStream_t>(stream));
 }
 
 pcpm_status_t pcpm_ws_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr,
