@@ -115,7 +115,8 @@ def measure(P, torch, r, c, args, label, tol=None, max_iters=None, update_order=
         f"r={m / max(info['eprime'], 1):.3f} updates in {'PNG' if info['update_order'] == 2 else 'bin'} order "
         f"build={build_s * 1e3:.1f} ms")
 
-    # timed region: the solves only (no per-launch events)
+    # timed region: the solves only (no per-launch events), in the default
+    # launch mode (one launch per phase)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, step_s = [], []
@@ -128,7 +129,19 @@ def measure(P, torch, r, c, args, label, tol=None, max_iters=None, update_order=
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t0
 
-    # separate pass for the per-kernel table: events around every launch
+    # the same solves in one persistent launch each (for comparison)
+    persist_ms = None
+    if png.launch_grid > 0:
+        png.set_launch(2)
+        P.pagerank(png, d=args.d, tol=tol, max_iters=max_iters, out=out, want_hist=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            P.pagerank(png, d=args.d, tol=tol, max_iters=max_iters, out=out, want_hist=False)
+        torch.cuda.synchronize()
+        persist_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    # per-kernel table: events around every launch, one launch per phase
+    png.set_launch(1)
     ev_steps = max(2, args.steps // 4)
     P.timing_enable(True)
     te = time.perf_counter()
@@ -139,6 +152,7 @@ def measure(P, torch, r, c, args, label, tol=None, max_iters=None, update_order=
     ev_ms = (time.perf_counter() - te) / ev_steps * 1e3
     P.timing_enable(False)
     kt = P.timing_collect()
+    png.set_launch(0)
 
     tot_iters = sum(iters)
     sec_per_iter = total_s / tot_iters
@@ -162,8 +176,10 @@ def measure(P, torch, r, c, args, label, tol=None, max_iters=None, update_order=
         "hbm_gbs_alg": it_bytes / sec_per_iter / 1e9,
         "iteration_frac_of_peak": it_bytes / sec_per_iter / 1e9 / HBM_PEAK_GBS,
         "build_ms": build_s * 1e3,
-        "kernels": kernels, "kernel_pass": {"solves": ev_steps, "ms_per_step_with_events": ev_ms,
-                                            "kernel_ms_per_iter": kern_iter_ms},
+        "launch": "per_phase", "launch_grid": png.launch_grid, "ms_per_step_persistent_launch": persist_ms,
+        "kernel_ms_per_step": kern_iter_ms * iters[-1],
+        "kernels": kernels, "kernel_pass": {"launch": "per_phase", "solves": ev_steps,
+                                            "ms_per_step_with_events": ev_ms, "kernel_ms_per_iter": kern_iter_ms},
         "gather_bytes": g_bytes, "scatter_bytes": s_bytes,
         "gather_frac_of_peak": g_bytes / (g_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "scatter_frac_of_peak": s_bytes / (s_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -173,7 +189,8 @@ def measure(P, torch, r, c, args, label, tol=None, max_iters=None, update_order=
     }
     log(f"[{label}] iters={iters} {result['ms_per_step']:.3f} ms/solve, {result['gteps']:.1f} GTEPS, "
         f"{result['hbm_gbs_alg']:.0f} GB/s (algorithmic, {result['iteration_frac_of_peak']:.3f} of peak); "
-        f"with events {ev_ms:.3f} ms/solve")
+        f"sum of kernel times {kern_iter_ms * iters[-1]:.3f} ms/solve; one persistent launch "
+        f"{persist_ms if persist_ms is None else round(persist_ms, 3)} ms/solve; with events {ev_ms:.3f} ms/solve")
     for k, v in sorted(kernels.items()):
         log(f"    {k:16s} launches={v['launches']:5d} avg={v['avg_ms'] * 1e3:9.1f} us")
     return result, out.cpu().numpy(), png
@@ -300,15 +317,22 @@ def ppr_detail(P, torch, args):
     r, c = graphgen.rmat(22, 16, seed=args.ppr_seed, relabel="random")
     n, m = len(r) - 1, len(c)
     rt, ct = torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()
-    one = autotune.tune(rt, ct, vectors=1, cache=None)
-    png1 = P.build_png(rt, ct, part_log2=one.part_log2, update_order=one.update_order)
+    png1, one = autotune.build(rt, ct, vectors=1)
     rows = []
     for k in (8, 32, 64):
-        tune = autotune.tune(rt, ct, vectors=k, cache=None)
-        png = P.build_png(rt, ct, part_log2=tune.part_log2, update_order=tune.update_order)
+        png, tune = autotune.build(rt, ct, vectors=k)
         off, seeds = graphgen.seed_sets(n, k, seed=k)
         reps = max(1, args.steps // 2)
         b_ms, res = _timed(torch, lambda: P.ppr_batch(png, off, seeds, tol=args.tol, max_iters=args.max_iters), reps)
+        p_ms = None
+        if png.launch_grid > 0:
+            png.set_launch(2)
+            try:
+                p_ms, _ = _timed(torch, lambda: P.ppr_batch(png, off, seeds, tol=args.tol,
+                                                            max_iters=args.max_iters), reps)
+            except P.PCPMError as e:
+                p_ms = f"error: {e}"
+            png.set_launch(0)
         singles = [(np.array([0, off[j + 1] - off[j]], np.int32), seeds[off[j]:off[j + 1]]) for j in range(k)]
 
         def one_by_one():
@@ -317,13 +341,16 @@ def ppr_detail(P, torch, args):
         s_ms, sres = _timed(torch, one_by_one, 1)
         vec_iters = int(res.iters.sum())
         rows.append({"k": k, "part_log2": tune.part_log2, "update_order": tune.update_order,
-                     "tile_width": tune.tile_width, "batched_ms": b_ms,
+                     "scatter_chunk": tune.scatter_chunk, "gather_chunk": tune.gather_chunk,
+                     "tune_ms_per_vector_iter": tune.ms_per_iter, "tune_table": tune.table,
+                     "tile_width": tune.tile_width, "batched_ms": b_ms, "batched_persistent_launch_ms": p_ms,
                      "one_at_a_time_ms": s_ms, "one_at_a_time_part_log2": one.part_log2,
                      "one_at_a_time_update_order": one.update_order,
                      "speedup": s_ms / b_ms, "iters_mean": float(res.iters.mean()), "iters_max": int(res.iters.max()),
                      "converged": bool(res.converged), "vector_gteps": m * vec_iters / (b_ms * 1e-3) / 1e9,
                      "single_iters_mean": float(np.mean([x.iters[0] for x in sres]))})
         log(f"[ppr] k={k} q=2^{tune.part_log2} order {tune.update_order} width {tune.tile_width}: {b_ms:.2f} ms batched "
+            f"(one persistent launch {p_ms} ms) "
             f"vs {s_ms:.2f} ms one at a time (q=2^{one.part_log2} order {one.update_order}, {s_ms / b_ms:.2f}x), "
             f"{rows[-1]['vector_gteps']:.1f} vector-GTEPS")
         png.close()
@@ -334,7 +361,8 @@ def ppr_detail(P, torch, args):
 def multigraph_detail(P, torch, args):
     """16 RMAT graphs (scale 14-20, edge factor 8-32, seeds 100-115, both
     extremes present) solved to tol in one handle, against one handle per
-    graph solved in turn; the partition size is the fastest of 2^12..2^14."""
+    graph solved in turn; partition size, update order and work-item chunks
+    from the autotuner (q = 2^12..2^14)."""
     import numpy as np
 
     import graphgen
@@ -343,25 +371,30 @@ def multigraph_detail(P, torch, args):
     scales = [s for s, _ in shapes]
     efs = [e for _, e in shapes]
     m_tot = sum(len(c) for _, c in graphs)
-    best = None
-    for pl in (12, 13, 14):
-        r, c, off, sizes = P.union_csr(graphs, pl)
-        png = P.build_png(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), part_log2=pl,
-                          graph_node_off=off, graph_nodes=sizes)
-        ms, _ = _timed(torch, lambda: P.pagerank(png, tol=0.0, max_iters=6, want_hist=False), 2)
-        if best is None or ms < best[1]:
-            if best is not None:
-                best[2].close()
-            best = (pl, ms, png)
-        else:
-            png.close()
-    pl, _, png = best
+    from paper_1709_07122_amd import autotune
+
+    r, c, off, sizes = P.union_csr(graphs, 14)  # offsets divisible by every candidate q
+    png, tune = autotune.build(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), candidates=(12, 13, 14),
+                               graph_node_off=off, graph_nodes=sizes)
+    pl = tune.part_log2
     reps = max(1, args.steps // 2)
     u_ms, res = _timed(torch, lambda: P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters,
                                                  want_hist=False), reps)
     it, resid = png.graph_results()
+    pp_ms = None
+    if png.launch_grid > 0:
+        png.set_launch(2)
+        pp_ms, _ = _timed(torch, lambda: P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters,
+                                                    want_hist=False), reps)
+    png.set_launch(1)
+    P.timing_enable(True)
+    P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters, want_hist=False)
+    torch.cuda.synchronize()
+    P.timing_enable(False)
+    kern_ms = sum(v[1] for name, v in P.timing_collect().items() if name != "pcpm_init")
     png.close()
-    singles = [P.build_png(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), part_log2=pl) for r, c in graphs]
+    singles = [P.build_png(torch.from_numpy(rg).cuda(), torch.from_numpy(cg).cuda(), part_log2=pl)
+               for rg, cg in graphs]
     s_ms, sres = _timed(torch, lambda: [P.pagerank(g, d=args.d, tol=args.tol, max_iters=args.max_iters,
                                                    want_hist=False) for g in singles], reps)
     for g in singles:
@@ -369,10 +402,14 @@ def multigraph_detail(P, torch, args):
     edge_iters = sum(len(c) * int(i) for (_, c), i in zip(graphs, it))
     out = {"graphs": [{"scale": int(sc), "edge_factor": int(ef), "n": len(r) - 1, "m": len(c), "iters": int(i)}
                       for (r, c), sc, ef, i in zip(graphs, scales, efs, it)],
-           "part_log2": pl, "m_total": m_tot, "one_handle_ms": u_ms, "one_handle_per_graph_ms": s_ms,
+           "part_log2": pl, "update_order": tune.update_order, "scatter_chunk": tune.scatter_chunk,
+           "gather_chunk": tune.gather_chunk, "tune_table": tune.table,
+           "m_total": m_tot, "one_handle_ms": u_ms, "launch": "per_phase",
+           "one_handle_kernel_ms": kern_ms, "one_handle_persistent_launch_ms": pp_ms,
+           "one_handle_per_graph_ms": s_ms,
            "speedup": s_ms / u_ms, "gteps": edge_iters / (u_ms * 1e-3) / 1e9, "all_converged": bool(np.all(resid < args.tol))}
-    log(f"[multi] 16 graphs, m={m_tot}, q=2^{pl}: {u_ms:.2f} ms in one handle vs {s_ms:.2f} ms one by one "
-        f"({s_ms / u_ms:.2f}x), {out['gteps']:.1f} GTEPS")
+    log(f"[multi] 16 graphs, m={m_tot}, q=2^{pl}: {u_ms:.2f} ms in one handle (kernels {kern_ms:.2f} ms; one "
+        f"persistent launch {pp_ms} ms) vs {s_ms:.2f} ms one by one ({s_ms / u_ms:.2f}x), {out['gteps']:.1f} GTEPS")
     return out
 
 
@@ -407,6 +444,31 @@ def copy_gbs(torch, nbytes=1 << 30, reps=5):
     ms = a.elapsed_time(b) / reps
     del x, y
     return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def stream_gbs(P, torch, nbytes=4 << 30, reps=5):
+    """Achieved rates of the library's plain HBM streams (pcpm_hbm_stream:
+    read, write, copy, with and without non-temporal stores), bytes moved
+    per second from HIP events on the launch stream."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    out = {}
+    for kind in P._pcpm.STREAM_KINDS:
+        size = nbytes // 2 if kind.startswith("copy") else nbytes
+        P.hbm_stream(kind, src, dst, size)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            P.hbm_stream(kind, src, dst, size)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        moved = 2 * size if kind.startswith("copy") else size
+        out[kind] = round(moved / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    log("[stream] " + ", ".join(f"{k} {v:.0f} GB/s" for k, v in out.items()))
+    return out
 
 
 def host_info():
@@ -583,6 +645,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_gbs_algorithmic": round(main_res["hbm_gbs_alg"], 1),
         "copy_gbs": round(copy_gbs(torch), 1),
+        "stream_gbs": stream_gbs(P, torch),
         "time_to_tol_ms": None if warm is None else {
             "cold": round(warm["cold_ms"], 3), "warm": round(warm["warm_ms"], 3),
             "warm_incl_indegree_count": round(warm["warm_ms_first"], 3),

@@ -54,7 +54,16 @@ typedef struct {
                             1..14 (the gather keeps an 8-byte exact sum per
                             node of a partition in the LDS of one compute
                             unit) with k = ceil(n/q) <= 16384;
-                            0 = 14 (q = 16384)                                */
+                            0 = autotune: the measured sweep of Sec. 5.3.2
+                            (Figs. 11-14) on this GPU -- every candidate q
+                            (tune_log2_mask) and update order is built and
+                            timed over a few iterations, then the work-item
+                            chunks of the fastest are varied and timed; the
+                            fastest configuration is built and returned, and
+                            remembered for the process (keyed by the graph's
+                            content, the options and the device), so a
+                            later build of the same graph skips the sweep.
+                            pcpm_tune_table gives the measurements.         */
   int32_t num_graphs;    /* 0 or 1: one graph.  G > 1: the CSR is the block-
                             diagonal union of G graphs; graph g owns nodes
                             [graph_node_off[g], graph_node_off[g] +
@@ -84,7 +93,31 @@ typedef struct {
                             edge e: sequential scatter writes, the gather
                             reads one run per segment), 0 = automatic: PNG
                             order when the average non-empty segment holds
-                            fewer than 300 updates.  Results are identical.  */
+                            fewer than 300 updates.  Results are identical.
+                            Under autotune, 0 times both orders.             */
+  int64_t tune_vectors;  /* autotune objective: 0 or 1 = time per PageRank
+                            iteration; v > 1 = time per vector-iteration of
+                            pcpm_ppr_batch with min(v, tile width) vectors
+                            (the tile width follows from q)                 */
+  int64_t tune_log2_mask;/* autotune candidates: bit s set = try q = 2^s
+                            (1 <= s <= 14); 0 = q in {2^12, 2^13, 2^14}.
+                            Candidates with k > 16384, or that a graph
+                            offset of a batch is not a multiple of, are
+                            skipped.  Caller-set scatter_chunk and
+                            gather_chunk are kept; 0 lets the sweep vary
+                            them (the automatic value, half, double).        */
+  int64_t num_cols;      /* generic SpMV (Sec. 3.5): the CSR is the n x
+                            num_cols matrix A (rows 0..n-1, columns in
+                            [0, num_cols)); the scatter runs over row
+                            partitions and the gather over column partitions,
+                            both of q rows / columns.  0 = num_cols = n.     */
+  int64_t allow_diagonal;/* 1: keep entries A[i][i] (rejected as self-loops
+                            otherwise).  A handle with allow_diagonal = 1 or
+                            num_cols != n holds a matrix: only pcpm_spmv,
+                            pcpm_png_info, pcpm_png_export_weights and
+                            pcpm_png_free take it (PCPM_ERR_INVALID_ARG from
+                            the PageRank calls); it cannot hold several
+                            graphs.                                          */
 } pcpm_build_opts_t;
 
 typedef struct {
@@ -101,6 +134,8 @@ typedef struct {
   double build_ms;       /* wall time of pcpm_build_png, device work included */
   int64_t weighted;      /* 1 if the build was given edge weights             */
   int64_t update_order;  /* 1 = bin order, 2 = PNG order (see the build opts) */
+  int64_t num_cols;      /* columns of a matrix handle (n for a graph)        */
+  int64_t matrix;        /* 1 for a matrix handle (SpMV only)                 */
 } pcpm_png_info_t;
 
 /*
@@ -155,9 +190,10 @@ void pcpm_png_free(pcpm_png_t g);
  * per (u, destination partition) (Alg. 3 without the 1/outdeg scaling); the
  * gather reads each weight with its destination ID and applies it to the
  * update before accumulating (Alg. 5).  x and y are device arrays of n floats
- * and must not overlap.  A non-square matrix (rows R, columns C) runs on a
- * square handle with n >= max(R, C): padded rows have no edges, x is zero
- * past R and y past C is zero.
+ * and must not overlap.  On a matrix handle (num_cols C, n = R rows) x has
+ * R entries and y has C: y = A^T x, with the scatter over row partitions and
+ * the gather over column partitions (Sec. 3.5); diagonal entries are
+ * allowed there (allow_diagonal).
  * Accuracy: each product w*x(u) is formed exactly in FP64 and rounded to a
  * multiple of 2^-s, s = min(50 - ceil(log2(max|w| max|x|)), 62 -
  * ceil(log2(W max|x|))) with W the largest sum over v of |w(u,v)| (computed
@@ -326,6 +362,62 @@ pcpm_status_t pcpm_ws_targets(const float* pr, int64_t n, float* y, void* stream
 /* Per-graph outcome of the last pcpm_pagerank on a handle: iterations run and
  * last residual of each of the G graphs (host arrays of G). */
 pcpm_status_t pcpm_graph_results(pcpm_png_t g, int32_t* iters /* (host) G */, double* resid /* (host) G */);
+
+/* One measurement of an autotuned build. */
+typedef struct {
+  int32_t part_log2, update_order;     /* the candidate's q and update order   */
+  int64_t scatter_chunk, gather_chunk; /* its work-item chunks (0 = automatic) */
+  double ms_per_iter;                  /* per iteration (per vector-iteration
+                                          for tune_vectors > 1)               */
+  double build_ms;                     /* its PNG build (0 for chunk variants,
+                                          which reuse the PNG)               */
+} pcpm_tune_entry_t;
+
+/* The measurements behind an autotuned handle (part_log2 = 0): up to
+ * max_entries entries into out (host), in the order measured; returns the
+ * number of entries (0 for a handle built with a given part_log2), and
+ * *best (host, nullable) the index of the chosen one, *cached (host,
+ * nullable) 1 if the sweep was taken from the process's cache (the table is
+ * then the original sweep's). */
+int32_t pcpm_tune_table(pcpm_png_t g, pcpm_tune_entry_t* out, int32_t max_entries, int32_t* best,
+                        int32_t* cached);
+
+/* Forget every configuration the autotuner remembers in this process. */
+void pcpm_tune_cache_clear(void);
+
+/* 64-bit content hash of a CSR graph (row_off n+1, col m, device arrays),
+ * the one the autotuner's cache keys on; equal graphs give equal hashes.
+ * Synchronises `stream`. */
+pcpm_status_t pcpm_graph_hash(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col, void* stream,
+                              uint64_t* out /* (host) */);
+
+/* Plain HBM streams, the measured ceiling the iteration kernels are compared
+ * with (the part STREAM plays for the paper's CPU, Sec. 5.1): kind 0 reads
+ * `bytes` from src (one float per workgroup, 4096 of them, goes to dst), 1
+ * writes `bytes` to dst, 2 the same with non-temporal stores, 3 copies
+ * `bytes` from src to dst, 4 the same with non-temporal stores.  bytes is a
+ * positive multiple of 16; device buffers, 16-byte aligned, not
+ * overlapping.  Asynchronous on `stream`. */
+pcpm_status_t pcpm_hbm_stream(int32_t kind, const void* src /* (device) */, void* dst /* (device) */, int64_t bytes,
+                              void* stream);
+
+/* How pcpm_pagerank and pcpm_ppr_batch run their iterations on a handle.
+ * mode 1: one launch per phase (scatter, gather, merge, finalize, refill)
+ * per iteration, iterations queued in batches between host checks of the
+ * FP64 residuals.  mode 2: one persistent cooperative launch for the whole
+ * solve or batch, one workgroup per resident slot (pcpm_launch_grid),
+ * grid-wide barriers between the phases, convergence and refills decided on
+ * the device.  mode 0 (the default) is mode 1, the faster on MI355X.
+ * Results are bit-identical in both modes.  spin_limit bounds every
+ * device-side wait of mode 2 (polls; 0 = the default, 2^22): a wait that
+ * runs past it makes the call return PCPM_ERR_DEVICE with undefined output,
+ * and the next call starts afresh.  PCPM_ERR_INVALID_ARG for another mode, or
+ * mode 2 on a device without cooperative launches. */
+pcpm_status_t pcpm_set_launch(pcpm_png_t g, int32_t mode, uint32_t spin_limit);
+
+/* Workgroups of the persistent solve on this handle's device (0 if it
+ * cannot run). */
+int32_t pcpm_launch_grid(pcpm_png_t g);
 
 /* Message of the calling thread's last failure ("" if none). */
 const char* pcpm_last_error(void);

@@ -255,15 +255,18 @@ def _sources(row_off) -> np.ndarray:
     return np.repeat(np.arange(len(row_off) - 1, dtype=np.int64), np.diff(row_off))
 
 
-def spmv(row_off, col, x, weights=None) -> np.ndarray:
+def spmv(row_off, col, x, weights=None, num_cols=None) -> np.ndarray:
     """Sec. 3.5: y(v) = sum over edges u->v of w(u,v) * x(u) in FP64, with
     w = 1 on every edge when ``weights`` is None (weights[e] belongs to the
-    CSR edge row -> col[e]); that is y = A^T x for the CSR matrix A."""
+    CSR edge row -> col[e]); that is y = A^T x for the CSR matrix A, whose
+    columns number ``num_cols`` (the rows' count when None; a non-square A
+    gives y a length other than x's)."""
     n = len(row_off) - 1
     x = np.asarray(x, dtype=np.float64)
     col = np.asarray(col, dtype=np.int64)
     w = np.ones(len(col)) if weights is None else np.asarray(weights, dtype=np.float64)
-    return np.bincount(col, weights=w * x[_sources(row_off)], minlength=n).astype(np.float64)
+    cols = n if num_cols is None else int(num_cols)
+    return np.bincount(col, weights=w * x[_sources(row_off)], minlength=cols).astype(np.float64)[:cols]
 
 
 def bin_weights(row_off, col, weights, q: int) -> np.ndarray:

@@ -31,7 +31,8 @@ STATUS_NAMES = {
 
 # every symbol include/pcpm.h declares
 EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
-           "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_last_error",
+           "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_set_launch", "pcpm_launch_grid", "pcpm_tune_table",
+           "pcpm_tune_cache_clear", "pcpm_graph_hash", "pcpm_hbm_stream", "pcpm_last_error",
            "pcpm_timing_enable", "pcpm_timing_collect", "pcpm_ws_features", "pcpm_ws_forward", "pcpm_ws_init",
            "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_backward_noalloc", "pcpm_ws_adam", "pcpm_ws_targets", "pcpm_spmv",
            "pcpm_png_export_weights", "pcpm_relabel"]
@@ -51,7 +52,15 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("part_log2", ctypes.c_int32), ("num_graphs", ctypes.c_int32),
                 ("graph_node_off", ctypes.c_void_p), ("graph_nodes", ctypes.c_void_p),
                 ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64),
-                ("build_chunk", ctypes.c_int64), ("weights", ctypes.c_void_p), ("update_order", ctypes.c_int64)]
+                ("build_chunk", ctypes.c_int64), ("weights", ctypes.c_void_p), ("update_order", ctypes.c_int64),
+                ("tune_vectors", ctypes.c_int64), ("tune_log2_mask", ctypes.c_int64),
+                ("num_cols", ctypes.c_int64), ("allow_diagonal", ctypes.c_int64)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("part_log2", ctypes.c_int32), ("update_order", ctypes.c_int32),
+                ("scatter_chunk", ctypes.c_int64), ("gather_chunk", ctypes.c_int64),
+                ("ms_per_iter", ctypes.c_double), ("build_ms", ctypes.c_double)]
 
 
 class PngInfo(ctypes.Structure):
@@ -59,7 +68,9 @@ class PngInfo(ctypes.Structure):
                 ("n", "m", "q", "k", "eprime", "nseg", "n_dangling", "scatter_items", "gather_items",
                  "split_bins", "device_bytes", "num_graphs")] + [("build_ms", ctypes.c_double),
                                                                  ("weighted", ctypes.c_int64),
-                                                                 ("update_order", ctypes.c_int64)]
+                                                                 ("update_order", ctypes.c_int64),
+                                                                 ("num_cols", ctypes.c_int64),
+                                                                 ("matrix", ctypes.c_int64)]
 
 
 class KernelTime(ctypes.Structure):
@@ -119,6 +130,18 @@ def lib():
     L.pcpm_ws_targets.argtypes = [vp, i64, vp, vp]
     L.pcpm_graph_results.restype = ctypes.c_int
     L.pcpm_graph_results.argtypes = [vp, vp, vp]
+    L.pcpm_tune_table.restype = i32
+    L.pcpm_tune_table.argtypes = [vp, ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.pcpm_tune_cache_clear.restype = None
+    L.pcpm_tune_cache_clear.argtypes = []
+    L.pcpm_graph_hash.restype = ctypes.c_int
+    L.pcpm_graph_hash.argtypes = [i64, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.pcpm_hbm_stream.restype = ctypes.c_int
+    L.pcpm_hbm_stream.argtypes = [i32, vp, vp, i64, vp]
+    L.pcpm_set_launch.restype = ctypes.c_int
+    L.pcpm_set_launch.argtypes = [vp, i32, ctypes.c_uint32]
+    L.pcpm_launch_grid.restype = i32
+    L.pcpm_launch_grid.argtypes = [vp]
     L.pcpm_last_error.restype = ctypes.c_char_p
     L.pcpm_last_error.argtypes = []
     L.pcpm_timing_enable.restype = None
@@ -216,6 +239,28 @@ class PNG:
         _check(lib().pcpm_graph_results(self.handle, it.ctypes.data, r.ctypes.data))
         return it, r
 
+    def tune_table(self):
+        """(entries, best index, cached) of an autotuned build (part_log2 = 0);
+        entries are dicts of part_log2, update_order, scatter_chunk,
+        gather_chunk, ms_per_iter, build_ms."""
+        cnt = int(lib().pcpm_tune_table(self.handle, None, 0, None, None))
+        arr = (TuneEntry * max(cnt, 1))()
+        best, cached = ctypes.c_int32(-1), ctypes.c_int32(0)
+        lib().pcpm_tune_table(self.handle, arr, cnt, ctypes.byref(best), ctypes.byref(cached))
+        rows = [{f: getattr(arr[i], f) for f, _ in TuneEntry._fields_} for i in range(cnt)]
+        return rows, int(best.value), bool(cached.value)
+
+    def set_launch(self, mode: int, spin_limit: int = 0):
+        """pcpm_set_launch: 0 automatic, 1 one launch per phase, 2 one
+        persistent launch per solve; spin_limit bounds its device-side waits
+        (0: the default)."""
+        _check(lib().pcpm_set_launch(self.handle, int(mode), int(spin_limit)))
+
+    @property
+    def launch_grid(self) -> int:
+        """Workgroups of the persistent solve (0: not available)."""
+        return int(lib().pcpm_launch_grid(self.handle))
+
     def close(self):
         if self._h:
             lib().pcpm_png_free(self._h)
@@ -228,15 +273,20 @@ class PNG:
             pass
 
 
-def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_chunk: int = 0,
+def build_png(row_off, col, part_log2: int = 14, scatter_chunk: int = 0, gather_chunk: int = 0,
               graph_node_off=None, graph_nodes=None, build_chunk: int = 0, weights=None, update_order: int = 0,
+              tune_vectors: int = 0, tune_log2_mask: int = 0, num_cols: int = 0, allow_diagonal: int = 0,
               stream=None) -> PNG:
     """pcpm_build_png on device CSR tensors (int32 row_off[n+1], col[m]).
 
+    part_log2 = 0 autotunes (tune_vectors, tune_log2_mask: see
+    pcpm_build_opts_t; PNG.tune_table() gives the measurements).
     For several graphs in one handle pass the padded union (see union_csr)
     with its graph_node_off (G+1) and graph_nodes (G).  weights: optional
     device float32 tensor of m edge weights in CSR order (for spmv).
-    update_order: 0 automatic, 1 bin order, 2 PNG order (see pcpm_build_opts_t)."""
+    update_order: 0 automatic, 1 bin order, 2 PNG order (see pcpm_build_opts_t).
+    num_cols / allow_diagonal: an n x num_cols matrix (diagonal entries
+    allowed) for generic SpMV; such a handle takes spmv only."""
     import torch
     n = row_off.numel() - 1
     m = col.numel()
@@ -247,21 +297,55 @@ def build_png(row_off, col, part_log2: int = 0, scatter_chunk: int = 0, gather_c
     gn = np.ascontiguousarray(graph_nodes if G else [0], dtype=np.int64)
     wp = None if weights is None else _dev_tensor(weights, torch.float32, m, "weights")
     opts = BuildOpts(int(part_log2), G, goff.ctypes.data if G else None, gn.ctypes.data if G else None,
-                     int(scatter_chunk), int(gather_chunk), int(build_chunk), wp, int(update_order))
+                     int(scatter_chunk), int(gather_chunk), int(build_chunk), wp, int(update_order),
+                     int(tune_vectors), int(tune_log2_mask), int(num_cols), int(allow_diagonal))
     h = ctypes.c_void_p()
     _check(lib().pcpm_build_png(n, m, rp, cp, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return PNG(h, row_off, col)
 
 
+def graph_hash(row_off, col, stream=None) -> int:
+    """pcpm_graph_hash: the 64-bit content hash the autotuner's cache keys on."""
+    import torch
+    n = row_off.numel() - 1
+    m = col.numel()
+    rp = _dev_tensor(row_off, torch.int32, n + 1, "row_off")
+    cp = _dev_tensor(col, torch.int32, m, "col") if m else ctypes.c_void_p(0)
+    h = ctypes.c_uint64(0)
+    _check(lib().pcpm_graph_hash(n, m, rp, cp, _stream(stream), ctypes.byref(h)))
+    return int(h.value)
+
+
+STREAM_KINDS = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "copy_nt": 4}
+
+
+def hbm_stream(kind: str, src, dst, nbytes: int, stream=None):
+    """pcpm_hbm_stream: a plain read / write / copy of nbytes on device
+    buffers (see the header); asynchronous."""
+    import torch
+    sp = _dev_tensor(src, torch.float32, name="src") if src is not None else ctypes.c_void_p(0)
+    dp = _dev_tensor(dst, torch.float32, name="dst")
+    need_dst = 4 * 4096 if kind == "read" else nbytes
+    if (src is not None and src.numel() * 4 < nbytes) or dst.numel() * 4 < need_dst:
+        raise ValueError("buffers smaller than the stream")
+    _check(lib().pcpm_hbm_stream(STREAM_KINDS[kind], sp, dp, int(nbytes), _stream(stream)))
+
+
+def tune_cache_clear():
+    lib().pcpm_tune_cache_clear()
+
+
 def spmv(png: PNG, x, out=None, stream=None):
     """pcpm_spmv: y(v) = sum over edges u->v of w(u,v) x(u) (w = 1 when the
-    handle is unweighted); x and the returned y are device float32 [n]."""
+    handle is unweighted); x (rows) and the returned y (columns) are device
+    float32 vectors: both of n entries for a graph."""
     import torch
     n = png.n
+    nc = png.info["num_cols"]
     xp = _dev_tensor(x, torch.float32, n, "x")
     if out is None:
-        out = torch.empty(n, dtype=torch.float32, device=x.device)
-    yp = _dev_tensor(out, torch.float32, n, "out")
+        out = torch.empty(nc, dtype=torch.float32, device=x.device)
+    yp = _dev_tensor(out, torch.float32, nc, "out")
     _check(lib().pcpm_spmv(png.handle, xp, yp, _stream(stream)))
     return out
 

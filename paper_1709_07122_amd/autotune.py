@@ -1,23 +1,21 @@
-"""Measured choice of the partition size q and of the update storage order
-(and, for batched personalised PageRank, of the vector tile width that q
-implies).
+"""Measured choice of the partition size q, the update storage order and the
+work-item chunks (and, for batched personalised PageRank, of the vector tile
+width that q implies).
 
 The paper picks its partition size by a sweep of execution time against
-partition size (Sec. 5.3.2, Figs. 11-14); this does the same sweep on the GPU:
-for each candidate q and each update order (bin order, PNG order) it builds
-the PNG, runs a few iterations through the library and keeps the fastest time
-per iteration (per vector for batched personalised PageRank).  PNG build
-time is reported beside it, not mixed in.
-Results are cached in a JSON file keyed by (n, m, vectors, device).
+partition size (Sec. 5.3.2, Figs. 11-14).  The library runs that sweep
+itself when a PNG is built with part_log2 = 0: every candidate q and update
+order is built and timed over a few iterations, then the work-item chunks
+of the fastest are varied, and the winner is remembered for the process
+(keyed by the graph's content hash, the options and the device).  This
+module asks for such a build and returns its measurements; it can also keep
+the winners in a JSON file across processes, keyed the same way.
 """
 from __future__ import annotations
 
 import json
 import os
-import time
 from dataclasses import asdict, dataclass, field
-
-import numpy as np
 
 from . import _pcpm as P
 
@@ -33,6 +31,8 @@ class TuneResult:
     table: list = field(default_factory=list)  # every candidate measured
     cached: bool = False
     update_order: int = 0        # 1 bin order, 2 PNG order (0: entries cached before the order was tuned)
+    scatter_chunk: int = 0       # work-item chunks of the winner (0: automatic)
+    gather_chunk: int = 0
 
 
 def _device_name():
@@ -41,8 +41,19 @@ def _device_name():
     return torch.cuda.get_device_name(torch.cuda.current_device())
 
 
-def _key(n, m, vectors):
-    return f"n={n};m={m};vectors={vectors};device={_device_name()}"
+def _mask(candidates) -> int:
+    mask = 0
+    for pl in candidates:
+        if not 1 <= int(pl) <= 14:
+            raise ValueError(f"candidate part_log2 {pl} outside [1, 14]")
+        mask |= 1 << int(pl)
+    return mask
+
+
+def _key(n, m, content_hash, vectors, mask, graph_node_off=None):
+    goff = "" if graph_node_off is None else ",".join(str(int(v)) for v in graph_node_off)
+    return (f"n={n};m={m};hash={content_hash:016x};vectors={vectors};mask={mask:x};graphs={goff};"
+            f"device={_device_name()}")
 
 
 def _load(path):
@@ -65,57 +76,47 @@ def _store(path, key, res: TuneResult):
     os.replace(tmp, path)
 
 
-def _time_solve(fn, iters, reps):
-    import torch
+def result_of(png: P.PNG) -> TuneResult:
+    """The TuneResult of an autotuned handle (built with part_log2 = 0)."""
+    rows, best, cached = png.tune_table()
+    if not rows:
+        raise ValueError("the handle was not autotuned (built with a given part_log2)")
+    b = rows[best]
+    # the PNG build of the winner's q and order (chunk variants reuse it)
+    build_ms = next(r["build_ms"] for r in rows
+                    if (r["part_log2"], r["update_order"]) == (b["part_log2"], b["update_order"]) and r["build_ms"] > 0)
+    return TuneResult(b["part_log2"], P.ppr_tile_width(png), b["ms_per_iter"], build_ms, rows, cached,
+                      b["update_order"], b["scatter_chunk"], b["gather_chunk"])
 
-    fn(max(1, iters // 2))  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        fn(iters)
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / (reps * iters) * 1e3
+
+def build(row_off, col, vectors: int = 1, candidates=(12, 13, 14), graph_node_off=None, graph_nodes=None,
+          **kw) -> tuple[P.PNG, TuneResult]:
+    """An autotuned PNG (the library's sweep) and its TuneResult."""
+    png = P.build_png(row_off, col, part_log2=0, tune_vectors=int(vectors), tune_log2_mask=_mask(candidates),
+                      graph_node_off=graph_node_off, graph_nodes=graph_nodes, **kw)
+    return png, result_of(png)
 
 
-def tune(row_off, col, vectors: int = 1, candidates=(12, 13, 14), iters: int = 6, reps: int = 2,
-         cache: str | None = DEFAULT_CACHE, seed: int = 0, force: bool = False, orders=(1, 2)) -> TuneResult:
-    """Pick part_log2 for PageRank (vectors = 1) or for batched personalised
-    PageRank with `vectors` right-hand sides, on device CSR tensors."""
+def tune(row_off, col, vectors: int = 1, candidates=(12, 13, 14), cache: str | None = DEFAULT_CACHE,
+         force: bool = False, graph_node_off=None, graph_nodes=None) -> TuneResult:
+    """The measured configuration for PageRank (vectors = 1) or for batched
+    personalised PageRank with `vectors` right-hand sides, on device CSR
+    tensors (a multi-graph union with its graph_node_off / graph_nodes).
+    With `cache`, winners are also kept in that JSON file, keyed by the
+    graph's content hash, the candidates, the batch and the device."""
     n, m = row_off.numel() - 1, col.numel()
-    key = _key(n, m, vectors)
+    key = None
     if cache and not force:
+        key = _key(n, m, P.graph_hash(row_off, col), vectors, _mask(candidates), graph_node_off)
         hit = _load(cache).get(key)
         if hit:
             hit["cached"] = True
             return TuneResult(**hit)
-    rows = []
-    cands = [(pl, order) for pl in candidates for order in orders]
-    for pl, order in cands:
-        if pl < 1 or pl > 14 or (n + (1 << pl) - 1) >> pl > 16384:
-            continue
-        t0 = time.perf_counter()
-        png = P.build_png(row_off, col, part_log2=pl, update_order=order)
-        build_ms = (time.perf_counter() - t0) * 1e3
-        width = P.ppr_tile_width(png)
-        if vectors <= 1:
-            ms = _time_solve(lambda it: P.pagerank(png, tol=0.0, max_iters=it, want_hist=False), iters, reps)
-            per = ms
-        else:
-            k = min(vectors, width)
-            rng = np.random.default_rng(seed)
-            seeds = np.concatenate([np.sort(rng.choice(n, size=min(8, n), replace=False)) for _ in range(k)])
-            off = np.arange(0, 8 * k + 1, 8, dtype=np.int32) if n >= 8 else np.arange(0, n * k + 1, n, dtype=np.int32)
-            ms = _time_solve(lambda it: P.ppr_batch(png, off, seeds.astype(np.int32), tol=0.0, max_iters=it),
-                             iters, reps)
-            per = ms / k
-        rows.append({"part_log2": pl, "update_order": order, "tile_width": width, "ms_per_iter": per,
-                     "build_ms": build_ms, "eprime": png.info["eprime"], "nseg": png.info["nseg"]})
-        png.close()
-    if not rows:
-        raise ValueError("no candidate partition size fits this graph")
-    best = min(rows, key=lambda r: r["ms_per_iter"])
-    res = TuneResult(best["part_log2"], best["tile_width"], best["ms_per_iter"], best["build_ms"], rows,
-                     update_order=best["update_order"])
+    if force:
+        P.tune_cache_clear()
+    png, res = build(row_off, col, vectors, candidates, graph_node_off, graph_nodes)
+    png.close()
     if cache:
+        key = key or _key(n, m, P.graph_hash(row_off, col), vectors, _mask(candidates), graph_node_off)
         _store(cache, key, res)
     return res

@@ -18,7 +18,11 @@
 //   tile flags   flags before every 1024-entry tile of both arrays
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "pcpm_device.hpp"
@@ -110,7 +114,9 @@ __global__ __launch_bounds__(256) void k_node_pass(int64_t n, int64_t m, const i
 // kept with an LDS max, so among empty rows that share an offset the
 // non-empty row after them wins.  Rows visited over all tiles: n + ntiles.
 constexpr int kEdgeBlock = 256;
-__global__ __launch_bounds__(kEdgeBlock) void k_edge_pass(int64_t n, int64_t m, const int32_t* __restrict__ row_off,
+// ncols: columns must lie in [0, ncols); self_loops: 1 rejects u -> u.
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_pass(int64_t ncols, int self_loops, int64_t m,
+                                                          const int32_t* __restrict__ row_off,
                                                           const int32_t* __restrict__ col, int32_t* __restrict__ src,
                                                           const int32_t* __restrict__ tile_row,
                                                           int32_t* __restrict__ counters, int s,
@@ -153,9 +159,9 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_pass(int64_t n, int64_t m, 
         // first edge of its row (a mark, or the tile's first row starting here): no predecessor
         const bool row_start = mk >= 0 || e == lo0;
         const int32_t prev = row_start ? -1 : col[e - 1];
-        if (c < 0 || static_cast<int64_t>(c) >= n) err |= kErrRange;
+        if (c < 0 || static_cast<int64_t>(c) >= ncols) err |= kErrRange;
         else if (!same_graph(u, c, s, part_group, part_valid)) err |= kErrGraphs;
-        if (c == u) err |= kErrSelfLoop;
+        if (self_loops && c == u) err |= kErrSelfLoop;
         if (c <= prev) err |= kErrOrder;
       }
     }
@@ -869,7 +875,8 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
                           static_cast<int32_t>(std::min(b, lo + step)), 0});
   }
   int32_t slot = 0;
-  for (int64_t p = 0; p < k; ++p) {
+  const int64_t k_dst = (g->n_cols + g->q - 1) / g->q;  // column partitions (k for a graph)
+  for (int64_t p = 0; p < k_dst; ++p) {
     const int64_t a = did_start[p], b = did_start[p + 1];
     const int64_t nch = std::max<int64_t>(1, (b - a + gc - 1) / gc);
     if (nch == 1) {
@@ -882,7 +889,7 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
       ga_items.push_back({static_cast<int32_t>(p), static_cast<int32_t>(lo),
                           static_cast<int32_t>(std::min(b, lo + step)), slot++});
     ++g->n_split_bins;
-    const int64_t qn = std::min<int64_t>(g->q, g->n - p * g->q);
+    const int64_t qn = std::min<int64_t>(g->q, g->n_cols - p * g->q);
     for (int64_t nl = 0; nl < qn; nl += 256) mg.push_back({static_cast<int32_t>(p), first, slot - first,
                                                            static_cast<int32_t>(nl)});
   }
@@ -955,7 +962,7 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
 
 static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col,
                            const pcpm_build_opts_t* opts, hipStream_t st, pcpm_png* g) {
-  const int s = (opts && opts->part_log2) ? opts->part_log2 : 14;
+  const int s = opts ? opts->part_log2 : 14;  // part_log2 = 0 (autotune) is handled by pcpm_build_png
   if (s < kMinLog2 || s > kMaxLog2)
     return set_error(PCPM_ERR_INVALID_ARG, "part_log2 %d outside [%d, %d]", s, kMinLog2, kMaxLog2);
   const int64_t q = int64_t{1} << s;
@@ -990,8 +997,9 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
                 row_off, g->outdeg, g->dmask, tile_row, counters, s, g->part_valid);
     const int64_t eblocks = std::min<int64_t>((ntiles_e + kEdgeBlock / kWave - 1) / (kEdgeBlock / kWave), 65536);
     if (m > 0)
-      PCPM_LAUNCH("pcpm_build_nodes", k_edge_pass, dim3(static_cast<unsigned>(eblocks)), dim3(kEdgeBlock), 0, st, n,
-                  m, row_off, col, src, tile_row, counters, s, g->part_group, g->part_valid);
+      PCPM_LAUNCH("pcpm_build_nodes", k_edge_pass, dim3(static_cast<unsigned>(eblocks)), dim3(kEdgeBlock), 0, st,
+                  g->n_cols, g->matrix ? 0 : 1, m, row_off, col, src, tile_row, counters, s, g->part_group,
+                  g->part_valid);
   }
   int32_t hc[4] = {0, 0, 0, 0};
   PCPM_TRY_HIP(hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st));
@@ -1158,8 +1166,11 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(dalloc(g, &g->upd, g->eprime + 1));  // + spare slot for masked stores
   PCPM_TRY(dalloc(g, &g->hist, kMaxHist));
   PCPM_TRY(dalloc(g, &g->ctl, 1));
+  PCPM_TRY(dalloc(g, &g->psync, 1));
+  PCPM_TRY(dalloc(g, &g->bin_done, g->k));
   PCPM_TRY(dalloc(g, &g->tmp_pr, n));
   PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->ctl_host), sizeof(Ctl), hipHostMallocDefault));
+  PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->psync_host), sizeof(PSync), hipHostMallocDefault));
   PCPM_TRY(build_items(g, opts, st));
 
   // ---- weight statistics (scale of pcpm_spmv) -----------------------------------
@@ -1187,6 +1198,274 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   return PCPM_OK;
 }
 
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t* __restrict__ a, int64_t len, int32_t v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * 256)
+    a[i] = v;
+}
+
+// ---- measured choice of the configuration (part_log2 = 0) --------------------------
+// The paper chooses its partition size from a sweep of execution time over
+// partition sizes (Sec. 5.3.2, Figs. 11-14); the same sweep runs here on the
+// GPU at build time: every candidate q and update order is built and a few
+// iterations are timed, then the work-item chunks of the fastest are varied
+// (the items are rebuilt on the same PNG) and timed.  The winner is kept per
+// process, keyed by the graph's content hash, the options and the device.
+
+// Order-dependent 64-bit hash of an int32 array: the wrapping sum over i of
+// a mix of (salt, i, a[i]); equal arrays give equal sums whatever the order
+// of the additions.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_hash(const int32_t* __restrict__ a, int64_t len, uint64_t salt,
+                                              unsigned long long* __restrict__ out) {
+  uint64_t h = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < len;
+       i += static_cast<int64_t>(gridDim.x) * 256)
+    h += mix64(salt ^ mix64(static_cast<uint64_t>(i) * 0x100000001B3ull + static_cast<uint32_t>(a[i])));
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) h += __shfl_xor(h, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, static_cast<unsigned long long>(h));
+}
+
+static pcpm_status_t graph_hash(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col, hipStream_t st,
+                                uint64_t* out) {
+  unsigned long long* d = nullptr;
+  PCPM_TRY_HIP(hipMalloc(&d, 16));
+  pcpm_status_t rc = PCPM_OK;
+  do {
+    if (hipMemsetAsync(d, 0, 16, st) != hipSuccess) { rc = set_error(PCPM_ERR_DEVICE, "hash: memset failed"); break; }
+    const unsigned b1 = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((n + 256) / 256, 4096)));
+    hipLaunchKernelGGL(k_hash, dim3(b1), dim3(256), 0, st, row_off, n + 1, uint64_t{0x726F775F6F6666ull}, d);
+    if (m > 0) {
+      const unsigned b2 = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((m + 255) / 256, 8192)));
+      hipLaunchKernelGGL(k_hash, dim3(b2), dim3(256), 0, st, col, m, uint64_t{0x636F6C756D6Eull}, d + 1);
+    }
+    if (hipGetLastError() != hipSuccess) { rc = set_error(PCPM_ERR_DEVICE, "hash: launch failed"); break; }
+    unsigned long long h[2] = {0, 0};
+    if (hipMemcpyAsync(h, d, 16, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+      rc = set_error(PCPM_ERR_DEVICE, "hash: copy failed");
+      break;
+    }
+    *out = h[0] * 0x9E3779B97F4A7C15ull ^ h[1] ^ static_cast<uint64_t>(n) << 1 ^ static_cast<uint64_t>(m) << 33;
+  } while (false);
+  (void)hipFree(d);
+  return rc;
+}
+
+struct TuneRecord {
+  std::vector<pcpm_tune_entry_t> table;
+  int32_t best = -1;
+};
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneRecord> g_tune_cache;
+
+static std::string tune_key(int64_t n, int64_t m, uint64_t h, const pcpm_build_opts_t& o, int64_t mask, int device) {
+  hipDeviceProp_t prop;
+  std::string name = hipGetDeviceProperties(&prop, device) == hipSuccess ? prop.name : "?";
+  char buf[512];
+  uint64_t gh = 0;
+  if (o.num_graphs > 1)
+    for (int64_t i = 0; i <= o.num_graphs; ++i) gh = gh * 1000003ull + static_cast<uint64_t>(o.graph_node_off[i]);
+  std::snprintf(buf, sizeof buf, "dev=%d:%s;n=%lld;m=%lld;h=%016llx;G=%d;gh=%016llx;w=%d;v=%lld;mask=%llx;o=%lld;sc=%lld;"
+                "gc=%lld;bc=%lld", device, name.c_str(), static_cast<long long>(n), static_cast<long long>(m),
+                static_cast<unsigned long long>(h), o.num_graphs, static_cast<unsigned long long>(gh),
+                o.weights ? 1 : 0, static_cast<long long>(o.tune_vectors), static_cast<unsigned long long>(mask),
+                static_cast<long long>(o.update_order), static_cast<long long>(o.scatter_chunk),
+                static_cast<long long>(o.gather_chunk), static_cast<long long>(o.build_chunk));
+  return buf;
+}
+
+// Work items again with other chunk sizes on the same PNG (the buffers that
+// depend on the items are reallocated; the batched working set is dropped).
+static pcpm_status_t rebuild_items(pcpm_png* g, const pcpm_build_opts_t& o, hipStream_t st) {
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  for (void* p : {static_cast<void*>(g->sc_items), static_cast<void*>(g->ga_items), static_cast<void*>(g->mg_items),
+                  static_cast<void*>(g->partial), static_cast<void*>(g->red), static_cast<void*>(g->red_start),
+                  static_cast<void*>(g->group_slots)})
+    if (p) dfree(g, p);
+  g->sc_items = g->ga_items = nullptr;
+  g->mg_items = nullptr;
+  g->partial = nullptr;
+  g->red = g->red_start = nullptr;
+  g->group_slots = nullptr;
+  g->n_split_bins = g->n_split_slots = 0;
+  g->scatter_order = 0;
+  if (g->ppr_kt) {
+    for (void* p : {static_cast<void*>(g->ppr_x[0]), static_cast<void*>(g->ppr_x[1]),
+                    static_cast<void*>(g->ppr_upd), static_cast<void*>(g->ppr_partial),
+                    static_cast<void*>(g->ppr_red), static_cast<void*>(g->ppr_vctl), static_cast<void*>(g->ppr_mask)})
+      if (p) dfree(g, p);
+    g->ppr_x[0] = g->ppr_x[1] = g->ppr_upd = nullptr;
+    g->ppr_partial = nullptr;
+    g->ppr_red = nullptr;
+    g->ppr_vctl = nullptr;
+    g->ppr_mask = nullptr;
+    g->ppr_kt = 0;
+  }
+  return build_items(g, &o, st);
+}
+
+// Time per iteration (per vector-iteration for vectors > 1) of a handle:
+// a warm-up, then `reps` runs of `iters` iterations.
+static pcpm_status_t time_handle(pcpm_png* g, int64_t vectors, float* work, hipStream_t st, double* ms) {
+  constexpr int kIters = 4, kReps = 2;
+  int kv = 1;
+  std::vector<int32_t> off, seeds;
+  if (vectors > 1) {  // kv seed sets of `per` consecutive nodes
+    kv = static_cast<int>(std::min<int64_t>(vectors, pcpm_ppr_tile_width(g)));
+    const int per = static_cast<int>(std::min<int64_t>(8, g->n));
+    for (int j = 0; j <= kv; ++j) off.push_back(j * per);
+    for (int j = 0; j < kv; ++j)
+      for (int i = 0; i < per; ++i)
+        seeds.push_back(static_cast<int32_t>((static_cast<int64_t>(j) * 7919 * per + i) % g->n));
+  }
+  std::vector<int32_t> it(kv);
+  std::vector<double> res(kv);
+  auto run = [&](int iters) -> pcpm_status_t {
+    int32_t i1 = 0;
+    double r1 = 0.0;
+    if (g->matrix) {  // a matrix: the SpMV itself (x and y in the two halves of work)
+      for (int i = 0; i < iters; ++i) PCPM_TRY(pcpm_spmv(g, work, work + g->n, st));
+      return hipStreamSynchronize(st) == hipSuccess ? PCPM_OK : set_error(PCPM_ERR_DEVICE, "sync failed");
+    }
+    if (vectors > 1)
+      return pcpm_ppr_batch(g, 0.85, kv, off.data(), seeds.data(), 0.0, iters, work, it.data(), res.data(), st);
+    return pcpm_pagerank(g, 0.85, 0.0, iters, nullptr, work, &i1, &r1, nullptr, st);
+  };
+  PCPM_TRY(run(2));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int r = 0; r < kReps; ++r) PCPM_TRY(run(kIters));
+  const double total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *ms = total / (kReps * kIters) / kv;
+  return PCPM_OK;
+}
+
+static pcpm_status_t tuned_build(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col,
+                                 const pcpm_build_opts_t* opts, hipStream_t st, pcpm_png** out) {
+  pcpm_build_opts_t o{};
+  if (opts) o = *opts;
+  int device = 0;
+  PCPM_TRY_HIP(hipGetDevice(&device));
+  const int64_t mask = o.tune_log2_mask ? o.tune_log2_mask : ((1 << 12) | (1 << 13) | (1 << 14));
+  if (mask & ~((int64_t{1} << (kMaxLog2 + 1)) - (int64_t{1} << kMinLog2)))
+    return set_error(PCPM_ERR_INVALID_ARG, "tune_log2_mask 0x%llx has bits outside [%d, %d]",
+                     static_cast<unsigned long long>(mask), kMinLog2, kMaxLog2);
+  if (o.num_graphs > 1 && !o.graph_node_off) return set_error(PCPM_ERR_INVALID_ARG, "graph_node_off is NULL");
+  uint64_t h = 0;
+  PCPM_TRY(graph_hash(n, m, row_off, col, st, &h));
+  const std::string key = tune_key(n, m, h, o, mask, device);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto hit = g_tune_cache.find(key);
+    if (hit != g_tune_cache.end()) {
+      const pcpm_tune_entry_t& e = hit->second.table[hit->second.best];
+      pcpm_build_opts_t b = o;
+      b.part_log2 = e.part_log2;
+      b.update_order = e.update_order;
+      b.scatter_chunk = e.scatter_chunk;
+      b.gather_chunk = e.gather_chunk;
+      pcpm_png* g = nullptr;
+      PCPM_TRY(pcpm_build_png(n, m, row_off, col, &b, st, &g));
+      g->tune_table = hit->second.table;
+      g->tune_best = hit->second.best;
+      g->tune_cached = 1;
+      *out = g;
+      return PCPM_OK;
+    }
+  }
+  // timing output: n * min(v, 16) floats
+  float* work = nullptr;
+  const int64_t wv = o.tune_vectors > 1 ? std::min<int64_t>(o.tune_vectors, 16) : 2;
+  const int64_t wn = std::max<int64_t>(n, o.num_cols);
+  PCPM_TRY_HIP(hipMalloc(&work, static_cast<size_t>(wn) * wv * sizeof(float)));
+  PCPM_TRY_HIP(hipMemsetAsync(work, 0, static_cast<size_t>(wn) * wv * sizeof(float), st));
+  struct Guard {
+    float* w;
+    pcpm_png* best = nullptr;
+    ~Guard() {
+      if (w) (void)hipFree(w);
+      if (best) free_handle(best);
+    }
+  } guard{work};
+  std::vector<pcpm_tune_entry_t> table;
+  int32_t best = -1;
+  pcpm_build_opts_t best_opts = o;
+  const int64_t orders[2] = {1, 2};
+  for (int s = kMinLog2; s <= kMaxLog2; ++s) {
+    if (!((mask >> s) & 1)) continue;
+    const int64_t q = int64_t{1} << s;
+    if ((n + q - 1) / q > kMaxParts) continue;
+    bool aligned = true;
+    for (int64_t i = 0; o.num_graphs > 1 && i <= o.num_graphs; ++i) aligned &= (o.graph_node_off[i] % q) == 0;
+    if (!aligned) continue;
+    for (int64_t order : orders) {
+      if (o.update_order && order != o.update_order) continue;
+      pcpm_build_opts_t b = o;
+      b.part_log2 = s;
+      b.update_order = order;
+      pcpm_png* g = nullptr;
+      const auto t0 = std::chrono::steady_clock::now();
+      PCPM_TRY(pcpm_build_png(n, m, row_off, col, &b, st, &g));
+      const double bms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      double ms = 0.0;
+      const pcpm_status_t rc = time_handle(g, o.tune_vectors, work, st, &ms);
+      if (rc != PCPM_OK) {
+        free_handle(g);
+        return rc;
+      }
+      table.push_back({s, static_cast<int32_t>(order), o.scatter_chunk, o.gather_chunk, ms, bms});
+      if (best < 0 || ms < table[best].ms_per_iter) {
+        best = static_cast<int32_t>(table.size() - 1);
+        best_opts = b;
+        if (guard.best) free_handle(guard.best);
+        guard.best = g;
+      } else {
+        free_handle(g);
+      }
+    }
+  }
+  if (best < 0) return set_error(PCPM_ERR_INVALID_ARG, "no autotune candidate fits this graph");
+  // work-item chunks of the fastest PNG: the automatic value, half and double
+  pcpm_png* g = guard.best;
+  const int64_t auto_sc = std::max<int64_t>(2 * ((g->eprime + g->k - 1) / g->k), 65536);
+  const int64_t auto_gc = std::max<int64_t>(2 * ((g->m + g->k - 1) / g->k), 65536);
+  for (int field = 0; field < 2; ++field) {
+    if ((field == 0 ? o.gather_chunk : o.scatter_chunk) != 0) continue;  // fixed by the caller
+    const int64_t a = field == 0 ? auto_gc : auto_sc;
+    for (int64_t c : {a / 2, a * 2}) {
+      pcpm_build_opts_t b = best_opts;
+      (field == 0 ? b.gather_chunk : b.scatter_chunk) = std::max<int64_t>(c, 4096);
+      PCPM_TRY(rebuild_items(g, b, st));
+      double ms = 0.0;
+      PCPM_TRY(time_handle(g, o.tune_vectors, work, st, &ms));
+      table.push_back({b.part_log2, static_cast<int32_t>(b.update_order), b.scatter_chunk, b.gather_chunk, ms, 0.0});
+      if (ms < table[best].ms_per_iter) {
+        best = static_cast<int32_t>(table.size() - 1);
+        best_opts = b;
+      }
+    }
+  }
+  PCPM_TRY(rebuild_items(g, best_opts, st));
+  g->tune_table = table;
+  g->tune_best = best;
+  g->tune_cached = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    TuneRecord& rec = g_tune_cache[key];
+    rec.table = table;
+    rec.best = best;
+  }
+  guard.best = nullptr;
+  *out = g;
+  return PCPM_OK;
+}
+
 }  // namespace pcpm
 
 extern "C" {
@@ -1203,14 +1482,49 @@ pcpm_status_t pcpm_build_png(int64_t n, int64_t m, const int32_t* row_off, const
   if (!is_device_ptr(row_off) || (m > 0 && !is_device_ptr(col)))
     return set_error(PCPM_ERR_INVALID_ARG, "row_off and col must be device pointers");
   const auto t0 = std::chrono::steady_clock::now();
+  if (opts && opts->part_log2 == 0) {  // autotune: the sweep builds and times candidates
+    pcpm_png* tg = nullptr;
+    PCPM_TRY(tuned_build(n, m, row_off, col, opts, static_cast<hipStream_t>(stream), &tg));
+    tg->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = tg;
+    return PCPM_OK;
+  }
+  // a matrix (generic SpMV, Sec. 3.5): n rows, num_cols columns, possibly
+  // diagonal entries; its node slots cover max(rows, cols), rows past n empty
+  const int64_t ncols = (opts && opts->num_cols > 0) ? opts->num_cols : n;
+  const bool matrix = ncols != n || (opts && opts->allow_diagonal);
+  if (ncols >= (int64_t{1} << 31)) return set_error(PCPM_ERR_OVERFLOW, "num_cols must be below 2^31");
+  if (matrix && opts->num_graphs > 1) return set_error(PCPM_ERR_INVALID_ARG, "a matrix handle holds one matrix");
   pcpm_png* g = new (std::nothrow) pcpm_png();
   if (!g) return set_error(PCPM_ERR_OOM, "host allocation failed");
   if (hipGetDevice(&g->device) != hipSuccess) {
     delete g;
     return set_error(PCPM_ERR_DEVICE, "no current HIP device");
   }
+  g->n_rows = n;
+  g->n_cols = ncols;
+  g->matrix = matrix;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  pcpm_status_t rc = build(n, m, row_off, col, opts, st, g);
+  const int64_t nslots = std::max(n, ncols);
+  int32_t* ext = nullptr;  // row offsets over every node slot
+  pcpm_status_t rc = PCPM_OK;
+  if (nslots > n) {
+    if (hipMalloc(&ext, static_cast<size_t>(nslots + 1) * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      free_handle(g);
+      return set_error(PCPM_ERR_OOM, "row offset extension of %lld entries", static_cast<long long>(nslots + 1));
+    }
+    if (hipMemcpyAsync(ext, row_off, static_cast<size_t>(n + 1) * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      rc = set_error(PCPM_ERR_DEVICE, "row offset copy failed");
+    else
+      hipLaunchKernelGGL(k_fill_i32, dim3(static_cast<unsigned>(std::min<int64_t>((nslots - n + 255) / 256, 4096))),
+                         dim3(256), 0, st, ext + n + 1, nslots - n, static_cast<int32_t>(m));
+  }
+  if (rc == PCPM_OK) rc = build(nslots, m, ext ? ext : row_off, col, opts, st, g);
+  if (ext) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(ext);
+  }
   if (rc != PCPM_OK) {
     (void)hipStreamSynchronize(st);
     free_handle(g);
@@ -1219,6 +1533,30 @@ pcpm_status_t pcpm_build_png(int64_t n, int64_t m, const int32_t* row_off, const
   g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = g;
   return PCPM_OK;
+}
+
+int32_t pcpm_tune_table(pcpm_png_t g, pcpm_tune_entry_t* out, int32_t max_entries, int32_t* best, int32_t* cached) {
+  if (!g) return 0;
+  const int32_t cnt = static_cast<int32_t>(g->tune_table.size());
+  for (int32_t i = 0; out && i < std::min(cnt, max_entries); ++i) out[i] = g->tune_table[i];
+  if (best) *best = g->tune_best;
+  if (cached) *cached = g->tune_cached;
+  return cnt;
+}
+
+void pcpm_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(pcpm::g_tune_mu);
+  pcpm::g_tune_cache.clear();
+}
+
+pcpm_status_t pcpm_graph_hash(int64_t n, int64_t m, const int32_t* row_off, const int32_t* col, void* stream,
+                              uint64_t* out) {
+  using namespace pcpm;
+  if (!out || n < 1 || m < 0 || !row_off || (m > 0 && !col))
+    return set_error(PCPM_ERR_INVALID_ARG, "bad size, NULL array or NULL output");
+  if (!is_device_ptr(row_off) || (m > 0 && !is_device_ptr(col)))
+    return set_error(PCPM_ERR_INVALID_ARG, "row_off and col must be device pointers");
+  return graph_hash(n, m, row_off, col, static_cast<hipStream_t>(stream), out);
 }
 
 pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out) {
@@ -1239,6 +1577,9 @@ pcpm_status_t pcpm_png_info(pcpm_png_t g, pcpm_png_info_t* out) {
   out->build_ms = g->build_ms;
   out->weighted = g->wbin ? 1 : 0;
   out->update_order = g->png_order ? 2 : 1;
+  out->num_cols = g->n_cols;
+  out->matrix = g->matrix ? 1 : 0;
+  if (g->matrix) out->n = g->n_rows;
   return PCPM_OK;
 }
 

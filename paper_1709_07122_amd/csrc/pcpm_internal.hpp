@@ -113,6 +113,20 @@ struct PprQueue {
   int32_t new_vec[16];
 };
 
+// Device state of a persistent solve (one cooperative launch runs all of a
+// solve's iterations): a grid barrier, work counters, and the flag of a
+// bounded wait that gave up.  On cache lines of its own, away from the
+// control block that every workgroup reads.
+struct alignas(256) PSync {
+  uint32_t bar_count;       // workgroups arrived at the current barrier
+  uint32_t bar_gen;         // barriers completed
+  int32_t err;              // a wait ran past its spin limit
+  int32_t applied;          // apply units finished, counted over the whole solve
+  int32_t ga_next;          // next gather item of this iteration
+  int32_t mg_next;          // next merge unit of this iteration
+  int32_t sc_next[kXcds];   // next scatter item of each XCD's range
+};
+
 // A unit of scatter or gather work: a contiguous range [lo, hi) of PNG edges
 // (scatter, part = source partition) or of destination IDs (gather, part =
 // destination partition).  aux: gather partial slot (-1 = whole bin).
@@ -125,6 +139,74 @@ struct Item {
 // starting at `first`.
 struct Merge {
   int32_t part, first, count, node_lo;
+};
+
+// Arguments of the persistent kernels (passed by value).
+struct PersistArgs {
+  Ctl* ctl;
+  GCtl* gctl;
+  PSync* ps;
+  int32_t* bin_done;
+  int64_t n, k;
+  int32_t s, n_sc, n_ga, n_mg, n_apply, max_iters;
+  uint32_t spin_limit;
+  const Item* sc_items;
+  const Item* ga_items;
+  const Merge* mg_items;
+  const int32_t* outdeg;
+  const uint16_t* png_src;
+  const int32_t* png_blk;
+  const int32_t* seg_delta;
+  float* upd;
+  int64_t spare;
+  const uint16_t* did;
+  const int32_t* did_blk;
+  const int32_t* did_sblk;
+  const uint32_t* dmask;
+  int64_t* partial;
+  double* red;
+  const int32_t* part_group;
+  const int32_t* part_valid;
+  const int32_t* group_slots;
+  double* hist;
+  float* x0;  // input of even iterations (the caller's output vector)
+  float* x1;  // input of odd iterations
+};
+
+struct PprPersistArgs {
+  Ctl* ctl;
+  VCtl* vctl;
+  PSync* ps;
+  int32_t* bin_done;
+  PprQueue* queue;
+  int64_t n, k, max_loops, spare;
+  int32_t s, n_sc, n_ga, n_mg, n_apply, kvec, refill;
+  uint32_t spin_limit;
+  double d;
+  const Item* sc_items;
+  const Item* ga_items;
+  const Merge* mg_items;
+  const int32_t* outdeg;
+  const uint16_t* png_src;
+  const int32_t* png_blk;
+  const int32_t* seg_delta;
+  float* upd;
+  const uint16_t* did;
+  const int32_t* did_blk;
+  const int32_t* did_sblk;
+  const uint32_t* dmask;
+  uint32_t* seedmask;
+  int64_t* partial;
+  double* red;
+  double* hist;
+  int32_t* out_it;
+  double* out_res;
+  int32_t* out_conv;
+  float* pr_out;
+  const int32_t* seeds;
+  const int32_t* seed_off;
+  float* x0;  // iterate tile read by even iterations
+  float* x1;
 };
 
 // ---- errors ----------------------------------------------------------------
@@ -201,6 +283,11 @@ __device__ __forceinline__ void unpack_tile(const uint32_t (&w)[kPairs], uint32_
 // ---- the handle ------------------------------------------------------------------
 struct pcpm_png {
   int64_t n = 0, m = 0, q = 0, k = 0, eprime = 0, nseg = 0, n_dangling = 0;
+  // rows and columns (n for a graph); a matrix handle (generic SpMV, Sec.
+  // 3.5: num_cols != rows or diagonal entries) has n = max(rows, cols) node
+  // slots, its scatter reading rows and its gather writing columns
+  int64_t n_rows = 0, n_cols = 0;
+  bool matrix = false;
   int part_log2 = 0;
   int device = 0;
   double build_ms = 0.0;
@@ -254,6 +341,16 @@ struct pcpm_png {
   pcpm::GCtl* gctl_host = nullptr;  // pinned mirror
   std::vector<int64_t> group_off, group_n;  // host copies
 
+  // persistent solves: grid barrier and work counters, finished split-bin
+  // items per bin (counted over a solve), workgroups of the cooperative
+  // launch (0: not possible on this device), launch mode (pcpm_set_launch)
+  pcpm::PSync* psync = nullptr;
+  pcpm::PSync* psync_host = nullptr;  // pinned mirror
+  int32_t* bin_done = nullptr;    // k
+  int32_t persist_grid = -1;      // -1: not yet queried
+  int32_t launch_mode = 0;
+  uint32_t spin_limit = 1u << 22; // polls before a device-side wait gives up
+
   // reductions and control
   double* red = nullptr;        // 3*(k + n_mg): (residual, dangling, -) partial sums per apply unit
   double* red_start = nullptr;  // 4*k: (non-finite count, dangling, L1 mass) of the start vector per partition,
@@ -287,6 +384,11 @@ struct pcpm_png {
   uint32_t* ws_indeg = nullptr;          // n
   float* ws_x = nullptr;                 // 2n
   double ws_indeg_ms = 0.0;
+
+  // autotuned builds (part_log2 = 0): the measurements and the chosen entry
+  std::vector<pcpm_tune_entry_t> tune_table;
+  int32_t tune_best = -1;
+  int32_t tune_cached = 0;
 
   std::vector<std::pair<void*, size_t>> allocations;
 };

@@ -57,14 +57,18 @@ constexpr int kMergeNodes = 256;  // nodes per merge workgroup (one per thread)
 //   x_new(v) = d * acc(v) + base_g,  base_g = (1-d)/n_g + d*D_g/n_g
 // for the partition's group g, plus their share of sum |x_new - x_old| and of
 // the next dangling mass.  Padding nodes (past the group's last node) stay 0;
-// a converged group keeps its iterate.
-template <int BS, class AccFn>
+// a converged group keeps its iterate.  G > 1: the workgroup holds G groups
+// of BS threads, each applying its own range (an empty one, with red_slot
+// NULL, for a group without work); every thread calls it, and each group
+// computes exactly what a workgroup of BS threads computes.
+template <int BS, class AccFn, int G = 1>
 __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const GCtl* __restrict__ gctl,
                                             const int32_t* __restrict__ part_group,
                                             const int32_t* __restrict__ part_valid, int part, int64_t v0, int i0,
                                             int i1, AccFn acc, const float* __restrict__ pr_in,
                                             float* __restrict__ pr_out, const uint32_t* __restrict__ dmask,
                                             double* __restrict__ red_slot) {
+  const int tid = static_cast<int>(threadIdx.x % BS);
   const GCtl& gc = gctl[part_group[part]];
   const double base = gc.base;
   const bool frozen = gc.done != 0;
@@ -76,7 +80,7 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
   // kU nodes per thread per step, loads first, so their latencies overlap;
   // a 1024-thread gather covers a whole 16K-node slice in one step
   constexpr int kU = BS >= 1024 ? 16 : 4;
-  for (int i = i0 + static_cast<int>(threadIdx.x); i < i1; i += kU * BS) {
+  for (int i = i0 + tid; i < i1; i += kU * BS) {
     float xo[kU];
     uint32_t dw[kU];
 #pragma unroll
@@ -103,29 +107,26 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
       }
     }
   }
-  block_sum<BS>(sums);
-  const double vmax = block_max<BS>(static_cast<double>(mx));
-  if (threadIdx.x == 0) {
+  group_sum<BS, G>(sums);
+  const double vmax = group_max<BS, G>(static_cast<double>(mx));
+  if (tid == 0 && red_slot) {
     red_slot[0] = sums[0];
     red_slot[1] = sums[1];
     red_slot[2] = vmax;
   }
 }
 
+// One scatter item (a range of one source pair's PNG edges) by the whole
+// workgroup; spr is its LDS staging area (2q floats).
 // kScale: stage PR(u)/outdeg(u) (PageRank); otherwise x(u) itself (SpMV).
 // kPng: updates in PNG order, else in bin order.
 template <int BS, bool kScale, bool kPng>
-__global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
-                                                const Item* __restrict__ items, const float* __restrict__ pr,
-                                                const int32_t* __restrict__ outdeg,
-                                                const uint16_t* __restrict__ png_src,
-                                                const int32_t* __restrict__ png_blk,
-                                                const int32_t* __restrict__ seg_delta, float* __restrict__ upd,
-                                                int64_t spare) {
-  if (ctl->done) return;
-  extern __shared__ float spr[];
-  // XCD-contiguous renumbering (the build arranges the item array for it)
-  const Item it = items[xcd_block(blockIdx.x, gridDim.x)];
+__device__ __forceinline__ void scatter_item(const Item it, float* __restrict__ spr, int64_t n, int s,
+                                             const float* __restrict__ pr, const int32_t* __restrict__ outdeg,
+                                             const uint16_t* __restrict__ png_src,
+                                             const int32_t* __restrict__ png_blk,
+                                             const int32_t* __restrict__ seg_delta, float* __restrict__ upd,
+                                             int64_t spare) {
   // a scatter item covers PNG edges of one partition pair: stage both slices
   const int64_t v0 = static_cast<int64_t>(it.part) << (s + 1);
   const int qn = static_cast<int>(min(int64_t{2} << s, n - v0));
@@ -204,26 +205,40 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
   }
 }
 
+template <int BS, bool kScale, bool kPng>
+__global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                const Item* __restrict__ items, const float* __restrict__ pr,
+                                                const int32_t* __restrict__ outdeg,
+                                                const uint16_t* __restrict__ png_src,
+                                                const int32_t* __restrict__ png_blk,
+                                                const int32_t* __restrict__ seg_delta, float* __restrict__ upd,
+                                                int64_t spare) {
+  if (ctl->done) return;
+  extern __shared__ float spr[];
+  // XCD-contiguous renumbering (the build arranges the item array for it)
+  scatter_item<BS, kScale, kPng>(items[xcd_block(blockIdx.x, gridDim.x)], spr, n, s, pr, outdeg, png_src, png_blk,
+                                 seg_delta, upd, spare);
+}
+
 // kMode 0: PageRank (apply, residual, dangling mass); 1: SpMV, y(v) = sum of
 // the updates; 2: SpMV with the edge weight stored beside each destination ID
 // applied to its update (Sec. 3.5).  In SpMV modes pr_out receives y.
 // kPng: updates in PNG order (an ID's update is at its message index plus
 // its segment's delta), else in bin order (at its message index).
+// One gather item (a range of one bin's destination IDs) by the whole
+// workgroup; acc is its LDS slice (q 64-bit sums).
 template <int BS, int kMode, bool kPng>
-__global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
-                                               const Item* __restrict__ items, const uint16_t* __restrict__ did,
-                                               const int32_t* __restrict__ did_blk,
-                                               const int32_t* __restrict__ did_sblk,
-                                               const int32_t* __restrict__ seg_delta, const float* __restrict__ upd,
-                                               const float* __restrict__ pr_in, float* __restrict__ pr_out,
-                                               const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
-                                               double* __restrict__ red, const GCtl* __restrict__ gctl,
-                                               const int32_t* __restrict__ part_group,
-                                               const int32_t* __restrict__ part_valid,
-                                               const float* __restrict__ wbin) {
-  if (ctl->done) return;
-  extern __shared__ unsigned long long acc[];
-  const Item it = items[blockIdx.x];
+__device__ __forceinline__ void gather_item(const Item it, unsigned long long* __restrict__ acc,
+                                            const Ctl* __restrict__ ctl, int64_t n, int s,
+                                            const uint16_t* __restrict__ did, const int32_t* __restrict__ did_blk,
+                                            const int32_t* __restrict__ did_sblk,
+                                            const int32_t* __restrict__ seg_delta, const float* __restrict__ upd,
+                                            const float* __restrict__ pr_in, float* __restrict__ pr_out,
+                                            const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
+                                            double* __restrict__ red, const GCtl* __restrict__ gctl,
+                                            const int32_t* __restrict__ part_group,
+                                            const int32_t* __restrict__ part_valid,
+                                            const float* __restrict__ wbin) {
   const int64_t q = int64_t{1} << s;
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
@@ -327,6 +342,48 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
                   [&](int i) { return static_cast<int64_t>(acc[i]); }, pr_in, pr_out, dmask, red + 3 * it.part);
 }
 
+template <int BS, int kMode, bool kPng>
+__global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                               const Item* __restrict__ items, const uint16_t* __restrict__ did,
+                                               const int32_t* __restrict__ did_blk,
+                                               const int32_t* __restrict__ did_sblk,
+                                               const int32_t* __restrict__ seg_delta, const float* __restrict__ upd,
+                                               const float* __restrict__ pr_in, float* __restrict__ pr_out,
+                                               const uint32_t* __restrict__ dmask, int64_t* __restrict__ partial,
+                                               double* __restrict__ red, const GCtl* __restrict__ gctl,
+                                               const int32_t* __restrict__ part_group,
+                                               const int32_t* __restrict__ part_valid,
+                                               const float* __restrict__ wbin) {
+  if (ctl->done) return;
+  extern __shared__ unsigned long long acc[];
+  gather_item<BS, kMode, kPng>(items[blockIdx.x], acc, ctl, n, s, did, did_blk, did_sblk, seg_delta, upd, pr_in,
+                               pr_out, dmask, partial, red, gctl, part_group, part_valid, wbin);
+}
+
+// Merge unit u of split bins: its nodes' partial slices summed in order, then
+// applied; its residual / dangling / largest-value triple goes to slot
+// red_base + u.
+// G > 1: G groups of BS threads, group g takes unit u (u < 0: no unit);
+// every thread of the workgroup calls it.
+template <int BS, int G = 1>
+__device__ __forceinline__ void merge_unit(const Merge mu, int64_t u, const Ctl* __restrict__ ctl, int64_t n, int s,
+                                           const int64_t* __restrict__ partial, const float* __restrict__ pr_in,
+                                           float* __restrict__ pr_out, const uint32_t* __restrict__ dmask,
+                                           double* __restrict__ red, int64_t red_base,
+                                           const GCtl* __restrict__ gctl, const int32_t* __restrict__ part_group,
+                                           const int32_t* __restrict__ part_valid) {
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  const int64_t* base = partial + static_cast<int64_t>(mu.first) * q;
+  const int cnt = mu.count;
+  auto acc = [&](int i) { return sum_slices(base + i, cnt, q); };
+  const bool has = u >= 0;
+  apply_nodes<BS, decltype(acc), G>(ctl, gctl, part_group, part_valid, mu.part, v0, has ? mu.node_lo : 0,
+                                    has ? min(qn, mu.node_lo + kMergeNodes) : 0, acc, pr_in, pr_out, dmask,
+                                    has ? red + 3 * (red_base + u) : nullptr);
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void k_merge(const Ctl* __restrict__ ctl, int64_t n, int s,
                                               const Merge* __restrict__ mg, const int64_t* __restrict__ partial,
@@ -336,15 +393,8 @@ __global__ __launch_bounds__(BS) void k_merge(const Ctl* __restrict__ ctl, int64
                                               const int32_t* __restrict__ part_group,
                                               const int32_t* __restrict__ part_valid) {
   if (ctl->done) return;
-  const Merge mu = mg[blockIdx.x];
-  const int64_t q = int64_t{1} << s;
-  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
-  const int qn = static_cast<int>(min(q, n - v0));
-  const int64_t* base = partial + static_cast<int64_t>(mu.first) * q;
-  const int cnt = mu.count;
-  auto acc = [&](int i) { return sum_slices(base + i, cnt, q); };
-  apply_nodes<BS>(ctl, gctl, part_group, part_valid, mu.part, v0, mu.node_lo, min(qn, mu.node_lo + kMergeNodes),
-                  acc, pr_in, pr_out, dmask, red + 3 * (red_base + blockIdx.x));
+  merge_unit<BS>(mg[blockIdx.x], blockIdx.x, ctl, n, s, partial, pr_in, pr_out, dmask, red, red_base, gctl,
+                 part_group, part_valid);
 }
 
 // Per-group totals of the apply units' (residual, dangling, mass) partial
@@ -384,52 +434,73 @@ __device__ __forceinline__ void group_sums_block(const int32_t* __restrict__ gro
 
 // End of an iteration: per-group residual, next dangling mass and base, group
 // convergence; then the largest residual, the iteration count and the flag
-// that makes the kernels of later iterations return at once.
-__global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
-                                                   const int32_t* __restrict__ group_slots,
-                                                   const double* __restrict__ red, int64_t k, int64_t nslots,
-                                                   double* __restrict__ hist) {
-  if (ctl->done) return;
+// that makes the kernels of later iterations return at once.  One workgroup
+// of 1024 threads.
+// Each group's control struct is read and written by one thread only, and
+// the workgroup-wide results (largest residual, all converged) go through
+// LDS: stores of different wavefronts to global memory are not ordered by a
+// workgroup barrier.
+__device__ __forceinline__ void finalize_body(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
+                                              const int32_t* __restrict__ group_slots,
+                                              const double* __restrict__ red, int64_t k, int64_t nslots,
+                                              double* __restrict__ hist) {
   double vmax = 0.0;  // largest value of the new iterate over all apply units
   for (int64_t j = threadIdx.x; j < nslots; j += 1024) vmax = fmax(vmax, red[3 * j + 2]);
   vmax = block_max<1024>(vmax);
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
+  constexpr int kW = 1024 / kWave;
+  __shared__ int s_bad[kW], s_done[kW];
+  __shared__ double s_rmax[kW];
   const int G = ctl->ngroups;
   const double d = ctl->d, tol = ctl->tol;
-  auto update = [&](int grp, const double (&sm)[3]) {
+  // the group's update; returns its residual and convergence after it
+  auto update = [&](int grp, const double (&sm)[3], int& bad) -> GCtl {
     GCtl& gc = gctl[grp];
     if (!gc.done) {
       gc.res = sm[0];
       gc.iter += 1;
       gc.dmass = sm[1];
       gc.base = (1.0 - d) * gc.inv_n + d * sm[1] * gc.inv_n;
-      if (!isfinite(sm[0]) || !isfinite(sm[1])) atomicOr(&bad, 1);
+      if (!isfinite(sm[0]) || !isfinite(sm[1])) bad = 1;
       else if (tol > 0.0 && sm[0] < tol) gc.done = 1;
     }
+    return gc;
   };
-  if (G < 1024 / kWave) {  // few groups: the whole workgroup sums each one
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  int bad = 0, all_done = 1;
+  double rmax = 0.0;
+  if (G < kW) {  // few groups: the whole workgroup sums each one, thread 0 updates it
     for (int grp = 0; grp < G; ++grp) {
       double sm[3];
       group_sums_block(group_slots, red, k, grp, sm);
-      if (threadIdx.x == 0) update(grp, sm);
+      if (threadIdx.x == 0) {
+        const GCtl gc = update(grp, sm, bad);
+        rmax = fmax(rmax, gc.res);
+        all_done &= gc.done;
+      }
       __syncthreads();
     }
-  } else {  // one wavefront per group
-    for (int grp = threadIdx.x / kWave; grp < G; grp += 1024 / kWave) {
+  } else {  // one wavefront per group, lane 0 updates it
+    for (int grp = w; grp < G; grp += kW) {
       double sm[3];
       group_sums(group_slots, red, k, grp, true, sm);
-      if ((threadIdx.x & (kWave - 1)) == 0) update(grp, sm);
+      if (lane == 0) {
+        const GCtl gc = update(grp, sm, bad);
+        rmax = fmax(rmax, gc.res);
+        all_done &= gc.done;
+      }
     }
+  }
+  if (lane == 0) {
+    s_bad[w] = bad;
+    s_done[w] = all_done;
+    s_rmax[w] = rmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double rmax = 0.0;
-    int all_done = 1;
-    for (int grp = 0; grp < G; ++grp) {
-      rmax = fmax(rmax, gctl[grp].res);
-      all_done &= gctl[grp].done;
+    for (int ww = 1; ww < kW; ++ww) {
+      bad |= s_bad[ww];
+      all_done &= s_done[ww];
+      rmax = fmax(rmax, s_rmax[ww]);
     }
     if (bad) rmax = NAN;
     const int32_t it = ctl->iter;
@@ -440,6 +511,97 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* 
     if (bad) ctl->nonfinite = 1;
     if (bad || all_done) ctl->done = 1;
     ctl->fx_shift = fx_shift_for(vmax, ctl->fx_cap);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
+                                                   const int32_t* __restrict__ group_slots,
+                                                   const double* __restrict__ red, int64_t k, int64_t nslots,
+                                                   double* __restrict__ hist) {
+  if (ctl->done) return;
+  finalize_body(ctl, gctl, group_slots, red, k, nslots, hist);
+}
+
+// ---- persistent solve ------------------------------------------------------------------
+// Every iteration of a solve in one cooperative launch (every workgroup
+// resident, one per CU at a 128 KB slice).  Per iteration:
+//   1. scatter items, each XCD's workgroups taking its contiguous range;
+//   2. grid barrier;
+//   3. gather items (largest first), then merge units, from one counter; a
+//      split bin's items count themselves finished in bin_done, and its
+//      merge units wait for that count; every apply unit (a whole-bin item
+//      or a merge unit) counts itself finished, and the workgroup that
+//      finishes the last one runs the finalize (FP64 sums, convergence);
+//   4. grid barrier (its last arrival resets the work counters); every
+//      workgroup reads the convergence flag and leaves when it is set.
+// Waits are bounded (PSync::err), so the kernel ends in every case.
+
+__global__ __launch_bounds__(256) void k_persist_init(PSync* __restrict__ ps, int32_t* __restrict__ bin_done,
+                                                      int64_t k) {
+  for (int64_t p = threadIdx.x; p < k; p += 256) bin_done[p] = 0;
+  if (threadIdx.x == 0) {
+    ps->bar_count = 0;
+    ps->bar_gen = 0;
+    ps->err = 0;
+    ps->applied = 0;
+    ps->ga_next = 0;
+    ps->mg_next = 0;
+    for (unsigned x = 0; x < kXcds; ++x) ps->sc_next[x] = 0;
+  }
+}
+
+template <bool kPng>
+__global__ __launch_bounds__(1024) void k_persist(const PersistArgs a) {
+  constexpr int BS = 1024;
+  constexpr int kMG = BS / kMergeNodes;  // merge units per workgroup, one per group of 256 threads
+  extern __shared__ unsigned long long lds[];
+  PSync* ps = a.ps;
+  auto reset = [&]() {  // by the last arrival at the iteration's second barrier
+    for (unsigned x = 0; x < kXcds; ++x) __hip_atomic_store(&ps->sc_next[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ps->ga_next, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ps->mg_next, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ps->applied, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  for (int32_t it = 0; it < a.max_iters; ++it) {
+    const float* in = (it & 1) ? a.x1 : a.x0;
+    float* out = (it & 1) ? a.x0 : a.x1;
+    for (;;) {
+      const int32_t j = grab_scatter(ps, a.n_sc);
+      if (j < 0) break;
+      scatter_item<BS, true, kPng>(a.sc_items[j], reinterpret_cast<float*>(lds), a.n, a.s, in, a.outdeg, a.png_src,
+                                   a.png_blk, a.seg_delta, a.upd, a.spare);
+    }
+    if (!grid_sync(ps, a.spin_limit, [] {})) return;
+    for (;;) {  // gather items, largest first
+      const int32_t j = grab(&ps->ga_next);
+      if (j >= a.n_ga) break;
+      const Item itm = a.ga_items[j];
+      gather_item<BS, 0, kPng>(itm, lds, a.ctl, a.n, a.s, a.did, a.did_blk, a.did_sblk, a.seg_delta, a.upd, in, out,
+                               a.dmask, a.partial, a.red, a.gctl, a.part_group, a.part_valid, nullptr);
+      if (itm.aux >= 0) {  // a split bin's slice: applied by its merge units
+        publish(&a.bin_done[itm.part]);
+      } else if (publish(&ps->applied) == a.n_apply - 1) {  // the iteration's last apply unit
+        finalize_body(a.ctl, a.gctl, a.group_slots, a.red, a.k, a.k + a.n_mg, a.hist);
+      }
+    }
+    for (;;) {  // merge units of split bins, kMG at a time
+      const int32_t u0 = grab(&ps->mg_next, kMG);
+      if (u0 >= a.n_mg) break;
+      const int32_t cnt = min(kMG, a.n_mg - u0);
+      for (int32_t c = 0; c < cnt; ++c) {  // every bin of these units has all its slices
+        const Merge mc = a.mg_items[u0 + c];
+        if (c > 0 && mc.part == a.mg_items[u0 + c - 1].part) continue;
+        const int32_t target = static_cast<int32_t>(static_cast<uint32_t>(mc.count) * static_cast<uint32_t>(it + 1));
+        if (!wait_at_least(ps, &a.bin_done[mc.part], target, a.spin_limit)) return;
+      }
+      const int g = static_cast<int>(threadIdx.x) / kMergeNodes;
+      merge_unit<kMergeNodes, kMG>(a.mg_items[u0 + (g < cnt ? g : 0)], g < cnt ? u0 + g : -1, a.ctl, a.n, a.s,
+                                   a.partial, in, out, a.dmask, a.red, a.k, a.gctl, a.part_group, a.part_valid);
+      if (publish(&ps->applied, cnt) + cnt == a.n_apply)
+        finalize_body(a.ctl, a.gctl, a.group_slots, a.red, a.k, a.k + a.n_mg, a.hist);
+    }
+    if (!grid_sync(ps, a.spin_limit, reset)) return;
+    if (ld_acquire(&a.ctl->done)) return;
   }
 }
 
@@ -636,6 +798,8 @@ static pcpm_status_t iter_lds_limits_for() {
     PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (2 << kMaxLog2) * 4));
   for (const void* f : gath)
     PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
+  PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_persist<kPng>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 8));
   return PCPM_OK;
 }
 
@@ -664,15 +828,17 @@ static pcpm_status_t reset_ctl(pcpm_png* g, double tol, double d, hipStream_t st
 
 // Scatter and gather of one pass in the handle's update order; kScale and
 // kMode as in k_scatter / k_gather.
+// The scatter stages the rows' values (n_rows of them), the gather writes
+// the columns' (n_cols): both n for a graph.
 template <bool kScale, int kMode, bool kPng>
 static pcpm_status_t scatter_gather(pcpm_png* g, const float* in, float* out, const char* sname, const char* gname,
                                     hipStream_t st) {
   if (g->n_sc)
     PCPM_LAUNCH(sname, (k_scatter<kScatterBlock, kScale, kPng>), dim3(static_cast<unsigned>(g->n_sc)),
-                dim3(kScatterBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->sc_items, in,
-                g->outdeg, g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
+                dim3(kScatterBlock), static_cast<size_t>(g->q) * 8, st, g->ctl, g->n_rows, g->part_log2, g->sc_items,
+                in, g->outdeg, g->png_src, g->png_blk, g->seg_delta, g->upd, g->eprime);
   PCPM_LAUNCH(gname, (k_gather<kGatherBlock, kMode, kPng>), dim3(static_cast<unsigned>(g->n_ga)), dim3(kGatherBlock),
-              static_cast<size_t>(g->q) * 8, st, g->ctl, g->n, g->part_log2, g->ga_items, g->did, g->did_blk,
+              static_cast<size_t>(g->q) * 8, st, g->ctl, g->n_cols, g->part_log2, g->ga_items, g->did, g->did_blk,
               g->did_sblk, g->seg_delta, g->upd, in, out, g->dmask, g->partial, g->red, g->gctl, g->part_group,
               g->part_valid, g->wbin);
   return PCPM_OK;
@@ -696,6 +862,91 @@ static pcpm_status_t run_iteration(pcpm_png* g, const float* in, float* out, hip
   return PCPM_OK;
 }
 
+// Workgroups of the persistent solve: as many as can be resident at once
+// (one per CU at a 128 KB slice), or 0 if the device cannot launch
+// cooperatively.
+static pcpm_status_t persist_grid(pcpm_png* g) {
+  if (g->persist_grid >= 0) return PCPM_OK;
+  PCPM_TRY(iter_lds_limits());
+  int cus = 0, coop = 0, per = 0;
+  PCPM_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  PCPM_TRY_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device));
+  const void* f = g->png_order ? reinterpret_cast<const void*>(k_persist<true>)
+                               : reinterpret_cast<const void*>(k_persist<false>);
+  PCPM_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 1024, static_cast<size_t>(g->q) * 8));
+  // every XCD's scatter range needs workgroups of its own (b % 8 for b < grid)
+  g->persist_grid = (coop && per * cus >= static_cast<int>(kXcds)) ? per * cus : 0;
+  return PCPM_OK;
+}
+
+// Mode 0 takes one launch per phase: on MI355X back-to-back launches queue
+// with gaps of a few microseconds, while the persistent solve pays for its
+// grid barriers and per-unit handoffs (measured slower on every workload).
+static bool use_persistent(const pcpm_png* g) { return g->persist_grid > 0 && g->launch_mode == 2; }
+
+// All iterations of a solve in one cooperative launch (a = pr_out holds the
+// start vector, b = tmp_pr).
+static pcpm_status_t run_persistent(pcpm_png* g, float* a, float* b, int32_t max_iters, hipStream_t st) {
+  PCPM_LAUNCH("pcpm_init", k_persist_init, dim3(1), dim3(256), 0, st, g->psync, g->bin_done, g->k);
+  PersistArgs pa;
+  pa.ctl = g->ctl;
+  pa.gctl = g->gctl;
+  pa.ps = g->psync;
+  pa.bin_done = g->bin_done;
+  pa.n = g->n;
+  pa.k = g->k;
+  pa.s = g->part_log2;
+  pa.n_sc = g->n_sc;
+  pa.n_ga = g->n_ga;
+  pa.n_mg = g->n_mg;
+  pa.n_apply = static_cast<int32_t>(g->k - g->n_split_bins) + g->n_mg;
+  pa.max_iters = max_iters;
+  pa.spin_limit = g->spin_limit;
+  pa.sc_items = g->sc_items;
+  pa.ga_items = g->ga_items;
+  pa.mg_items = g->mg_items;
+  pa.outdeg = g->outdeg;
+  pa.png_src = g->png_src;
+  pa.png_blk = g->png_blk;
+  pa.seg_delta = g->seg_delta;
+  pa.upd = g->upd;
+  pa.spare = g->eprime;
+  pa.did = g->did;
+  pa.did_blk = g->did_blk;
+  pa.did_sblk = g->did_sblk;
+  pa.dmask = g->dmask;
+  pa.partial = g->partial;
+  pa.red = g->red;
+  pa.part_group = g->part_group;
+  pa.part_valid = g->part_valid;
+  pa.group_slots = g->group_slots;
+  pa.hist = g->hist;
+  pa.x0 = a;
+  pa.x1 = b;
+  void* args[] = {&pa};
+  const void* f = g->png_order ? reinterpret_cast<const void*>(k_persist<true>)
+                               : reinterpret_cast<const void*>(k_persist<false>);
+  {
+    TimerScope ts("pcpm_persist", st);
+    PCPM_TRY_HIP(hipLaunchCooperativeKernel(f, dim3(static_cast<unsigned>(g->persist_grid)), dim3(1024), args,
+                                            static_cast<unsigned>(g->q * 8), st));
+  }
+  PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(g->psync_host, g->psync, sizeof(PSync), hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  if (g->psync_host->err)
+    return set_error(PCPM_ERR_DEVICE, "a device-side wait of the persistent solve ran past its limit of %u polls",
+                     g->spin_limit);
+  return PCPM_OK;
+}
+
+// The PageRank calls take graphs, not matrix handles.
+static pcpm_status_t check_graph(const pcpm_png* g) {
+  if (g->matrix)
+    return set_error(PCPM_ERR_INVALID_ARG, "the handle holds a matrix (num_cols or allow_diagonal): pcpm_spmv only");
+  return PCPM_OK;
+}
+
 static pcpm_status_t check_device(pcpm_png* g) {
   int dev = -1;
   PCPM_TRY_HIP(hipGetDevice(&dev));
@@ -704,15 +955,54 @@ static pcpm_status_t check_device(pcpm_png* g) {
   return PCPM_OK;
 }
 
+// End of a solve whose control block is in ctl_host: results to the caller,
+// the last iterate into a.
+static pcpm_status_t finish_solve(pcpm_png* g, float* a, const float* b, double tol, int32_t* iters, double* resid,
+                                  double* res_hist, hipStream_t st) {
+  const Ctl c = *g->ctl_host;
+  *iters = c.iter;
+  *resid = c.res;
+  if (c.iter > 0 && ((c.iter - 1) % 2) == 0)  // last output went to b
+    PCPM_TRY_HIP(hipMemcpyAsync(a, b, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
+  if (res_hist && c.iter > 0)
+    PCPM_TRY_HIP(hipMemcpyAsync(res_hist, g->hist, static_cast<size_t>(c.iter) * 8, hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  if (c.nonfinite) return set_error(PCPM_ERR_NUMERIC, "non-finite rank, residual or dangling mass");
+  if (tol > 0.0 && !c.done)
+    return set_error(PCPM_ERR_NOT_CONVERGED, "residual %.3e still above tol %.3e after %d iterations", c.res, tol,
+                     c.iter);
+  return PCPM_OK;
+}
+
 }  // namespace pcpm
 
 extern "C" {
+
+pcpm_status_t pcpm_set_launch(pcpm_png_t g, int32_t mode, uint32_t spin_limit) {
+  using namespace pcpm;
+  if (!g) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle");
+  PCPM_TRY(check_graph(g));
+  if (mode < 0 || mode > 2) return set_error(PCPM_ERR_INVALID_ARG, "launch mode %d is not 0, 1 or 2", mode);
+  PCPM_TRY(check_device(g));
+  PCPM_TRY(persist_grid(g));
+  if (mode == 2 && g->persist_grid <= 0)
+    return set_error(PCPM_ERR_INVALID_ARG, "the device cannot run the persistent solve (no cooperative launch)");
+  g->launch_mode = mode;
+  g->spin_limit = spin_limit ? spin_limit : (1u << 22);
+  return PCPM_OK;
+}
+
+int32_t pcpm_launch_grid(pcpm_png_t g) {
+  if (!g || pcpm::persist_grid(g) != PCPM_OK) return 0;
+  return g->persist_grid;
+}
 
 pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr_out, double* resid, void* stream) {
   using namespace pcpm;
   if (!g || !pr_in || !pr_out) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or vector");
   if (!(d >= 0.0 && d < 1.0)) return set_error(PCPM_ERR_INVALID_ARG, "d must lie in [0, 1)");
   if (pr_in == pr_out) return set_error(PCPM_ERR_INVALID_ARG, "pr_in and pr_out must differ");
+  PCPM_TRY(check_graph(g));
   PCPM_TRY(check_device(g));
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the start statistics clear padding entries, so they run on a copy
@@ -737,15 +1027,16 @@ pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x, float* y, void* stream) {
   if (!g || !x || !y) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or vector");
   {
     const uintptr_t xa = reinterpret_cast<uintptr_t>(x), ya = reinterpret_cast<uintptr_t>(y);
-    const uintptr_t bytes = static_cast<uintptr_t>(g->n) * sizeof(float);
-    if (xa < ya + bytes && ya < xa + bytes) return set_error(PCPM_ERR_INVALID_ARG, "x and y must not overlap");
+    const uintptr_t xbytes = static_cast<uintptr_t>(g->n_rows) * sizeof(float);
+    const uintptr_t ybytes = static_cast<uintptr_t>(g->n_cols) * sizeof(float);
+    if (xa < ya + ybytes && ya < xa + xbytes) return set_error(PCPM_ERR_INVALID_ARG, "x and y must not overlap");
   }
   PCPM_TRY(check_device(g));
   hipStream_t st = static_cast<hipStream_t>(stream);
   constexpr int kMaxBlocks = 1024;
   if (!g->spmv_blockmax) PCPM_TRY(dalloc(g, &g->spmv_blockmax, kMaxBlocks));
-  const int nb = static_cast<int>(std::min<int64_t>((g->n + 255) / 256, kMaxBlocks));
-  PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_absmax, dim3(nb), dim3(256), 0, st, x, g->n, g->spmv_blockmax);
+  const int nb = static_cast<int>(std::min<int64_t>((g->n_rows + 255) / 256, kMaxBlocks));
+  PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_absmax, dim3(nb), dim3(256), 0, st, x, g->n_rows, g->spmv_blockmax);
   if (!g->wstats_ready) PCPM_TRY(weight_stats(g, st));  // unweighted handle, first call
   PCPM_LAUNCH("pcpm_spmv_scale", k_spmv_scale, dim3(1), dim3(1024), 0, st, g->ctl, g->spmv_blockmax, nb, g->wstats);
   if (g->wbin)
@@ -754,7 +1045,7 @@ pcpm_status_t pcpm_spmv(pcpm_png_t g, const float* x, float* y, void* stream) {
     PCPM_TRY((scatter_gather<false, 1>(g, x, y, "pcpm_spmv_scatter", "pcpm_spmv_gather", st)));
   if (g->n_mg)
     PCPM_LAUNCH("pcpm_spmv_merge", k_spmv_merge, dim3(static_cast<unsigned>(g->n_mg)), dim3(kMergeNodes), 0, st,
-                g->ctl, g->n, g->part_log2, g->mg_items, g->partial, y);
+                g->ctl, g->n_cols, g->part_log2, g->mg_items, g->partial, y);
   return PCPM_OK;
 }
 
@@ -766,6 +1057,7 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
   if (max_iters < 1 || max_iters > kMaxHist)
     return set_error(PCPM_ERR_INVALID_ARG, "max_iters must lie in [1, %d]", kMaxHist);
   if (!(tol == tol)) return set_error(PCPM_ERR_INVALID_ARG, "tol is NaN");
+  PCPM_TRY(check_graph(g));
   PCPM_TRY(check_device(g));
   hipStream_t st = static_cast<hipStream_t>(stream);
   float* a = pr_out;
@@ -779,6 +1071,11 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
                 g->part_log2, g->gctl, g->part_group, g->part_valid);
   }
   PCPM_TRY(start_solve(g, tol, d, a, st));
+  PCPM_TRY(persist_grid(g));
+  if (use_persistent(g)) {
+    PCPM_TRY(run_persistent(g, a, b, max_iters, st));
+    return finish_solve(g, a, b, tol, iters, resid, res_hist, st);
+  }
   // Iterations are queued in batches between host checks of the device
   // control block.  After the first batch the batch length is the number of
   // iterations the observed per-iteration residual ratio predicts until tol,
@@ -805,19 +1102,7 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
     }
     next = std::min(want, max_iters - launched);
   }
-  const Ctl c = *g->ctl_host;
-  *iters = c.iter;
-  *resid = c.res;
-  if (c.iter > 0 && ((c.iter - 1) % 2) == 0)  // last output went to b
-    PCPM_TRY_HIP(hipMemcpyAsync(a, b, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
-  if (res_hist && c.iter > 0)
-    PCPM_TRY_HIP(hipMemcpyAsync(res_hist, g->hist, static_cast<size_t>(c.iter) * 8, hipMemcpyDeviceToHost, st));
-  PCPM_TRY_HIP(hipStreamSynchronize(st));
-  if (c.nonfinite) return set_error(PCPM_ERR_NUMERIC, "non-finite rank, residual or dangling mass");
-  if (tol > 0.0 && !c.done)
-    return set_error(PCPM_ERR_NOT_CONVERGED, "residual %.3e still above tol %.3e after %d iterations", c.res, tol,
-                     c.iter);
-  return PCPM_OK;
+  return finish_solve(g, a, b, tol, iters, resid, res_hist, st);
 }
 
 pcpm_status_t pcpm_graph_results(pcpm_png_t g, int32_t* iters, double* resid) {

@@ -54,16 +54,13 @@ __device__ __forceinline__ void copy_kt(float* __restrict__ dst, const float* __
 // delta gives, with a ballot per 64 entries decoding the segments.  The next
 // tile's source IDs are loaded while this one is written.
 template <int KT, bool kPng>
-__global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
-                                                           const Item* __restrict__ items, const float* __restrict__ x,
-                                                           const int32_t* __restrict__ outdeg,
-                                                           const uint16_t* __restrict__ png_src,
-                                                           const int32_t* __restrict__ png_blk,
-                                                           const int32_t* __restrict__ seg_delta,
-                                                           float* __restrict__ upd, int64_t spare) {
-  if (ctl->done) return;
-  extern __shared__ float spr[];  // 2q * KT scaled values of the source partition pair
-  const Item it = items[xcd_block(blockIdx.x, gridDim.x)];  // as in the plain scatter
+__device__ __forceinline__ void ppr_scatter_item(const Item it, float* __restrict__ spr, int64_t n, int s,
+                                                 const float* __restrict__ x, const int32_t* __restrict__ outdeg,
+                                                 const uint16_t* __restrict__ png_src,
+                                                 const int32_t* __restrict__ png_blk,
+                                                 const int32_t* __restrict__ seg_delta, float* __restrict__ upd,
+                                                 int64_t spare) {
+  // spr: 2q * KT scaled values of the source partition pair
   const int64_t v0 = static_cast<int64_t>(it.part) << (s + 1);  // a partition pair
   const int qn = static_cast<int>(min(int64_t{2} << s, n - v0));
   for (int i = threadIdx.x; i < qn * KT; i += kPprScatterBlock) {
@@ -131,17 +128,35 @@ __global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __r
   }
 }
 
+template <int KT, bool kPng>
+__global__ __launch_bounds__(kPprScatterBlock) void k_ppr_scatter(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                           const Item* __restrict__ items, const float* __restrict__ x,
+                                                           const int32_t* __restrict__ outdeg,
+                                                           const uint16_t* __restrict__ png_src,
+                                                           const int32_t* __restrict__ png_blk,
+                                                           const int32_t* __restrict__ seg_delta,
+                                                           float* __restrict__ upd, int64_t spare) {
+  if (ctl->done) return;
+  extern __shared__ float spr[];
+  ppr_scatter_item<KT, kPng>(items[xcd_block(blockIdx.x, gridDim.x)], spr, n, s, x, outdeg, png_src, png_blk,
+                             seg_delta, upd, spare);  // as in the plain scatter
+}
+
 // Apply for nodes n0..n1-1 of a destination partition and all KT vectors:
 //   x'(v, j) = d * acc(v, j) + [v in S_j] * ((1-d) + d*D_j)/|S_j|
 // and each vector's share of the residual and of the next dangling mass.
-// Thread i serves vector i % KT; kU nodes per step, loads first.
-template <int KT, int BS, class AccFn>
+// Thread i serves vector i % KT; kU nodes per step, loads first.  G > 1: G
+// groups of BS threads in the workgroup, each applying its own range (an
+// empty one with red_slot NULL for a group without work) exactly as a
+// workgroup of BS threads does; every thread calls it.
+template <int KT, int BS, class AccFn, int G = 1>
 __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCtl* __restrict__ vctl, int64_t v0,
                                           int n0, int n1, AccFn acc, const float* __restrict__ x_in,
                                           float* __restrict__ x_out, const uint32_t* __restrict__ dmask,
                                           const uint32_t* __restrict__ seedmask, double* __restrict__ red_slot) {
   static_assert(BS % KT == 0 && kWave % KT == 0, "vectors per tile must divide the wavefront");
-  const int kk = threadIdx.x % KT;
+  const int tid = static_cast<int>(threadIdx.x % BS), grp = static_cast<int>(threadIdx.x / BS);
+  const int kk = tid % KT;
   const bool frozen = vctl[kk].done != 0;
   const double coef = vctl[kk].coef;
   const double d = ctl->d;
@@ -150,7 +165,7 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
   float mx = 0.0f;  // largest new value: the next fixed-point scale
   constexpr int kU = 4;
   constexpr int kStep = BS / KT;
-  for (int node = n0 + static_cast<int>(threadIdx.x) / KT; node < n1; node += kU * kStep) {
+  for (int node = n0 + tid / KT; node < n1; node += kU * kStep) {
     float xo[kU];
     uint32_t sm[kU], dw[kU];
 #pragma unroll
@@ -182,24 +197,25 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
     dm += __shfl_xor(dm, off);
     mx = fmaxf(mx, __shfl_xor(mx, off));
   }
-  __shared__ double sh[(BS / kWave) * KT * 3];
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  __shared__ double shg[G][(BS / kWave) * KT * 3];
+  double* sh = shg[grp];
+  const int w = tid / kWave, lane = tid & (kWave - 1);
   if (lane < KT) {
     sh[(w * KT + lane) * 3] = r;
     sh[(w * KT + lane) * 3 + 1] = dm;
     sh[(w * KT + lane) * 3 + 2] = static_cast<double>(mx);
   }
   __syncthreads();
-  if (threadIdx.x < KT) {
+  if (tid < KT && red_slot) {
     double rs = 0.0, ds = 0.0, ms = 0.0;
     for (int ww = 0; ww < BS / kWave; ++ww) {
-      rs += sh[(ww * KT + threadIdx.x) * 3];
-      ds += sh[(ww * KT + threadIdx.x) * 3 + 1];
-      ms = fmax(ms, sh[(ww * KT + threadIdx.x) * 3 + 2]);
+      rs += sh[(ww * KT + tid) * 3];
+      ds += sh[(ww * KT + tid) * 3 + 1];
+      ms = fmax(ms, sh[(ww * KT + tid) * 3 + 2]);
     }
-    red_slot[threadIdx.x * 3] = rs;
-    red_slot[threadIdx.x * 3 + 1] = ds;
-    red_slot[threadIdx.x * 3 + 2] = ms;
+    red_slot[tid * 3] = rs;
+    red_slot[tid * 3 + 1] = ds;
+    red_slot[tid * 3 + 2] = ms;
   }
 }
 
@@ -211,24 +227,16 @@ __device__ __forceinline__ void apply_ppr(const Ctl* __restrict__ ctl, const VCt
 // them on 32/KT bank pairs).  The next tile's IDs are loaded while this one is
 // accumulated; the update values of kG sub-blocks are in flight together.
 template <int KT, bool kPng>
-__global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
-                                                                const Item* __restrict__ items,
-                                                                const uint16_t* __restrict__ did,
-                                                                const int32_t* __restrict__ did_blk,
-                                                                const int32_t* __restrict__ did_sblk,
-                                                                const int32_t* __restrict__ seg_delta,
-                                                                const float* __restrict__ upd,
-                                                                const float* __restrict__ x_in,
-                                                                float* __restrict__ x_out,
-                                                                const uint32_t* __restrict__ dmask,
-                                                                const uint32_t* __restrict__ seedmask,
-                                                                int64_t* __restrict__ partial,
-                                                                double* __restrict__ red,
-                                                                const VCtl* __restrict__ vctl) {
-  if (ctl->done) return;
-  constexpr int BS = kPprGatherBlock;
-  extern __shared__ unsigned long long acc[];  // q * KT fixed-point sums
-  const Item it = items[blockIdx.x];
+__device__ __forceinline__ void ppr_gather_item(const Item it, unsigned long long* __restrict__ acc,
+                                                const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                const uint16_t* __restrict__ did, const int32_t* __restrict__ did_blk,
+                                                const int32_t* __restrict__ did_sblk,
+                                                const int32_t* __restrict__ seg_delta, const float* __restrict__ upd,
+                                                const float* __restrict__ x_in, float* __restrict__ x_out,
+                                                const uint32_t* __restrict__ dmask,
+                                                const uint32_t* __restrict__ seedmask, int64_t* __restrict__ partial,
+                                                double* __restrict__ red, const VCtl* __restrict__ vctl) {
+  constexpr int BS = kPprGatherBlock;  // acc: q * KT fixed-point sums
   const int64_t q = int64_t{1} << s;
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
@@ -311,6 +319,50 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
                     x_out, dmask, seedmask, red + static_cast<int64_t>(it.part) * KT * 3);
 }
 
+template <int KT, bool kPng>
+__global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __restrict__ ctl, int64_t n, int s,
+                                                                const Item* __restrict__ items,
+                                                                const uint16_t* __restrict__ did,
+                                                                const int32_t* __restrict__ did_blk,
+                                                                const int32_t* __restrict__ did_sblk,
+                                                                const int32_t* __restrict__ seg_delta,
+                                                                const float* __restrict__ upd,
+                                                                const float* __restrict__ x_in,
+                                                                float* __restrict__ x_out,
+                                                                const uint32_t* __restrict__ dmask,
+                                                                const uint32_t* __restrict__ seedmask,
+                                                                int64_t* __restrict__ partial,
+                                                                double* __restrict__ red,
+                                                                const VCtl* __restrict__ vctl) {
+  if (ctl->done) return;
+  extern __shared__ unsigned long long acc[];
+  ppr_gather_item<KT, kPng>(items[blockIdx.x], acc, ctl, n, s, did, did_blk, did_sblk, seg_delta, upd, x_in, x_out,
+                            dmask, seedmask, partial, red, vctl);
+}
+
+// Merge unit u (u < 0: none, for a group without work; G groups of
+// kPprBlock threads as in apply_ppr).
+template <int KT, int G = 1>
+__device__ __forceinline__ void ppr_merge_unit(const Merge mu, int64_t u, const Ctl* __restrict__ ctl, int64_t n,
+                                               int s, const int64_t* __restrict__ partial,
+                                               const float* __restrict__ x_in, float* __restrict__ x_out,
+                                               const uint32_t* __restrict__ dmask,
+                                               const uint32_t* __restrict__ seedmask, double* __restrict__ red,
+                                               int64_t red_base, const VCtl* __restrict__ vctl) {
+  const int64_t q = int64_t{1} << s;
+  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
+  const int qn = static_cast<int>(min(q, n - v0));
+  const int64_t* base = partial + static_cast<int64_t>(mu.first) * q * KT;
+  const int cnt = mu.count;
+  auto acc = [&](int nd, int vec) {  // partial slices are [KT][q]
+    return sum_slices(base + static_cast<int64_t>(vec) * q + nd, cnt, q * KT);
+  };
+  const bool has = u >= 0;
+  apply_ppr<KT, kPprBlock, decltype(acc), G>(ctl, vctl, v0, has ? mu.node_lo : 0, has ? min(qn, mu.node_lo + 256) : 0,
+                                             acc, x_in, x_out, dmask, seedmask,
+                                             has ? red + (red_base + u) * KT * 3 : nullptr);
+}
+
 template <int KT>
 __global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__ ctl, int64_t n, int s,
                                                          const Merge* __restrict__ mg,
@@ -321,17 +373,8 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__
                                                          double* __restrict__ red, int64_t red_base,
                                                          const VCtl* __restrict__ vctl) {
   if (ctl->done) return;
-  const Merge mu = mg[blockIdx.x];
-  const int64_t q = int64_t{1} << s;
-  const int64_t v0 = static_cast<int64_t>(mu.part) << s;
-  const int qn = static_cast<int>(min(q, n - v0));
-  const int64_t* base = partial + static_cast<int64_t>(mu.first) * q * KT;
-  const int cnt = mu.count;
-  auto acc = [&](int nd, int vec) {  // partial slices are [KT][q]
-    return sum_slices(base + static_cast<int64_t>(vec) * q + nd, cnt, q * KT);
-  };
-  apply_ppr<KT, kPprBlock>(ctl, vctl, v0, mu.node_lo, min(qn, mu.node_lo + 256), acc, x_in, x_out, dmask, seedmask,
-                           red + (red_base + blockIdx.x) * KT * 3);
+  ppr_merge_unit<KT>(mg[blockIdx.x], blockIdx.x, ctl, n, s, partial, x_in, x_out, dmask, seedmask, red, red_base,
+                     vctl);
 }
 
 // Per-vector residual, dangling mass and jump coefficient; one wavefront per
@@ -339,19 +382,18 @@ __global__ __launch_bounds__(kPprBlock) void k_ppr_merge(const Ctl* __restrict__
 // finished (below tol, or at the iteration limit) records the vector's
 // iteration count, residual and convergence, and takes the next vector of the
 // queue; the batch is done when every slot is idle.
-__global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VCtl* __restrict__ vctl, int kt,
-                                                       const double* __restrict__ red, int64_t nslots,
-                                                       double* __restrict__ hist, PprQueue* __restrict__ queue,
-                                                       int32_t* __restrict__ out_it, double* __restrict__ out_res,
-                                                       int32_t* __restrict__ out_conv) {
-  if (ctl->done) return;
+// Per-vector sums by one wavefront per slot go through LDS; every field of the
+// control structs is then read and written by thread 0 alone (stores of
+// different wavefronts to one struct are not ordered by a workgroup barrier).
+__device__ __forceinline__ void ppr_finalize_body(Ctl* __restrict__ ctl, VCtl* __restrict__ vctl, int kt,
+                                                  const double* __restrict__ red, int64_t nslots,
+                                                  double* __restrict__ hist, PprQueue* __restrict__ queue,
+                                                  int32_t* __restrict__ out_it, double* __restrict__ out_res,
+                                                  int32_t* __restrict__ out_conv) {
   double vmax = 0.0;  // largest value of the new iterates (all vectors of the tile)
   for (int64_t j = threadIdx.x; j < nslots * kt; j += 1024) vmax = fmax(vmax, red[3 * j + 2]);
   vmax = block_max<1024>(vmax);
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  const double d = ctl->d, tol = ctl->tol;
+  __shared__ double s_r[16], s_dm[16];
   const int lane = threadIdx.x & (kWave - 1);
   for (int kk = threadIdx.x / kWave; kk < kt; kk += 1024 / kWave) {
     double r = 0.0, dm = 0.0;
@@ -365,19 +407,26 @@ __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VC
       dm += __shfl_xor(dm, off);
     }
     if (lane == 0) {
-      VCtl& vc = vctl[kk];
-      if (!vc.done) {
-        vc.res = r;
-        vc.iter += 1;
-        vc.dmass = dm;
-        vc.coef = ((1.0 - d) + d * dm) * vc.inv_s;
-        if (!isfinite(r) || !isfinite(dm)) atomicOr(&bad, 1);
-        else if (tol > 0.0 && r < tol) vc.done = 1;
-      }
+      s_r[kk] = r;
+      s_dm[kk] = dm;
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    const double d = ctl->d, tol = ctl->tol;
+    int bad = 0;
+    for (int kk = 0; kk < kt; ++kk) {
+      VCtl& vc = vctl[kk];
+      if (!vc.done) {
+        const double r = s_r[kk], dm = s_dm[kk];
+        vc.res = r;
+        vc.iter += 1;
+        vc.dmass = dm;
+        vc.coef = ((1.0 - d) + d * dm) * vc.inv_s;
+        if (!isfinite(r) || !isfinite(dm)) bad = 1;
+        else if (tol > 0.0 && r < tol) vc.done = 1;
+      }
+    }
     double rmax = 0.0;  // largest residual of the vectors still running
     for (int kk = 0; kk < kt; ++kk)
       if (vctl[kk].vec >= 0 && !vctl[kk].done) rmax = fmax(rmax, vctl[kk].res);
@@ -394,7 +443,7 @@ __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VC
         queue->old_vec[kk] = vc.vec;
         queue->new_vec[kk] = nv;
         vc.vec = nv;
-        vc.done = 1;  // keeps its column until k_ppr_refill_seeds starts the next vector
+        vc.done = 1;  // keeps its column until the refill starts the next vector
         pending = 1;
         any_new |= nv >= 0;
       }
@@ -414,21 +463,30 @@ __global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VC
   }
 }
 
+__global__ __launch_bounds__(1024) void k_ppr_finalize(Ctl* __restrict__ ctl, VCtl* __restrict__ vctl, int kt,
+                                                       const double* __restrict__ red, int64_t nslots,
+                                                       double* __restrict__ hist, PprQueue* __restrict__ queue,
+                                                       int32_t* __restrict__ out_it, double* __restrict__ out_res,
+                                                       int32_t* __restrict__ out_conv) {
+  if (ctl->done) return;
+  ppr_finalize_body(ctl, vctl, kt, red, nslots, hist, queue, out_it, out_res, out_conv);
+}
+
 // Refill, first part (whole grid): the finished vectors' columns go to
 // pr_out[v][vec], and the columns of slots that start a new vector are
 // cleared.  Nothing to do unless the last iteration planned a refill.
+// Nodes t0, t0 + stride, ... of the refill's first part.
 template <int KT>
-__global__ __launch_bounds__(256) void k_ppr_refill_cols(const PprQueue* __restrict__ queue, float* __restrict__ x,
-                                                         float* __restrict__ out, int64_t n, int k) {
-  if (!queue->pending) return;
+__device__ __forceinline__ void ppr_refill_cols_nodes(const PprQueue* __restrict__ queue, float* __restrict__ x,
+                                                      float* __restrict__ out, int64_t n, int k, int64_t t0,
+                                                      int64_t stride) {
   int ov[KT], nv[KT];
 #pragma unroll
   for (int c = 0; c < KT; ++c) {
     ov[c] = queue->old_vec[c];
     nv[c] = queue->new_vec[c];
   }
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  for (int64_t v = t0; v < n; v += stride) {
     float row[KT];
     copy_kt<KT>(row, x + v * KT);
     bool clear = false;
@@ -444,16 +502,22 @@ __global__ __launch_bounds__(256) void k_ppr_refill_cols(const PprQueue* __restr
   }
 }
 
+template <int KT>
+__global__ __launch_bounds__(256) void k_ppr_refill_cols(const PprQueue* __restrict__ queue, float* __restrict__ x,
+                                                         float* __restrict__ out, int64_t n, int k) {
+  if (!queue->pending) return;
+  ppr_refill_cols_nodes<KT>(queue, x, out, n, k, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x,
+                            static_cast<int64_t>(gridDim.x) * blockDim.x);
+}
+
 // Refill, second part (one workgroup): seed bits of the finished vectors are
 // cleared, then each new vector gets x_0 = t_j on its seeds, its seed bits,
 // dangling mass and jump coefficient; one wavefront per slot.
-__global__ __launch_bounds__(1024) void k_ppr_refill_seeds(PprQueue* __restrict__ queue, float* __restrict__ x,
-                                                           uint32_t* __restrict__ mask,
-                                                           const int32_t* __restrict__ seeds,
-                                                           const int32_t* __restrict__ seed_off, int kt,
-                                                           VCtl* __restrict__ vctl,
-                                                           const uint32_t* __restrict__ dmask, double d) {
-  if (!queue->pending) return;
+__device__ __forceinline__ void ppr_refill_seeds_body(PprQueue* __restrict__ queue, float* __restrict__ x,
+                                                      uint32_t* __restrict__ mask, const int32_t* __restrict__ seeds,
+                                                      const int32_t* __restrict__ seed_off, int kt,
+                                                      VCtl* __restrict__ vctl, const uint32_t* __restrict__ dmask,
+                                                      double d) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int kk = threadIdx.x / kWave; kk < kt; kk += 1024 / kWave) {
     const int ov = queue->old_vec[kk];
@@ -491,6 +555,16 @@ __global__ __launch_bounds__(1024) void k_ppr_refill_seeds(PprQueue* __restrict_
   if (threadIdx.x == 0) queue->pending = 0;
 }
 
+__global__ __launch_bounds__(1024) void k_ppr_refill_seeds(PprQueue* __restrict__ queue, float* __restrict__ x,
+                                                           uint32_t* __restrict__ mask,
+                                                           const int32_t* __restrict__ seeds,
+                                                           const int32_t* __restrict__ seed_off, int kt,
+                                                           VCtl* __restrict__ vctl,
+                                                           const uint32_t* __restrict__ dmask, double d) {
+  if (!queue->pending) return;
+  ppr_refill_seeds_body(queue, x, mask, seeds, seed_off, kt, vctl, dmask, d);
+}
+
 // pr_out[v][j] = x[v][j] for the first kv slots (batches that fit one tile:
 // every vector keeps its slot, and its last iterate, to the end).
 __global__ __launch_bounds__(256) void k_ppr_store(float* __restrict__ out, const float* __restrict__ x, int64_t n,
@@ -501,6 +575,20 @@ __global__ __launch_bounds__(256) void k_ppr_store(float* __restrict__ out, cons
     const int64_t v = i / kv;
     const int j = static_cast<int>(i - v * kv);
     out[v * k + j] = x[v * kt + j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ppr_persist_init(PSync* __restrict__ ps, int32_t* __restrict__ bin_done,
+                                                          int64_t k) {
+  for (int64_t p = threadIdx.x; p < k; p += 256) bin_done[p] = 0;
+  if (threadIdx.x == 0) {
+    ps->bar_count = 0;
+    ps->bar_gen = 0;
+    ps->err = 0;
+    ps->applied = 0;
+    ps->ga_next = 0;
+    ps->mg_next = 0;
+    for (unsigned x = 0; x < kXcds; ++x) ps->sc_next[x] = 0;
   }
 }
 
@@ -564,6 +652,82 @@ __global__ void k_ppr_ctl(Ctl* ctl, double tol, double d) {
   }
 }
 
+// ---- persistent batch ---------------------------------------------------------
+// Every iteration of the batch in one cooperative launch, phase by phase as
+// the plain persistent solve (scatter items; grid barrier; gather items and
+// merge units, the last apply unit running the finalize and the refill plan;
+// grid barrier), then, when the finalize planned a refill, the finished
+// columns stored and cleared by the whole grid, a barrier, the new vectors'
+// seeds by workgroup 0 and a barrier.  The launch ends when every slot is
+// idle (or a bounded wait gives up).
+
+template <int KT, bool kPng>
+__global__ __launch_bounds__(1024) void k_ppr_persist(const PprPersistArgs a) {
+  constexpr int BS = 1024;
+  constexpr int kMG = BS / kPprBlock;  // merge units per workgroup, one per group of kPprBlock threads
+  extern __shared__ unsigned long long lds[];
+  PSync* ps = a.ps;
+  auto reset = [&]() {  // by the last arrival at the iteration's second barrier
+    for (unsigned x = 0; x < kXcds; ++x) __hip_atomic_store(&ps->sc_next[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ps->ga_next, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ps->mg_next, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ps->applied, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  const int64_t nslots = a.k + a.n_mg;
+  for (int64_t it = 0; it < a.max_loops; ++it) {
+    const float* in = (it & 1) ? a.x1 : a.x0;
+    float* out = (it & 1) ? a.x0 : a.x1;
+    for (;;) {
+      const int32_t j = grab_scatter(ps, a.n_sc);
+      if (j < 0) break;
+      ppr_scatter_item<KT, kPng>(a.sc_items[j], reinterpret_cast<float*>(lds), a.n, a.s, in, a.outdeg, a.png_src,
+                                 a.png_blk, a.seg_delta, a.upd, a.spare);
+    }
+    if (!grid_sync(ps, a.spin_limit, [] {})) return;
+    for (;;) {
+      const int32_t j = grab(&ps->ga_next);
+      if (j >= a.n_ga) break;
+      const Item itm = a.ga_items[j];
+      ppr_gather_item<KT, kPng>(itm, lds, a.ctl, a.n, a.s, a.did, a.did_blk, a.did_sblk, a.seg_delta, a.upd, in, out,
+                                a.dmask, a.seedmask, a.partial, a.red, a.vctl);
+      if (itm.aux >= 0) {
+        publish(&a.bin_done[itm.part]);
+      } else if (publish(&ps->applied) == a.n_apply - 1) {
+        ppr_finalize_body(a.ctl, a.vctl, KT, a.red, nslots, a.hist, a.queue, a.out_it, a.out_res, a.out_conv);
+      }
+    }
+    for (;;) {
+      const int32_t u0 = grab(&ps->mg_next, kMG);
+      if (u0 >= a.n_mg) break;
+      const int32_t cnt = min(kMG, a.n_mg - u0);
+      for (int32_t c = 0; c < cnt; ++c) {
+        const Merge mc = a.mg_items[u0 + c];
+        if (c > 0 && mc.part == a.mg_items[u0 + c - 1].part) continue;
+        const int32_t target = static_cast<int32_t>(static_cast<uint32_t>(mc.count) * static_cast<uint32_t>(it + 1));
+        if (!wait_at_least(ps, &a.bin_done[mc.part], target, a.spin_limit)) return;
+      }
+      const int g = static_cast<int>(threadIdx.x) / kPprBlock;
+      ppr_merge_unit<KT, kMG>(a.mg_items[u0 + (g < cnt ? g : 0)], g < cnt ? u0 + g : -1, a.ctl, a.n, a.s, a.partial,
+                              in, out, a.dmask, a.seedmask, a.red, a.k, a.vctl);
+      if (publish(&ps->applied, cnt) + cnt == a.n_apply)
+        ppr_finalize_body(a.ctl, a.vctl, KT, a.red, nslots, a.hist, a.queue, a.out_it, a.out_res, a.out_conv);
+    }
+    if (!grid_sync(ps, a.spin_limit, reset)) return;
+    if (a.refill && ld_acquire(&a.queue->pending)) {
+      // the finished columns stored and cleared by the whole grid, then the
+      // new vectors' seeds by workgroup 0
+      ppr_refill_cols_nodes<KT>(a.queue, out, a.pr_out, a.n, a.kvec,
+                                static_cast<int64_t>(blockIdx.x) * BS + threadIdx.x,
+                                static_cast<int64_t>(gridDim.x) * BS);
+      if (!grid_sync(ps, a.spin_limit, [] {})) return;
+      if (blockIdx.x == 0)
+        ppr_refill_seeds_body(a.queue, out, a.seedmask, a.seeds, a.seed_off, KT, a.vctl, a.dmask, a.d);
+      if (!grid_sync(ps, a.spin_limit, [] {})) return;
+    }
+    if (ld_acquire(&a.ctl->done)) return;
+  }
+}
+
 // ---- host ------------------------------------------------------------------
 
 template <int KT>
@@ -572,8 +736,90 @@ static pcpm_status_t ppr_set_lds(int s) {
                         reinterpret_cast<const void*>(k_ppr_scatter<KT, true>)})
     PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (2 << s) * KT * 4));
   for (const void* f : {reinterpret_cast<const void*>(k_ppr_gather<KT, false>),
-                        reinterpret_cast<const void*>(k_ppr_gather<KT, true>)})
+                        reinterpret_cast<const void*>(k_ppr_gather<KT, true>),
+                        reinterpret_cast<const void*>(k_ppr_persist<KT, false>),
+                        reinterpret_cast<const void*>(k_ppr_persist<KT, true>)})
     PCPM_TRY_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (1 << s) * KT * 8));
+  return PCPM_OK;
+}
+
+// Workgroups of the persistent batch (all resident), 0 if it cannot run here
+// or the handle asks for one launch per phase.
+template <int KT>
+static pcpm_status_t ppr_persist_grid(pcpm_png* g, int* grid) {
+  *grid = 0;
+  if (g->launch_mode != 2) return PCPM_OK;
+  int cus = 0, coop = 0, per = 0;
+  PCPM_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  PCPM_TRY_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, g->device));
+  const void* f = g->png_order ? reinterpret_cast<const void*>(k_ppr_persist<KT, true>)
+                               : reinterpret_cast<const void*>(k_ppr_persist<KT, false>);
+  PCPM_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, 1024, static_cast<size_t>(g->q) * KT * 8));
+  if (coop && per * cus >= static_cast<int>(kXcds)) *grid = per * cus;
+  return PCPM_OK;
+}
+
+template <int KT>
+static pcpm_status_t ppr_run_persistent(pcpm_png* g, int grid, double d, int k, int64_t cap, float* pr_out, float* a,
+                                        float* b, hipStream_t st) {
+  PCPM_LAUNCH("pcpm_ppr_init", k_ppr_persist_init, dim3(1), dim3(256), 0, st, g->psync, g->bin_done, g->k);
+  PprPersistArgs pa;
+  pa.ctl = g->ctl;
+  pa.vctl = g->ppr_vctl;
+  pa.ps = g->psync;
+  pa.bin_done = g->bin_done;
+  pa.queue = g->ppr_queue;
+  pa.n = g->n;
+  pa.k = g->k;
+  pa.max_loops = cap;
+  pa.spare = g->eprime;
+  pa.s = g->part_log2;
+  pa.n_sc = g->n_sc;
+  pa.n_ga = g->n_ga;
+  pa.n_mg = g->n_mg;
+  pa.n_apply = static_cast<int32_t>(g->k - g->n_split_bins) + g->n_mg;
+  pa.kvec = k;
+  pa.refill = k > KT ? 1 : 0;
+  pa.spin_limit = g->spin_limit;
+  pa.d = d;
+  pa.sc_items = g->sc_items;
+  pa.ga_items = g->ga_items;
+  pa.mg_items = g->mg_items;
+  pa.outdeg = g->outdeg;
+  pa.png_src = g->png_src;
+  pa.png_blk = g->png_blk;
+  pa.seg_delta = g->seg_delta;
+  pa.upd = g->ppr_upd;
+  pa.did = g->did;
+  pa.did_blk = g->did_blk;
+  pa.did_sblk = g->did_sblk;
+  pa.dmask = g->dmask;
+  pa.seedmask = g->ppr_mask;
+  pa.partial = g->ppr_partial;
+  pa.red = g->ppr_red;
+  pa.hist = g->hist;
+  pa.out_it = g->ppr_out_it;
+  pa.out_res = g->ppr_out_res;
+  pa.out_conv = g->ppr_out_conv;
+  pa.pr_out = pr_out;
+  pa.seeds = g->ppr_seeds;
+  pa.seed_off = g->ppr_seed_off;
+  pa.x0 = a;
+  pa.x1 = b;
+  void* args[] = {&pa};
+  const void* f = g->png_order ? reinterpret_cast<const void*>(k_ppr_persist<KT, true>)
+                               : reinterpret_cast<const void*>(k_ppr_persist<KT, false>);
+  {
+    TimerScope ts("pcpm_ppr_persist", st);
+    PCPM_TRY_HIP(hipLaunchCooperativeKernel(f, dim3(static_cast<unsigned>(grid)), dim3(1024), args,
+                                            static_cast<unsigned>(g->q * KT * 8), st));
+  }
+  PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipMemcpyAsync(g->psync_host, g->psync, sizeof(PSync), hipMemcpyDeviceToHost, st));
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  if (g->psync_host->err)
+    return set_error(PCPM_ERR_DEVICE, "a device-side wait of the persistent batch ran past its limit of %u polls",
+                     g->spin_limit);
   return PCPM_OK;
 }
 
@@ -681,8 +927,14 @@ static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_i
   // most ceil(k/KT) * max_iters iterations, and the last vectors finish
   // within max_iters more.
   const int64_t cap = (static_cast<int64_t>(k + KT - 1) / KT + 1) * max_iters;
+  int grid = 0;
+  PCPM_TRY(ppr_persist_grid<KT>(g, &grid));
   int64_t launched = 0;
   int64_t next = std::min<int64_t>(tol > 0.0 ? 4 : 64, cap);
+  if (grid > 0) {
+    PCPM_TRY(ppr_run_persistent<KT>(g, grid, d, k, cap, pr_out, a, b, st));
+    launched = cap;  // the launch ran every iteration it needed
+  }
   while (launched < cap) {
     for (int64_t i = 0; i < next; ++i) {
       const bool even = ((launched + i) % 2) == 0;
@@ -703,7 +955,9 @@ static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_i
     }
     next = std::min(want, cap - launched);
   }
-  if (!g->ctl_host->done) return set_error(PCPM_ERR_DEVICE, "personalised PageRank did not drain its queue");
+  if (!g->ctl_host->done)
+    return set_error(PCPM_ERR_DEVICE, "personalised PageRank did not drain its queue in %d iterations (cap %lld)",
+                     g->ctl_host->iter, static_cast<long long>(cap));
   if (k <= KT) {
     const int it_done = g->ctl_host->iter;
     const float* xr = (it_done > 0 && ((it_done - 1) % 2) == 0) ? b : a;
@@ -741,7 +995,8 @@ pcpm_status_t pcpm_ppr_batch(pcpm_png_t g, double d, int32_t k, const int32_t* s
   using namespace pcpm;
   if (!g || !seed_off || !seeds || !pr_out || !iters || !resid)
     return set_error(PCPM_ERR_INVALID_ARG, "NULL handle, seed list or output");
-  if (g->ngroups != 1) return set_error(PCPM_ERR_INVALID_ARG, "personalised PageRank needs a single-graph handle");
+  if (g->ngroups != 1 || g->matrix)
+    return set_error(PCPM_ERR_INVALID_ARG, "personalised PageRank needs a single-graph handle (not a matrix)");
   if (k < 1) return set_error(PCPM_ERR_INVALID_ARG, "k must be >= 1");
   if (!(d >= 0.0 && d < 1.0)) return set_error(PCPM_ERR_INVALID_ARG, "d must lie in [0, 1)");
   if (max_iters < 1 || max_iters > kMaxHist)

@@ -490,7 +490,8 @@ pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* firs
   using namespace pcpm;
   if (!g || !feat) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or output");
   if (!(d >= 0.0 && d < 1.0)) return set_error(PCPM_ERR_INVALID_ARG, "d must lie in [0, 1)");
-  if (g->ngroups != 1) return set_error(PCPM_ERR_INVALID_ARG, "warm start needs a single-graph handle");
+  if (g->ngroups != 1 || g->matrix)
+    return set_error(PCPM_ERR_INVALID_ARG, "warm start needs a single-graph handle (not a matrix)");
   PCPM_TRY(ws_check_device_ptr(feat, "feat"));
   hipStream_t st = static_cast<hipStream_t>(stream);
   PCPM_TRY(ws_prepare(g, st));

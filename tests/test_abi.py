@@ -74,7 +74,7 @@ def test_binding_structs_match_the_header(tmp_path):
     offsets (a mismatch would pass wrong arguments without any error)."""
     _pcpm = P._pcpm
     for struct, cls in (("pcpm_build_opts_t", _pcpm.BuildOpts), ("pcpm_png_info_t", _pcpm.PngInfo),
-                        ("pcpm_kernel_time_t", _pcpm.KernelTime)):
+                        ("pcpm_kernel_time_t", _pcpm.KernelTime), ("pcpm_tune_entry_t", _pcpm.TuneEntry)):
         fields = [f for f, _ in cls._fields_]
         size, offsets = _c_layout(tmp_path, struct, fields)
         assert ctypes.sizeof(cls) == size, struct

@@ -173,28 +173,6 @@ def test_rejects_bad_weights_and_overlap():
     png.close()
 
 
-def test_rectangular_matrix_on_a_square_handle():
-    rows, cols = 700, 2000
-    rng = np.random.default_rng(13)
-    src = rng.integers(0, rows, 9000)
-    dst = rng.integers(0, cols, 9000)
-    keep = np.ones(len(src), bool)
-    r0, c0 = graphgen.from_edges(max(rows, cols), src[keep], dst[keep])  # canonical (dedup, no self loops)
-    r0 = r0[:rows + 1]  # rows past `rows` are empty anyway
-    r, c = P.square_csr(r0, c0, cols)
-    w = rng.standard_normal(len(c)).astype(np.float32)
-    x = np.zeros(len(r) - 1, np.float32)
-    x[:rows] = rng.standard_normal(rows).astype(np.float32)
-    png = P.build_png(dev(r), dev(c), part_log2=8, weights=dev(w))
-    y = P.spmv(png, dev(x)).cpu().numpy()[:cols]
-    A = np.zeros((rows, cols))
-    for u in range(rows):
-        for e in range(r[u], r[u + 1]):
-            A[u, c[e]] += w[e]
-    np.testing.assert_allclose(y, A.T @ x[:rows].astype(np.float64), rtol=1e-5, atol=1e-6)
-    png.close()
-
-
 def test_multi_graph_handle():
     graphs = [graphgen.rmat(s, 8, seed=20 + s, relabel="random") for s in (9, 11, 8)]
     r, c, off, sizes = P.union_csr(graphs, 9)
@@ -212,3 +190,74 @@ def test_graph_without_edges():
     png = P.build_png(dev(r), dev(np.zeros(1, np.int32))[:0], part_log2=5)
     assert np.all(P.spmv(png, dev(np.ones(99, np.float32))).cpu().numpy() == 0.0)
     png.close()
+
+
+def matrix_csr(rows, cols, src, dst):
+    """Canonical CSR of an R x C matrix's entries (sorted, duplicates
+    dropped, diagonal entries kept)."""
+    key = np.unique(np.asarray(src, np.int64) * cols + np.asarray(dst, np.int64))
+    u, v = key // cols, key % cols
+    r = np.zeros(rows + 1, np.int32)
+    r[1:] = np.cumsum(np.bincount(u, minlength=rows))
+    return r, v.astype(np.int32)
+
+
+def check_matrix(y, r, c, x, w, cols):
+    ref = oracle.spmv(r, c, x.astype(np.float64), None if w is None else w.astype(np.float64), num_cols=cols)
+    aw = np.ones(len(c)) if w is None else np.abs(w.astype(np.float64))
+    xmax = float(np.abs(x.astype(np.float64)).max())
+    wcol = np.bincount(c, weights=aw, minlength=cols).max()
+    s = min(50 - int(np.ceil(np.log2(aw.max() * xmax))), 62 - int(np.ceil(np.log2(wcol * xmax)))) - 1
+    indeg = np.bincount(c, minlength=cols)
+    bound = indeg * 2.0 ** -s + 2.0 ** -23 * np.abs(ref) + 2.0 ** -150
+    err = np.abs(y.astype(np.float64) - ref)
+    assert len(y) == cols and np.all(err <= bound), (err / bound).max()
+
+
+@pytest.mark.parametrize("rows,cols,part_log2,order,weighted", [
+    (700, 2000, 8, 1, True),      # more columns than rows
+    (5000, 1300, 8, 2, True),     # more rows than columns
+    (3001, 3001, 7, 1, False),    # square, with diagonal entries
+    (20000, 70000, 12, 2, True),  # several partitions each way, ragged tails
+    (90000, 9000, 10, 1, False),
+])
+def test_matrix_handle_rows_and_columns_partitioned_separately(rows, cols, part_log2, order, weighted):
+    """Sec. 3.5: an R x C matrix with diagonal entries; x has R entries and y
+    has C (no square padding); the oracle's y = A^T x within the bound."""
+    rng = np.random.default_rng(rows + cols)
+    nnz = 12 * max(rows, cols)
+    src = rng.integers(0, rows, nnz)
+    dst = rng.integers(0, cols, nnz)
+    diag = np.arange(min(rows, cols))[::3]  # a third of the diagonal
+    r, c = matrix_csr(rows, cols, np.concatenate([src, diag]), np.concatenate([dst, diag]))
+    assert np.any(c[np.repeat(np.arange(rows), np.diff(r))] == np.repeat(np.arange(rows), np.diff(r)))
+    w = rng.standard_normal(len(c)).astype(np.float32) if weighted else None
+    x = rng.standard_normal(rows).astype(np.float32)
+    png = P.build_png(dev(r), dev(c), part_log2=part_log2, weights=None if w is None else dev(w),
+                      update_order=order, num_cols=cols, allow_diagonal=1)
+    assert png.info["matrix"] == 1 and png.info["num_cols"] == cols and png.n == rows
+    y = P.spmv(png, dev(x))
+    assert y.numel() == cols
+    check_matrix(y.cpu().numpy(), r, c, x, w, cols)
+    y2 = P.spmv(png, dev(x))
+    assert torch.equal(y, y2)
+    # a matrix handle takes SpMV only
+    with pytest.raises(P.PCPMError) as ei:
+        P.pagerank(png, tol=0.0, max_iters=2)
+    assert ei.value.status == P.PCPM_ERR_INVALID_ARG
+    png.close()
+
+
+def test_diagonal_entries_need_a_matrix_handle():
+    r, c = matrix_csr(50, 50, [0, 1, 2, 3], [0, 2, 2, 1])  # 0->0 and 2->2 on the diagonal
+    with pytest.raises(P.PCPMError) as ei:
+        P.build_png(dev(r), dev(c), part_log2=4)
+    assert ei.value.status == P.PCPM_ERR_GRAPH
+    png = P.build_png(dev(r), dev(c), part_log2=4, allow_diagonal=1)
+    x = np.arange(50, dtype=np.float32)
+    y = P.spmv(png, dev(x)).cpu().numpy()
+    want = np.zeros(50)
+    want[0] += x[0]; want[2] += x[1] + x[2]; want[1] += x[3]
+    np.testing.assert_array_equal(y, want.astype(np.float32))
+    with pytest.raises(P.PCPMError):
+        P.build_png(dev(r), dev(c), part_log2=4, num_cols=2, allow_diagonal=1)  # column 2 lies outside 2 columns

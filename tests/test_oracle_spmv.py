@@ -27,6 +27,25 @@ def test_spmv_equals_dense_transpose_product(seed):
     np.testing.assert_allclose(oracle.spmv(r, c, x), dense(r, c).T @ x, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("rows,cols", [(7, 19), (23, 5), (9, 9)])
+def test_rectangular_spmv_with_diagonal_equals_dense_product(rows, cols):
+    """A non-square matrix with diagonal entries (Sec. 3.5): y has one entry
+    per column, y = A^T x by the dense product."""
+    rng = np.random.default_rng(rows * 31 + cols)
+    A = np.where(rng.random((rows, cols)) < 0.35, rng.standard_normal((rows, cols)), 0.0)
+    for i in range(min(rows, cols)):
+        A[i, i] = float(i + 1)  # every diagonal entry present
+    u, v = np.nonzero(A)
+    r = np.zeros(rows + 1, np.int32)
+    r[1:] = np.cumsum(np.bincount(u, minlength=rows))
+    w = A[u, v]
+    x = rng.standard_normal(rows)
+    y = oracle.spmv(r, v, x, w, num_cols=cols)
+    assert y.shape == (cols,)
+    np.testing.assert_allclose(y, A.T @ x, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(oracle.spmv(r, v, x, num_cols=cols), (A != 0).T @ x, rtol=1e-12, atol=1e-12)
+
+
 def test_spmv_star_and_cycle():
     n = 6
     # in-star: every leaf points at node 0
