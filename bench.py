@@ -295,6 +295,29 @@ def warm_detail(P, torch, png, args):
     return res
 
 
+def warm_eval_detail(P, torch, args, seeds=(2000, 2001, 2002, 2003)):
+    """The learned warm start on the held-out RMAT-24 graphs (EF 16, random
+    labels): iterations and time to tol from the uniform start and from the
+    committed network's start vector, per graph."""
+    import graphgen
+    from paper_1709_07122_amd import warmstart as ws
+
+    params = ws.load(ws.DEFAULT_WEIGHTS)
+    rows = []
+    for sd in seeds:
+        r, c = graphgen.rmat(24, 16, seed=sd, relabel="random")
+        png = P.build_png(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), part_log2=args.part_log2)
+        row = {"seed": sd, **ws.compare(png, params, d=args.d, tol=args.tol, reps=max(1, args.steps // 2))}
+        row["warm_incl_count_over_cold"] = row["warm_ms_first"] / row["cold_ms"]
+        rows.append(row)
+        png.close()
+        log(f"[warm-eval] seed {sd}: cold {row['cold_iters']} iters {row['cold_ms']:.2f} ms; warm {row['warm_iters']} "
+            f"iters {row['warm_ms']:.2f} ms ({row['warm_ms_first']:.2f} ms with the in-degree count, "
+            f"{row['warm_incl_count_over_cold']:.3f} of cold)")
+        del r, c
+    return {"graphs": "RMAT-24 EF16 random labels, seeds 2000-2003 (not in the training set)", "rows": rows}
+
+
 def _timed(torch, fn, reps):
     fn()
     torch.cuda.synchronize()
@@ -586,6 +609,8 @@ def main():
         detail["indegree"] = ind_res
         del ri, ci
 
+    if not args.no_warm and args.iters == 0 and args.graph == "rmat":
+        detail["warm_eval"] = warm_eval_detail(P, torch, args)
     if not args.no_spmv:
         detail["spmv"] = spmv_detail(P, torch, r, c, args)
     if not args.no_batched:

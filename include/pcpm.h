@@ -93,7 +93,7 @@ typedef struct {
                             edge e: sequential scatter writes, the gather
                             reads one run per segment), 0 = automatic: PNG
                             order when the average non-empty segment holds
-                            fewer than 300 updates.  Results are identical.
+                            fewer than 360 updates.  Results are identical.
                             Under autotune, 0 times both orders.             */
   int64_t tune_vectors;  /* autotune objective: 0 or 1 = time per PageRank
                             iteration; v > 1 = time per vector-iteration of

@@ -36,9 +36,10 @@ constexpr int kTile = kWave * kSub;
 
 constexpr int kMaxHist = 100000;   // residual history kept on the device
 // Updates go in PNG order when the average non-empty (pair, bin) segment is
-// shorter than this many updates (measured crossover on MI355X: RMAT with
-// random labels at 2^24 nodes, 333 per segment, runs as fast either way).
-constexpr int64_t kPngOrderRun = 300;
+// shorter than this many updates (measured on MI355X with the non-temporal
+// PNG-order stores: RMAT-24 with random labels, 333 per segment, ran 1.5%
+// faster in PNG order; with in-degree labels, 399 per segment, 7% slower).
+constexpr int64_t kPngOrderRun = 360;
 constexpr int kMaxParts = 16384;   // k limit (LDS cursors of the fill kernel)
 constexpr int kMinLog2 = 1;
 constexpr int kMaxLog2 = 14;       // 16384 * 8 B = 128 KB fixed-point slice in LDS

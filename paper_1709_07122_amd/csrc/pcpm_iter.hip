@@ -130,23 +130,36 @@ __device__ __forceinline__ void scatter_item(const Item it, float* __restrict__ 
   // a scatter item covers PNG edges of one partition pair: stage both slices
   const int64_t v0 = static_cast<int64_t>(it.part) << (s + 1);
   const int qn = static_cast<int>(min(int64_t{2} << s, n - v0));
-  for (int i = threadIdx.x; i < qn; i += BS) {
-    if constexpr (kScale) {
-      const int od = outdeg[v0 + i];
-      spr[i] = od > 0 ? pr[v0 + i] / static_cast<float>(od) : 0.0f;
-    } else {
-      spr[i] = pr[v0 + i];
-    }
-  }
-  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t qmask = (2u << s) - 1u;  // source IDs are local to the pair
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
   uint32_t w[kPairs], wn[kPairs];
   int64_t t = lo / kTile + threadIdx.x / kWave;
+  // the first tile's source IDs are in flight during the staging
   if (t < t_end) load_tile_words(png_src + t * kTile, lane, w);
+  // kSU nodes per thread per step, loads first, so their latencies overlap
+  constexpr int kSU = 8;
+  for (int i0 = threadIdx.x; i0 < qn; i0 += kSU * BS) {
+    float xv[kSU];
+    int od[kSU];
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      const int64_t v = v0 + min(i0 + u * BS, qn - 1);
+      xv[u] = pr[v];
+      if constexpr (kScale) od[u] = outdeg[v];
+    }
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      const int i = i0 + u * BS;
+      if (i < qn) {
+        if constexpr (kScale) spr[i] = od[u] > 0 ? xv[u] / static_cast<float>(od[u]) : 0.0f;
+        else spr[i] = xv[u];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t qmask = (2u << s) - 1u;  // source IDs are local to the pair
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     // the next tile's loads overlap this tile's work

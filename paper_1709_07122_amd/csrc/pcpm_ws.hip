@@ -51,9 +51,10 @@ __device__ __forceinline__ v4s bf16_op(float a, float b, float c, float d) {
 
 // ---- features -------------------------------------------------------------------
 // In-degrees: one workgroup per gather item counts the destination IDs of its
-// range of a bin in an LDS slice of 32-bit counters, then adds the nonzero
-// counts to the global array (the items of a split bin share nodes).
-constexpr int kCountBlock = 512;
+// range of a bin in an LDS slice of 32-bit counters, reading 1024-ID tiles
+// with eight 4-byte loads per lane as the gather does; a whole bin stores its
+// counts, the items of a split bin add theirs to the (zeroed) global array.
+constexpr int kCountBlock = 1024;
 
 __global__ __launch_bounds__(kCountBlock) void k_ws_count(int64_t n, int s, const Item* __restrict__ items,
                                                          const uint16_t* __restrict__ did,
@@ -63,23 +64,37 @@ __global__ __launch_bounds__(kCountBlock) void k_ws_count(int64_t n, int s, cons
   const int64_t q = int64_t{1} << s;
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
-  const uint32_t qmask = static_cast<uint32_t>(q - 1);  // also drops the message flag
+  const uint32_t qmask = static_cast<uint32_t>(q - 1);  // also drops the message and segment flags
   for (int i = threadIdx.x; i < qn; i += kCountBlock) cnt[i] = 0u;
   __syncthreads();
-  constexpr int kU = 4;
+  const int lane = threadIdx.x & (kWave - 1);
   const int64_t lo = it.lo, hi = it.hi;
-  for (int64_t e = lo + threadIdx.x; e < hi; e += kU * kCountBlock) {
-    uint32_t x[kU];
+  const int64_t t_end = (hi + kTile - 1) / kTile;
+  constexpr int kNW = kCountBlock / kWave;
+  for (int64_t t = lo / kTile + threadIdx.x / kWave; t < t_end; t += kNW) {
+    const int64_t tb = t * kTile;
+    uint32_t w[kPairs], x[kSub];
+    load_tile_words(did + tb, lane, w);
+    unpack_tile(w, x);
+    if (tb >= lo && tb + kTile <= hi) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) x[u] = did[tile_pos(min(e + u * kCountBlock, hi - 1))];
+      for (int j = 0; j < kSub; ++j) atomicAdd(&cnt[x[j] & qmask], 1u);
+    } else {
 #pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (e + u * kCountBlock < hi) atomicAdd(&cnt[x[u] & qmask], 1u);
+      for (int j = 0; j < kSub; ++j) {
+        const int64_t e = tb + j * kWave + lane;
+        if (e >= lo && e < hi) atomicAdd(&cnt[x[j] & qmask], 1u);
+      }
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < qn; i += kCountBlock) {
-    const uint32_t c = cnt[i];
-    if (c) atomicAdd(&indeg[v0 + i], c);
+  if (it.aux < 0) {
+    for (int i = threadIdx.x; i < qn; i += kCountBlock) indeg[v0 + i] = cnt[i];
+  } else {
+    for (int i = threadIdx.x; i < qn; i += kCountBlock) {
+      const uint32_t c = cnt[i];
+      if (c) atomicAdd(&indeg[v0 + i], c);
+    }
   }
 }
 
@@ -162,15 +177,21 @@ __global__ __launch_bounds__(256) void k_ws_forward(const float* __restrict__ P,
       }
     }
     float part = 0.0f;
+    // the two output blocks' accumulation chains interleaved, so that one
+    // block's MFMA issues while the other's result is pending
+    v16f h2[2] = {zero, zero};
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+#pragma unroll
+      for (int ob = 0; ob < 2; ++ob)
+        h2[ob] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][kb], b2op[kb], h2[ob], 0, 0, 0);
+    }
 #pragma unroll
     for (int ob = 0; ob < 2; ++ob) {
-      v16f h2 = zero;
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) h2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][kb], b2op[kb], h2, 0, 0, 0);
 #pragma unroll
       for (int v = 0; v < 16; v += 2) {
         const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
-        const uint32_t pk = bf16_pack2(fmaxf(h2[v] + b2s[row], 0.0f), fmaxf(h2[v + 1] + b2s[row + 1], 0.0f));
+        const uint32_t pk = bf16_pack2(fmaxf(h2[ob][v] + b2s[row], 0.0f), fmaxf(h2[ob][v + 1] + b2s[row + 1], 0.0f));
         part += w3s[row] * __uint_as_float(pk << 16);
         part += w3s[row + 1] * __uint_as_float(pk & 0xFFFF0000u);
       }
@@ -394,7 +415,6 @@ static pcpm_status_t ws_prepare(pcpm_png* g, hipStream_t st) {
   const int64_t n = g->n;
   if (!g->ws_x) PCPM_TRY(dalloc(g, &g->ws_x, 2 * n));
   if (g->ws_indeg) return PCPM_OK;
-  const auto t0 = std::chrono::steady_clock::now();
   uint32_t* indeg = nullptr;
   PCPM_TRY(dalloc(g, &indeg, n));
   static bool lds_set = false;
@@ -403,6 +423,9 @@ static pcpm_status_t ws_prepare(pcpm_png* g, hipStream_t st) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kMaxLog2) * 4));
     lds_set = true;
   }
+  // the count's time (the array's allocation above is not part of it)
+  PCPM_TRY_HIP(hipStreamSynchronize(st));
+  const auto t0 = std::chrono::steady_clock::now();
   PCPM_LAUNCH("pcpm_ws_features", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, indeg, g->ws_x, n, 0.0f);
   if (g->n_ga)
     PCPM_LAUNCH("pcpm_ws_features", k_ws_count, dim3(static_cast<unsigned>(g->n_ga)), dim3(kCountBlock),
