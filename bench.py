@@ -62,8 +62,10 @@ def workload_name(args):
     if args.graph == "uniform":
         g = f"a uniform random directed graph of {args.nodes} nodes and {args.draws} edge draws (seed {args.seed})"
     else:
+        labels = ("random node labels" if args.labels == "random" else
+                  "random node labels, then in-degree order from pcpm_relabel")
         g = (f"RMAT scale {args.scale}, edge factor {args.edge_factor:g} (a,b,c=.57,.19,.19, seed {args.seed}), "
-             f"random node labels")
+             f"{labels}")
     stop = f"{args.iters} iterations" if args.iters > 0 else f"to L1 residual {args.tol:g}"
     return f"PageRank d={args.d} {stop} on {g}, partition {1 << args.part_log2} nodes"
 
@@ -131,7 +133,7 @@ def measure(P, torch, r, c, args, label, tol=None, max_iters=None, update_order=
 
     # the same solves in one persistent launch each (for comparison)
     persist_ms = None
-    if png.launch_grid > 0:
+    if png.launch_grid > 0 and not args.no_persistent:
         png.set_launch(2)
         P.pagerank(png, d=args.d, tol=tol, max_iters=max_iters, out=out, want_hist=False)
         torch.cuda.synchronize()
@@ -348,7 +350,7 @@ def ppr_detail(P, torch, args):
         reps = max(1, args.steps // 2)
         b_ms, res = _timed(torch, lambda: P.ppr_batch(png, off, seeds, tol=args.tol, max_iters=args.max_iters), reps)
         p_ms = None
-        if png.launch_grid > 0:
+        if png.launch_grid > 0 and not args.no_persistent:
             png.set_launch(2)
             try:
                 p_ms, _ = _timed(torch, lambda: P.ppr_batch(png, off, seeds, tol=args.tol,
@@ -363,6 +365,20 @@ def ppr_detail(P, torch, args):
 
         s_ms, sres = _timed(torch, one_by_one, 1)
         vec_iters = int(res.iters.sum())
+        # per-kernel table of one batch (events around every launch); a launch
+        # of the gather serves one tile of kt vector slots: 2m + 4kt E' + 8kt n
+        # algorithmic bytes (IDs, updates, fixed-point slice out as ranks and
+        # residual inputs)
+        P.timing_enable(True)
+        P.ppr_batch(png, off, seeds, tol=args.tol, max_iters=args.max_iters)
+        torch.cuda.synchronize()
+        P.timing_enable(False)
+        kt_tab = {name: {"launches": v[0], "avg_ms": v[1] / max(1, v[0])} for name, v in P.timing_collect().items()}
+        ktw = tune.tile_width
+        ep = png.info["eprime"]
+        g_bytes = 2 * m + 4 * ktw * ep + 8 * ktw * n
+        g_avg = kt_tab.get("pcpm_ppr_gather", {}).get("avg_ms")
+        g_gbs = g_bytes / (g_avg * 1e-3) / 1e9 if g_avg else None
         rows.append({"k": k, "part_log2": tune.part_log2, "update_order": tune.update_order,
                      "scatter_chunk": tune.scatter_chunk, "gather_chunk": tune.gather_chunk,
                      "tune_ms_per_vector_iter": tune.ms_per_iter, "tune_table": tune.table,
@@ -371,11 +387,14 @@ def ppr_detail(P, torch, args):
                      "one_at_a_time_update_order": one.update_order,
                      "speedup": s_ms / b_ms, "iters_mean": float(res.iters.mean()), "iters_max": int(res.iters.max()),
                      "converged": bool(res.converged), "vector_gteps": m * vec_iters / (b_ms * 1e-3) / 1e9,
-                     "single_iters_mean": float(np.mean([x.iters[0] for x in sres]))})
+                     "single_iters_mean": float(np.mean([x.iters[0] for x in sres])),
+                     "kernels": kt_tab, "eprime": ep, "gather_bytes_per_launch": g_bytes, "gather_gbs": g_gbs,
+                     "gather_frac_of_peak": None if g_gbs is None else g_gbs / HBM_PEAK_GBS})
         log(f"[ppr] k={k} q=2^{tune.part_log2} order {tune.update_order} width {tune.tile_width}: {b_ms:.2f} ms batched "
             f"(one persistent launch {p_ms} ms) "
             f"vs {s_ms:.2f} ms one at a time (q=2^{one.part_log2} order {one.update_order}, {s_ms / b_ms:.2f}x), "
-            f"{rows[-1]['vector_gteps']:.1f} vector-GTEPS")
+            f"{rows[-1]['vector_gteps']:.1f} vector-GTEPS; gather "
+            + (f"{g_avg * 1e3:.1f} us/launch ({g_gbs / HBM_PEAK_GBS:.3f} of peak)" if g_avg else "not timed"))
         png.close()
     png1.close()
     return {"graph": f"RMAT-22 EF16 seed {args.ppr_seed} random labels", "n": n, "m": m, "tol": args.tol, "rows": rows}
@@ -405,7 +424,7 @@ def multigraph_detail(P, torch, args):
                                                  want_hist=False), reps)
     it, resid = png.graph_results()
     pp_ms = None
-    if png.launch_grid > 0:
+    if png.launch_grid > 0 and not args.no_persistent:
         png.set_launch(2)
         pp_ms, _ = _timed(torch, lambda: P.pagerank(png, d=args.d, tol=args.tol, max_iters=args.max_iters,
                                                     want_hist=False), reps)
@@ -547,10 +566,14 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iters", type=int, default=200)
     ap.add_argument("--no-indegree", action="store_true", help="skip the in-degree-sorted labelling")
+    ap.add_argument("--labels", choices=("random", "indegree"), default="random",
+                    help="labelling of the main RMAT graph (indegree: relabelled on the GPU, no separate leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the personalised and multi-graph legs")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start leg")
     ap.add_argument("--no-spmv", action="store_true", help="skip the weighted SpMV leg")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the comparison runs in one persistent (cooperative) launch")
     ap.add_argument("--no-paper-scale", action="store_true",
                     help="skip the 20-iteration legs on RMAT-26 EF24 and the uniform 50M/1B graph")
     ap.add_argument("--update-order", type=int, default=0, choices=(0, 1, 2),
@@ -590,9 +613,16 @@ def main():
         r, c = graphgen.apply_labels(raw_r, raw_c, perm)
         raw_r = raw_c = None
     log(f"generated {args.graph}: n={n} m={len(c)} in {time.perf_counter() - t:.1f} s")
+    main_name = "random"
+    if args.graph == "rmat" and args.labels == "indegree":
+        r, c, rl_ms = relabel_detail(P, torch, r, c)
+        main_name = "indegree"
+        args.no_indegree = args.no_warm = True
 
-    main_res, x_gpu, png = measure(P, torch, r, c, args, "random")
-    detail = {"random": main_res}
+    main_res, x_gpu, png = measure(P, torch, r, c, args, main_name)
+    if main_name == "indegree":
+        main_res["relabel_ms"] = rl_ms
+    detail = {main_name: main_res}
     warm = None
     if not args.no_warm and args.iters == 0:
         warm = warm_detail(P, torch, png, args)
@@ -664,7 +694,8 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (counter_traffic("pcpm::k_gather<1024, 0, %s>" % (
                 "true" if main_res["update_order"] == "png" else "false")) if args.graph == "rmat" and args.part_log2 == 14
-                        and args.scale == 24 and args.edge_factor == 16 and args.seed == 2 else None),
+                        and args.scale == 24 and args.edge_factor == 16 and args.seed == 2 and args.labels == "random"
+                        else None),
             "bytes_per_launch": main_res["gather_bytes"], "avg_launch_ms": g["avg_ms"],
         },
         "cpu_baseline": cpu,

@@ -317,6 +317,16 @@ pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* firs
  * (device arrays); the prediction of log(n * PR(v)).  Runs on MFMA. */
 pcpm_status_t pcpm_ws_forward(const float* params, const float* feat, int64_t n, float* yhat, void* stream);
 
+/* The warm-start prediction for the handle's nodes without a feature matrix:
+ * yhat (device, n floats) equals pcpm_ws_forward(params, F) for the matrix F
+ * that pcpm_ws_features(g, d, F) writes, bit for bit, with the features
+ * formed in the forward kernel from the in-degrees, out-degrees, dangling
+ * mask and first iterate (one PCPM iteration, as pcpm_ws_features runs).
+ * Same handle requirements, in-degree count and *first_call_ms as
+ * pcpm_ws_features. */
+pcpm_status_t pcpm_ws_predict(pcpm_png_t g, const float* params, double d, float* yhat,
+                              double* first_call_ms /* (host) nullable */, void* stream);
+
 /* pr0 = softmax of yhat over the n nodes (max-shifted, FP64 sum): a start
  * vector of unit mass for pcpm_pagerank.  If any prediction is non-finite the
  * uniform vector 1/n is written instead and *fallback (host) is 1.  work:

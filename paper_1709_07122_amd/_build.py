@@ -20,6 +20,9 @@ HIPCC_FLAGS = [
     "-shared",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in ordinary VGPRs: the warm-start forward's epilogue reads
+    # them directly instead of copying each one out of an accumulator register
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall",
     "-Wno-unused-result",
 ]

@@ -33,7 +33,7 @@ STATUS_NAMES = {
 EXPORTS = ["pcpm_build_png", "pcpm_png_info", "pcpm_png_export", "pcpm_png_free", "pcpm_iterate",
            "pcpm_pagerank", "pcpm_ppr_batch", "pcpm_ppr_tile_width", "pcpm_graph_results", "pcpm_set_launch", "pcpm_launch_grid", "pcpm_tune_table",
            "pcpm_tune_cache_clear", "pcpm_graph_hash", "pcpm_hbm_stream", "pcpm_last_error",
-           "pcpm_timing_enable", "pcpm_timing_collect", "pcpm_ws_features", "pcpm_ws_forward", "pcpm_ws_init",
+           "pcpm_timing_enable", "pcpm_timing_collect", "pcpm_ws_features", "pcpm_ws_forward", "pcpm_ws_predict", "pcpm_ws_init",
            "pcpm_ws_work_floats", "pcpm_ws_backward", "pcpm_ws_backward_noalloc", "pcpm_ws_adam", "pcpm_ws_targets", "pcpm_spmv",
            "pcpm_png_export_weights", "pcpm_relabel"]
 
@@ -116,6 +116,8 @@ def lib():
     L.pcpm_ws_features.argtypes = [vp, dbl, vp, ctypes.POINTER(dbl), vp]
     L.pcpm_ws_forward.restype = ctypes.c_int
     L.pcpm_ws_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.pcpm_ws_predict.restype = ctypes.c_int
+    L.pcpm_ws_predict.argtypes = [vp, vp, dbl, vp, ctypes.POINTER(dbl), vp]
     L.pcpm_ws_init.restype = ctypes.c_int
     L.pcpm_ws_init.argtypes = [vp, i64, vp, vp, ctypes.POINTER(i32), vp]
     L.pcpm_ws_work_floats.restype = i64
@@ -511,6 +513,20 @@ def ws_features(png: PNG, d: float = 0.85, stream=None):
     _check(lib().pcpm_ws_features(png.handle, float(d), _dev_tensor(feat, torch.float32, name="feat"),
                                   ctypes.byref(ms), _stream(stream)))
     return feat, ms.value
+
+
+def ws_predict(png: PNG, params, d: float = 0.85, out=None, stream=None):
+    """The network's prediction for every node of the handle with the
+    features formed inside the forward (pcpm_ws_predict): equal to
+    ws_forward(params, ws_features(png, d)[0]).  Returns (yhat, ms of the
+    per-handle in-degree count done by the first call)."""
+    import torch
+    if out is None:
+        out = torch.empty(png.n, dtype=torch.float32, device=png.row_off.device)
+    ms = ctypes.c_double(0.0)
+    _check(lib().pcpm_ws_predict(png.handle, _dev_tensor(params, torch.float32, WS_PARAMS, "params"), float(d),
+                                 _dev_tensor(out, torch.float32, png.n, "yhat"), ctypes.byref(ms), _stream(stream)))
+    return out, ms.value
 
 
 def ws_forward(params, feat, stream=None):

@@ -107,20 +107,29 @@ __global__ __launch_bounds__(256) void k_ws_prep(uint32_t* __restrict__ indeg, f
   }
 }
 
-__global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, const uint32_t* __restrict__ indeg,
-                                                     const int32_t* __restrict__ outdeg,
-                                                     const uint32_t* __restrict__ dmask,
-                                                     const float* __restrict__ pr1, int64_t n) {
-  const float fn = static_cast<float>(n);
+// The four features of node v (the other four are zero).
+struct FeatSrc {
+  const uint32_t* indeg;
+  const int32_t* outdeg;
+  const uint32_t* dmask;
+  const float* pr1;
+  float fn;  // n
+};
+
+__device__ __forceinline__ float4 node_features(const FeatSrc& fs, int64_t v) {
+  float4 f;
+  f.x = log1pf(static_cast<float>(fs.indeg[v]));
+  f.y = log1pf(static_cast<float>(fs.outdeg[v]));
+  f.z = static_cast<float>((fs.dmask[v >> 5] >> (v & 31)) & 1u);
+  f.w = logf(fs.pr1[v] * fs.fn);  // FP32 is ample: the network sees the value rounded to BF16
+  return f;
+}
+
+__global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, const FeatSrc fs, int64_t n) {
   for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
        v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    float4 f;
-    f.x = log1pf(static_cast<float>(indeg[v]));
-    f.y = log1pf(static_cast<float>(outdeg[v]));
-    f.z = static_cast<float>((dmask[v >> 5] >> (v & 31)) & 1u);
-    f.w = logf(pr1[v] * fn);  // FP32 is ample: the network sees the value rounded to BF16
     float4* out = reinterpret_cast<float4*>(feat + kF * v);
-    out[0] = f;
+    out[0] = node_features(fs, v);
     out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
 }
@@ -128,134 +137,197 @@ __global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, c
 // ---- inference on MFMA ------------------------------------------------------------
 // One wavefront evaluates 32 nodes with transposed products, so the output of
 // each layer is already the B operand of the next:
-//   h1^T = W1 X^T (2 MFMA 32x32x8),  h2^T = W2 h1^T (16),  y = w3 . h2 + b3.
-// Lane l owns node l%32; in a 32x32 output block its value v is row
-// 8(v/4) + 4(l/32) + v%4, which for K-block t of the next product is exactly
-// the four B values that lane must supply (v = 4t .. 4t+3).
-__global__ __launch_bounds__(256) void k_ws_forward(const float* __restrict__ P, const float* __restrict__ feat,
-                                                    int64_t n, float* __restrict__ yhat) {
-  __shared__ float b1s[kH], b2s[kH], w3s[kH];
-  for (int i = threadIdx.x; i < kH; i += 256) {
-    b1s[i] = P[kOB1 + i];
-    b2s[i] = P[kOB2 + i];
-    w3s[i] = bf16_round(P[kOW3 + i]);
-  }
-  __syncthreads();
-  const float b3 = P[kOB3];
+//   h1^T = W1 X^T + b1 (2 MFMA 32x32x8),  h2^T = W2 h1^T + b2 (8 MFMA
+//   32x32x16),  y = w3 . h2 + b3 (BF16 dot products).
+// Lane l owns node l%32.  In a 32x32 output block its value v is row
+// 8(v/4) + 4(l/32) + v%4; values 8p .. 8p+7 of hidden block c are therefore
+// rows 16t + 8(i/4) + 4(l/32) + i%4 (t = 2c + p, i = 0..7), which is what the
+// lane supplies as B operand slot i of K-block t of the next product, and the
+// A operand (W2) takes its columns in that same order.  The biases enter as
+// the accumulator input, ReLU acts on the packed BF16 values (as 16-bit
+// integers the negative ones, -0 included, are exactly those below zero,
+// and rounding commutes with it), and the output layer is 16 two-wide BF16
+// dot products per lane with FP32 sums.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v2s __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  const v2s z = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(v2s, bf16_pack2(a, b)), z));
+}
+
+constexpr int kFwdBlock = 256;
+constexpr int kFwdMaxBlocks = 2048;
+
+// kFused: the features are formed from their sources (in-degrees, out-degrees,
+// dangling mask, first iterate) as k_ws_features forms them, instead of read
+// from a feature matrix; the prediction is the same bit for bit.
+template <bool kFused>
+__global__ __launch_bounds__(kFwdBlock) void k_ws_forward(const float* __restrict__ P, const float* __restrict__ feat,
+                                                          const FeatSrc fs, int64_t n, float* __restrict__ yhat) {
   const int l = threadIdx.x & (kWave - 1);
   const int col = l & 31, half = l >> 5;
-  // A fragments: row 32*ob + col, columns 4*half .. +4 of each K-block
-  v4s a1[2], a2[2][8];
+  // A fragments: row 32*ob + col; W1 columns 4*half .. +3, W2 columns in the
+  // B operand's slot order
+  v4s a1[2];
+  v8bf a2[2][4];
+  v16f c1[2], c2[2];
+  bf16x2 w3p[2][8];
 #pragma unroll
   for (int ob = 0; ob < 2; ++ob) {
-    const float* w1 = P + kOW1 + (32 * ob + col) * kF + 4 * half;
+    const int r = 32 * ob + col;
+    const float* w1 = P + kOW1 + r * kF + 4 * half;
     a1[ob] = bf16_op(w1[0], w1[1], w1[2], w1[3]);
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      const float* w2 = P + kOW2 + (32 * ob + col) * kH + 8 * kb + 4 * half;
-      a2[ob][kb] = bf16_op(w2[0], w2[1], w2[2], w2[3]);
+    for (int t = 0; t < 4; ++t) {
+      const float* w2 = P + kOW2 + r * kH + 16 * t + 4 * half;
+      uint32_t pk[4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        pk[2 * j] = bf16_pack2(w2[8 * j], w2[8 * j + 1]);
+        pk[2 * j + 1] = bf16_pack2(w2[8 * j + 2], w2[8 * j + 3]);
+      }
+      a2[ob][t] = __builtin_bit_cast(v8bf, make_uint4(pk[0], pk[1], pk[2], pk[3]));
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
+      c1[ob][v] = P[kOB1 + row];
+      c2[ob][v] = P[kOB2 + row];
+    }
+#pragma unroll
+    for (int v = 0; v < 16; v += 2) {
+      const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
+      w3p[ob][v / 2] = __builtin_bit_cast(bf16x2, bf16_pack2(P[kOW3 + row], P[kOW3 + row + 1]));
     }
   }
-  const int64_t waves = static_cast<int64_t>(gridDim.x) * (256 / kWave);
-  for (int64_t base = (static_cast<int64_t>(blockIdx.x) * (256 / kWave) + threadIdx.x / kWave) * 32; base < n;
+  const float b3 = P[kOB3];
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kFwdBlock / kWave);
+  for (int64_t base = (static_cast<int64_t>(blockIdx.x) * (kFwdBlock / kWave) + threadIdx.x / kWave) * 32; base < n;
        base += waves * 32) {
     const int64_t node = base + col;
     float4 fv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (node < n) fv = *reinterpret_cast<const float4*>(feat + kF * node + 4 * half);
+    if constexpr (kFused) {
+      if (node < n && half == 0) fv = node_features(fs, node);
+    } else {
+      if (node < n) fv = *reinterpret_cast<const float4*>(feat + kF * node + 4 * half);
+    }
     const v4s bx = bf16_op(fv.x, fv.y, fv.z, fv.w);
-    const v16f zero = {};
-    v4s b2op[8];
+    uint32_t hp[2][8];  // relu(h1) as packed BF16 pairs (v, v+1)
 #pragma unroll
     for (int ob = 0; ob < 2; ++ob) {
-      const v16f h1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[ob], bx, zero, 0, 0, 0);
+      const v16f h1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[ob], bx, c1[ob], 0, 0, 0);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int row = 32 * ob + 8 * t + 4 * half;
-        b2op[4 * ob + t] = bf16_op(fmaxf(h1[4 * t] + b1s[row], 0.0f), fmaxf(h1[4 * t + 1] + b1s[row + 1], 0.0f),
-                                   fmaxf(h1[4 * t + 2] + b1s[row + 2], 0.0f),
-                                   fmaxf(h1[4 * t + 3] + b1s[row + 3], 0.0f));
-      }
+      for (int v = 0; v < 16; v += 2) hp[ob][v / 2] = relu_bf16x2(h1[v], h1[v + 1]);
     }
-    float part = 0.0f;
-    // the two output blocks' accumulation chains interleaved, so that one
-    // block's MFMA issues while the other's result is pending
-    v16f h2[2] = {zero, zero};
+    v16f h2[2] = {c2[0], c2[1]};
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
+    for (int t = 0; t < 4; ++t) {
+      const v8bf b = __builtin_bit_cast(
+          v8bf, make_uint4(hp[t / 2][4 * (t % 2)], hp[t / 2][4 * (t % 2) + 1], hp[t / 2][4 * (t % 2) + 2],
+                           hp[t / 2][4 * (t % 2) + 3]));
 #pragma unroll
-      for (int ob = 0; ob < 2; ++ob)
-        h2[ob] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a2[ob][kb], b2op[kb], h2[ob], 0, 0, 0);
+      for (int ob = 0; ob < 2; ++ob) h2[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[ob][t], b, h2[ob], 0, 0, 0);
     }
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ob = 0; ob < 2; ++ob) {
 #pragma unroll
-      for (int v = 0; v < 16; v += 2) {
-        const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
-        const uint32_t pk = bf16_pack2(fmaxf(h2[ob][v] + b2s[row], 0.0f), fmaxf(h2[ob][v + 1] + b2s[row + 1], 0.0f));
-        part += w3s[row] * __uint_as_float(pk << 16);
-        part += w3s[row + 1] * __uint_as_float(pk & 0xFFFF0000u);
-      }
+      for (int v = 0; v < 16; v += 2)
+        part[v / 4] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, relu_bf16x2(h2[ob][v], h2[ob][v + 1])),
+                                                      w3p[ob][v / 2], part[v / 4], false);
     }
-    part += __shfl_xor(part, 32);  // lanes l and l^32 hold the two halves of node col's rows
-    if (half == 0 && node < n) yhat[node] = part + b3;
+    float y = (part[0] + part[1]) + (part[2] + part[3]);
+    y += __shfl_xor(y, 32);  // lanes l and l^32 hold the two halves of node col's rows
+    if (half == 0 && node < n) yhat[node] = y + b3;
   }
 }
 
 // ---- start vector: softmax over nodes --------------------------------------------
-constexpr int kSoftBlocks = 256;
+// Two passes.  k_ws_soft_part: every thread keeps a running maximum m and the
+// sum s of exp(y - m) over its nodes (FP64; s is rescaled when m grows), and
+// the workgroup combines its threads' pairs into one (M, S, non-finite flag).
+// k_ws_soft_norm: every workgroup combines the kSoftBlocks partial pairs
+// (one load per thread) and writes exp(y - M) / S, or the uniform vector if
+// a prediction was non-finite or S is not a positive finite number.
+constexpr int kSoftBlocks = 1024;
+constexpr int kSoftThreads = 256;
 
-__global__ __launch_bounds__(256) void k_ws_max(const float* __restrict__ y, int64_t n, float* __restrict__ red) {
-  float mx = -INFINITY;
-  float bad = 0.0f;
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
-       v += static_cast<int64_t>(gridDim.x) * 256) {
-    const float yv = y[v];
-    if (!isfinite(yv)) bad = 1.0f;
-    mx = fmaxf(mx, yv);
+struct SoftPair {
+  double m, s, bad;
+};
+
+__device__ __forceinline__ SoftPair soft_combine(SoftPair a, SoftPair b) {
+  const double m = fmax(a.m, b.m);
+  SoftPair r;
+  r.m = m;
+  r.s = (a.s > 0.0 ? a.s * exp(a.m - m) : 0.0) + (b.s > 0.0 ? b.s * exp(b.m - m) : 0.0);
+  r.bad = fmax(a.bad, b.bad);
+  return r;
+}
+
+// workgroup-wide combination of one pair per thread; the result in every thread
+__device__ __forceinline__ SoftPair soft_block(SoftPair p) {
+  __shared__ double sh[3][kSoftThreads / kWave];
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    SoftPair o;
+    o.m = __shfl_xor(p.m, off);
+    o.s = __shfl_xor(p.s, off);
+    o.bad = __shfl_xor(p.bad, off);
+    p = soft_combine(p, o);
   }
-  __shared__ float sm[256], sb[256];
-  sm[threadIdx.x] = mx;
-  sb[threadIdx.x] = bad;
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    sh[0][w] = p.m;
+    sh[1][w] = p.s;
+    sh[2][w] = p.bad;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < 256; ++i) {
-      mx = fmaxf(mx, sm[i]);
-      bad = fmaxf(bad, sb[i]);
+  SoftPair r = {sh[0][0], sh[1][0], sh[2][0]};
+  for (int i = 1; i < kSoftThreads / kWave; ++i) r = soft_combine(r, SoftPair{sh[0][i], sh[1][i], sh[2][i]});
+  return r;
+}
+
+__global__ __launch_bounds__(kSoftThreads) void k_ws_soft_part(const float* __restrict__ y, int64_t n,
+                                                               double* __restrict__ red) {
+  SoftPair p = {-INFINITY, 0.0, 0.0};
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * kSoftThreads + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * kSoftThreads) {
+    const float yv = y[v];
+    if (!isfinite(yv)) {
+      p.bad = 1.0;
+      continue;
     }
-    red[2 * blockIdx.x] = mx;
-    red[2 * blockIdx.x + 1] = bad;
+    const double yd = static_cast<double>(yv);
+    if (yd > p.m) {
+      p.s = p.s * exp(p.m - yd) + 1.0;
+      p.m = yd;
+    } else {
+      p.s += exp(yd - p.m);
+    }
+  }
+  const SoftPair r = soft_block(p);
+  if (threadIdx.x == 0) {
+    red[3 * blockIdx.x] = r.m;
+    red[3 * blockIdx.x + 1] = r.s;
+    red[3 * blockIdx.x + 2] = r.bad;
   }
 }
 
-__global__ __launch_bounds__(256) void k_ws_expsum(const float* __restrict__ y, int64_t n,
-                                                   const float* __restrict__ red, double* __restrict__ dred) {
-  float mx = -INFINITY;
-  for (int i = 0; i < kSoftBlocks; ++i) mx = fmaxf(mx, red[2 * i]);
-  double sums[1] = {0.0};
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
-       v += static_cast<int64_t>(gridDim.x) * 256)
-    sums[0] += exp(static_cast<double>(y[v]) - static_cast<double>(mx));
-  block_sum<256>(sums);
-  if (threadIdx.x == 0) dred[blockIdx.x] = sums[0];
-}
-
-__global__ __launch_bounds__(256) void k_ws_normalise(const float* __restrict__ y, int64_t n,
-                                                      const float* __restrict__ red, const double* __restrict__ dred,
-                                                      float* __restrict__ pr0, int32_t* __restrict__ flag) {
-  float mx = -INFINITY, bad = 0.0f;
-  for (int i = 0; i < kSoftBlocks; ++i) {
-    mx = fmaxf(mx, red[2 * i]);
-    bad = fmaxf(bad, red[2 * i + 1]);
-  }
-  double sum = 0.0;
-  for (int i = 0; i < kSoftBlocks; ++i) sum += dred[i];
-  const bool fallback = bad > 0.0f || !(sum > 0.0) || !isfinite(sum);
+__global__ __launch_bounds__(kSoftThreads) void k_ws_soft_norm(const float* __restrict__ y, int64_t n,
+                                                               const double* __restrict__ red,
+                                                               float* __restrict__ pr0, int32_t* __restrict__ flag) {
+  SoftPair p = {-INFINITY, 0.0, 0.0};
+  for (int i = threadIdx.x; i < kSoftBlocks; i += kSoftThreads)
+    p = soft_combine(p, SoftPair{red[3 * i], red[3 * i + 1], red[3 * i + 2]});
+  const SoftPair r = soft_block(p);
+  const bool fallback = r.bad > 0.0 || !(r.s > 0.0) || !isfinite(r.s);
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = fallback ? 1 : 0;
-  const double inv = fallback ? 0.0 : 1.0 / sum;
+  const double inv = fallback ? 0.0 : 1.0 / r.s;
   const float uni = static_cast<float>(1.0 / static_cast<double>(n));
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n;
-       v += static_cast<int64_t>(gridDim.x) * 256)
-    pr0[v] = fallback ? uni : static_cast<float>(exp(static_cast<double>(y[v]) - static_cast<double>(mx)) * inv);
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * kSoftThreads + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * kSoftThreads)
+    pr0[v] = fallback ? uni : static_cast<float>(exp(static_cast<double>(y[v]) - r.m) * inv);
 }
 
 // ---- training: loss gradient over a minibatch -------------------------------------
@@ -408,6 +480,16 @@ __global__ __launch_bounds__(256) void k_ws_targets(const float* __restrict__ pr
     y[v] = static_cast<float>(log(static_cast<double>(pr[v]) * static_cast<double>(n)));
 }
 
+// 32 nodes per wavefront, 4 wavefronts per workgroup
+static unsigned forward_blocks(int64_t n) {
+  const int64_t groups = (n + 31) / 32;
+  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, kFwdMaxBlocks)));
+}
+
+static FeatSrc feat_src(const pcpm_png* g) {
+  return FeatSrc{g->ws_indeg, g->outdeg, g->dmask, g->ws_x + g->n, static_cast<float>(g->n)};
+}
+
 static unsigned grid_for(int64_t n) { return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192))); }
 
 // In-degrees of a handle (counted on first use) and the rank buffers.
@@ -523,8 +605,28 @@ pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* firs
   const float uni = static_cast<float>(1.0 / static_cast<double>(n));
   PCPM_LAUNCH("pcpm_ws_features", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, nullptr, g->ws_x, n, uni);
   PCPM_TRY(pcpm_iterate(g, d, g->ws_x, g->ws_x + n, nullptr, stream));
-  PCPM_LAUNCH("pcpm_ws_features", k_ws_features, dim3(grid_for(n)), dim3(256), 0, st, feat, g->ws_indeg, g->outdeg,
-              g->dmask, g->ws_x + n, n);
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_features, dim3(grid_for(n)), dim3(256), 0, st, feat, feat_src(g), n);
+  return PCPM_OK;
+}
+
+pcpm_status_t pcpm_ws_predict(pcpm_png_t g, const float* params, double d, float* yhat, double* first_call_ms,
+                              void* stream) {
+  using namespace pcpm;
+  if (!g || !yhat) return set_error(PCPM_ERR_INVALID_ARG, "NULL handle or output");
+  if (!(d >= 0.0 && d < 1.0)) return set_error(PCPM_ERR_INVALID_ARG, "d must lie in [0, 1)");
+  if (g->ngroups != 1 || g->matrix)
+    return set_error(PCPM_ERR_INVALID_ARG, "warm start needs a single-graph handle (not a matrix)");
+  PCPM_TRY(ws_check_device_ptr(params, "params"));
+  PCPM_TRY(ws_check_device_ptr(yhat, "yhat"));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PCPM_TRY(ws_prepare(g, st));
+  if (first_call_ms) *first_call_ms = g->ws_indeg_ms;
+  const int64_t n = g->n;
+  const float uni = static_cast<float>(1.0 / static_cast<double>(n));
+  PCPM_LAUNCH("pcpm_ws_predict", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, nullptr, g->ws_x, n, uni);
+  PCPM_TRY(pcpm_iterate(g, d, g->ws_x, g->ws_x + n, nullptr, stream));
+  PCPM_LAUNCH("pcpm_ws_predict", k_ws_forward<true>, dim3(forward_blocks(n)), dim3(kFwdBlock), 0, st, params,
+              nullptr, feat_src(g), n, yhat);
   return PCPM_OK;
 }
 
@@ -535,9 +637,8 @@ pcpm_status_t pcpm_ws_forward(const float* params, const float* feat, int64_t n,
   PCPM_TRY(ws_check_device_ptr(feat, "feat"));
   PCPM_TRY(ws_check_device_ptr(yhat, "yhat"));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t groups = (n + 31) / 32;  // 32 nodes per wavefront, 4 wavefronts per workgroup
-  const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 16384)));
-  PCPM_LAUNCH("pcpm_ws_forward", k_ws_forward, dim3(blocks), dim3(256), 0, st, params, feat, n, yhat);
+  PCPM_LAUNCH("pcpm_ws_forward", k_ws_forward<false>, dim3(forward_blocks(n)), dim3(kFwdBlock), 0, st, params, feat,
+              FeatSrc{}, n, yhat);
   return PCPM_OK;
 }
 
@@ -548,12 +649,10 @@ pcpm_status_t pcpm_ws_init(const float* yhat, int64_t n, float* pr0, float* work
   PCPM_TRY(ws_check_device_ptr(pr0, "pr0"));
   PCPM_TRY(ws_check_device_ptr(work, "work"));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  float* red = work;                                            // 2 * kSoftBlocks floats
-  double* dred = reinterpret_cast<double*>(work + 2 * kSoftBlocks);  // kSoftBlocks doubles
-  int32_t* flag = reinterpret_cast<int32_t*>(work + 4 * kSoftBlocks);
-  PCPM_LAUNCH("pcpm_ws_init", k_ws_max, dim3(kSoftBlocks), dim3(256), 0, st, yhat, n, red);
-  PCPM_LAUNCH("pcpm_ws_init", k_ws_expsum, dim3(kSoftBlocks), dim3(256), 0, st, yhat, n, red, dred);
-  PCPM_LAUNCH("pcpm_ws_init", k_ws_normalise, dim3(grid_for(n)), dim3(256), 0, st, yhat, n, red, dred, pr0, flag);
+  double* red = reinterpret_cast<double*>(work);                   // 3 * kSoftBlocks doubles
+  int32_t* flag = reinterpret_cast<int32_t*>(work + 6 * kSoftBlocks);
+  PCPM_LAUNCH("pcpm_ws_init", k_ws_soft_part, dim3(kSoftBlocks), dim3(kSoftThreads), 0, st, yhat, n, red);
+  PCPM_LAUNCH("pcpm_ws_init", k_ws_soft_norm, dim3(grid_for(n)), dim3(kSoftThreads), 0, st, yhat, n, red, pr0, flag);
   PCPM_TRY_HIP(hipMemcpyAsync(fallback, flag, 4, hipMemcpyDeviceToHost, st));
   PCPM_TRY_HIP(hipStreamSynchronize(st));
   return PCPM_OK;
@@ -561,7 +660,7 @@ pcpm_status_t pcpm_ws_init(const float* yhat, int64_t n, float* pr0, float* work
 
 int64_t pcpm_ws_work_floats(int64_t b) {
   const int64_t parts = std::max<int64_t>(1, std::min<int64_t>((b + pcpm::kChunk - 1) / pcpm::kChunk, 1024));
-  return std::max<int64_t>(parts * PCPM_WS_PARAMS + 4 * (parts + 1), 4 * pcpm::kSoftBlocks + 4);
+  return std::max<int64_t>(parts * PCPM_WS_PARAMS + 4 * (parts + 1), 6 * pcpm::kSoftBlocks + 4);
 }
 
 pcpm_status_t pcpm_ws_backward(const float* params, const float* feat, const float* target, int64_t rows,

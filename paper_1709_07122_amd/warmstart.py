@@ -153,26 +153,27 @@ def train(specs, epochs: int = 30, batch: int = 16384, lr: float = 3e-3, seed: i
 
 def warm_start(png, params, d: float = 0.85):
     """Start vector predicted for this handle: (pr0, used_uniform)."""
-    feat, _ = P.ws_features(png, d)
-    return P.ws_init(P.ws_forward(params, feat))
+    yhat, _ = P.ws_predict(png, params, d)
+    return P.ws_init(yhat)
 
 
 def compare(png, params, d: float = 0.85, tol: float = 1e-6, reps: int = 3):
     """Iterations and time to tol from the uniform start and from the learned
-    start.  The warm time covers features (one PCPM iteration and the feature
-    kernel), the MLP, the normalisation and the solve; the in-degree count,
-    done once per handle, is reported apart and added in warm_ms_first."""
+    start.  The warm time covers the prediction (one PCPM iteration for the
+    first iterate, then the MLP with the features formed in its kernel), the
+    normalisation and the solve; the in-degree count, done once per handle,
+    is reported apart and added in warm_ms_first."""
     import torch
 
-    _, count_ms = P.ws_features(png, d)
     out = torch.empty(png.n, dtype=torch.float32, device="cuda")
+    yhat, count_ms = P.ws_predict(png, params, d)
 
     def cold():
         return P.pagerank(png, d=d, tol=tol, max_iters=500, out=out, want_hist=False)
 
     def warm():
-        f, _ = P.ws_features(png, d)
-        pr0, fb = P.ws_init(P.ws_forward(params, f))
+        P.ws_predict(png, params, d, out=yhat)
+        pr0, fb = P.ws_init(yhat)
         return P.pagerank(png, d=d, tol=tol, max_iters=500, init=pr0, out=out, want_hist=False), fb
 
     cold()

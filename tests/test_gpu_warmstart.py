@@ -212,6 +212,24 @@ def test_features_need_a_single_graph():
     png = P.build_png(dev(row_off), dev(col), part_log2=8, graph_node_off=offs, graph_nodes=sizes)
     with pytest.raises(P.PCPMError):
         P.ws_features(png)
+    with pytest.raises(P.PCPMError):
+        P.ws_predict(png, P.warmstart.load(P.warmstart.DEFAULT_WEIGHTS))
+    png.close()
+
+
+@pytest.mark.parametrize("scale,part_log2,d", [(10, 9, 0.85), (15, 14, 0.85), (13, 11, 0.5)])
+def test_predict_equals_forward_of_the_features(scale, part_log2, d):
+    """The fused prediction (features formed inside the forward kernel) is the
+    forward pass of the feature matrix, bit for bit, on a fresh handle (the
+    in-degree count runs inside it) and on a second call."""
+    r, c = graphgen.rmat(scale, 16, seed=scale, relabel="random")
+    params = P.warmstart.load(P.warmstart.DEFAULT_WEIGHTS)
+    png = P.build_png(dev(r), dev(c), part_log2=part_log2)
+    y1, _ = P.ws_predict(png, params, d)
+    y2, _ = P.ws_predict(png, params, d)
+    f, _ = P.ws_features(png, d)
+    ref = P.ws_forward(params, f)
+    assert torch.equal(y1, ref) and torch.equal(y2, ref)
     png.close()
 
 
