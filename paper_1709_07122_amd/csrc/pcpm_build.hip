@@ -893,33 +893,40 @@ static pcpm_status_t build_items(pcpm_png* g, const pcpm_build_opts_t* opts, hip
     for (int64_t nl = 0; nl < qn; nl += 256) mg.push_back({static_cast<int32_t>(p), first, slot - first,
                                                            static_cast<int32_t>(nl)});
   }
-  // gather: largest work first
-  auto bigger = [](const Item& x, const Item& y) { return (x.hi - x.lo) > (y.hi - y.lo); };
-  std::stable_sort(ga_items.begin(), ga_items.end(), bigger);
-  // Scatter: workgroup b runs array entry xcd_block(b, n), so XCD x runs one
-  // contiguous range of the array.  With items in source-partition order,
-  // partitions p and p+1, whose segments lie next to each other in every bin,
-  // run together on one XCD and the cache lines they share fill in its L2
-  // before they are written back.  That order suits partitions of similar
-  // work; if it would load one XCD more than 10% above the mean, the array
-  // instead holds the items largest first in dispatch order.
+  // Workgroup b of a scatter or gather launch runs array entry xcd_block(b, n),
+  // so XCD x runs one contiguous range of the array.  Scatter: with items in
+  // source-partition order, pairs p and p+1, whose segments lie next to each
+  // other in every bin, run together on one XCD and the cache lines they
+  // share fill in its L2 once.  That order suits pairs of similar work; if it
+  // would load one XCD more than 10% above the mean, the array instead holds
+  // the items largest first in dispatch order.  Gather: always largest first.
+  // Neighbouring bins together on one XCD would share lines too, but with
+  // PNG-ordered updates their segments of a source pair are neighbours, so
+  // 32 workgroups would read one small region of the update array at a time
+  // (measured: the RMAT-24 gather 350 -> 461 us); bins in size order spread
+  // the reads over the whole run of each pair.
+  auto largest_first = [](std::vector<Item>& items) {
+    const unsigned ni = static_cast<unsigned>(items.size());
+    std::vector<Item> lpt = items;
+    std::stable_sort(lpt.begin(), lpt.end(), [](const Item& x, const Item& y) { return (x.hi - x.lo) > (y.hi - y.lo); });
+    for (unsigned b = 0; b < ni; ++b) items[xcd_block(b, ni)] = lpt[b];
+  };
   {
-    const unsigned nsc = static_cast<unsigned>(sc_items.size());
+    const unsigned ni = static_cast<unsigned>(sc_items.size());
     std::vector<int64_t> xw(kXcds, 0);
     int64_t tot = 0;
-    for (unsigned b = 0; b < nsc; ++b) {
-      const Item& it = sc_items[xcd_block(b, nsc)];
+    for (unsigned b = 0; b < ni; ++b) {
+      const Item& it = sc_items[xcd_block(b, ni)];
       xw[b % kXcds] += it.hi - it.lo;
       tot += it.hi - it.lo;
     }
-    const int64_t worst = nsc ? *std::max_element(xw.begin(), xw.end()) : 0;
-    if (nsc && worst * 10 > 11 * ((tot + kXcds - 1) / kXcds)) {
-      std::vector<Item> lpt = sc_items;
-      std::stable_sort(lpt.begin(), lpt.end(), bigger);
-      for (unsigned b = 0; b < nsc; ++b) sc_items[xcd_block(b, nsc)] = lpt[b];
+    const int64_t worst = ni ? *std::max_element(xw.begin(), xw.end()) : 0;
+    if (ni && worst * 10 > 11 * ((tot + kXcds - 1) / kXcds)) {
+      largest_first(sc_items);
       g->scatter_order = 1;
     }
   }
+  largest_first(ga_items);
 
   g->n_sc = static_cast<int32_t>(sc_items.size());
   g->n_ga = static_cast<int32_t>(ga_items.size());
@@ -1090,7 +1097,8 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   const int64_t order = opts ? opts->update_order : 0;
   if (order < 0 || order > 2) return set_error(PCPM_ERR_INVALID_ARG, "update_order must be 0, 1 or 2");
   g->png_order = order == 2 || (order == 0 && g->eprime < kPngOrderRun * g->nseg);
-  PCPM_TRY(dalloc(g, &g->seg_delta, g->nseg));
+  PCPM_TRY(dalloc(g, &g->seg_delta, g->nseg + kWave));  // padded for the gathers' 64-wide delta loads
+  PCPM_TRY_HIP(hipMemsetAsync(g->seg_delta + g->nseg, 0, kWave * sizeof(int32_t), st));
   if (g->png_order) {
     PCPM_LAUNCH("pcpm_build_segdelta", k_segdelta_bins, dim3(kk), dim3(256), 0, st, static_cast<int32_t>(k), cnt,
                 g->wo, g->png_off, g->upd_start, g->png_base, segbase, g->seg_delta);

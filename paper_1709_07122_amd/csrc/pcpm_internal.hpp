@@ -272,6 +272,60 @@ __device__ __forceinline__ void load_tile_words(const uint16_t* tile, int lane, 
   for (int j = 0; j < kPairs; ++j) w[j] = p[j * kWave + lane];
 }
 
+// Update slots of one tile of destination IDs (Alg. 5): an ID's message index
+// in bin order is the number of message flags so far (inclusive) minus one;
+// blk = message flags before the tile.  With updates in PNG order the slot
+// adds the delta of the ID's (bin, source pair) segment, the segment index
+// counting segment flags the same way (sblk = segment flags before the
+// tile).  dl holds, in lane i, the delta of segment max(sblk - 1, 0) + i,
+// loaded ahead of the tile; a tile that reaches past those 64 segments reads
+// its deltas from seg_delta instead.
+template <bool kPng>
+__device__ __forceinline__ void tile_slots(const uint32_t (&x)[kSub], int32_t blk, int32_t sblk, int32_t dl,
+                                           const int32_t* __restrict__ seg_delta, int32_t (&slot)[kSub]) {
+  int32_t run = blk - 1, srun = sblk - 1;
+  int32_t seg[kSub];
+#pragma unroll
+  for (int j = 0; j < kSub; ++j) {
+    const bool f = (x[j] & kDidFlag) != 0u;
+    const uint64_t bal = wave_ballot(f);
+    slot[j] = run + lanes_below(bal) + (f ? 1 : 0);
+    run += __popcll(bal);
+    if constexpr (kPng) {
+      const bool sf = (x[j] & kSegFlag) != 0u;
+      const uint64_t sbal = wave_ballot(sf);
+      seg[j] = srun + lanes_below(sbal) + (sf ? 1 : 0);
+      srun += __popcll(sbal);
+    }
+  }
+  if constexpr (kPng) {
+    const int32_t sbase = max(sblk - 1, 0);
+    if (srun - sbase < kWave) {
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) slot[j] += __builtin_amdgcn_ds_bpermute((seg[j] - sbase) << 2, dl);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) slot[j] += seg_delta[seg[j]];
+    }
+  }
+}
+
+// Deltas of the 64 segments from max(sblk - 1, 0) on, one per lane (the
+// array is padded by kWave entries past its last segment).
+__device__ __forceinline__ int32_t tile_deltas(const int32_t* __restrict__ seg_delta, int32_t sblk, int lane) {
+  return seg_delta[max(sblk - 1, 0) + lane];
+}
+
+// Flag counts before tile t, by a vector load that keeps its place among the
+// wavefront's other loads: lane 0 gets blk[t], lane 1 sblk[t] (PNG order) or
+// blk[t + 1] (bin order, where sblk is NULL).  A scalar load would instead
+// make every later wait on LDS results wait for it too.
+__device__ __forceinline__ int32_t load_counts(const int32_t* __restrict__ blk, const int32_t* __restrict__ sblk,
+                                               int64_t t, int lane) {
+  const int32_t* p = sblk ? ((lane & 1) ? sblk + t : blk + t) : blk + t + (lane & 1);
+  return *p;
+}
+
 // Entry 64j + lane of the tile, j = 0..kSub-1.
 __device__ __forceinline__ void unpack_tile(const uint32_t (&w)[kPairs], uint32_t (&x)[kSub]) {
 #pragma unroll
@@ -301,7 +355,7 @@ struct pcpm_png {
   // scatter side: PNG in (source pair, destination partition, source partition, node) order
   uint16_t* png_src = nullptr;  // ceil(E'/kTile)*kTile, in partition-pair order: u - 2Pq, bit 15 = pair segment start
   int32_t* png_blk = nullptr;   // bin order: pair-segment flags before each PNG tile, ceil(E'/kTile)+1
-  int32_t* seg_delta = nullptr; // nseg, one per non-empty (pair, bin) segment.  Bin order: update slot minus PNG
+  int32_t* seg_delta = nullptr; // nseg + kWave (padding), one per non-empty (pair, bin) segment.  Bin order: update slot minus PNG
                                 // position, segments in (pair, bin) order.  PNG order: PNG position minus
                                 // message index, segments in (bin, pair) order
   bool png_order = false;       // updates stored in PNG order (else bin order)
@@ -382,7 +436,7 @@ struct pcpm_png {
 
   // warm start: in-degrees (computed once per handle) and two rank vectors
   // for the first iterate from the uniform start
-  uint32_t* ws_indeg = nullptr;          // n
+  float2* ws_sfeat = nullptr;            // n: log1p(in-degree), log1p(out-degree)
   float* ws_x = nullptr;                 // 2n
   double ws_indeg_ms = 0.0;
 

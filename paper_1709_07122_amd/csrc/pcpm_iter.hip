@@ -135,9 +135,17 @@ __device__ __forceinline__ void scatter_item(const Item it, float* __restrict__ 
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
   uint32_t w[kPairs], wn[kPairs];
-  int64_t t = lo / kTile + threadIdx.x / kWave;
-  // the first tile's source IDs are in flight during the staging
-  if (t < t_end) load_tile_words(png_src + t * kTile, lane, w);
+  int64_t t = lo / kTile + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  // the first tile's source IDs (bin order: also its pair-segment counts and
+  // deltas, and the counts of the next tile) are in flight during the staging
+  int32_t cv = 0, cvn = 0, dl = 0;
+  if (t < t_end) {
+    load_tile_words(png_src + t * kTile, lane, w);
+    if constexpr (!kPng) {
+      cv = load_counts(png_blk, nullptr, t, lane);
+      if (t + kNW < t_end) cvn = load_counts(png_blk, nullptr, t + kNW, lane);
+    }
+  }
   // kSU nodes per thread per step, loads first, so their latencies overlap
   constexpr int kSU = 8;
   for (int i0 = threadIdx.x; i0 < qn; i0 += kSU * BS) {
@@ -158,12 +166,22 @@ __device__ __forceinline__ void scatter_item(const Item it, float* __restrict__ 
       }
     }
   }
+  if constexpr (!kPng) {
+    if (t < t_end) dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 0), lane);
+  }
   __syncthreads();
   const uint32_t qmask = (2u << s) - 1u;  // source IDs are local to the pair
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     // the next tile's loads overlap this tile's work
-    if (t + kNW < t_end) load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
+    int32_t dln = 0, cvnn = 0;
+    if (t + kNW < t_end) {
+      load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
+      if constexpr (!kPng) {
+        dln = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cvn, 0), lane);
+        if (t + 2 * kNW < t_end) cvnn = load_counts(png_blk, nullptr, t + 2 * kNW, lane);
+      }
+    }
     uint32_t x[kSub];
     unpack_tile(w, x);
     if constexpr (kPng) {
@@ -188,33 +206,46 @@ __device__ __forceinline__ void scatter_item(const Item it, float* __restrict__ 
       // need no predicate.  A source ID masked with 2q-1 is its slot in the
       // pair's rank slice (entries of other pairs, in edge tiles, only read a
       // stale slot and store to the spare update slot E').
-      int32_t run = png_blk[t];
+      // The segment index counts pair-segment flags as the gather counts
+      // messages (flags before the tile: lane 0 of cv); the deltas of the
+      // tile's first 64 segments came in with the tile (dl), others are read.
+      const int32_t sb = __builtin_amdgcn_readlane(cv, 0);
+      int32_t run = sb - 1;
       int32_t seg[kSub];
 #pragma unroll
       for (int j = 0; j < kSub; ++j) {
         const bool f = (x[j] & kDidFlag) != 0u;
         const uint64_t bal = wave_ballot(f);
-        seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
+        seg[j] = run + lanes_below(bal) + (f ? 1 : 0);
         run += __popcll(bal);
       }
-      int32_t dl[kSub];
+      const int32_t sbase = max(sb - 1, 0);
+      int32_t d[kSub];
+      if (run - sbase < kWave) {
 #pragma unroll
-      for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
+        for (int j = 0; j < kSub; ++j) d[j] = __builtin_amdgcn_ds_bpermute((seg[j] - sbase) << 2, dl);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kSub; ++j) d[j] = seg_delta[seg[j]];
+      }
       if (tb >= lo && tb + kTile <= hi) {
         float* ut = upd + tb;
 #pragma unroll
-        for (int j = 0; j < kSub; ++j) ut[static_cast<int64_t>(j * kWave + lane + dl[j])] = spr[x[j] & qmask];
+        for (int j = 0; j < kSub; ++j) ut[static_cast<int64_t>(j * kWave + lane + d[j])] = spr[x[j] & qmask];
       } else {
 #pragma unroll
         for (int j = 0; j < kSub; ++j) {
           const int64_t e = tb + j * kWave + lane;
           const bool in = e >= lo && e < hi;
-          upd[in ? e + dl[j] : spare] = spr[x[j] & qmask];
+          upd[in ? e + d[j] : spare] = spr[x[j] & qmask];
         }
       }
     }
 #pragma unroll
     for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
+    cv = cvn;
+    cvn = cvnn;
+    dl = dln;
   }
 }
 
@@ -263,42 +294,39 @@ __device__ __forceinline__ void gather_item(const Item it, unsigned long long* _
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
+  // Each wavefront walks every kNW-th tile.  Its loads go out in this order:
+  // this tile's updates, then the next tile's IDs and segment deltas and the
+  // flag counts of the tile after that.  Loads return in order, so the wait
+  // for the updates does not wait for the prefetches, which stay in flight
+  // through this tile's adds.
   uint32_t w[kPairs], wn[kPairs];
-  int64_t t = lo / kTile + threadIdx.x / kWave;
-  if (t < t_end) load_tile_words(did + t * kTile, lane, w);
-  for (; t < t_end; t += kNW) {
+  const int64_t t0 = lo / kTile + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int32_t* sblk_arr = kPng ? did_sblk : nullptr;
+  int32_t cv = 0, cvn = 0, dl = 0;
+  if (t0 < t_end) {
+    load_tile_words(did + t0 * kTile, lane, w);
+    cv = load_counts(did_blk, sblk_arr, t0, lane);
+    if (t0 + kNW < t_end) cvn = load_counts(did_blk, sblk_arr, t0 + kNW, lane);
+    if constexpr (kPng) dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 1), lane);
+  }
+  for (int64_t t = t0; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    // the next tile's IDs are in flight during this tile's work
-    if (t + kNW < t_end) load_tile_words(did + (t + kNW) * kTile, lane, wn);
+    const int32_t blk = __builtin_amdgcn_readlane(cv, 0);
     uint32_t x[kSub];
     unpack_tile(w, x);
-    // Alg. 5 update pointer: an ID's message index in bin order is the number
-    // of message flags so far (inclusive) minus one.  Every entry has a valid
-    // index (entry 0 of the array carries every flag and padding follows the
-    // last message), so the update loads need no predicate.
+    // Every entry has a valid update slot (entry 0 of the array carries
+    // every flag and padding follows the last message), so the update loads
+    // need no predicate.
     float val[kSub];
     if constexpr (kPng) {
-      // plus its (bin, source pair) segment's delta, the segment index
-      // counting segment flags the same way
-      int32_t run = did_blk[t] - 1, srun = did_sblk[t] - 1;  // counts before this tile, minus one
-      int32_t msg[kSub], seg[kSub];
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) {
-        const bool f = (x[j] & kDidFlag) != 0u, sf = (x[j] & kSegFlag) != 0u;
-        const uint64_t bal = wave_ballot(f), sbal = wave_ballot(sf);
-        msg[j] = run + lanes_below(bal) + (f ? 1 : 0);
-        seg[j] = srun + lanes_below(sbal) + (sf ? 1 : 0);
-        run += __popcll(bal);
-        srun += __popcll(sbal);
-      }
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) msg[j] += seg_delta[seg[j]];
+      int32_t msg[kSub];
+      tile_slots<true>(x, blk, __builtin_amdgcn_readlane(cv, 1), dl, seg_delta, msg);
 #pragma unroll
       for (int j = 0; j < kSub; ++j) val[j] = upd[msg[j]];
     } else {
-      // a tile's updates lie in [did_blk[t]-1, did_blk[t+1]-1]: a per-tile
-      // base and 32-bit lane offsets
-      const char* ub = reinterpret_cast<const char*>(upd) + (static_cast<int64_t>(did_blk[t]) - 1) * 4;
+      // a tile's updates lie in [blk-1, blk_next-1]: a per-tile base and
+      // 32-bit lane offsets
+      const char* ub = reinterpret_cast<const char*>(upd) + (static_cast<int64_t>(blk) - 1) * 4;
       int32_t run = 0;  // flags in the earlier sub-blocks of this tile
       uint32_t off[kSub];
 #pragma unroll
@@ -316,6 +344,13 @@ __device__ __forceinline__ void gather_item(const Item it, unsigned long long* _
     if constexpr (kMode == 2) {
 #pragma unroll
       for (int j = 0; j < kSub; ++j) wv[j] = wbin[tb + j * kWave + lane];
+    }
+    // prefetch: the next tile's IDs and deltas, the counts of the one after
+    int32_t dln = 0, cvnn = 0;
+    if (t + kNW < t_end) {
+      load_tile_words(did + (t + kNW) * kTile, lane, wn);
+      if constexpr (kPng) dln = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cvn, 1), lane);
+      if (t + 2 * kNW < t_end) cvnn = load_counts(did_blk, sblk_arr, t + 2 * kNW, lane);
     }
     // the update (times its weight, formed exactly in FP64) as a fixed-point integer
     auto fixed = [&](int j) -> int64_t {
@@ -335,6 +370,9 @@ __device__ __forceinline__ void gather_item(const Item it, unsigned long long* _
     }
 #pragma unroll
     for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
+    cv = cvn;
+    cvn = cvnn;
+    dl = dln;
   }
   __syncthreads();
   if (it.aux >= 0) {
@@ -369,7 +407,8 @@ __global__ __launch_bounds__(BS) void k_gather(const Ctl* __restrict__ ctl, int6
                                                const float* __restrict__ wbin) {
   if (ctl->done) return;
   extern __shared__ unsigned long long acc[];
-  gather_item<BS, kMode, kPng>(items[blockIdx.x], acc, ctl, n, s, did, did_blk, did_sblk, seg_delta, upd, pr_in,
+  // the build arranges the item array for the XCD-contiguous renumbering
+  gather_item<BS, kMode, kPng>(items[xcd_block(blockIdx.x, gridDim.x)], acc, ctl, n, s, did, did_blk, did_sblk, seg_delta, upd, pr_in,
                                pr_out, dmask, partial, red, gctl, part_group, part_valid, wbin);
 }
 
@@ -585,10 +624,10 @@ __global__ __launch_bounds__(1024) void k_persist(const PersistArgs a) {
                                    a.png_blk, a.seg_delta, a.upd, a.spare);
     }
     if (!grid_sync(ps, a.spin_limit, [] {})) return;
-    for (;;) {  // gather items, largest first
+    for (;;) {  // gather items in the order of a launch per phase
       const int32_t j = grab(&ps->ga_next);
       if (j >= a.n_ga) break;
-      const Item itm = a.ga_items[j];
+      const Item itm = a.ga_items[xcd_block(static_cast<unsigned>(j), static_cast<unsigned>(a.n_ga))];
       gather_item<BS, 0, kPng>(itm, lds, a.ctl, a.n, a.s, a.did, a.did_blk, a.did_sblk, a.seg_delta, a.upd, in, out,
                                a.dmask, a.partial, a.red, a.gctl, a.part_group, a.part_valid, nullptr);
       if (itm.aux >= 0) {  // a split bin's slice: applied by its merge units

@@ -250,42 +250,39 @@ __device__ __forceinline__ void ppr_gather_item(const Item it, unsigned long lon
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = BS / kWave;
   constexpr int kG = KT >= 16 ? 2 : (KT >= 8 ? 4 : (KT >= 4 ? 8 : 16));
+  // Loads go out as in the single-vector gather: the first value group of
+  // this tile, then the next tile's IDs and segment deltas and the flag
+  // counts of the tile after that, so the prefetches stay in flight through
+  // this tile's adds.
   uint32_t w[kPairs], wn[kPairs];
-  int64_t t = lo / kTile + threadIdx.x / kWave;
-  if (t < t_end) load_tile_words(did + t * kTile, lane, w);
-  for (; t < t_end; t += kNW) {
+  const int64_t t0 = lo / kTile + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int32_t* sblk_arr = kPng ? did_sblk : nullptr;
+  int32_t cv = 0, cvn = 0, dl = 0;
+  if (t0 < t_end) {
+    load_tile_words(did + t0 * kTile, lane, w);
+    cv = load_counts(did_blk, sblk_arr, t0, lane);
+    if (t0 + kNW < t_end) cvn = load_counts(did_blk, sblk_arr, t0 + kNW, lane);
+    if constexpr (kPng) dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 1), lane);
+  }
+  for (int64_t t = t0; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    if (t + kNW < t_end) load_tile_words(did + (t + kNW) * kTile, lane, wn);
     uint32_t xs[kSub];
     unpack_tile(w, xs);
-    // an ID's update slot: its message index in bin order (message flags so
-    // far, inclusive, minus one), plus, for PNG-ordered updates, its (bin,
-    // source pair) segment's delta; every entry has a valid slot
-    int32_t run = did_blk[t] - 1, srun = kPng ? did_sblk[t] - 1 : 0;
-    int32_t slot[kSub], seg[kSub];
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const bool f = (xs[j] & kDidFlag) != 0u;
-      const uint64_t bal = wave_ballot(f);
-      slot[j] = run + lanes_below(bal) + (f ? 1 : 0);
-      run += __popcll(bal);
-      if constexpr (kPng) {
-        const bool sf = (xs[j] & kSegFlag) != 0u;
-        const uint64_t sbal = wave_ballot(sf);
-        seg[j] = srun + lanes_below(sbal) + (sf ? 1 : 0);
-        srun += __popcll(sbal);
-      }
-    }
-    if constexpr (kPng) {
-#pragma unroll
-      for (int j = 0; j < kSub; ++j) slot[j] += seg_delta[seg[j]];
-    }
+    // every entry has a valid update slot
+    int32_t slot[kSub];
+    tile_slots<kPng>(xs, __builtin_amdgcn_readlane(cv, 0), __builtin_amdgcn_readlane(cv, 1), dl, seg_delta, slot);
+    int32_t dln = 0, cvnn = 0;
     const bool full = tb >= lo && tb + kTile <= hi;
 #pragma unroll
     for (int g0 = 0; g0 < kSub; g0 += kG) {
       float val[kG][KT];
 #pragma unroll
       for (int jj = 0; jj < kG; ++jj) copy_kt<KT>(val[jj], upd + static_cast<int64_t>(slot[g0 + jj]) * KT);
+      if (g0 == 0 && t + kNW < t_end) {  // prefetch (g0 is a constant after unrolling)
+        load_tile_words(did + (t + kNW) * kTile, lane, wn);
+        if constexpr (kPng) dln = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cvn, 1), lane);
+        if (t + 2 * kNW < t_end) cvnn = load_counts(did_blk, sblk_arr, t + 2 * kNW, lane);
+      }
       if (full) {
 #pragma unroll
         for (int jj = 0; jj < kG; ++jj) {
@@ -308,6 +305,9 @@ __device__ __forceinline__ void ppr_gather_item(const Item it, unsigned long lon
     }
 #pragma unroll
     for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
+    cv = cvn;
+    cvn = cvnn;
+    dl = dln;
   }
   __syncthreads();
   if (it.aux >= 0) {
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kPprGatherBlock) void k_ppr_gather(const Ctl* __res
                                                                 const VCtl* __restrict__ vctl) {
   if (ctl->done) return;
   extern __shared__ unsigned long long acc[];
-  ppr_gather_item<KT, kPng>(items[blockIdx.x], acc, ctl, n, s, did, did_blk, did_sblk, seg_delta, upd, x_in, x_out,
+  ppr_gather_item<KT, kPng>(items[xcd_block(blockIdx.x, gridDim.x)], acc, ctl, n, s, did, did_blk, did_sblk, seg_delta, upd, x_in, x_out,
                             dmask, seedmask, partial, red, vctl);
 }
 
@@ -687,7 +687,7 @@ __global__ __launch_bounds__(1024) void k_ppr_persist(const PprPersistArgs a) {
     for (;;) {
       const int32_t j = grab(&ps->ga_next);
       if (j >= a.n_ga) break;
-      const Item itm = a.ga_items[j];
+      const Item itm = a.ga_items[xcd_block(static_cast<unsigned>(j), static_cast<unsigned>(a.n_ga))];
       ppr_gather_item<KT, kPng>(itm, lds, a.ctl, a.n, a.s, a.did, a.did_blk, a.did_sblk, a.seg_delta, a.upd, in, out,
                                 a.dmask, a.seedmask, a.partial, a.red, a.vctl);
       if (itm.aux >= 0) {

@@ -8,8 +8,9 @@
 //     iterate of Eq. 1 from the uniform vector; s1(v) = sum_{u->v} 1/outdeg(u)
 //     is the one-SpMV aggregate of the in-neighbours' degrees
 //   4..7 zero padding (the MFMA K-block is 8 wide)
-// In-degrees are counted once per handle from the destination-ID bins; the
-// first iterate is one PCPM iteration (scatter + gather + apply).
+// In-degrees are counted once per handle from the destination-ID bins, and
+// features 0 and 1 are kept per handle from then on; the first iterate is one
+// PCPM iteration (scatter + gather + apply) from the uniform vector.
 //
 // Parameters (FP32 master copy, 4801 floats): W1[64][8], b1[64], W2[64][64],
 // b2[64], w3[64], b3.  Compute is BF16 x BF16 -> FP32: weights, features and
@@ -107,22 +108,31 @@ __global__ __launch_bounds__(256) void k_ws_prep(uint32_t* __restrict__ indeg, f
   }
 }
 
+// The graph's own features of every node, formed once per handle:
+// (log1p(in-degree), log1p(out-degree)).
+__global__ __launch_bounds__(256) void k_ws_static(const uint32_t* __restrict__ indeg,
+                                                   const int32_t* __restrict__ outdeg, int64_t n,
+                                                   float2* __restrict__ sfeat) {
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    sfeat[v] = make_float2(log1pf(static_cast<float>(indeg[v])), log1pf(static_cast<float>(outdeg[v])));
+}
+
 // The four features of node v (the other four are zero).
 struct FeatSrc {
-  const uint32_t* indeg;
-  const int32_t* outdeg;
+  const float2* sfeat;  // log1p of in- and out-degree
   const uint32_t* dmask;
-  const float* pr1;
-  float fn;  // n
+  const float* pr1;     // first iterate
+  float fn;             // n
 };
 
+__device__ __forceinline__ float log_n_pr1(const FeatSrc& fs, float pr1) {
+  return logf(pr1 * fs.fn);  // FP32 is ample: the network sees the value rounded to BF16
+}
+
 __device__ __forceinline__ float4 node_features(const FeatSrc& fs, int64_t v) {
-  float4 f;
-  f.x = log1pf(static_cast<float>(fs.indeg[v]));
-  f.y = log1pf(static_cast<float>(fs.outdeg[v]));
-  f.z = static_cast<float>((fs.dmask[v >> 5] >> (v & 31)) & 1u);
-  f.w = logf(fs.pr1[v] * fs.fn);  // FP32 is ample: the network sees the value rounded to BF16
-  return f;
+  const float2 sf = fs.sfeat[v];
+  return make_float4(sf.x, sf.y, static_cast<float>((fs.dmask[v >> 5] >> (v & 31)) & 1u), log_n_pr1(fs, fs.pr1[v]));
 }
 
 __global__ __launch_bounds__(256) void k_ws_features(float* __restrict__ feat, const FeatSrc fs, int64_t n) {
@@ -158,6 +168,31 @@ __device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
 
 constexpr int kFwdBlock = 256;
 constexpr int kFwdMaxBlocks = 2048;
+
+// One node's inputs to the forward as loaded by this lane (fused: the low
+// half loads the node's per-handle features, first iterate and dangling
+// flag, the high half nothing; otherwise this lane's four features).
+struct FwdRaw {
+  float4 f;
+  float pr1;
+};
+
+template <bool kFused>
+__device__ __forceinline__ FwdRaw load_fwd_raw(const float* __restrict__ feat, const FeatSrc& fs, int64_t node,
+                                               int64_t n, int half) {
+  FwdRaw r = {make_float4(0.0f, 0.0f, 0.0f, 0.0f), 1.0f};
+  if (node >= n) return r;
+  if constexpr (kFused) {
+    if (half == 0) {
+      const float2 sf = fs.sfeat[node];
+      r.f = make_float4(sf.x, sf.y, static_cast<float>((fs.dmask[node >> 5] >> (node & 31)) & 1u), 0.0f);
+      r.pr1 = fs.pr1[node];
+    }
+  } else {
+    r.f = *reinterpret_cast<const float4*>(feat + kF * node + 4 * half);
+  }
+  return r;
+}
 
 // kFused: the features are formed from their sources (in-degrees, out-degrees,
 // dangling mask, first iterate) as k_ws_features forms them, instead of read
@@ -202,15 +237,18 @@ __global__ __launch_bounds__(kFwdBlock) void k_ws_forward(const float* __restric
     }
   }
   const float b3 = P[kOB3];
-  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kFwdBlock / kWave);
-  for (int64_t base = (static_cast<int64_t>(blockIdx.x) * (kFwdBlock / kWave) + threadIdx.x / kWave) * 32; base < n;
-       base += waves * 32) {
+  // The inputs of the wavefront's next 32 nodes are loaded while the
+  // current ones go through the network.
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * (kFwdBlock / kWave) * 32;
+  int64_t base = (static_cast<int64_t>(blockIdx.x) * (kFwdBlock / kWave) + threadIdx.x / kWave) * 32;
+  FwdRaw raw = load_fwd_raw<kFused>(feat, fs, base + col, n, half);
+  for (; base < n; base += stride) {
     const int64_t node = base + col;
-    float4 fv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const FwdRaw cur = raw;
+    raw = load_fwd_raw<kFused>(feat, fs, base + stride + col, n, half);
+    float4 fv = cur.f;
     if constexpr (kFused) {
-      if (node < n && half == 0) fv = node_features(fs, node);
-    } else {
-      if (node < n) fv = *reinterpret_cast<const float4*>(feat + kF * node + 4 * half);
+      if (half == 0 && node < n) fv.w = log_n_pr1(fs, cur.pr1);
     }
     const v4s bx = bf16_op(fv.x, fv.y, fv.z, fv.w);
     uint32_t hp[2][8];  // relu(h1) as packed BF16 pairs (v, v+1)
@@ -244,12 +282,12 @@ __global__ __launch_bounds__(kFwdBlock) void k_ws_forward(const float* __restric
 }
 
 // ---- start vector: softmax over nodes --------------------------------------------
-// Two passes.  k_ws_soft_part: every thread keeps a running maximum m and the
-// sum s of exp(y - m) over its nodes (FP64; s is rescaled when m grows), and
-// the workgroup combines its threads' pairs into one (M, S, non-finite flag).
-// k_ws_soft_norm: every workgroup combines the kSoftBlocks partial pairs
-// (one load per thread) and writes exp(y - M) / S, or the uniform vector if
-// a prediction was non-finite or S is not a positive finite number.
+// k_ws_soft_part: every thread keeps a running maximum m and the sum s of
+// exp(y - m) over its nodes (FP64; s is rescaled when m grows), and the
+// workgroup combines its threads' pairs into one (M, S, non-finite flag).
+// k_ws_soft_final: one workgroup combines the kSoftBlocks partial pairs.
+// k_ws_soft_norm writes exp(y - M) / S, or the uniform vector if a
+// prediction was non-finite or S is not a positive finite number.
 constexpr int kSoftBlocks = 1024;
 constexpr int kSoftThreads = 256;
 
@@ -314,13 +352,22 @@ __global__ __launch_bounds__(kSoftThreads) void k_ws_soft_part(const float* __re
   }
 }
 
-__global__ __launch_bounds__(kSoftThreads) void k_ws_soft_norm(const float* __restrict__ y, int64_t n,
-                                                               const double* __restrict__ red,
-                                                               float* __restrict__ pr0, int32_t* __restrict__ flag) {
+__global__ __launch_bounds__(kSoftThreads) void k_ws_soft_final(double* __restrict__ red) {
   SoftPair p = {-INFINITY, 0.0, 0.0};
   for (int i = threadIdx.x; i < kSoftBlocks; i += kSoftThreads)
     p = soft_combine(p, SoftPair{red[3 * i], red[3 * i + 1], red[3 * i + 2]});
   const SoftPair r = soft_block(p);
+  if (threadIdx.x == 0) {
+    red[3 * kSoftBlocks] = r.m;
+    red[3 * kSoftBlocks + 1] = r.s;
+    red[3 * kSoftBlocks + 2] = r.bad;
+  }
+}
+
+__global__ __launch_bounds__(kSoftThreads) void k_ws_soft_norm(const float* __restrict__ y, int64_t n,
+                                                               const double* __restrict__ red,
+                                                               float* __restrict__ pr0, int32_t* __restrict__ flag) {
+  const SoftPair r = {red[3 * kSoftBlocks], red[3 * kSoftBlocks + 1], red[3 * kSoftBlocks + 2]};
   const bool fallback = r.bad > 0.0 || !(r.s > 0.0) || !isfinite(r.s);
   if (blockIdx.x == 0 && threadIdx.x == 0) *flag = fallback ? 1 : 0;
   const double inv = fallback ? 0.0 : 1.0 / r.s;
@@ -487,18 +534,25 @@ static unsigned forward_blocks(int64_t n) {
 }
 
 static FeatSrc feat_src(const pcpm_png* g) {
-  return FeatSrc{g->ws_indeg, g->outdeg, g->dmask, g->ws_x + g->n, static_cast<float>(g->n)};
+  return FeatSrc{g->ws_sfeat, g->dmask, g->ws_x + g->n, static_cast<float>(g->n)};
 }
 
 static unsigned grid_for(int64_t n) { return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192))); }
 
-// In-degrees of a handle (counted on first use) and the rank buffers.
+// Per-handle state of the warm start, formed on first use: the uniform
+// vector and a buffer for the first iterate (ws_x), the in-degrees counted
+// from the bins and the per-node features that depend on the graph alone.
 static pcpm_status_t ws_prepare(pcpm_png* g, hipStream_t st) {
   const int64_t n = g->n;
+  if (g->ws_sfeat) return PCPM_OK;
   if (!g->ws_x) PCPM_TRY(dalloc(g, &g->ws_x, 2 * n));
-  if (g->ws_indeg) return PCPM_OK;
+  float2* sfeat = nullptr;
+  PCPM_TRY(dalloc(g, &sfeat, n));
   uint32_t* indeg = nullptr;
-  PCPM_TRY(dalloc(g, &indeg, n));
+  if (dalloc(g, &indeg, n) != PCPM_OK) {
+    dfree(g, sfeat);
+    return PCPM_ERR_OOM;
+  }
   static bool lds_set = false;
   if (!lds_set) {
     PCPM_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ws_count),
@@ -508,12 +562,15 @@ static pcpm_status_t ws_prepare(pcpm_png* g, hipStream_t st) {
   // the count's time (the array's allocation above is not part of it)
   PCPM_TRY_HIP(hipStreamSynchronize(st));
   const auto t0 = std::chrono::steady_clock::now();
-  PCPM_LAUNCH("pcpm_ws_features", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, indeg, g->ws_x, n, 0.0f);
+  const float uni = static_cast<float>(1.0 / static_cast<double>(n));
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, indeg, g->ws_x, n, uni);
   if (g->n_ga)
     PCPM_LAUNCH("pcpm_ws_features", k_ws_count, dim3(static_cast<unsigned>(g->n_ga)), dim3(kCountBlock),
                 static_cast<size_t>(g->q) * 4, st, n, g->part_log2, g->ga_items, g->did, indeg);
+  PCPM_LAUNCH("pcpm_ws_features", k_ws_static, dim3(grid_for(n)), dim3(256), 0, st, indeg, g->outdeg, n, sfeat);
   PCPM_TRY_HIP(hipStreamSynchronize(st));
-  g->ws_indeg = indeg;
+  dfree(g, indeg);
+  g->ws_sfeat = sfeat;
   g->ws_indeg_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return PCPM_OK;
 }
@@ -602,9 +659,7 @@ pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* firs
   PCPM_TRY(ws_prepare(g, st));
   if (first_call_ms) *first_call_ms = g->ws_indeg_ms;
   const int64_t n = g->n;
-  const float uni = static_cast<float>(1.0 / static_cast<double>(n));
-  PCPM_LAUNCH("pcpm_ws_features", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, nullptr, g->ws_x, n, uni);
-  PCPM_TRY(pcpm_iterate(g, d, g->ws_x, g->ws_x + n, nullptr, stream));
+  PCPM_TRY(pcpm_iterate(g, d, g->ws_x, g->ws_x + n, nullptr, stream));  // from the uniform vector
   PCPM_LAUNCH("pcpm_ws_features", k_ws_features, dim3(grid_for(n)), dim3(256), 0, st, feat, feat_src(g), n);
   return PCPM_OK;
 }
@@ -622,9 +677,7 @@ pcpm_status_t pcpm_ws_predict(pcpm_png_t g, const float* params, double d, float
   PCPM_TRY(ws_prepare(g, st));
   if (first_call_ms) *first_call_ms = g->ws_indeg_ms;
   const int64_t n = g->n;
-  const float uni = static_cast<float>(1.0 / static_cast<double>(n));
-  PCPM_LAUNCH("pcpm_ws_predict", k_ws_prep, dim3(grid_for(n)), dim3(256), 0, st, nullptr, g->ws_x, n, uni);
-  PCPM_TRY(pcpm_iterate(g, d, g->ws_x, g->ws_x + n, nullptr, stream));
+  PCPM_TRY(pcpm_iterate(g, d, g->ws_x, g->ws_x + n, nullptr, stream));  // from the uniform vector
   PCPM_LAUNCH("pcpm_ws_predict", k_ws_forward<true>, dim3(forward_blocks(n)), dim3(kFwdBlock), 0, st, params,
               nullptr, feat_src(g), n, yhat);
   return PCPM_OK;
@@ -649,9 +702,10 @@ pcpm_status_t pcpm_ws_init(const float* yhat, int64_t n, float* pr0, float* work
   PCPM_TRY(ws_check_device_ptr(pr0, "pr0"));
   PCPM_TRY(ws_check_device_ptr(work, "work"));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  double* red = reinterpret_cast<double*>(work);                   // 3 * kSoftBlocks doubles
-  int32_t* flag = reinterpret_cast<int32_t*>(work + 6 * kSoftBlocks);
+  double* red = reinterpret_cast<double*>(work);                   // 3 * (kSoftBlocks + 1) doubles
+  int32_t* flag = reinterpret_cast<int32_t*>(work + 6 * (kSoftBlocks + 1));
   PCPM_LAUNCH("pcpm_ws_init", k_ws_soft_part, dim3(kSoftBlocks), dim3(kSoftThreads), 0, st, yhat, n, red);
+  PCPM_LAUNCH("pcpm_ws_init", k_ws_soft_final, dim3(1), dim3(kSoftThreads), 0, st, red);
   PCPM_LAUNCH("pcpm_ws_init", k_ws_soft_norm, dim3(grid_for(n)), dim3(kSoftThreads), 0, st, yhat, n, red, pr0, flag);
   PCPM_TRY_HIP(hipMemcpyAsync(fallback, flag, 4, hipMemcpyDeviceToHost, st));
   PCPM_TRY_HIP(hipStreamSynchronize(st));
@@ -660,7 +714,7 @@ pcpm_status_t pcpm_ws_init(const float* yhat, int64_t n, float* pr0, float* work
 
 int64_t pcpm_ws_work_floats(int64_t b) {
   const int64_t parts = std::max<int64_t>(1, std::min<int64_t>((b + pcpm::kChunk - 1) / pcpm::kChunk, 1024));
-  return std::max<int64_t>(parts * PCPM_WS_PARAMS + 4 * (parts + 1), 6 * pcpm::kSoftBlocks + 4);
+  return std::max<int64_t>(parts * PCPM_WS_PARAMS + 4 * (parts + 1), 6 * (pcpm::kSoftBlocks + 1) + 4);
 }
 
 pcpm_status_t pcpm_ws_backward(const float* params, const float* feat, const float* target, int64_t rows,
