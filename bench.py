@@ -292,8 +292,14 @@ def warm_detail(P, torch, png, args):
 
     params = ws.load(ws.DEFAULT_WEIGHTS)
     res = ws.compare(png, params, d=args.d, tol=args.tol, reps=max(1, args.steps))
+    kern = res.get("warm_kernels", {})
+    pred = (kern.get("pcpm_ws_predict") or {}).get("total_ms")
+    fwd = (kern.get("pcpm_ws_forward_on_features") or {}).get("total_ms")
+    soft = (kern.get("pcpm_ws_init") or {}).get("total_ms")
+    us = lambda v: "n/a" if v is None else f"{v * 1e3:.1f} us"
     log(f"[warm] cold {res['cold_iters']} iters {res['cold_ms']:.2f} ms; warm {res['warm_iters']} iters "
-        f"{res['warm_ms']:.2f} ms ({res['warm_ms_first']:.2f} ms with the in-degree count)")
+        f"{res['warm_ms']:.2f} ms ({res['warm_ms_first']:.2f} ms with the in-degree count); MLP forward on the "
+        f"feature matrix {us(fwd)}, fused prediction (features + forward) {us(pred)}, softmax {us(soft)}")
     return res
 
 

@@ -308,8 +308,10 @@ int32_t pcpm_ppr_tile_width(pcpm_png_t g);
  * log(n * PR_1(v)) with PR_1 the first iterate of Eq. 1 from 1/n (the
  * one-SpMV aggregate sum_{u->v} 1/outdeg(u) of the in-neighbours' degrees),
  * then four zeros.  In-degrees are counted from the destination-ID bins on
- * the first call and kept in the handle (that count's time, in ms, goes to
- * *first_call_ms when non-NULL); every call runs one PCPM iteration. */
+ * the first call, and the first two features are kept in the handle from
+ * then on (8 bytes per node; the time of that count and of forming them, in
+ * ms, goes to *first_call_ms when non-NULL); every call runs one PCPM
+ * iteration from the uniform vector. */
 pcpm_status_t pcpm_ws_features(pcpm_png_t g, double d, float* feat, double* first_call_ms /* (host) nullable */,
                                void* stream);
 
@@ -320,8 +322,8 @@ pcpm_status_t pcpm_ws_forward(const float* params, const float* feat, int64_t n,
 /* The warm-start prediction for the handle's nodes without a feature matrix:
  * yhat (device, n floats) equals pcpm_ws_forward(params, F) for the matrix F
  * that pcpm_ws_features(g, d, F) writes, bit for bit, with the features
- * formed in the forward kernel from the in-degrees, out-degrees, dangling
- * mask and first iterate (one PCPM iteration, as pcpm_ws_features runs).
+ * formed in the forward kernel from the kept log-degrees, the dangling mask
+ * and the first iterate (one PCPM iteration, as pcpm_ws_features runs).
  * Same handle requirements, in-degree count and *first_call_ms as
  * pcpm_ws_features. */
 pcpm_status_t pcpm_ws_predict(pcpm_png_t g, const float* params, double d, float* yhat,

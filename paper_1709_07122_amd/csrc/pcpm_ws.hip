@@ -221,39 +221,50 @@ __global__ __launch_bounds__(kFwdBlock) void k_ws_forward(const float* __restric
   const int l = threadIdx.x & (kWave - 1);
   const int col = l & 31, half = l >> 5;
   // A fragments: row 32*ob + col; W1 columns 4*half .. +3, W2 columns in the
-  // B operand's slot order
+  // B operand's slot order.  W2's fragments and w3 wait in LDS (written by
+  // the first wavefront) and are read where they are used, which keeps the
+  // kernel at three wavefronts per SIMD; W1 and the biases stay in registers.
+  __shared__ uint4 s_a2[2][4][kWave];
+  __shared__ uint4 s_w3[2][4];  // [half]: w3 of the half's 32 rows as packed pairs
   v4s a1[2];
-  v8bf a2[2][4];
   v16f c1[2], c2[2];
-  bf16x2 w3p[2][8];
 #pragma unroll
   for (int ob = 0; ob < 2; ++ob) {
     const int r = 32 * ob + col;
     const float* w1 = P + kOW1 + r * kF + 4 * half;
     a1[ob] = bf16_op(w1[0], w1[1], w1[2], w1[3]);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const float* w2 = P + kOW2 + r * kH + 16 * t + 4 * half;
-      uint32_t pk[4];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        pk[2 * j] = bf16_pack2(w2[8 * j], w2[8 * j + 1]);
-        pk[2 * j + 1] = bf16_pack2(w2[8 * j + 2], w2[8 * j + 3]);
-      }
-      a2[ob][t] = __builtin_bit_cast(v8bf, make_uint4(pk[0], pk[1], pk[2], pk[3]));
-    }
-#pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
       c1[ob][v] = P[kOB1 + row];
       c2[ob][v] = P[kOB2 + row];
     }
+  }
+  if (threadIdx.x < kWave) {
 #pragma unroll
-    for (int v = 0; v < 16; v += 2) {
-      const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
-      w3p[ob][v / 2] = __builtin_bit_cast(bf16x2, bf16_pack2(P[kOW3 + row], P[kOW3 + row + 1]));
+    for (int ob = 0; ob < 2; ++ob) {
+      const int r = 32 * ob + col;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float* w2 = P + kOW2 + r * kH + 16 * t + 4 * half;
+        s_a2[ob][t][l] = make_uint4(bf16_pack2(w2[0], w2[1]), bf16_pack2(w2[2], w2[3]), bf16_pack2(w2[8], w2[9]),
+                                    bf16_pack2(w2[10], w2[11]));
+      }
+    }
+    if (col == 0) {
+      uint32_t pk[16];
+#pragma unroll
+      for (int ob = 0; ob < 2; ++ob)
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          const int row = 32 * ob + 8 * (v / 4) + 4 * half + (v % 4);
+          pk[8 * ob + v / 2] = bf16_pack2(P[kOW3 + row], P[kOW3 + row + 1]);
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s_w3[half][i] = make_uint4(pk[4 * i], pk[4 * i + 1], pk[4 * i + 2], pk[4 * i + 3]);
     }
   }
+  __syncthreads();
   const float b3 = P[kOB3];
   // The inputs of the wavefront's next 32 nodes are loaded while the
   // current ones go through the network.
@@ -261,6 +272,8 @@ __global__ __launch_bounds__(kFwdBlock) void k_ws_forward(const float* __restric
   int64_t base = (static_cast<int64_t>(blockIdx.x) * (kFwdBlock / kWave) + threadIdx.x / kWave) * 32;
   FwdRaw raw = load_fwd_raw<kFused>(feat, fs, base + col, n, half);
   for (; base < n; base += stride) {
+    // LDS reads stay inside the loop (not hoisted into registers)
+    __asm__ volatile("" ::: "memory");
     const int64_t node = base + col;
     const FwdRaw cur = raw;
     raw = load_fwd_raw<kFused>(feat, fs, base + stride + col, n, half);
@@ -283,7 +296,17 @@ __global__ __launch_bounds__(kFwdBlock) void k_ws_forward(const float* __restric
           v8bf, make_uint4(hp[t / 2][4 * (t % 2)], hp[t / 2][4 * (t % 2) + 1], hp[t / 2][4 * (t % 2) + 2],
                            hp[t / 2][4 * (t % 2) + 3]));
 #pragma unroll
-      for (int ob = 0; ob < 2; ++ob) h2[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[ob][t], b, h2[ob], 0, 0, 0);
+      for (int ob = 0; ob < 2; ++ob)
+        h2[ob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, s_a2[ob][t][l]), b, h2[ob], 0, 0, 0);
+    }
+    uint32_t w3p[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint4 q = s_w3[half][i];
+      w3p[4 * i] = q.x;
+      w3p[4 * i + 1] = q.y;
+      w3p[4 * i + 2] = q.z;
+      w3p[4 * i + 3] = q.w;
     }
     float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -291,7 +314,8 @@ __global__ __launch_bounds__(kFwdBlock) void k_ws_forward(const float* __restric
 #pragma unroll
       for (int v = 0; v < 16; v += 2)
         part[v / 4] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, relu_bf16x2(h2[ob][v], h2[ob][v + 1])),
-                                                      w3p[ob][v / 2], part[v / 4], false);
+                                                      __builtin_bit_cast(bf16x2, w3p[8 * ob + v / 2]), part[v / 4],
+                                                      false);
     }
     float y = (part[0] + part[1]) + (part[2] + part[3]);
     y += __shfl_xor(y, 32);  // lanes l and l^32 hold the two halves of node col's rows

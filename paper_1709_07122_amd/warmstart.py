@@ -189,9 +189,27 @@ def compare(png, params, d: float = 0.85, tol: float = 1e-6, reps: int = 3):
         rw, fb = warm()
     torch.cuda.synchronize()
     warm_ms = (time.perf_counter() - t) / reps * 1e3
+    # per-kernel times of one more warm solve (events around every launch):
+    # pcpm_ws_predict is the network's forward, pcpm_ws_init the softmax
+    P.timing_enable(True)
+    warm()
+    torch.cuda.synchronize()
+    P.timing_enable(False)
+    kernels = {name: {"launches": v[0], "total_ms": v[1]} for name, v in P.timing_collect().items()}
+    # the network's forward alone, on the feature matrix (pcpm_ws_forward)
+    feat, _ = P.ws_features(png, d)
+    P.ws_forward(params, feat)
+    torch.cuda.synchronize()
+    P.timing_enable(True)
+    P.ws_forward(params, feat)
+    torch.cuda.synchronize()
+    P.timing_enable(False)
+    fwd = P.timing_collect().get("pcpm_ws_forward")
+    kernels["pcpm_ws_forward_on_features"] = {"launches": fwd[0], "total_ms": fwd[1]} if fwd else None
+    del feat
     return {"cold_iters": rc.iters, "warm_iters": rw.iters, "cold_ms": cold_ms, "warm_ms": warm_ms,
             "warm_ms_first": warm_ms + count_ms, "indeg_count_ms": count_ms, "cold_resid": rc.resid,
-            "warm_resid": rw.resid, "fallback": fb}
+            "warm_resid": rw.resid, "fallback": fb, "warm_kernels": kernels}
 
 
 def main(argv=None):
