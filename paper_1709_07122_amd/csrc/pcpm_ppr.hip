@@ -74,11 +74,28 @@ __device__ __forceinline__ void ppr_scatter_item(const Item it, float* __restric
   const int64_t t_end = (hi + kTile - 1) / kTile;
   constexpr int kNW = kPprScatterBlock / kWave;
   uint32_t w[kPairs], wn[kPairs];
-  int64_t t = lo / kTile + threadIdx.x / kWave;
-  if (t < t_end) load_tile_words(png_src + t * kTile, lane, w);
+  int64_t t = lo / kTile + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  // bin order: the tile's pair-segment counts and deltas come in with its
+  // IDs, the counts of the next tile one step earlier (as in the gather)
+  int32_t cv = 0, cvn = 0, dl = 0;
+  if (t < t_end) {
+    load_tile_words(png_src + t * kTile, lane, w);
+    if constexpr (!kPng) {
+      cv = load_counts(png_blk, nullptr, t, lane);
+      if (t + kNW < t_end) cvn = load_counts(png_blk, nullptr, t + kNW, lane);
+      dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 0), lane);
+    }
+  }
   for (; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
-    if (t + kNW < t_end) load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
+    int32_t dln = 0, cvnn = 0;
+    if (t + kNW < t_end) {
+      load_tile_words(png_src + (t + kNW) * kTile, lane, wn);
+      if constexpr (!kPng) {
+        dln = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cvn, 0), lane);
+        if (t + 2 * kNW < t_end) cvnn = load_counts(png_blk, nullptr, t + 2 * kNW, lane);
+      }
+    }
     uint32_t xs[kSub];
     unpack_tile(w, xs);
     if constexpr (kPng) {
@@ -96,35 +113,46 @@ __device__ __forceinline__ void ppr_scatter_item(const Item it, float* __restric
       }
     } else {
       // every entry of a tile has a valid segment (entry 0 is flagged and
-      // padding follows the last segment): no predicate on these loads
-      int32_t run = png_blk[t];
+      // padding follows the last segment); its delta comes from the 64 that
+      // came in with the tile (dl) or from seg_delta
+      const int32_t sb = __builtin_amdgcn_readlane(cv, 0);
+      int32_t run = sb - 1;
       int32_t seg[kSub];
 #pragma unroll
       for (int j = 0; j < kSub; ++j) {
         const bool f = (xs[j] & kDidFlag) != 0u;
         const uint64_t bal = wave_ballot(f);
-        seg[j] = run + lanes_below(bal) + (f ? 0 : -1);
+        seg[j] = run + lanes_below(bal) + (f ? 1 : 0);
         run += __popcll(bal);
       }
-      int32_t dl[kSub];
+      const int32_t sbase = max(sb - 1, 0);
+      int32_t d[kSub];
+      if (run - sbase < kWave) {
 #pragma unroll
-      for (int j = 0; j < kSub; ++j) dl[j] = seg_delta[seg[j]];
+        for (int j = 0; j < kSub; ++j) d[j] = __builtin_amdgcn_ds_bpermute((seg[j] - sbase) << 2, dl);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kSub; ++j) d[j] = seg_delta[seg[j]];
+      }
       if (tb >= lo && tb + kTile <= hi) {
         float* ut = upd + tb * KT;
 #pragma unroll
         for (int j = 0; j < kSub; ++j)
-          copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane + dl[j]) * KT, spr + (xs[j] & qmask) * KT);
+          copy_kt<KT>(ut + static_cast<int64_t>(j * kWave + lane + d[j]) * KT, spr + (xs[j] & qmask) * KT);
       } else {
 #pragma unroll
         for (int j = 0; j < kSub; ++j) {
           const int64_t e = tb + j * kWave + lane;
           const bool in = e >= lo && e < hi;
-          copy_kt<KT>(upd + (in ? e + dl[j] : spare) * KT, spr + (xs[j] & qmask) * KT);
+          copy_kt<KT>(upd + (in ? e + d[j] : spare) * KT, spr + (xs[j] & qmask) * KT);
         }
       }
     }
 #pragma unroll
     for (int j = 0; j < kPairs; ++j) w[j] = wn[j];
+    cv = cvn;
+    cvn = cvnn;
+    dl = dln;
   }
 }
 
