@@ -61,13 +61,36 @@ constexpr int kMergeNodes = 256;  // nodes per merge workgroup (one per thread)
 // of BS threads, each applying its own range (an empty one, with red_slot
 // NULL, for a group without work); every thread calls it, and each group
 // computes exactly what a workgroup of BS threads computes.
-template <int BS, class AccFn, int G = 1>
+//
+// The apply's node loads: kU nodes per thread per step, all issued before
+// any is used, so their latencies overlap; a 1024-thread gather covers a
+// whole 16K-node slice in one step.
+template <int BS>
+struct NodeLoads {
+  static constexpr int kU = BS >= 1024 ? 16 : 4;
+  float xo[kU];     // previous iterate
+  uint32_t dw[kU];  // dangling-mask word of each node
+  // thread-relative node i of the range [.., i1) and the kU-1 nodes BS apart
+  __device__ __forceinline__ void load(const float* __restrict__ pr_in, const uint32_t* __restrict__ dmask,
+                                       int64_t v0, int i, int i1) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t v = v0 + min(i + u * BS, i1 - 1);
+      xo[u] = pr_in[v];
+      dw[u] = dmask[v >> 5];
+    }
+  }
+};
+
+// kPre: the caller has loaded this thread's nodes into *pre, and the range
+// fits in one step (i1 - i0 <= kU * BS).
+template <int BS, class AccFn, int G = 1, bool kPre = false>
 __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const GCtl* __restrict__ gctl,
                                             const int32_t* __restrict__ part_group,
                                             const int32_t* __restrict__ part_valid, int part, int64_t v0, int i0,
                                             int i1, AccFn acc, const float* __restrict__ pr_in,
                                             float* __restrict__ pr_out, const uint32_t* __restrict__ dmask,
-                                            double* __restrict__ red_slot) {
+                                            double* __restrict__ red_slot, const NodeLoads<BS>* pre = nullptr) {
   const int tid = static_cast<int>(threadIdx.x % BS);
   const GCtl& gc = gctl[part_group[part]];
   const double base = gc.base;
@@ -77,19 +100,8 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
   const double unit = ldexp(1.0, -ctl->fx_shift);
   double sums[2] = {0.0, 0.0};  // residual, dangling mass
   float mx = 0.0f;               // largest new value: the next fixed-point scale
-  // kU nodes per thread per step, loads first, so their latencies overlap;
-  // a 1024-thread gather covers a whole 16K-node slice in one step
-  constexpr int kU = BS >= 1024 ? 16 : 4;
-  for (int i = i0 + tid; i < i1; i += kU * BS) {
-    float xo[kU];
-    uint32_t dw[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int ii = i + u * BS;
-      const int64_t v = v0 + min(ii, i1 - 1);
-      xo[u] = pr_in[v];
-      dw[u] = dmask[v >> 5];
-    }
+  constexpr int kU = NodeLoads<BS>::kU;
+  auto step = [&](int i, const NodeLoads<BS>& nl) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int ii = i + u * BS;
@@ -98,13 +110,22 @@ __device__ __forceinline__ void apply_nodes(const Ctl* __restrict__ ctl, const G
         float xn = 0.0f;
         if (ii < valid) {
           const double sv = static_cast<double>(acc(ii)) * unit;
-          xn = frozen ? xo[u] : static_cast<float>(fma(d, sv, base));
+          xn = frozen ? nl.xo[u] : static_cast<float>(fma(d, sv, base));
         }
         mx = fmaxf(mx, fabsf(xn));
-        sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(xo[u]));
-        if ((dw[u] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
+        sums[0] += fabs(static_cast<double>(xn) - static_cast<double>(nl.xo[u]));
+        if ((nl.dw[u] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xn);
         __builtin_nontemporal_store(xn, pr_out + v);  // read by the next scatter, not this kernel
       }
+    }
+  };
+  if constexpr (kPre) {
+    if (i0 + tid < i1) step(i0 + tid, *pre);
+  } else {
+    for (int i = i0 + tid; i < i1; i += kU * BS) {
+      NodeLoads<BS> nl;
+      nl.load(pr_in, dmask, v0, i, i1);
+      step(i, nl);
     }
   }
   group_sum<BS, G>(sums);
@@ -271,7 +292,9 @@ __global__ __launch_bounds__(BS) void k_scatter(const Ctl* __restrict__ ctl, int
 // its segment's delta), else in bin order (at its message index).
 // One gather item (a range of one bin's destination IDs) by the whole
 // workgroup; acc is its LDS slice (q 64-bit sums).
-template <int BS, int kMode, bool kPng>
+// kEarlyApply: the apply's node loads go out before the final barrier (the
+// persistent kernel, short of registers already, leaves them where they are).
+template <int BS, int kMode, bool kPng, bool kEarlyApply = true>
 __device__ __forceinline__ void gather_item(const Item it, unsigned long long* __restrict__ acc,
                                             const Ctl* __restrict__ ctl, int64_t n, int s,
                                             const uint16_t* __restrict__ did, const int32_t* __restrict__ did_blk,
@@ -288,8 +311,6 @@ __device__ __forceinline__ void gather_item(const Item it, unsigned long long* _
   const int qn = static_cast<int>(min(q, n - v0));
   const FixedConv to_fixed(ctl->fx_shift);
   const uint32_t qmask = static_cast<uint32_t>(q - 1);
-  for (int i = threadIdx.x; i < qn; i += BS) acc[i] = 0ull;
-  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t lo = it.lo, hi = it.hi;
   const int64_t t_end = (hi + kTile - 1) / kTile;
@@ -303,12 +324,26 @@ __device__ __forceinline__ void gather_item(const Item it, unsigned long long* _
   const int64_t t0 = lo / kTile + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t* sblk_arr = kPng ? did_sblk : nullptr;
   int32_t cv = 0, cvn = 0, dl = 0;
+  // The first tiles' loads go out before the slice is cleared and stay in
+  // flight through the clear and the barrier.  Not in the weighted gather:
+  // there the registers they hold through the clear make the loop spill.
+  constexpr bool kEarly = kMode != 2;
+  if constexpr (!kEarly) {
+    for (int i = threadIdx.x; i < qn; i += BS) acc[i] = 0ull;
+    __syncthreads();
+  }
   if (t0 < t_end) {
     load_tile_words(did + t0 * kTile, lane, w);
     cv = load_counts(did_blk, sblk_arr, t0, lane);
     if (t0 + kNW < t_end) cvn = load_counts(did_blk, sblk_arr, t0 + kNW, lane);
-    if constexpr (kPng) dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 1), lane);
   }
+  if constexpr (kEarly) {
+    for (int i = threadIdx.x; i < qn; i += BS) acc[i] = 0ull;
+  }
+  if constexpr (kPng) {
+    if (t0 < t_end) dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 1), lane);
+  }
+  if constexpr (kEarly) __syncthreads();
   for (int64_t t = t0; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     const int32_t blk = __builtin_amdgcn_readlane(cv, 0);
@@ -374,6 +409,13 @@ __device__ __forceinline__ void gather_item(const Item it, unsigned long long* _
     cvn = cvnn;
     dl = dln;
   }
+  // A whole bin's apply is one step of node loads at 1024 threads: they go
+  // out before the barrier, while the other wavefronts finish their adds.
+  constexpr bool kPre = kEarlyApply && kMode == 0 && NodeLoads<BS>::kU * BS >= (1 << kMaxLog2);
+  NodeLoads<BS> pre;
+  if constexpr (kPre) {
+    if (it.aux < 0 && static_cast<int>(threadIdx.x) < qn) pre.load(pr_in, dmask, v0, threadIdx.x, qn);
+  }
   __syncthreads();
   if (it.aux >= 0) {
     int64_t* dst = partial + static_cast<int64_t>(it.aux) * q;
@@ -389,8 +431,9 @@ __device__ __forceinline__ void gather_item(const Item it, unsigned long long* _
           pr_out + v0 + i);
     return;
   }
-  apply_nodes<BS>(ctl, gctl, part_group, part_valid, it.part, v0, 0, qn,
-                  [&](int i) { return static_cast<int64_t>(acc[i]); }, pr_in, pr_out, dmask, red + 3 * it.part);
+  auto slice = [&](int i) { return static_cast<int64_t>(acc[i]); };
+  apply_nodes<BS, decltype(slice), 1, kPre>(ctl, gctl, part_group, part_valid, it.part, v0, 0, qn, slice, pr_in,
+                                           pr_out, dmask, red + 3 * it.part, &pre);
 }
 
 template <int BS, int kMode, bool kPng>
@@ -628,7 +671,7 @@ __global__ __launch_bounds__(1024) void k_persist(const PersistArgs a) {
       const int32_t j = grab(&ps->ga_next);
       if (j >= a.n_ga) break;
       const Item itm = a.ga_items[xcd_block(static_cast<unsigned>(j), static_cast<unsigned>(a.n_ga))];
-      gather_item<BS, 0, kPng>(itm, lds, a.ctl, a.n, a.s, a.did, a.did_blk, a.did_sblk, a.seg_delta, a.upd, in, out,
+      gather_item<BS, 0, kPng, false>(itm, lds, a.ctl, a.n, a.s, a.did, a.did_blk, a.did_sblk, a.seg_delta, a.upd, in, out,
                                a.dmask, a.partial, a.red, a.gctl, a.part_group, a.part_valid, nullptr);
       if (itm.aux >= 0) {  // a split bin's slice: applied by its merge units
         publish(&a.bin_done[itm.part]);

@@ -102,6 +102,52 @@ def test_tiles_spanning_more_than_64_segments():
     assert np.abs(out[1][0].view(np.float32).astype(np.float64) - ref).sum() < 1e-5
 
 
+def bins_on_tile_boundaries(n=4096, part_log2=7, seed=9):
+    """Every bin holds a multiple of 1024 destination IDs, so every bin starts
+    a tile, and each bin draws its sources from all source pairs: the segment
+    before a bin's first tile is the previous bin's last (from the last pair),
+    whose delta exceeds those of the bin's own first segments."""
+    q = 1 << part_log2
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    for b in range(n // q):
+        want = 1024 * (1 + b % 3)
+        u = rng.integers(0, n, 3 * want)
+        v = b * q + rng.integers(0, q, 3 * want)
+        key = np.unique((u * n + v)[u != v])
+        key = rng.permutation(key)[:want]
+        src.append(key // n)
+        dst.append(key % n)
+    return graphgen.from_edges(n, np.concatenate(src), np.concatenate(dst))
+
+
+def test_bins_that_start_on_a_tile_boundary():
+    """With PNG-ordered updates the gather reads an interior tile through
+    offsets from the tile's first slot; a tile that starts a bin must take
+    that slot from its own first segment, not the previous bin's last.  Both
+    orders and the oracle agree on a graph where every bin starts a tile."""
+    r, c = bins_on_tile_boundaries()
+    n, q = len(r) - 1, 1 << 7
+    per_bin = np.bincount(c // q, minlength=n // q)
+    assert (per_bin % 1024 == 0).all() and per_bin.min() > 0
+    pairs = np.repeat(np.arange(n), np.diff(r)) // (2 * q)
+    assert all(len(np.unique(pairs[c // q == b])) == n // (2 * q) for b in range(n // q))
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(n).astype(np.float32)
+    off, seeds = graphgen.seed_sets(n, 5, seed=2)
+    out = {}
+    for order in (1, 2):
+        png = P.build_png(dev(r), dev(c), part_log2=7, update_order=order)
+        res = P.pagerank(png, tol=0.0, max_iters=10)
+        out[order] = (bits(res.pr), bits(P.spmv(png, dev(x))),
+                      bits(P.ppr_batch(png, off, seeds, tol=0.0, max_iters=8).pr))
+        png.close()
+    for a, b in zip(out[1], out[2]):
+        np.testing.assert_array_equal(a, b)
+    ref = oracle.pagerank(r, c, iters=10).x
+    assert np.abs(out[2][0].view(np.float32).astype(np.float64) - ref).sum() < 1e-5
+
+
 def test_multi_graph_handle_in_both_orders():
     graphs = [graphgen.rmat(s, 8, seed=40 + s, relabel="random") for s in (9, 11, 8)]
     r, c, goff, sizes = P.union_csr(graphs, 9)
