@@ -269,8 +269,6 @@ __device__ __forceinline__ void ppr_gather_item(const Item it, unsigned long lon
   const int64_t v0 = static_cast<int64_t>(it.part) << s;
   const int qn = static_cast<int>(min(q, n - v0));
   const FixedConv to_fixed(ctl->fx_shift);
-  for (int i = threadIdx.x; i < q * KT; i += BS) acc[i] = 0ull;
-  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t qmask = static_cast<uint32_t>(q - 1);
   const uint32_t qs = static_cast<uint32_t>(q);
@@ -286,12 +284,17 @@ __device__ __forceinline__ void ppr_gather_item(const Item it, unsigned long lon
   const int64_t t0 = lo / kTile + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t* sblk_arr = kPng ? did_sblk : nullptr;
   int32_t cv = 0, cvn = 0, dl = 0;
+  // the first tiles' loads stay in flight through the clear of the slice
   if (t0 < t_end) {
     load_tile_words(did + t0 * kTile, lane, w);
     cv = load_counts(did_blk, sblk_arr, t0, lane);
     if (t0 + kNW < t_end) cvn = load_counts(did_blk, sblk_arr, t0 + kNW, lane);
-    if constexpr (kPng) dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 1), lane);
   }
+  for (int i = threadIdx.x; i < q * KT; i += BS) acc[i] = 0ull;
+  if constexpr (kPng) {
+    if (t0 < t_end) dl = tile_deltas(seg_delta, __builtin_amdgcn_readlane(cv, 1), lane);
+  }
+  __syncthreads();
   for (int64_t t = t0; t < t_end; t += kNW) {
     const int64_t tb = t * kTile;
     uint32_t xs[kSub];
