@@ -779,28 +779,20 @@ __global__ __launch_bounds__(256) void k_ctl_init(Ctl* __restrict__ ctl, GCtl* _
   }
 }
 
-// 1/n_g on every real node of its group, 0 on padding.  One workgroup per
-// partition.
-__global__ __launch_bounds__(256) void k_fill_uniform(float* __restrict__ x, int64_t n, int s,
-                                                      const GCtl* __restrict__ gctl,
-                                                      const int32_t* __restrict__ part_group,
-                                                      const int32_t* __restrict__ part_valid) {
-  const int64_t v0 = static_cast<int64_t>(blockIdx.x) << s;
-  const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
-  const int valid = part_valid[blockIdx.x];
-  const float u = static_cast<float>(gctl[part_group[blockIdx.x]].inv_n);
-  for (int i = threadIdx.x; i < qn; i += 256) x[v0 + i] = i < valid ? u : 0.0f;
-}
-
 // Start vector statistics per partition: non-finite count, dangling mass and
 // L1 mass, into the partition's start slot, and its largest |value| (after
-// the 3k slots).  Padding entries are cleared.
+// the 3k slots).  Padding entries are cleared.  fill: the start vector is
+// written here, 1/n_g on every real node of group g, instead of read.
+// One workgroup per partition.
 __global__ __launch_bounds__(256) void k_start_parts(float* __restrict__ x, const uint32_t* __restrict__ dmask,
                                                      int64_t n, int s, const int32_t* __restrict__ part_valid,
-                                                     double* __restrict__ red) {
+                                                     double* __restrict__ red, bool fill,
+                                                     const GCtl* __restrict__ gctl,
+                                                     const int32_t* __restrict__ part_group) {
   const int64_t v0 = static_cast<int64_t>(blockIdx.x) << s;
   const int qn = static_cast<int>(min(int64_t{1} << s, n - v0));
   const int valid = part_valid[blockIdx.x];
+  const float u = fill ? static_cast<float>(gctl[part_group[blockIdx.x]].inv_n) : 0.0f;
   double sums[3] = {0.0, 0.0, 0.0};
   float mx = 0.0f;
   for (int i = threadIdx.x; i < qn; i += 256) {
@@ -809,7 +801,13 @@ __global__ __launch_bounds__(256) void k_start_parts(float* __restrict__ x, cons
       x[v] = 0.0f;
       continue;
     }
-    const float xv = x[v];
+    float xv;
+    if (fill) {
+      xv = u;
+      x[v] = u;
+    } else {
+      xv = x[v];
+    }
     if (!isfinite(xv)) sums[0] += 1.0;
     if ((dmask[v >> 5] >> (v & 31)) & 1u) sums[1] += static_cast<double>(xv);
     sums[2] += fabs(static_cast<double>(xv));
@@ -907,10 +905,12 @@ pcpm_status_t iter_lds_limits() {
   return PCPM_OK;
 }
 
-static pcpm_status_t start_solve(pcpm_png* g, double /*tol*/, double /*d*/, float* x0, hipStream_t st) {
+// fill: x0 receives the uniform start vector (1/n_g per group) instead of
+// holding the caller's.
+static pcpm_status_t start_solve(pcpm_png* g, float* x0, bool fill, hipStream_t st) {
   const unsigned kk = static_cast<unsigned>(g->k);
   PCPM_LAUNCH("pcpm_init", k_start_parts, dim3(kk), dim3(256), 0, st, x0, g->dmask, g->n, g->part_log2,
-              g->part_valid, g->red_start);
+              g->part_valid, g->red_start, fill, g->gctl, g->part_group);
   PCPM_LAUNCH("pcpm_init", k_start_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->gctl, g->group_slots,
               g->red_start, g->k);
   return PCPM_OK;
@@ -1103,7 +1103,7 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
   // the start statistics clear padding entries, so they run on a copy
   PCPM_TRY_HIP(hipMemcpyAsync(g->tmp_pr, pr_in, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
   PCPM_TRY(reset_ctl(g, 0.0, d, st));
-  PCPM_TRY(start_solve(g, 0.0, d, g->tmp_pr, st));
+  PCPM_TRY(start_solve(g, g->tmp_pr, false, st));
   PCPM_TRY(run_iteration(g, g->tmp_pr, pr_out, st));
   if (!resid) {
     const unsigned nb = static_cast<unsigned>(std::min<int64_t>((g->n + 255) / 256, 1024));
@@ -1158,14 +1158,9 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
   float* a = pr_out;
   float* b = g->tmp_pr;
   PCPM_TRY(reset_ctl(g, tol, d, st));
-  if (init) {
-    if (init != pr_out)
-      PCPM_TRY_HIP(hipMemcpyAsync(a, init, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
-  } else {
-    PCPM_LAUNCH("pcpm_init", k_fill_uniform, dim3(static_cast<unsigned>(g->k)), dim3(256), 0, st, a, g->n,
-                g->part_log2, g->gctl, g->part_group, g->part_valid);
-  }
-  PCPM_TRY(start_solve(g, tol, d, a, st));
+  if (init && init != pr_out)
+    PCPM_TRY_HIP(hipMemcpyAsync(a, init, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
+  PCPM_TRY(start_solve(g, a, !init, st));
   PCPM_TRY(persist_grid(g));
   if (use_persistent(g)) {
     PCPM_TRY(run_persistent(g, a, b, max_iters, st));
