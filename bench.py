@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import math
 import os
 import sys
@@ -461,17 +462,26 @@ def multigraph_detail(P, torch, args):
     return out
 
 
+def kernel_source_key(src: str) -> str:
+    """sha256 prefix of kernel source code with its comments and whitespace
+    removed: edits to comments leave the key (and the counters) valid."""
+    import hashlib
+
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"\s+", " ", src).strip()
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
-    import hashlib
-
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", "pcpm_rmat24_random.json")))
-        src = open(os.path.join(ROOT, "paper_1709_07122_amd", "csrc", "pcpm_iter.hip"), "rb").read()
+        src = open(os.path.join(ROOT, "paper_1709_07122_amd", "csrc", "pcpm_iter.hip")).read()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != prof.get("kernel_source_sha256_16"):
+    if kernel_source_key(src) != prof.get("kernel_source_key"):
         return None
     k = prof["kernels"].get(kernel)
     return None if k is None else int(k["traffic_bytes"])

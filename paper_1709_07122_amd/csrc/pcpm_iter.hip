@@ -11,6 +11,13 @@
 //               bin): destination IDs are streamed, the update of an ID is
 //               found from the running count of message flags, and sums
 //               build up in an LDS slice of the destination partition.
+//               A whole bin is applied in place; a split bin stores its
+//               partial slice for k_merge.
+//   k_merge     applies split bins, adding their partial slices in order;
+//               one workgroup per slice of a split bin's nodes.
+//   k_finalize  one workgroup: residual and next dangling mass in FP64, in a
+//               fixed order; sets the convergence flag that makes the kernels
+//               of later iterations return at once.
 //
 // Updates are stored in one of two orders, chosen per handle at build time:
 //   bin order   (Sec. 3.1) the updates of bin p' are contiguous, in message
@@ -24,13 +31,6 @@
 // Short segments make the scatter's runs of writes costly on HBM (partial
 // lines, scattered rows), while runs of reads cost less; the build takes PNG
 // order when the average segment is short.
-//               A whole bin is applied in place; a split bin stores its
-//               partial slice for k_merge.
-//   k_merge     applies split bins, adding their partial slices in order;
-//               one workgroup per slice of a split bin's nodes.
-//   k_finalize  one workgroup: residual and next dangling mass in FP64, in a
-//               fixed order; sets the convergence flag that makes the kernels
-//               of later iterations return at once.
 //
 // Sums in the gather are kept in 64-bit fixed point: every FP32 update is
 // rounded to a multiple of 2^-fx_shift and added with LDS integer atomics.
