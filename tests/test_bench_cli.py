@@ -19,3 +19,15 @@ def test_help_lists_the_legs():
     assert r.returncode == 0
     for flag in ("--gpus", "--steps", "--warmup", "--no-indegree", "--no-spmv", "--update-order"):
         assert flag in r.stdout
+
+
+def test_counter_summary_is_matched_to_the_kernel_code():
+    """The bench reports counter traffic only while the kernel code is the one
+    profiled: comments and layout may change, code may not."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    src = "// header\nint f(int x) {  /* twice */ return 2 * x; }\n"
+    key = bench.kernel_source_key(src)
+    assert bench.kernel_source_key("// other header\nint f(int x) {\n  return 2 * x;  // doubled\n}\n") == key
+    assert bench.kernel_source_key("int f(int x) { return 3 * x; }\n") != key
