@@ -511,20 +511,54 @@ __device__ __forceinline__ void group_sums(const int32_t* __restrict__ group_slo
     for (int c = 0; c < 3; ++c) s[c] += __shfl_xor(s[c], off);
 }
 
-// The same sums over the whole workgroup (for few groups): a fixed strided
-// assignment and a fixed reduction order, so the result is reproducible;
-// valid in thread 0.
-__device__ __forceinline__ void group_sums_block(const int32_t* __restrict__ group_slots,
-                                                 const double* __restrict__ red, int64_t k, int grp,
-                                                 double (&s)[3]) {
+// A group's apply slots at the end of an iteration: the sums of the residual
+// and dangling parts and the largest value of the new iterate.  By one
+// wavefront (valid in lane 0, summed in the order of group_sums) or, kBlock,
+// by the whole workgroup for few groups (valid in thread 0; a fixed strided
+// assignment and reduction order, one barrier), so results are reproducible.
+template <bool kBlock>
+__device__ __forceinline__ void group_stats(const int32_t* __restrict__ group_slots, const double* __restrict__ red,
+                                            int64_t k, int grp, double (&s)[3]) {
+  const int t = kBlock ? static_cast<int>(threadIdx.x) : static_cast<int>(threadIdx.x & (kWave - 1));
+  constexpr int kStride = kBlock ? 1024 : kWave;
   s[0] = s[1] = s[2] = 0.0;
   const int p0 = group_slots[2 * grp], p1 = group_slots[2 * grp + 2];
-  for (int j = p0 + static_cast<int>(threadIdx.x); j < p1; j += 1024)
-    for (int c = 0; c < 3; ++c) s[c] += red[3 * j + c];
   const int u0 = group_slots[2 * grp + 1], u1 = group_slots[2 * grp + 3];
-  for (int j = u0 + static_cast<int>(threadIdx.x); j < u1; j += 1024)
-    for (int c = 0; c < 3; ++c) s[c] += red[3 * (k + j) + c];
-  block_sum<1024, 3>(s);
+  for (int j = p0 + t; j < p1; j += kStride) {
+    s[0] += red[3 * j];
+    s[1] += red[3 * j + 1];
+    s[2] = fmax(s[2], red[3 * j + 2]);
+  }
+  for (int j = u0 + t; j < u1; j += kStride) {
+    s[0] += red[3 * (k + j)];
+    s[1] += red[3 * (k + j) + 1];
+    s[2] = fmax(s[2], red[3 * (k + j) + 2]);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    s[0] += __shfl_xor(s[0], off);
+    s[1] += __shfl_xor(s[1], off);
+    s[2] = fmax(s[2], __shfl_xor(s[2], off));
+  }
+  if constexpr (kBlock) {
+    constexpr int kW = 1024 / kWave;
+    __shared__ double sh[3 * kW];
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      sh[3 * w] = s[0];
+      sh[3 * w + 1] = s[1];
+      sh[3 * w + 2] = s[2];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s[0] = s[1] = s[2] = 0.0;
+      for (int ww = 0; ww < kW; ++ww) {
+        s[0] += sh[3 * ww];
+        s[1] += sh[3 * ww + 1];
+        s[2] = fmax(s[2], sh[3 * ww + 2]);
+      }
+    }
+  }
 }
 
 // End of an iteration: per-group residual, next dangling mass and base, group
@@ -537,14 +571,11 @@ __device__ __forceinline__ void group_sums_block(const int32_t* __restrict__ gro
 // workgroup barrier.
 __device__ __forceinline__ void finalize_body(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
                                               const int32_t* __restrict__ group_slots,
-                                              const double* __restrict__ red, int64_t k, int64_t nslots,
+                                              const double* __restrict__ red, int64_t k, int64_t /*nslots*/,
                                               double* __restrict__ hist) {
-  double vmax = 0.0;  // largest value of the new iterate over all apply units
-  for (int64_t j = threadIdx.x; j < nslots; j += 1024) vmax = fmax(vmax, red[3 * j + 2]);
-  vmax = block_max<1024>(vmax);
   constexpr int kW = 1024 / kWave;
   __shared__ int s_bad[kW], s_done[kW];
-  __shared__ double s_rmax[kW];
+  __shared__ double s_rmax[kW], s_vmax[kW];
   const int G = ctl->ngroups;
   const double d = ctl->d, tol = ctl->tol;
   // the group's update; returns its residual and convergence after it
@@ -563,25 +594,28 @@ __device__ __forceinline__ void finalize_body(Ctl* __restrict__ ctl, GCtl* __res
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   int bad = 0, all_done = 1;
   double rmax = 0.0;
+  double vmax = 0.0;  // largest value of the new iterate over all apply units (the groups cover them all)
   if (G < kW) {  // few groups: the whole workgroup sums each one, thread 0 updates it
     for (int grp = 0; grp < G; ++grp) {
       double sm[3];
-      group_sums_block(group_slots, red, k, grp, sm);
+      group_stats<true>(group_slots, red, k, grp, sm);
       if (threadIdx.x == 0) {
         const GCtl gc = update(grp, sm, bad);
         rmax = fmax(rmax, gc.res);
         all_done &= gc.done;
+        vmax = fmax(vmax, sm[2]);
       }
       __syncthreads();
     }
   } else {  // one wavefront per group, lane 0 updates it
     for (int grp = w; grp < G; grp += kW) {
       double sm[3];
-      group_sums(group_slots, red, k, grp, true, sm);
+      group_stats<false>(group_slots, red, k, grp, sm);
       if (lane == 0) {
         const GCtl gc = update(grp, sm, bad);
         rmax = fmax(rmax, gc.res);
         all_done &= gc.done;
+        vmax = fmax(vmax, sm[2]);
       }
     }
   }
@@ -589,6 +623,7 @@ __device__ __forceinline__ void finalize_body(Ctl* __restrict__ ctl, GCtl* __res
     s_bad[w] = bad;
     s_done[w] = all_done;
     s_rmax[w] = rmax;
+    s_vmax[w] = vmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -596,6 +631,7 @@ __device__ __forceinline__ void finalize_body(Ctl* __restrict__ ctl, GCtl* __res
       bad |= s_bad[ww];
       all_done &= s_done[ww];
       rmax = fmax(rmax, s_rmax[ww]);
+      vmax = fmax(vmax, s_vmax[ww]);
     }
     if (bad) rmax = NAN;
     const int32_t it = ctl->iter;
