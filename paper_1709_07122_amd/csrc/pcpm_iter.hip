@@ -792,28 +792,6 @@ __global__ __launch_bounds__(1024) void k_spmv_scale(Ctl* __restrict__ ctl, cons
 }
 
 // ---- start of a solve ----------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ctl_init(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl, int G, double tol,
-                                                  double d) {
-  for (int grp = threadIdx.x; grp < G; grp += 256) {
-    gctl[grp].base = 0.0;
-    gctl[grp].dmass = 0.0;
-    gctl[grp].res = 0.0;
-    gctl[grp].iter = 0;
-    gctl[grp].done = 0;
-  }
-  if (threadIdx.x == 0) {
-    ctl->res = 0.0;
-    ctl->res_prev = 0.0;
-    ctl->tol = tol;
-    ctl->d = d;
-    ctl->iter = 0;
-    ctl->done = 0;
-    ctl->nonfinite = 0;
-    ctl->fx_shift = 50;
-    ctl->fx_cap = 61;
-    ctl->ngroups = G;
-  }
-}
 
 // Start vector statistics per partition: non-finite count, dangling mass and
 // L1 mass, into the partition's start slot, and its largest |value| (after
@@ -867,7 +845,8 @@ __global__ __launch_bounds__(256) void k_start_parts(float* __restrict__ x, cons
 // value sets it.
 __global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, GCtl* __restrict__ gctl,
                                                          const int32_t* __restrict__ group_slots,
-                                                         const double* __restrict__ red, int64_t k) {
+                                                         const double* __restrict__ red, int64_t k, int G,
+                                                         double tol, double d) {
   double vmax = 0.0;  // largest |value| of the start vector
   for (int64_t j = threadIdx.x; j < k; j += 1024) vmax = fmax(vmax, red[3 * k + j]);
   vmax = block_max<1024>(vmax);
@@ -876,14 +855,16 @@ __global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, 
   if (threadIdx.x == 0) bad = 0;
   if (threadIdx.x < 1024 / kWave) mass_w[threadIdx.x] = 0.0;
   __syncthreads();
-  const int G = ctl->ngroups;
-  const double d = ctl->d;
   double wmass = 0.0;
+  // each group's control struct is set by one thread: the one that sums it
   for (int grp = threadIdx.x / kWave; grp < G; grp += 1024 / kWave) {
     double sm[3];
     group_sums(group_slots, red, k, grp, false, sm);
     if ((threadIdx.x & (kWave - 1)) == 0) {
       GCtl& gc = gctl[grp];
+      gc.res = 0.0;
+      gc.iter = 0;
+      gc.done = 0;
       gc.dmass = sm[1];
       gc.base = (1.0 - d) * gc.inv_n + d * sm[1] * gc.inv_n;
       if (sm[0] > 0.0 || !isfinite(sm[1]) || !isfinite(sm[2])) atomicOr(&bad, 1);
@@ -897,12 +878,16 @@ __global__ __launch_bounds__(1024) void k_start_finalize(Ctl* __restrict__ ctl, 
     for (int w = 0; w < 1024 / kWave; ++w) mass += mass_w[w];
     int e = 0;
     if (isfinite(mass) && mass > 1.0) e = static_cast<int>(ceil(log2(mass)));
+    ctl->res = 0.0;
+    ctl->res_prev = 0.0;
+    ctl->tol = tol;
+    ctl->d = d;
+    ctl->iter = 0;
+    ctl->ngroups = G;
     ctl->fx_cap = 61 - min(e, 1000);
     ctl->fx_shift = fx_shift_for(vmax, ctl->fx_cap);
-    if (bad) {
-      ctl->nonfinite = 1;
-      ctl->done = 1;
-    }
+    ctl->nonfinite = bad ? 1 : 0;
+    ctl->done = bad ? 1 : 0;
   }
 }
 
@@ -941,19 +926,15 @@ pcpm_status_t iter_lds_limits() {
   return PCPM_OK;
 }
 
-// fill: x0 receives the uniform start vector (1/n_g per group) instead of
-// holding the caller's.
-static pcpm_status_t start_solve(pcpm_png* g, float* x0, bool fill, hipStream_t st) {
+// Start of a solve: the control block reset for damping d and tolerance tol,
+// and the start vector's statistics.  fill: x0 receives the uniform start
+// vector (1/n_g per group) instead of holding the caller's.
+static pcpm_status_t start_solve(pcpm_png* g, float* x0, bool fill, double tol, double d, hipStream_t st) {
   const unsigned kk = static_cast<unsigned>(g->k);
   PCPM_LAUNCH("pcpm_init", k_start_parts, dim3(kk), dim3(256), 0, st, x0, g->dmask, g->n, g->part_log2,
               g->part_valid, g->red_start, fill, g->gctl, g->part_group);
   PCPM_LAUNCH("pcpm_init", k_start_finalize, dim3(1), dim3(1024), 0, st, g->ctl, g->gctl, g->group_slots,
-              g->red_start, g->k);
-  return PCPM_OK;
-}
-
-static pcpm_status_t reset_ctl(pcpm_png* g, double tol, double d, hipStream_t st) {
-  PCPM_LAUNCH("pcpm_init", k_ctl_init, dim3(1), dim3(256), 0, st, g->ctl, g->gctl, g->ngroups, tol, d);
+              g->red_start, g->k, static_cast<int>(g->ngroups), tol, d);
   return PCPM_OK;
 }
 
@@ -1138,8 +1119,7 @@ pcpm_status_t pcpm_iterate(pcpm_png_t g, double d, const float* pr_in, float* pr
   hipStream_t st = static_cast<hipStream_t>(stream);
   // the start statistics clear padding entries, so they run on a copy
   PCPM_TRY_HIP(hipMemcpyAsync(g->tmp_pr, pr_in, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
-  PCPM_TRY(reset_ctl(g, 0.0, d, st));
-  PCPM_TRY(start_solve(g, g->tmp_pr, false, st));
+  PCPM_TRY(start_solve(g, g->tmp_pr, false, 0.0, d, st));
   PCPM_TRY(run_iteration(g, g->tmp_pr, pr_out, st));
   if (!resid) {
     const unsigned nb = static_cast<unsigned>(std::min<int64_t>((g->n + 255) / 256, 1024));
@@ -1193,10 +1173,9 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
   hipStream_t st = static_cast<hipStream_t>(stream);
   float* a = pr_out;
   float* b = g->tmp_pr;
-  PCPM_TRY(reset_ctl(g, tol, d, st));
   if (init && init != pr_out)
     PCPM_TRY_HIP(hipMemcpyAsync(a, init, static_cast<size_t>(g->n) * 4, hipMemcpyDeviceToDevice, st));
-  PCPM_TRY(start_solve(g, a, !init, st));
+  PCPM_TRY(start_solve(g, a, !init, tol, d, st));
   PCPM_TRY(persist_grid(g));
   if (use_persistent(g)) {
     PCPM_TRY(run_persistent(g, a, b, max_iters, st));
