@@ -1177,7 +1177,8 @@ static pcpm_status_t build(int64_t n, int64_t m, const int32_t* row_off, const i
   PCPM_TRY(dalloc(g, &g->psync, 1));
   PCPM_TRY(dalloc(g, &g->bin_done, g->k));
   PCPM_TRY(dalloc(g, &g->tmp_pr, n));
-  PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->ctl_host), sizeof(Ctl), hipHostMallocDefault));
+  PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->ctl_host), 2 * sizeof(Ctl), hipHostMallocDefault));
+  for (hipEvent_t& e : g->ctl_ev) PCPM_TRY_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   PCPM_TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&g->psync_host), sizeof(PSync), hipHostMallocDefault));
   PCPM_TRY(build_items(g, opts, st));
 

@@ -412,7 +412,8 @@ struct pcpm_png {
                                 // then the largest |value| per partition
   double* hist = nullptr;       // kMaxHist residuals (largest over groups)
   pcpm::Ctl* ctl = nullptr;
-  pcpm::Ctl* ctl_host = nullptr;  // pinned mirror
+  pcpm::Ctl* ctl_host = nullptr;  // pinned mirrors: two slots, [0] for single reads
+  hipEvent_t ctl_ev[2] = {nullptr, nullptr};  // completion of the copy into each slot
   float* tmp_pr = nullptr;      // n: second rank buffer
 
   // batched personalised PageRank working set (grown by pcpm_ppr_batch)

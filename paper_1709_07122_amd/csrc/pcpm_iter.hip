@@ -1067,11 +1067,10 @@ static pcpm_status_t check_device(pcpm_png* g) {
   return PCPM_OK;
 }
 
-// End of a solve whose control block is in ctl_host: results to the caller,
-// the last iterate into a.
-static pcpm_status_t finish_solve(pcpm_png* g, float* a, const float* b, double tol, int32_t* iters, double* resid,
-                                  double* res_hist, hipStream_t st) {
-  const Ctl c = *g->ctl_host;
+// End of a solve with final control block c: results to the caller, the
+// last iterate into a.
+static pcpm_status_t finish_solve(pcpm_png* g, const Ctl& c, float* a, const float* b, double tol, int32_t* iters,
+                                  double* resid, double* res_hist, hipStream_t st) {
   *iters = c.iter;
   *resid = c.res;
   if (c.iter > 0 && ((c.iter - 1) % 2) == 0)  // last output went to b
@@ -1179,35 +1178,57 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
   PCPM_TRY(persist_grid(g));
   if (use_persistent(g)) {
     PCPM_TRY(run_persistent(g, a, b, max_iters, st));
-    return finish_solve(g, a, b, tol, iters, resid, res_hist, st);
+    return finish_solve(g, g->ctl_host[0], a, b, tol, iters, resid, res_hist, st);
   }
-  // Iterations are queued in batches between host checks of the device
-  // control block.  After the first batch the batch length is the number of
-  // iterations the observed per-iteration residual ratio predicts until tol,
-  // so few iterations are queued past convergence (those return at once).
+  // Iterations go out in batches, each followed by a copy of the control
+  // block into one of two pinned slots and an event.  The host waits for the
+  // older of the two batches in flight and sizes the next one from the
+  // residual ratio it shows, counting the iterations already queued behind
+  // it, so the device always has work queued while the host decides.
+  // Iterations queued past convergence return at once.
   int launched = 0;
-  int next = std::min(tol > 0.0 ? 4 : 64, max_iters);
-  while (launched < max_iters) {
-    for (int i = 0; i < next; ++i) {
+  int pending[2] = {-1, -1};  // FIFO of slots whose copy is in flight
+  int npend = 0;
+  auto queue = [&](int count) -> pcpm_status_t {
+    const int slot = npend == 0 ? 0 : 1 - pending[npend - 1];
+    for (int i = 0; i < count; ++i) {
       const int it = launched + i;
       const bool even = (it % 2) == 0;
       PCPM_TRY(run_iteration(g, even ? a : b, even ? b : a, st));
     }
-    launched += next;
-    PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    PCPM_TRY_HIP(hipStreamSynchronize(st));
-    if (g->ctl_host->done) break;
+    launched += count;
+    PCPM_TRY_HIP(hipMemcpyAsync(&g->ctl_host[slot], g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    PCPM_TRY_HIP(hipEventRecord(g->ctl_ev[slot], st));
+    pending[npend++] = slot;
+    return PCPM_OK;
+  };
+  const int batch0 = tol > 0.0 ? 4 : 64;
+  PCPM_TRY(queue(std::min(batch0, max_iters)));
+  if (launched < max_iters) PCPM_TRY(queue(std::min(batch0, max_iters - launched)));
+  Ctl c{};
+  for (;;) {
+    const int slot = pending[0];
+    PCPM_TRY_HIP(hipEventSynchronize(g->ctl_ev[slot]));
+    c = g->ctl_host[slot];
+    pending[0] = pending[1];
+    --npend;
+    if (c.done) break;  // what is still in flight returns at once
+    if (launched >= max_iters) {
+      if (npend == 0) break;
+      continue;
+    }
     int want = 64;
     if (tol > 0.0) {
-      const double res = g->ctl_host->res, prev = g->ctl_host->res_prev;
+      const double res = c.res, prev = c.res_prev;
       double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
       rho = std::min(std::max(rho, 0.05), 0.995);
       const double est = std::ceil(std::log(tol / res) / std::log(rho));
-      want = static_cast<int>(std::min(std::max(est, 1.0), 16.0));
+      const int ahead = launched - c.iter;  // queued behind this copy
+      want = static_cast<int>(std::min(std::max(est - ahead, 1.0), 16.0));
     }
-    next = std::min(want, max_iters - launched);
+    PCPM_TRY(queue(std::min(want, max_iters - launched)));
   }
-  return finish_solve(g, a, b, tol, iters, resid, res_hist, st);
+  return finish_solve(g, c, a, b, tol, iters, resid, res_hist, st);
 }
 
 pcpm_status_t pcpm_graph_results(pcpm_png_t g, int32_t* iters, double* resid) {

@@ -116,6 +116,10 @@ void free_handle(pcpm_png* g) {
   for (auto& a : g->allocations) (void)hipFree(a.first);
   g->allocations.clear();
   if (g->ctl_host) (void)hipHostFree(g->ctl_host);
+  for (hipEvent_t& e : g->ctl_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (g->psync_host) (void)hipHostFree(g->psync_host);
   g->psync_host = nullptr;
   if (g->gctl_host) (void)hipHostFree(g->gctl_host);
