@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -477,4 +479,55 @@ int64_t scan_tmp_ints(int64_t L);
 // Queue the weight statistics into g->wstats on st (pcpm_build.hip).
 pcpm_status_t weight_stats(pcpm_png* g, hipStream_t st);
 pcpm_status_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t L, int32_t* tmp, hipStream_t st);
+
+// Iterations 0 .. up to max_iters - 1 of a solve whose kernels keep the
+// device control block g->ctl and return at once once it says done.  They go
+// out in batches, each followed by a copy of the control block into one of
+// the two pinned slots of g->ctl_host and an event; the host waits for the
+// older of the two batches in flight and sizes the next one from the
+// residual decay it shows (tol > 0), counting the iterations already queued,
+// so the device always has work queued while the host decides.  step(it)
+// queues iteration it.  *last receives the last control block read: the
+// final one once it says done, or after max_iters iterations.
+template <class Step>
+pcpm_status_t pipelined_iterations(pcpm_png* g, double tol, int64_t max_iters, hipStream_t st, Step step,
+                                   Ctl* last) {
+  int64_t launched = 0;
+  int pending[2] = {-1, -1};  // FIFO of slots whose copy is in flight
+  int npend = 0;
+  auto queue = [&](int64_t count) -> pcpm_status_t {
+    const int slot = npend == 0 ? 0 : 1 - pending[npend - 1];
+    for (int64_t i = 0; i < count; ++i) PCPM_TRY(step(launched + i));
+    launched += count;
+    PCPM_TRY_HIP(hipMemcpyAsync(&g->ctl_host[slot], g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    PCPM_TRY_HIP(hipEventRecord(g->ctl_ev[slot], st));
+    pending[npend++] = slot;
+    return PCPM_OK;
+  };
+  const int64_t batch0 = tol > 0.0 ? 4 : 64;
+  PCPM_TRY(queue(std::min(batch0, max_iters)));
+  if (launched < max_iters) PCPM_TRY(queue(std::min(batch0, max_iters - launched)));
+  for (;;) {
+    const int slot = pending[0];
+    PCPM_TRY_HIP(hipEventSynchronize(g->ctl_ev[slot]));
+    *last = g->ctl_host[slot];
+    pending[0] = pending[1];
+    --npend;
+    if (last->done) return PCPM_OK;  // what is still in flight returns at once
+    if (launched >= max_iters) {
+      if (npend == 0) return PCPM_OK;
+      continue;
+    }
+    int64_t want = 64;
+    if (tol > 0.0) {
+      const double res = last->res, prev = last->res_prev;
+      double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
+      rho = std::min(std::max(rho, 0.05), 0.995);
+      const double est = res > 0.0 ? std::ceil(std::log(tol / res) / std::log(rho)) : 1.0;
+      const double ahead = static_cast<double>(launched - last->iter);  // queued behind this copy
+      want = static_cast<int64_t>(std::min(std::max(est - ahead, 1.0), 16.0));
+    }
+    PCPM_TRY(queue(std::min(want, max_iters - launched)));
+  }
+}
 }  // namespace pcpm

@@ -1180,54 +1180,10 @@ pcpm_status_t pcpm_pagerank(pcpm_png_t g, double d, double tol, int32_t max_iter
     PCPM_TRY(run_persistent(g, a, b, max_iters, st));
     return finish_solve(g, g->ctl_host[0], a, b, tol, iters, resid, res_hist, st);
   }
-  // Iterations go out in batches, each followed by a copy of the control
-  // block into one of two pinned slots and an event.  The host waits for the
-  // older of the two batches in flight and sizes the next one from the
-  // residual ratio it shows, counting the iterations already queued behind
-  // it, so the device always has work queued while the host decides.
-  // Iterations queued past convergence return at once.
-  int launched = 0;
-  int pending[2] = {-1, -1};  // FIFO of slots whose copy is in flight
-  int npend = 0;
-  auto queue = [&](int count) -> pcpm_status_t {
-    const int slot = npend == 0 ? 0 : 1 - pending[npend - 1];
-    for (int i = 0; i < count; ++i) {
-      const int it = launched + i;
-      const bool even = (it % 2) == 0;
-      PCPM_TRY(run_iteration(g, even ? a : b, even ? b : a, st));
-    }
-    launched += count;
-    PCPM_TRY_HIP(hipMemcpyAsync(&g->ctl_host[slot], g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    PCPM_TRY_HIP(hipEventRecord(g->ctl_ev[slot], st));
-    pending[npend++] = slot;
-    return PCPM_OK;
-  };
-  const int batch0 = tol > 0.0 ? 4 : 64;
-  PCPM_TRY(queue(std::min(batch0, max_iters)));
-  if (launched < max_iters) PCPM_TRY(queue(std::min(batch0, max_iters - launched)));
   Ctl c{};
-  for (;;) {
-    const int slot = pending[0];
-    PCPM_TRY_HIP(hipEventSynchronize(g->ctl_ev[slot]));
-    c = g->ctl_host[slot];
-    pending[0] = pending[1];
-    --npend;
-    if (c.done) break;  // what is still in flight returns at once
-    if (launched >= max_iters) {
-      if (npend == 0) break;
-      continue;
-    }
-    int want = 64;
-    if (tol > 0.0) {
-      const double res = c.res, prev = c.res_prev;
-      double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
-      rho = std::min(std::max(rho, 0.05), 0.995);
-      const double est = std::ceil(std::log(tol / res) / std::log(rho));
-      const int ahead = launched - c.iter;  // queued behind this copy
-      want = static_cast<int>(std::min(std::max(est - ahead, 1.0), 16.0));
-    }
-    PCPM_TRY(queue(std::min(want, max_iters - launched)));
-  }
+  PCPM_TRY(pipelined_iterations(
+      g, tol, max_iters, st,
+      [&](int64_t it) { return (it % 2) == 0 ? run_iteration(g, a, b, st) : run_iteration(g, b, a, st); }, &c));
   return finish_solve(g, c, a, b, tol, iters, resid, res_hist, st);
 }
 

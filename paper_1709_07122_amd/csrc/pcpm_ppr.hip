@@ -960,37 +960,24 @@ static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_i
   const int64_t cap = (static_cast<int64_t>(k + KT - 1) / KT + 1) * max_iters;
   int grid = 0;
   PCPM_TRY(ppr_persist_grid<KT>(g, &grid));
-  int64_t launched = 0;
-  int64_t next = std::min<int64_t>(tol > 0.0 ? 4 : 64, cap);
+  Ctl c{};
   if (grid > 0) {
-    PCPM_TRY(ppr_run_persistent<KT>(g, grid, d, k, cap, pr_out, a, b, st));
-    launched = cap;  // the launch ran every iteration it needed
+    PCPM_TRY(ppr_run_persistent<KT>(g, grid, d, k, cap, pr_out, a, b, st));  // every iteration it needed
+    c = g->ctl_host[0];
+  } else {
+    PCPM_TRY(pipelined_iterations(
+        g, tol, cap, st,
+        [&](int64_t it) {
+          return (it % 2) == 0 ? ppr_iteration<KT>(g, a, b, pr_out, k, d, st)
+                               : ppr_iteration<KT>(g, b, a, pr_out, k, d, st);
+        },
+        &c));
   }
-  while (launched < cap) {
-    for (int64_t i = 0; i < next; ++i) {
-      const bool even = ((launched + i) % 2) == 0;
-      PCPM_TRY(ppr_iteration<KT>(g, even ? a : b, even ? b : a, pr_out, k, d, st));
-    }
-    launched += next;
-    PCPM_TRY_HIP(hipMemcpyAsync(g->ctl_host, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    PCPM_TRY_HIP(hipStreamSynchronize(st));
-    if (g->ctl_host->done) break;
-    int64_t want = 64;
-    if (tol > 0.0) {
-      const double res = g->ctl_host->res, prev = g->ctl_host->res_prev;
-      double rho = (prev > 0.0 && res > 0.0) ? res / prev : 0.5;
-      rho = std::min(std::max(rho, 0.05), 0.995);
-      want = res > 0.0 ? static_cast<int64_t>(std::min(std::max(std::ceil(std::log(tol / res) / std::log(rho)), 1.0),
-                                                        16.0))
-                       : 1;
-    }
-    next = std::min(want, cap - launched);
-  }
-  if (!g->ctl_host->done)
+  if (!c.done)
     return set_error(PCPM_ERR_DEVICE, "personalised PageRank did not drain its queue in %d iterations (cap %lld)",
-                     g->ctl_host->iter, static_cast<long long>(cap));
+                     c.iter, static_cast<long long>(cap));
   if (k <= KT) {
-    const int it_done = g->ctl_host->iter;
+    const int it_done = c.iter;
     const float* xr = (it_done > 0 && ((it_done - 1) % 2) == 0) ? b : a;
     const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((n * k + 255) / 256, 8192));
     PCPM_LAUNCH("pcpm_ppr_store", k_ppr_store, dim3(blocks), dim3(256), 0, st, pr_out, xr, n, k, k, KT);
@@ -1004,7 +991,7 @@ static pcpm_status_t ppr_run(pcpm_png* g, double d, int k, double tol, int max_i
     iters[j] = it[j];
     if (!conv[j]) *all_converged = false;
   }
-  if (g->ctl_host->nonfinite) *nonfinite = true;
+  if (c.nonfinite) *nonfinite = true;
   return PCPM_OK;
 }
 
