@@ -246,6 +246,29 @@ def test_not_converged_keeps_valid_output():
     assert_ranks_close(res.pr.cpu().numpy(), oracle.pagerank(r, c, iters=5).x)
 
 
+@pytest.mark.parametrize("max_iters", [1, 2, 3, 4, 5, 7, 8, 9, 13, 30])
+def test_queued_iterations_past_the_end_change_nothing(max_iters):
+    """The solve keeps batches of iterations in flight while the host reads
+    the control block: whatever it queues past convergence or past max_iters
+    must leave the result, the iteration count and the residual history those
+    of exactly that many iterations."""
+    r, c = graphgen.rmat(12, 16, seed=4, relabel="random")
+    png = build(r, c, part_log2=8)
+    fixed = P.pagerank(png, tol=0.0, max_iters=max_iters)
+    assert fixed.iters == max_iters
+    capped = P.pagerank(png, tol=1e-12, max_iters=max_iters)
+    assert capped.status == P.PCPM_ERR_NOT_CONVERGED and capped.iters == max_iters
+    np.testing.assert_array_equal(capped.pr.cpu().numpy().view(np.uint32), fixed.pr.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(capped.res_hist, fixed.res_hist)
+    # to a tolerance the solve stops after the first iteration below it
+    tol = float(fixed.res_hist[-1]) * 1.0000001
+    conv = P.pagerank(png, tol=tol, max_iters=100)
+    first = int(np.argmax(fixed.res_hist < tol)) + 1
+    assert conv.converged and conv.iters == first
+    again = P.pagerank(png, tol=0.0, max_iters=first)
+    np.testing.assert_array_equal(conv.pr.cpu().numpy().view(np.uint32), again.pr.cpu().numpy().view(np.uint32))
+
+
 def test_poisoned_init_is_reported():
     r, c = graphgen.rmat(10, 8, seed=3)
     n = len(r) - 1
