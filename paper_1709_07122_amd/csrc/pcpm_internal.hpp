@@ -238,6 +238,13 @@ struct TimerScope {
   hipEvent_t start = nullptr;
 };
 
+// Position in the timing record (the number of launches recorded so far),
+// and removal of the records from a position on: a solve drops the launches
+// of iterations it queued past convergence (they return at once and would
+// dilute the per-kernel averages).  Assumes one thread records at a time.
+size_t timing_mark();
+void timing_discard_from(size_t pos);
+
 // Launch with optional event timing and a launch-error check.
 #define PCPM_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                     \
   do {                                                                                  \
@@ -495,9 +502,13 @@ pcpm_status_t pipelined_iterations(pcpm_png* g, double tol, int64_t max_iters, h
   int64_t launched = 0;
   int pending[2] = {-1, -1};  // FIFO of slots whose copy is in flight
   int npend = 0;
+  std::vector<size_t> marks;  // timing-record position at the start of each iteration
   auto queue = [&](int64_t count) -> pcpm_status_t {
     const int slot = npend == 0 ? 0 : 1 - pending[npend - 1];
-    for (int64_t i = 0; i < count; ++i) PCPM_TRY(step(launched + i));
+    for (int64_t i = 0; i < count; ++i) {
+      marks.push_back(timing_mark());
+      PCPM_TRY(step(launched + i));
+    }
     launched += count;
     PCPM_TRY_HIP(hipMemcpyAsync(&g->ctl_host[slot], g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     PCPM_TRY_HIP(hipEventRecord(g->ctl_ev[slot], st));
@@ -513,7 +524,10 @@ pcpm_status_t pipelined_iterations(pcpm_png* g, double tol, int64_t max_iters, h
     *last = g->ctl_host[slot];
     pending[0] = pending[1];
     --npend;
-    if (last->done) return PCPM_OK;  // what is still in flight returns at once
+    if (last->done) {  // what is still in flight returns at once
+      if (last->iter >= 0 && static_cast<size_t>(last->iter) < marks.size()) timing_discard_from(marks[last->iter]);
+      return PCPM_OK;
+    }
     if (launched >= max_iters) {
       if (npend == 0) return PCPM_OK;
       continue;

@@ -54,6 +54,26 @@ TimerScope::~TimerScope() {
   g_launches.push_back({name, start, stop});
 }
 
+size_t timing_mark() {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  return g_launches.size();
+}
+
+void timing_discard_from(size_t pos) {
+  std::vector<TimedLaunch> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (pos >= g_launches.size()) return;
+    drop.assign(g_launches.begin() + static_cast<std::ptrdiff_t>(pos), g_launches.end());
+    g_launches.resize(pos);
+  }
+  for (auto& l : drop) {
+    (void)hipEventSynchronize(l.stop);
+    (void)hipEventDestroy(l.start);
+    (void)hipEventDestroy(l.stop);
+  }
+}
+
 // ---- plain HBM streams (the measured ceiling of the iteration kernels) ----------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kStreamBlock = 256;
