@@ -392,6 +392,7 @@ def ppr_detail(P, torch, args):
                      "tile_width": tune.tile_width, "batched_ms": b_ms, "batched_persistent_launch_ms": p_ms,
                      "one_at_a_time_ms": s_ms, "one_at_a_time_part_log2": one.part_log2,
                      "one_at_a_time_update_order": one.update_order,
+                     "one_at_a_time_chunks": [one.scatter_chunk, one.gather_chunk],
                      "speedup": s_ms / b_ms, "iters_mean": float(res.iters.mean()), "iters_max": int(res.iters.max()),
                      "converged": bool(res.converged), "vector_gteps": m * vec_iters / (b_ms * 1e-3) / 1e9,
                      "single_iters_mean": float(np.mean([x.iters[0] for x in sres])),
