@@ -415,8 +415,9 @@ pcpm_status_t pcpm_hbm_stream(int32_t kind, const void* src /* (device) */, void
 
 /* How pcpm_pagerank and pcpm_ppr_batch run their iterations on a handle.
  * mode 1: one launch per phase (scatter, gather, merge, finalize, refill)
- * per iteration, iterations queued in batches between host checks of the
- * FP64 residuals.  mode 2: one persistent cooperative launch for the whole
+ * per iteration, iterations queued in batches, two batches in flight while
+ * the host reads the FP64 residual after the older one (iterations queued
+ * past convergence return at once and change nothing).  mode 2: one persistent cooperative launch for the whole
  * solve or batch, one workgroup per resident slot (pcpm_launch_grid),
  * grid-wide barriers between the phases, convergence and refills decided on
  * the device.  mode 0 (the default) is mode 1, the faster on MI355X.
