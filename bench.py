@@ -575,7 +575,8 @@ def main():
     ap.add_argument("--draws", type=int, default=1_000_000_000, help="uniform graph: edge draws")
     ap.add_argument("--iters", type=int, default=0, help="fixed iteration count (0: iterate to --tol)")
     ap.add_argument("--cpu-iters", type=int, default=0,
-                    help="oracle iterations of the CPU baseline (0: as many as the GPU solve took)")
+                    help="oracle iterations of the CPU baseline (0: as many as the GPU solve took, at least 100, "
+                         "about 10 s of host work at RMAT-24)")
     ap.add_argument("--edge-factor", type=float, default=16)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--part-log2", type=int, default=14)
@@ -644,7 +645,7 @@ def main():
     if not args.no_warm and args.iters == 0:
         warm = warm_detail(P, torch, png, args)
         detail["warm_start"] = warm
-    cpu_iters = args.cpu_iters if args.cpu_iters > 0 else main_res["iters"]
+    cpu_iters = args.cpu_iters if args.cpu_iters > 0 else max(main_res["iters"], 100)
     if not args.no_cpu_baseline and cpu_iters != main_res["iters"]:
         x_gpu = P.pagerank(png, d=args.d, tol=0.0, max_iters=cpu_iters, want_hist=False).pr.cpu().numpy()
     png.close()
