@@ -269,6 +269,35 @@ def test_queued_iterations_past_the_end_change_nothing(max_iters):
     np.testing.assert_array_equal(conv.pr.cpu().numpy().view(np.uint32), again.pr.cpu().numpy().view(np.uint32))
 
 
+def test_timing_counts_only_the_iterations_that_ran():
+    """Per-kernel timing leaves out the launches of iterations queued past
+    convergence (they return at once and would dilute the averages): a solve
+    of c iterations records c launches of each per-iteration kernel, in PageRank
+    and in batched personalised PageRank."""
+    r, c = graphgen.rmat(12, 16, seed=4, relabel="random")
+    n = len(r) - 1
+    png = build(r, c, part_log2=8)
+    P.timing_collect()
+    P.timing_enable(True)
+    try:
+        res = P.pagerank(png, tol=1e-6, max_iters=100)
+        torch.cuda.synchronize()
+        kt = P.timing_collect()
+        assert res.converged
+        for name in ("pcpm_scatter", "pcpm_gather", "pcpm_finalize"):
+            assert kt[name][0] == res.iters, (name, kt[name], res.iters)
+        off, seeds = graphgen.seed_sets(n, 3, seed=4)
+        ppr = P.ppr_batch(png, off, seeds, tol=1e-6, max_iters=100)
+        torch.cuda.synchronize()
+        kt = P.timing_collect()
+        assert ppr.converged
+        # three vectors share one tile: the batch runs as long as its slowest vector
+        assert kt["pcpm_ppr_gather"][0] == int(ppr.iters.max())
+    finally:
+        P.timing_enable(False)
+        P.timing_collect()
+
+
 def test_poisoned_init_is_reported():
     r, c = graphgen.rmat(10, 8, seed=3)
     n = len(r) - 1
