@@ -370,7 +370,7 @@ def ppr_detail(P, torch, args):
         def one_by_one():
             return [P.ppr_batch(png1, o, s, tol=args.tol, max_iters=args.max_iters) for o, s in singles]
 
-        s_ms, sres = _timed(torch, one_by_one, 1)
+        s_ms, sres = _timed(torch, one_by_one, reps)
         vec_iters = int(res.iters.sum())
         # per-kernel table of one batch (events around every launch); a launch
         # of the gather serves one tile of kt vector slots: 2m + 4kt E' + 8kt n
