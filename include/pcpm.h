@@ -440,7 +440,10 @@ const char* pcpm_last_error(void);
  * launch stream).  pcpm_timing_enable(1) starts recording, (0) stops it.
  * pcpm_timing_collect synchronises the recorded events, fills up to
  * max_entries (host) records, returns how many kernels had launches and
- * clears the record.
+ * clears the record.  The launches of iterations that pcpm_pagerank or
+ * pcpm_ppr_batch queued past convergence (they return at once) are dropped
+ * from the record, so a solve of c iterations records c launches of each
+ * per-iteration kernel.  Meant for one recording thread at a time.
  */
 typedef struct {
   char name[48];
